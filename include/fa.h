@@ -1,0 +1,260 @@
+/*
+ * fa.h -- polynomially preconditioned Krylov approximation of A^{-1/2} b and
+ * A^{1/2} b on an MI355X (gfx950), behind a plain C ABI.
+ *
+ * Method (Frommer, Ramirez-Hidalgo, Schweitzer, Tsolakis, "Polynomial
+ * preconditioning for the action of the matrix square root and inverse square
+ * root", arXiv 2401.06684):
+ *
+ *   Problem (Sec. 1): given A in C^{n x n} and b, approximate f(A) b for
+ *   f(z) = z^{-1/2} or z^{1/2} (principal branch, cut on (-inf, 0], Sec. 3)
+ *   with a polynomial Krylov method, without shifted linear solves.
+ *
+ *   Identity (Sec. 3, eq. prec_identity): with q ~ z^{-1/2} a polynomial whose
+ *   values on spec(A) lie in the open right half-plane,
+ *       A^{-1/2} b = (A q(A)^2)^{-1/2} q(A) b.
+ *   Left preconditioning (Algorithm 1): Arnoldi on A q(A)^2 from c = q(A) b,
+ *   f_m = V_m H_m^{-1/2} e_1 ||c||.  Each step applies A once and q(A) twice
+ *   (the three-stage product of Algorithm 1; q^2 is never formed).
+ *   Square root (Sec. 4): A^{1/2} b = A^{-1/2} (A b).
+ *   Stopping (Sec. 3.1, Sec. 6): every k steps the relative change of the
+ *   iterate ||f_j - f_{j-k}|| / ||f_j||, computed from the coefficient vectors
+ *   because V is orthonormal; k = max(1, 64 / (degree + 1)) by default.
+ *
+ * Everything on the path runs on the device (the operator, the polynomial
+ * chain, Gram-Schmidt, the final combination) except the small dense
+ * H_m^{-1/2} e_1, evaluated in FP64 on the host (Schur method, Sec. 3.1).
+ *
+ * Conventions for every entry point:
+ *   - Return value: 0 = FA_OK, > 0 = warning (outputs valid), < 0 = error
+ *     (outputs undefined).  fa_status_string() names each code.
+ *   - "d_" arguments are device pointers (memory of the current HIP device),
+ *     "h_" arguments host pointers.  All device memory is owned by the caller;
+ *     the library never allocates device memory.  It borrows operator arrays
+ *     given to fa_create_* until fa_destroy.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  All device
+ *     work of a call is enqueued on it; calls that return host results
+ *     synchronize that stream before returning.
+ *   - FP64 vectors are contiguous double[n]; complex vectors (FA_C128) are
+ *     contiguous interleaved (re, im) double pairs, i.e. C99 double complex,
+ *     same layout as torch.complex128.
+ *   - An fa_op is immutable after fa_poly_setup; concurrent fa_apply calls on
+ *     one op are allowed with distinct workspaces and streams.
+ */
+#ifndef FA_H
+#define FA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fa_op_s* fa_op;
+
+/* status codes */
+enum {
+  FA_OK = 0,
+  FA_WARN_NOT_CONVERGED = 1, /* m_max reached; x = f_{m_max} is returned           */
+  FA_ERR_ARG = -1,           /* invalid argument (null pointer, size, kind, ...)    */
+  FA_ERR_NO_POLY = -2,       /* fa_apply before fa_poly_setup                        */
+  FA_ERR_BRANCH = -3,        /* q not positive on the spectral interval, or a Ritz
+                                value with Re <= 0: the principal root is not
+                                guaranteed (Sec. 3, Sec. 5.1, Sec. 5.2)              */
+  FA_ERR_HESSENBERG = -4,    /* H_m has an eigenvalue on (-inf, 0]: no principal
+                                H_m^{-1/2}                                            */
+  FA_ERR_WORKSPACE = -5,     /* workspace null, misaligned or too small              */
+  FA_ERR_HIP = -6,           /* a HIP runtime call failed                            */
+  FA_ERR_NONFINITE = -7,     /* NaN or Inf met in b or in the iteration              */
+  FA_ERR_NO_INTERVAL = -8,   /* Chebyshev setup without a spectral interval          */
+  FA_ERR_UNSUPPORTED = -9    /* combination not available for this operator          */
+};
+
+/* value types */
+enum { FA_F64 = 0, FA_C128 = 1 };
+
+/* functions */
+enum { FA_INVSQRT = 0, FA_SQRT = 1 };
+
+/* matrix-free operators for fa_create_stencil */
+enum {
+  FA_STENCIL7 = 0, /* real 7-point (3D) or 5-point (nz = 1) stencil, zero Dirichlet  */
+  FA_WILSON4D = 1  /* Wilson-Dirac-like operator, periodic 4D lattice, complex       */
+};
+
+/* polynomial constructions for fa_poly_setup */
+enum {
+  FA_POLY_AUTO = 0, /* CHEB when the op has a real spectral interval, else RITZ     */
+  FA_POLY_CHEB = 1, /* Chebyshev interpolant of z^{-1/2} on [lo, hi], Sec. 5.1      */
+  FA_POLY_RITZ = 2  /* interpolant at Ritz values, Newton form, Leja order, Sec. 5.2 */
+};
+
+/* flags */
+enum {
+  FA_HERMITIAN = 1u,     /* create: A is Hermitian; apply uses Lanczos (3-term)        */
+  FA_FORCE_ARNOLDI = 4u, /* apply: Gram-Schmidt (CGS2) even for a Hermitian op          */
+  FA_PROFILE = 8u        /* apply: time every polynomial-chain launch with HIP events   */
+};
+
+typedef struct {
+  int32_t iters;          /* m: Krylov dimension of the returned iterate               */
+  int32_t converged;      /* 1 if est <= tol or a lucky breakdown occurred              */
+  int32_t breakdown;      /* 1 if h_{m+1,m} vanished (Krylov space invariant)           */
+  int32_t checks;         /* number of host evaluations of H_j^{-1/2} e_1               */
+  int64_t mvms;           /* products with A in fa_apply: m (2K + 1) + K (+1 for sqrt)  */
+  int64_t mvms_setup;     /* products with A in fa_poly_setup (Ritz: d)                 */
+  int64_t inner_products; /* length-n inner products in the iteration (CGS2: 2j + 1 at
+                             step j; Lanczos: 2 per step)                                */
+  double est_rel_change;  /* last ||f_j - f_{j-k}|| / ||f_j||                           */
+  double h_last;          /* h_{m+1,m}                                                  */
+  double ms_total;        /* wall time of fa_apply                                      */
+  double ms_host_fH;      /* host time spent in H_j^{-1/2} e_1                          */
+  double ms_chain;        /* FA_PROFILE: summed device time of chain launches           */
+  int64_t n_chain;        /* FA_PROFILE: number of chain launches timed                 */
+  double chain_bytes;     /* algorithmic HBM bytes of one chain launch (see DESIGN)     */
+} fa_stats;
+
+/*
+ * fa_create_csr -- borrow a CSR matrix (the sparse matrix-vector product of
+ * Sec. 6, Examples 1 and 3).
+ *   n, nnz       : order and stored entries (n >= 1, nnz >= 0, < 2^31)
+ *   d_rowptr     : int32[n + 1], d_rowptr[0] = 0, nondecreasing, d_rowptr[n] = nnz
+ *   d_colind     : int32[nnz], column indices in [0, n)
+ *   d_vals       : double[nnz] (FA_F64) or double complex[nnz] (FA_C128)
+ *   dtype        : FA_F64 or FA_C128 (vectors passed to fa_apply use the same type)
+ *   flags        : FA_HERMITIAN to select Lanczos in fa_apply
+ * The arrays are not copied or validated on the device; they must stay alive
+ * and unchanged until fa_destroy.  A CSR op has no spectral interval until
+ * fa_set_spectral_interval is called.
+ * Errors: FA_ERR_ARG.
+ */
+int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
+                  const int32_t* d_colind, const void* d_vals, int dtype, uint32_t flags,
+                  void* hip_stream);
+
+/*
+ * fa_create_stencil -- a matrix-free operator.
+ *   FA_STENCIL7: dims = {nx, ny, nz, 1}, x fastest (index i + nx (j + ny k));
+ *     params = 7 doubles {c0, c_xm, c_xp, c_ym, c_yp, c_zm, c_zp}:
+ *       (A u)_p = c0 u_p + c_xm u_{p-ex} + c_xp u_{p+ex} + c_ym u_{p-ey} + ...
+ *     neighbours outside the grid are zero.  Real (FA_F64) vectors.  When
+ *     c_dm c_dp > 0 in every direction the spectrum is real and the op gets the
+ *     exact interval c0 -+ sum_d 2 sqrt(c_dm c_dp) cos(pi / (N_d + 1)) (for the
+ *     Laplacian, the interval stated in Sec. 6, Example 1).
+ *   FA_WILSON4D: dims = {Lx, Ly, Lz, Lt} (each >= 2), params = {m0} (1 double):
+ *       (D psi)(x) = (4 + m0) psi(x) - 1/2 sum_mu [(I - g_mu) U_mu(x) psi(x + mu)
+ *                                                + (I + g_mu) U_mu(x - mu)^H psi(x - mu)]
+ *     periodic, chiral-basis Euclidean gamma matrices; 12 complex per site,
+ *     vectors [t][z][y][x][spin 4][colour 3] (FA_C128).  d_links: device
+ *     double complex[4][Lt][Lz][Ly][Lx][3][3] (direction mu = x, y, z, t, row
+ *     major 3x3), borrowed.  The Wilson-Dirac operator is the matrix of
+ *     Sec. 6, Example 2 (without clover term and chemical potential).
+ *   flags: FA_HERMITIAN allowed only for symmetric stencils.
+ * Errors: FA_ERR_ARG.
+ */
+int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double* params,
+                      int nparams, const void* d_links, uint32_t flags, void* hip_stream);
+
+/* Set (or replace) the real interval [lo, hi], 0 < lo < hi, assumed to hold
+ * spec(A); used by FA_POLY_CHEB (Sec. 5.1).  Errors: FA_ERR_ARG. */
+int fa_set_spectral_interval(fa_op op, double lo, double hi);
+
+/* Query the interval; returns FA_ERR_NO_INTERVAL if the op has none. */
+int fa_get_spectral_interval(fa_op op, double* lo, double* hi);
+
+/* Bytes of device workspace fa_poly_setup needs for `degree` (0 for CHEB). */
+size_t fa_poly_workspace_bytes(fa_op op, int degree, int method);
+
+/*
+ * fa_poly_setup -- choose the preconditioning polynomial q of degree K
+ * (K + 1 = the paper's d coefficients; K = 0 means q == 1, the plain method).
+ *   FA_POLY_CHEB (Sec. 5.1): Chebyshev interpolant of z^{-1/2} at the K + 1
+ *     first-kind Chebyshev points of [lo, hi]; q is checked positive on 10^4
+ *     points of [lo, hi] plus the nodes (else FA_ERR_BRANCH).
+ *   FA_POLY_RITZ (Sec. 5.2): K + 1 Arnoldi steps on A from d_start (a device
+ *     vector of length n, the caller's random start vector; it is normalized
+ *     internally and not modified); the Ritz values (eigenvalues of H_{K+1})
+ *     are the interpolation nodes of z^{-1/2}, stored in Newton form on the
+ *     Leja ordering with capacity scaling.  A Ritz value with Re <= 0 gives
+ *     FA_ERR_BRANCH.  Real operators whose Ritz values are not all real give
+ *     FA_ERR_UNSUPPORTED.  If Arnoldi breaks down after j < K + 1 steps the
+ *     degree becomes j - 1.  Needs d_workspace of fa_poly_workspace_bytes.
+ * Runs on hip_stream and synchronizes it.  Errors: FA_ERR_ARG, FA_ERR_BRANCH,
+ * FA_ERR_NO_INTERVAL, FA_ERR_WORKSPACE, FA_ERR_UNSUPPORTED, FA_ERR_HIP.
+ */
+int fa_poly_setup(fa_op op, int degree, int method, const void* d_start, void* d_workspace,
+                  size_t ws_bytes, void* hip_stream);
+
+/*
+ * fa_poly_get -- read back the polynomial (host arrays of at least degree + 1
+ * entries each; any pointer may be NULL).
+ *   method: FA_POLY_CHEB / FA_POLY_RITZ, or -1 for q == 1.
+ *   CHEB: coef[i] = c_i, interval = {lo, hi}.
+ *   RITZ: nodes_re/im = Leja-ordered Ritz values, coef_re/im = scaled Newton
+ *         coefficients eta_j, *rho = scaling: q(z) = sum_j eta_j prod_{i<j} (z - theta_i)/rho.
+ */
+int fa_poly_get(fa_op op, int* degree, int* method, double* coef_re, double* coef_im,
+                double* nodes_re, double* nodes_im, double* interval, double* rho);
+
+/* Bytes of device workspace fa_apply needs for Krylov dimension m_max:
+ * (m_max + 1) basis vectors + 3 chain vectors + reduction scratch + H. */
+size_t fa_workspace_bytes(fa_op op, int m_max, uint32_t flags);
+
+/*
+ * fa_apply -- x ~ A^{-1/2} b (kind FA_INVSQRT) or A^{1/2} b (FA_SQRT) by
+ * left polynomially preconditioned Arnoldi (Algorithm 1) with classical
+ * Gram-Schmidt applied twice, or Lanczos for FA_HERMITIAN ops.
+ *   d_b, d_x     : device vectors of length n (d_x must not alias d_b)
+ *   m_max        : maximal Krylov dimension (>= 1)
+ *   tol          : stop when ||f_j - f_{j-k}|| / ||f_j|| <= tol; tol <= 0 runs
+ *                  exactly m_max steps
+ *   check_every  : k; 0 selects max(1, 64 / (degree + 1))
+ *   d_workspace  : >= fa_workspace_bytes(op, m_max, flags) bytes, 256-byte aligned
+ *   stats        : filled if not NULL
+ * A zero b returns x = 0.  A lucky breakdown returns the exact iterate of the
+ * invariant Krylov space.  Returns FA_WARN_NOT_CONVERGED if m_max is reached
+ * with est > tol (x = f_{m_max}).
+ * Errors: FA_ERR_ARG, FA_ERR_NO_POLY, FA_ERR_WORKSPACE, FA_ERR_HESSENBERG,
+ * FA_ERR_NONFINITE, FA_ERR_HIP.
+ */
+int fa_apply(fa_op op, int kind, const void* d_b, void* d_x, int m_max, double tol,
+             int check_every, void* d_workspace, size_t ws_bytes, uint32_t flags,
+             void* hip_stream, fa_stats* stats);
+
+/* y = A x on the device (one operator application, the "mvm" of the paper's
+ * tables).  x, y: device vectors of length n, not aliased. */
+int fa_op_apply(fa_op op, const void* d_x, void* d_y, void* hip_stream);
+
+/* y = q(A) x by the polynomial's recurrence (Clenshaw for CHEB, Horner for
+ * RITZ), K products with A.  d_workspace: >= fa_workspace_bytes(op, 1, 0). */
+int fa_poly_apply(fa_op op, const void* d_x, void* d_y, void* d_workspace, size_t ws_bytes,
+                  void* hip_stream);
+
+/* Order n of the operator and its value type (FA_F64 / FA_C128). */
+int fa_op_info(fa_op op, int64_t* n, int* dtype);
+
+int fa_destroy(fa_op op);
+const char* fa_status_string(int status);
+
+/*
+ * fa_dense_invsqrt_e1 -- host-only FP64 routine used at every stopping check:
+ * z = H^{-1/2} (beta e_1) for an m x m upper Hessenberg H (column-major, leading
+ * dimension ldh >= m), by reduction to complex Schur form with shifted QR,
+ * the principal square root of the triangular factor (Bjorck-Hammarling
+ * recurrence) and a triangular solve (Sec. 3.1).  dtype FA_F64: h and z are
+ * double arrays; FA_C128: interleaved complex.  Needs no GPU.
+ * Errors: FA_ERR_ARG, FA_ERR_HESSENBERG (eigenvalue on (-inf, 0] or QR did not
+ * converge).
+ */
+int fa_dense_invsqrt_e1(int m, int dtype, const double* h_H, int ldh, double beta, double* h_z);
+
+/* Host-only: z = T^{-1/2} (beta e_1) for the symmetric tridiagonal T with
+ * diagonal alpha[m] and off-diagonal offd[m-1] (Lanczos).  Errors as above. */
+int fa_dense_tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double beta,
+                                double* z);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FA_H */

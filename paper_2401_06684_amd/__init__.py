@@ -1,0 +1,272 @@
+"""MI355X-native polynomially preconditioned Krylov approximation of A^{-1/2} b
+and A^{1/2} b (Frommer, Ramirez-Hidalgo, Schweitzer, Tsolakis, arXiv 2401.06684).
+
+Thin binding over the C ABI of ``libfa.so`` (include/fa.h): every step of the
+method runs in the library's HIP kernels and host runtime; this module only
+marshals arguments.  PyTorch provides device memory and the current stream.
+
+    import torch, paper_2401_06684_amd as fa
+    op = fa.Stencil7((nx, ny, nz), coeffs)          # or fa.CSR(...), fa.Wilson(...)
+    op.poly_setup(16)                                # Chebyshev on the exact interval
+    x, stats = op.apply(b, kind="invsqrt", m_max=200, tol=1e-8)
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import (FA_C128, FA_F64, FA_FORCE_ARNOLDI, FA_HERMITIAN, FA_INVSQRT,  # noqa: F401
+                   FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_RITZ, FA_PROFILE, FA_SQRT, FAError,
+                   check, lib)
+
+__all__ = ["Stencil7", "CSR", "Wilson", "FAError", "lib", "dense_invsqrt_e1",
+           "dense_tridiag_invsqrt_e1"]
+
+_KIND = {"invsqrt": FA_INVSQRT, "sqrt": FA_SQRT}
+_METHOD = {"auto": FA_POLY_AUTO, "cheb": FA_POLY_CHEB, "ritz": FA_POLY_RITZ}
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def workspace(nbytes, device):
+    """A 256-byte aligned device buffer of nbytes (torch-owned)."""
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, C.c_void_p(buf.data_ptr() + off), int(nbytes)
+
+
+class Operator:
+    """Common part of all operators: polynomial setup and fa_apply."""
+
+    dtype = torch.float64
+
+    def __init__(self, handle, device, keep):
+        self._h = handle
+        self.device = device
+        self._keep = keep  # borrowed device arrays stay alive with the op
+        n = C.c_int64()
+        dt = C.c_int()
+        check(lib().fa_op_info(self._h, C.byref(n), C.byref(dt)), "fa_op_info")
+        self.n = n.value
+        self.dtype = torch.complex128 if dt.value == FA_C128 else torch.float64
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                lib().fa_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # ---- spectral interval / polynomial ----------------------------------
+    def set_spectral_interval(self, lo, hi):
+        check(lib().fa_set_spectral_interval(self._h, lo, hi), "fa_set_spectral_interval")
+
+    def spectral_interval(self):
+        lo, hi = C.c_double(), C.c_double()
+        st = lib().fa_get_spectral_interval(self._h, C.byref(lo), C.byref(hi))
+        if st == _lib.FA_ERR_NO_INTERVAL:
+            return None
+        check(st, "fa_get_spectral_interval")
+        return lo.value, hi.value
+
+    def poly_setup(self, degree, method="auto", start=None):
+        """Choose q of the given degree (0: plain method).  method: auto|cheb|ritz.
+
+        For Ritz polynomials `start` is the start vector of the setup Arnoldi
+        run (a device tensor of length n).
+        """
+        m = _METHOD[method]
+        nbytes = lib().fa_poly_workspace_bytes(self._h, degree, m)
+        keep = None
+        wsp = C.c_void_p(0)
+        if nbytes:
+            keep, wsp, nbytes = workspace(nbytes, self.device)
+        sp = C.c_void_p(0)
+        if start is not None:
+            start = self._vec(start, "start")
+            sp = _ptr(start)
+        st = lib().fa_poly_setup(self._h, degree, m, sp, wsp, nbytes, _stream(self.device))
+        check(st, "fa_poly_setup")
+        del keep
+
+    def poly(self):
+        """The polynomial as a dict (method, degree, coefficients, nodes, ...)."""
+        deg, meth = C.c_int(), C.c_int()
+        check(lib().fa_poly_get(self._h, C.byref(deg), C.byref(meth), None, None, None, None,
+                                None, None), "fa_poly_get")
+        K = deg.value
+        arr = lambda: (C.c_double * (K + 1))()  # noqa: E731
+        cr, ci, nr, ni = arr(), arr(), arr(), arr()
+        iv = (C.c_double * 2)()
+        rho = C.c_double()
+        check(lib().fa_poly_get(self._h, None, None, cr, ci, nr, ni, iv, C.byref(rho)),
+              "fa_poly_get")
+        meth_name = {-1: "one", FA_POLY_CHEB: "cheb", FA_POLY_RITZ: "ritz"}[meth.value]
+        out = {"method": meth_name, "degree": K}
+        if meth_name == "cheb":
+            out.update(c=list(cr), interval=(iv[0], iv[1]))
+        elif meth_name == "ritz":
+            out.update(eta=[complex(a, b) for a, b in zip(cr, ci)],
+                       theta=[complex(a, b) for a, b in zip(nr, ni)], rho=rho.value)
+        return out
+
+    # ---- application -------------------------------------------------------
+    def _vec(self, v, name):
+        if not (isinstance(v, torch.Tensor) and v.is_cuda):
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if v.dtype != self.dtype or v.numel() != self.n or not v.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of {self.n} entries")
+        return v
+
+    def workspace_bytes(self, m_max):
+        return lib().fa_workspace_bytes(self._h, m_max, 0)
+
+    def _workspace(self, m_max):
+        nbytes = self.workspace_bytes(m_max)
+        ws = self._ws.get("apply")
+        if ws is None or ws[2] < nbytes:
+            self._ws.pop("apply", None)
+            ws = workspace(nbytes, self.device)
+            self._ws["apply"] = ws
+        return ws
+
+    def release_workspace(self):
+        self._ws.clear()
+
+    def apply(self, b, kind="invsqrt", m_max=100, tol=1e-10, check_every=0, out=None,
+              force_arnoldi=False, profile=False, raise_not_converged=False):
+        """x ~ A^{-1/2} b or A^{1/2} b.  Returns (x, stats dict)."""
+        b = self._vec(b, "b")
+        x = out if out is not None else torch.empty_like(b)
+        self._vec(x, "out")
+        _, wsp, nbytes = self._workspace(m_max)
+        flags = (FA_FORCE_ARNOLDI if force_arnoldi else 0) | (FA_PROFILE if profile else 0)
+        stats = _lib.fa_stats()
+        st = lib().fa_apply(self._h, _KIND[kind], _ptr(b), _ptr(x), m_max, float(tol),
+                            check_every, wsp, nbytes, flags, _stream(self.device),
+                            C.byref(stats))
+        check(st, "fa_apply")
+        if st == _lib.FA_WARN_NOT_CONVERGED and raise_not_converged:
+            raise FAError(st, "fa_apply")
+        d = stats.as_dict()
+        d["status"] = st
+        return x, d
+
+    def op_apply(self, x, out=None):
+        """y = A x (one operator application)."""
+        x = self._vec(x, "x")
+        y = out if out is not None else torch.empty_like(x)
+        check(lib().fa_op_apply(self._h, _ptr(x), _ptr(y), _stream(self.device)), "fa_op_apply")
+        return y
+
+    def poly_apply(self, x, out=None):
+        """y = q(A) x."""
+        x = self._vec(x, "x")
+        y = out if out is not None else torch.empty_like(x)
+        nbytes = lib().fa_workspace_bytes(self._h, 1, 0)
+        keep, wsp, nbytes = workspace(nbytes, self.device)
+        check(lib().fa_poly_apply(self._h, _ptr(x), _ptr(y), wsp, nbytes, _stream(self.device)),
+              "fa_poly_apply")
+        torch.cuda.current_stream(self.device).synchronize()
+        del keep
+        return y
+
+
+class Stencil7(Operator):
+    """Real 7-point (nz > 1) or 5-point (nz = 1) stencil, zero Dirichlet boundary.
+
+    coeffs = [c0, c_xm, c_xp, c_ym, c_yp, c_zm, c_zp]; vectors are x-fastest.
+    """
+
+    def __init__(self, dims, coeffs, hermitian=False, device="cuda"):
+        nx, ny, nz = (int(d) for d in dims)
+        h = C.c_void_p()
+        d4 = (C.c_int32 * 4)(nx, ny, nz, 1)
+        c7 = (C.c_double * 7)(*[float(c) for c in coeffs])
+        st = lib().fa_create_stencil(C.byref(h), _lib.FA_STENCIL7, d4, c7, 7, None,
+                                     FA_HERMITIAN if hermitian else 0, None)
+        check(st, "fa_create_stencil")
+        super().__init__(h, torch.device(device), None)
+        self.dims = (nx, ny, nz)
+
+
+class CSR(Operator):
+    """Sparse matrix in CSR form (int32 indices; float64 or complex128 values)."""
+
+    def __init__(self, rowptr, colind, vals, hermitian=False, device="cuda"):
+        dev = torch.device(device)
+        rp = torch.as_tensor(rowptr).to(device=dev, dtype=torch.int32).contiguous()
+        ci = torch.as_tensor(colind).to(device=dev, dtype=torch.int32).contiguous()
+        va = torch.as_tensor(vals).to(device=dev).contiguous()
+        if va.dtype not in (torch.float64, torch.complex128):
+            va = va.to(torch.float64)
+        dt = FA_C128 if va.dtype == torch.complex128 else FA_F64
+        n = rp.numel() - 1
+        h = C.c_void_p()
+        st = lib().fa_create_csr(C.byref(h), n, ci.numel(), _ptr(rp), _ptr(ci), _ptr(va), dt,
+                                 FA_HERMITIAN if hermitian else 0, None)
+        check(st, "fa_create_csr")
+        super().__init__(h, dev, (rp, ci, va))
+
+
+class Wilson(Operator):
+    """Wilson-Dirac-like operator on a periodic 4D lattice (12 complex per site).
+
+    links: complex128 tensor [4][Lt][Lz][Ly][Lx][3][3] (mu = x, y, z, t).
+    """
+
+    def __init__(self, links, m0, device="cuda"):
+        dev = torch.device(device)
+        U = torch.as_tensor(links).to(device=dev, dtype=torch.complex128).contiguous()
+        if U.dim() != 7 or U.shape[0] != 4 or tuple(U.shape[-2:]) != (3, 3):
+            raise ValueError("links must have shape (4, Lt, Lz, Ly, Lx, 3, 3)")
+        Lt, Lz, Ly, Lx = (int(s) for s in U.shape[1:5])
+        h = C.c_void_p()
+        d4 = (C.c_int32 * 4)(Lx, Ly, Lz, Lt)
+        p = (C.c_double * 1)(float(m0))
+        st = lib().fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1, _ptr(U), 0, None)
+        check(st, "fa_create_stencil")
+        super().__init__(h, dev, (U,))
+        self.lattice = (Lt, Lz, Ly, Lx)
+
+
+def dense_invsqrt_e1(H, beta):
+    """Host routine: H^{-1/2} (beta e_1) for an upper Hessenberg numpy array."""
+    import numpy as np
+    H = np.asarray(H)
+    m = H.shape[0]
+    cplx = np.iscomplexobj(H)
+    flat = np.ascontiguousarray(H.astype(np.complex128 if cplx else np.float64).reshape(-1, order="F"))
+    src = flat.view(np.float64) if cplx else flat
+    z = np.zeros(2 * m if cplx else m)
+    dp = C.POINTER(C.c_double)
+    st = lib().fa_dense_invsqrt_e1(m, FA_C128 if cplx else FA_F64, src.ctypes.data_as(dp), m,
+                                   float(beta), z.ctypes.data_as(dp))
+    check(st, "fa_dense_invsqrt_e1")
+    return z.view(np.complex128) if cplx else z
+
+
+def dense_tridiag_invsqrt_e1(alpha, offd, beta):
+    """Host routine: T^{-1/2} (beta e_1) for a symmetric tridiagonal T."""
+    import numpy as np
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    o = np.ascontiguousarray(offd, dtype=np.float64)
+    if o.size == 0:
+        o = np.zeros(1)
+    z = np.zeros(a.size)
+    dp = C.POINTER(C.c_double)
+    st = lib().fa_dense_tridiag_invsqrt_e1(a.size, a.ctypes.data_as(dp), o.ctypes.data_as(dp),
+                                           float(beta), z.ctypes.data_as(dp))
+    check(st, "fa_dense_tridiag_invsqrt_e1")
+    return z

@@ -1,0 +1,298 @@
+// C ABI of the library (declared in include/fa.h): argument validation and
+// dispatch to the runtime.  No exception crosses the boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dense.hpp"
+#include "fa_internal.hpp"
+#include "solver.hpp"
+
+using namespace fa;
+
+struct fa_op_s {
+  Op op;
+};
+
+namespace {
+hipStream_t stream_of(void* s) { return (hipStream_t)s; }
+
+// exact real eigenvalue interval of a 7-point stencil when every direction's
+// off-diagonal pair has a positive product (diagonally similar to symmetric):
+// c0 -+ sum_d 2 sqrt(c_dm c_dp) cos(pi / (N_d + 1))
+bool stencil_interval(const Op& op, double* lo, double* hi) {
+  double spread = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const int N = op.dims[d];
+    const double p = op.coef[1 + 2 * d] * op.coef[2 + 2 * d];
+    if (N == 1 || p == 0.0) continue;
+    if (p < 0.0) return false;
+    spread += 2.0 * std::sqrt(p) * std::cos(M_PI / (N + 1));
+  }
+  *lo = op.coef[0] - spread;
+  *hi = op.coef[0] + spread;
+  return true;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return FA_ERR_ARG;
+  } catch (...) {
+    return FA_ERR_ARG;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
+                  const int32_t* d_colind, const void* d_vals, int dtype, uint32_t flags,
+                  void* hip_stream) {
+  (void)hip_stream;
+  if (!out || n < 1 || n >= (int64_t(1) << 31) || nnz < 0 || nnz >= (int64_t(1) << 31) ||
+      !d_rowptr || (nnz > 0 && (!d_colind || !d_vals)) || (dtype != FA_F64 && dtype != FA_C128) ||
+      (flags & ~uint32_t(FA_HERMITIAN)))
+    return FA_ERR_ARG;
+  return guarded([&] {
+    fa_op h = new fa_op_s;
+    Op& op = h->op;
+    op.kind = OP_CSR;
+    op.dtype = dtype;
+    op.n = n;
+    op.flags = flags;
+    op.rowptr = d_rowptr;
+    op.colind = d_colind;
+    op.vals = d_vals;
+    op.nnz = nnz;
+    // lanes per row: the power of two nearest above the mean row length
+    const double avg = (double)nnz / (double)n;
+    int g = 1;
+    while (g < 64 && g < avg) g <<= 1;
+    op.csr_group = g;
+    *out = h;
+    return FA_OK;
+  });
+}
+
+int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double* params,
+                      int nparams, const void* d_links, uint32_t flags, void* hip_stream) {
+  (void)hip_stream;
+  if (!out || !dims || !params) return FA_ERR_ARG;
+  if (flags & ~uint32_t(FA_HERMITIAN)) return FA_ERR_ARG;
+  for (int d = 0; d < 4; ++d)
+    if (dims[d] < 1) return FA_ERR_ARG;
+  return guarded([&] {
+    Op op;
+    if (kind == FA_STENCIL7) {
+      if (nparams != 7 || dims[3] != 1) return FA_ERR_ARG;
+      const int64_t n = (int64_t)dims[0] * dims[1] * dims[2];
+      if (n >= (int64_t(1) << 31)) return FA_ERR_ARG;
+      op.kind = OP_STENCIL7;
+      op.dtype = FA_F64;
+      op.n = n;
+      for (int i = 0; i < 7; ++i) {
+        if (!std::isfinite(params[i])) return FA_ERR_ARG;
+        op.coef[i] = params[i];
+      }
+      for (int d = 0; d < 3; ++d) op.dims[d] = dims[d];
+      if (flags & FA_HERMITIAN)
+        for (int d = 0; d < 3; ++d)
+          if (op.coef[1 + 2 * d] != op.coef[2 + 2 * d]) return FA_ERR_ARG;
+      double lo, hi;
+      if (stencil_interval(op, &lo, &hi) && lo > 0.0) {
+        op.has_interval = true;
+        op.lo = lo;
+        op.hi = hi;
+      }
+    } else if (kind == FA_WILSON4D) {
+      if (nparams != 1 || !d_links || (flags & FA_HERMITIAN)) return FA_ERR_ARG;
+      for (int d = 0; d < 4; ++d)
+        if (dims[d] < 2) return FA_ERR_ARG;
+      const int64_t V = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
+      if (V * 12 >= (int64_t(1) << 31)) return FA_ERR_ARG;
+      op.kind = OP_WILSON;
+      op.dtype = FA_C128;
+      op.n = V * 12;
+      for (int d = 0; d < 4; ++d) op.dims[d] = dims[d];
+      op.links = d_links;
+      op.m0 = params[0];
+      if (!std::isfinite(op.m0)) return FA_ERR_ARG;
+    } else {
+      return FA_ERR_ARG;
+    }
+    op.flags = flags;
+    fa_op h = new fa_op_s;
+    h->op = op;
+    *out = h;
+    return FA_OK;
+  });
+}
+
+int fa_set_spectral_interval(fa_op op, double lo, double hi) {
+  if (!op || !(lo > 0.0) || !(hi > lo) || !std::isfinite(hi)) return FA_ERR_ARG;
+  op->op.has_interval = true;
+  op->op.lo = lo;
+  op->op.hi = hi;
+  return FA_OK;
+}
+
+int fa_get_spectral_interval(fa_op op, double* lo, double* hi) {
+  if (!op || !lo || !hi) return FA_ERR_ARG;
+  if (!op->op.has_interval) return FA_ERR_NO_INTERVAL;
+  *lo = op->op.lo;
+  *hi = op->op.hi;
+  return FA_OK;
+}
+
+size_t fa_poly_workspace_bytes(fa_op op, int degree, int method) {
+  if (!op || degree < 0) return 0;
+  if (method == FA_POLY_AUTO) method = op->op.has_interval ? FA_POLY_CHEB : FA_POLY_RITZ;
+  return poly_workspace_bytes(op->op, degree, method);
+}
+
+int fa_poly_setup(fa_op op, int degree, int method, const void* d_start, void* d_workspace,
+                  size_t ws_bytes, void* hip_stream) {
+  if (!op || degree < 0 || method < FA_POLY_AUTO || method > FA_POLY_RITZ) return FA_ERR_ARG;
+  return guarded([&] {
+    int64_t mv = 0;
+    return poly_setup(op->op, degree, method, d_start, d_workspace, ws_bytes,
+                      stream_of(hip_stream), &mv);
+  });
+}
+
+int fa_poly_get(fa_op op, int* degree, int* method, double* coef_re, double* coef_im,
+                double* nodes_re, double* nodes_im, double* interval, double* rho) {
+  if (!op) return FA_ERR_ARG;
+  if (!op->op.poly_ready) return FA_ERR_NO_POLY;
+  const Poly& q = op->op.poly;
+  if (degree) *degree = q.degree;
+  if (method) *method = q.method;
+  if (q.method == FA_POLY_CHEB) {
+    for (int i = 0; i <= q.degree; ++i) {
+      if (coef_re) coef_re[i] = q.c[i];
+      if (coef_im) coef_im[i] = 0.0;
+    }
+    if (interval) {
+      interval[0] = q.a;
+      interval[1] = q.b;
+    }
+  } else if (q.method == FA_POLY_RITZ) {
+    for (int i = 0; i <= q.degree; ++i) {
+      if (coef_re) coef_re[i] = q.eta[i].real();
+      if (coef_im) coef_im[i] = q.eta[i].imag();
+      if (nodes_re) nodes_re[i] = q.theta[i].real();
+      if (nodes_im) nodes_im[i] = q.theta[i].imag();
+    }
+    if (rho) *rho = q.rho;
+  }
+  return FA_OK;
+}
+
+size_t fa_workspace_bytes(fa_op op, int m_max, uint32_t flags) {
+  (void)flags;
+  if (!op || m_max < 1) return 0;
+  return make_layout(op->op, m_max).bytes;
+}
+
+int fa_apply(fa_op op, int kind, const void* d_b, void* d_x, int m_max, double tol,
+             int check_every, void* d_workspace, size_t ws_bytes, uint32_t flags,
+             void* hip_stream, fa_stats* stats) {
+  if (!op || !d_b || !d_x || d_b == d_x || m_max < 1 || check_every < 0 ||
+      (kind != FA_INVSQRT && kind != FA_SQRT) || !std::isfinite(tol) ||
+      (flags & ~uint32_t(FA_FORCE_ARNOLDI | FA_PROFILE)))
+    return FA_ERR_ARG;
+  if (!op->op.poly_ready) return FA_ERR_NO_POLY;
+  if ((int64_t)m_max > op->op.n) return FA_ERR_ARG;
+  return guarded([&] {
+    return apply(op->op, kind, d_b, d_x, m_max, tol, check_every, d_workspace, ws_bytes, flags,
+                 stream_of(hip_stream), stats);
+  });
+}
+
+int fa_op_apply(fa_op op, const void* d_x, void* d_y, void* hip_stream) {
+  if (!op || !d_x || !d_y || d_x == d_y) return FA_ERR_ARG;
+  return op_apply(op->op, d_x, d_y, stream_of(hip_stream));
+}
+
+int fa_poly_apply(fa_op op, const void* d_x, void* d_y, void* d_workspace, size_t ws_bytes,
+                  void* hip_stream) {
+  if (!op || !d_x || !d_y || d_x == d_y) return FA_ERR_ARG;
+  if (!op->op.poly_ready) return FA_ERR_NO_POLY;
+  const Layout L = make_layout(op->op, 1);
+  if (!d_workspace || ws_bytes < L.bytes || ((uintptr_t)d_workspace & 255)) return FA_ERR_WORKSPACE;
+  return guarded([&] {
+    return poly_apply_public(op->op, d_x, d_y, d_workspace, stream_of(hip_stream));
+  });
+}
+
+int fa_op_info(fa_op op, int64_t* n, int* dtype) {
+  if (!op) return FA_ERR_ARG;
+  if (n) *n = op->op.n;
+  if (dtype) *dtype = op->op.dtype;
+  return FA_OK;
+}
+
+int fa_destroy(fa_op op) {
+  delete op;
+  return FA_OK;
+}
+
+const char* fa_status_string(int status) {
+  switch (status) {
+    case FA_OK: return "FA_OK";
+    case FA_WARN_NOT_CONVERGED: return "FA_WARN_NOT_CONVERGED: m_max reached before the stopping test";
+    case FA_ERR_ARG: return "FA_ERR_ARG: invalid argument";
+    case FA_ERR_NO_POLY: return "FA_ERR_NO_POLY: fa_poly_setup has not been called";
+    case FA_ERR_BRANCH: return "FA_ERR_BRANCH: polynomial not in the right half-plane on the spectrum";
+    case FA_ERR_HESSENBERG: return "FA_ERR_HESSENBERG: H_m has an eigenvalue on (-inf, 0]";
+    case FA_ERR_WORKSPACE: return "FA_ERR_WORKSPACE: workspace null, misaligned or too small";
+    case FA_ERR_HIP: return "FA_ERR_HIP: a HIP runtime call failed";
+    case FA_ERR_NONFINITE: return "FA_ERR_NONFINITE: NaN or Inf in the input or iteration";
+    case FA_ERR_NO_INTERVAL: return "FA_ERR_NO_INTERVAL: no spectral interval for Chebyshev";
+    case FA_ERR_UNSUPPORTED: return "FA_ERR_UNSUPPORTED: combination not available for this operator";
+    default: return "unknown status";
+  }
+}
+
+int fa_dense_invsqrt_e1(int m, int dtype, const double* h_H, int ldh, double beta, double* h_z) {
+  if (m < 1 || ldh < m || !h_H || !h_z || (dtype != FA_F64 && dtype != FA_C128)) return FA_ERR_ARG;
+  return guarded([&] {
+    std::vector<cd> H((size_t)m * m), z(m);
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) {
+        const size_t k = (size_t)j * ldh + i;
+        H[(size_t)j * m + i] =
+            (i > j + 1) ? cd(0.0) : (dtype == FA_C128 ? cd(h_H[2 * k], h_H[2 * k + 1]) : cd(h_H[k], 0.0));
+      }
+    const int st = hess_invsqrt_e1(m, H.data(), m, beta, z.data());
+    if (st != DENSE_OK) return FA_ERR_HESSENBERG;
+    for (int i = 0; i < m; ++i) {
+      if (dtype == FA_C128) {
+        h_z[2 * i] = z[i].real();
+        h_z[2 * i + 1] = z[i].imag();
+      } else {
+        h_z[i] = z[i].real();
+      }
+    }
+    return FA_OK;
+  });
+}
+
+int fa_dense_tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double beta,
+                                double* z) {
+  if (m < 1 || !alpha || !z || (m > 1 && !offd)) return FA_ERR_ARG;
+  return guarded([&] {
+    std::vector<double> of(std::max(m - 1, 1), 0.0);
+    for (int i = 0; i + 1 < m; ++i) of[i] = offd[i];
+    const int st = tridiag_invsqrt_e1(m, alpha, of.data(), beta, z);
+    return st == DENSE_OK ? FA_OK : FA_ERR_HESSENBERG;
+  });
+}
+
+}  // extern "C"

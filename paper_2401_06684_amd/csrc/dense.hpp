@@ -1,0 +1,59 @@
+// Host FP64 dense linear algebra for the small problems of the method:
+//   - H_m^{-1/2} e_1 for an upper Hessenberg H_m (Sec. 3.1: Schur form, principal
+//     square root of the triangular factor, then a solve),
+//   - T_m^{-1/2} e_1 for a symmetric tridiagonal T_m (Lanczos),
+//   - eigenvalues of H_d (Ritz values, Sec. 5.2),
+//   - Chebyshev interpolation coefficients (Sec. 5.1), Leja ordering and Newton
+//     divided differences (Sec. 5.2).
+// No LAPACK: everything is written here so the library has no host BLAS/LAPACK
+// dependency.
+#pragma once
+#include <complex>
+#include <vector>
+
+namespace fa {
+
+using cd = std::complex<double>;
+
+enum DenseStatus { DENSE_OK = 0, DENSE_BRANCH = 1, DENSE_NOCONV = 2 };
+
+// Complex Schur form of an upper Hessenberg matrix by the single-shift QR
+// algorithm with Wilkinson shifts.  T (m x m, column-major, ld m) is
+// overwritten by the upper triangular factor; the plane rotations are kept so
+// that Q^H v and Q v can be applied to vectors afterwards (H = Q T Q^H).
+struct Schur {
+  int m = 0;
+  std::vector<cd> T;
+  struct Rot { int k; double c; cd s; };
+  std::vector<Rot> rots;
+  int compute(int m, const cd* H, int ldh);  // DENSE_OK or DENSE_NOCONV
+  void apply_QH(cd* v) const;                // v <- Q^H v
+  void apply_Q(cd* v) const;                 // v <- Q v
+  cd t(int i, int j) const { return T[(size_t)j * m + i]; }
+};
+
+// z = H^{-1/2} (beta e_1); H complex upper Hessenberg (column-major, ldh).
+int hess_invsqrt_e1(int m, const cd* H, int ldh, double beta, cd* z);
+
+// z = T^{-1/2} (beta e_1); T symmetric tridiagonal.
+int tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double beta,
+                       double* z);
+
+// eigenvalues of an upper Hessenberg matrix
+int hess_eigenvalues(int m, const cd* H, int ldh, cd* ev);
+
+// c_0..c_K of the Chebyshev interpolant of z^{-1/2} on [a, b] at K+1
+// first-kind Chebyshev points.
+void cheb_coefficients(double a, double b, int K, double* c);
+// value of sum_i c_i T_i((2z - a - b)/(b - a)) at a real point (Clenshaw)
+double cheb_eval(const double* c, int K, double a, double b, double z);
+
+// Leja ordering (largest modulus first, then maximal product of distances;
+// with pair_conjugates a non-real node is followed by its conjugate).
+std::vector<cd> leja_order(const std::vector<cd>& nodes, bool pair_conjugates);
+// capacity estimate rho = (prod_{i<d-1} |t_{d-1} - t_i|)^{1/(d-1)}
+double leja_capacity(const std::vector<cd>& t);
+// scaled Newton divided differences of z^{-1/2}: eta_j = f[t_0..t_j] rho^j
+std::vector<cd> newton_invsqrt(const std::vector<cd>& t, double rho);
+
+}  // namespace fa

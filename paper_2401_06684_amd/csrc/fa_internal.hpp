@@ -1,0 +1,99 @@
+// Internal declarations shared by the runtime (host) and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/fa.h"
+
+namespace fa {
+
+using cd = std::complex<double>;
+
+// complex FP64 on the device: interleaved (re, im), 16-byte aligned
+struct __attribute__((aligned(16))) cplx {
+  double x, y;
+};
+
+enum OpKind { OP_CSR = 0, OP_STENCIL7 = 1, OP_WILSON = 2 };
+
+// the preconditioning polynomial, in the representation the chain kernels use
+struct Poly {
+  int method = -1;  // -1: q == 1; FA_POLY_CHEB; FA_POLY_RITZ
+  int degree = 0;   // K
+  double a = 0, b = 0;        // CHEB interval
+  std::vector<double> c;      // CHEB coefficients c_0..c_K
+  std::vector<cd> theta;      // RITZ Leja-ordered nodes
+  std::vector<cd> eta;        // RITZ scaled Newton coefficients
+  double rho = 1.0;           // RITZ scaling
+};
+
+struct Op {
+  OpKind kind;
+  int dtype;  // FA_F64 / FA_C128
+  int64_t n;
+  uint32_t flags;
+  // CSR
+  const int32_t* rowptr = nullptr;
+  const int32_t* colind = nullptr;
+  const void* vals = nullptr;
+  int64_t nnz = 0;
+  int csr_group = 1;  // lanes per row
+  // stencil
+  int dims[4] = {1, 1, 1, 1};
+  double coef[7] = {0, 0, 0, 0, 0, 0, 0};
+  // Wilson
+  const void* links = nullptr;
+  double m0 = 0.0;
+  // spectral interval
+  bool has_interval = false;
+  double lo = 0, hi = 0;
+  Poly poly;
+  bool poly_ready = false;
+};
+
+// One fused chain launch: out = alpha A x + beta x + g0 y0 + g1 y1, with y0 /
+// y1 optional (nullptr).  out may alias y1 (each point reads its own y1 entry
+// before writing), never x.  Coefficients are complex; real ops use .real().
+struct ChainCoef {
+  cd alpha, beta, g0, g1;
+};
+
+// algorithmic bytes moved by one chain launch (x read once, y0, y1 read,
+// out written, plus the operator's own data)
+double chain_bytes(const Op& op, bool has_y0, bool has_y1);
+
+// ---- kernel launchers (kernels_*.hip) ----
+hipError_t launch_chain(const Op& op, const void* x, const void* y0, const void* y1, void* out,
+                        const ChainCoef& k, hipStream_t s);
+
+// Gram-Schmidt building blocks on a column-major basis V (ld = ldv elements).
+// Partial sums go to `part` (ncols x nblk), the second stage writes `h`.
+struct RedPlan {
+  int nblk;     // blocks of the first stage
+  int rows;     // rows per block
+};
+RedPlan red_plan(int64_t n);
+// h[c] = sum_r conj(V[r, c]) w[r], c < ncols (h may be null); hsum_mode 1 also
+// stores hsum[c] = h[c], mode 2 adds it (CGS2: H(:, j) = h1 + h2), 0 ignores hsum
+hipError_t launch_project(int dtype, int64_t n, int ncols, const void* V, int64_t ldv,
+                          const void* w, void* part, void* h, void* hsum, int hsum_mode,
+                          hipStream_t s);
+// w[r] -= sum_c V[r, c] h[c]; if nrm2 != null also nrm2 = ||w_new||^2 (double)
+hipError_t launch_update(int dtype, int64_t n, int ncols, const void* V, int64_t ldv,
+                         const void* h, void* w, void* part, double* nrm2, hipStream_t s);
+// x[r] = sum_c V[r, c] z[c]
+hipError_t launch_combine(int dtype, int64_t n, int ncols, const void* V, int64_t ldv,
+                          const void* z, void* x, hipStream_t s);
+// out = w / sqrt(nrm2) (nrm2 on device); hout (if not null) = sqrt(nrm2) as a T
+hipError_t launch_normalize(int dtype, int64_t n, const void* w, const double* nrm2,
+                            void* out, void* hout, hipStream_t s);
+// y = a * x for a scalar on the host
+hipError_t launch_scale(int dtype, int64_t n, cd a, const void* x, void* y, hipStream_t s);
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline size_t elem_size(int dtype) { return dtype == FA_C128 ? 16 : 8; }
+
+}  // namespace fa

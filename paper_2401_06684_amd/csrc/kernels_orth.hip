@@ -1,0 +1,257 @@
+// Gram-Schmidt building blocks for the Arnoldi process on the preconditioned
+// operator (Algorithm 1: h_ij = <w, v_i>, w <- w - v_i h_ij, h_{j+1,j} = ||w||,
+// v_{j+1} = w / h_{j+1,j}), written as tall-skinny matrix-vector products over
+// the device-resident basis V (column-major, leading dimension ldv):
+//   project : h = V^H w          (GEMV with V^H; two-stage deterministic sum)
+//   update  : w <- w - V h       (GEMV with V), optionally ||w||^2 on the fly
+//   combine : x = V z            (the final f_m = V_m z_m)
+//   normalize: v = w / ||w||
+// Classical Gram-Schmidt applied twice is project + update, twice.
+//
+// Reductions never use floating-point atomics: every block writes its partial
+// sums to a scratch array and a second kernel adds them in a fixed order, so
+// results are bitwise reproducible from run to run.
+#include <hip/hip_runtime.h>
+
+#include "devmath.hpp"
+#include "fa_internal.hpp"
+
+namespace fa {
+
+constexpr int kThreads = 256;
+constexpr int kRpt = 4;  // rows per thread in the GEMV sweeps
+constexpr int kCb = 8;   // columns per reduction round in project
+
+RedPlan red_plan(int64_t n) {
+  RedPlan p;
+  p.rows = kThreads * kRpt;
+  p.nblk = (int)((n + p.rows - 1) / p.rows);
+  return p;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* sh /* [4] */) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  T r = sh[0];
+  r += sh[1];
+  r += sh[2];
+  r += sh[3];
+  __syncthreads();
+  return r;
+}
+
+// part[c * nblk + blk] = sum over the block's rows of conj(V[r, c]) w[r]
+template <typename T>
+__global__ __launch_bounds__(kThreads) void project_k(int64_t n, int ncols, const T* __restrict__ V,
+                                                      int64_t ldv, const T* __restrict__ w,
+                                                      T* __restrict__ part, int nblk) {
+  __shared__ T red[kThreads / 64][kCb];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * (kThreads * kRpt) + tid;
+  T wr[kRpt];
+#pragma unroll
+  for (int q = 0; q < kRpt; ++q) {
+    const int64_t r = r0 + (int64_t)q * kThreads;
+    wr[q] = (r < n) ? w[r] : zero(T{});
+  }
+  for (int c0 = 0; c0 < ncols; c0 += kCb) {
+    T acc[kCb];
+#pragma unroll
+    for (int cc = 0; cc < kCb; ++cc) {
+      acc[cc] = zero(T{});
+      if (c0 + cc < ncols) {
+        const T* col = V + (int64_t)(c0 + cc) * ldv;
+#pragma unroll
+        for (int q = 0; q < kRpt; ++q) {
+          const int64_t r = r0 + (int64_t)q * kThreads;
+          if (r < n) acc[cc] = cmad(col[r], wr[q], acc[cc]);
+        }
+      }
+    }
+#pragma unroll
+    for (int cc = 0; cc < kCb; ++cc) acc[cc] = wave_sum(acc[cc]);
+    if (lane == 0) {
+#pragma unroll
+      for (int cc = 0; cc < kCb; ++cc) red[wv][cc] = acc[cc];
+    }
+    __syncthreads();
+    if (tid < kCb && c0 + tid < ncols) {
+      T s = red[0][tid];
+      s += red[1][tid];
+      s += red[2][tid];
+      s += red[3][tid];
+      part[(int64_t)(c0 + tid) * nblk + blockIdx.x] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// second stage: h[c] = sum_b part[c * nblk + b] in a fixed order; mode 1 also
+// stores hsum[c] = h[c], mode 2 adds it (CGS2: H(:, j) = h1 + h2)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void reduce_cols_k(int nblk, const T* __restrict__ part,
+                                                          T* h, T* hsum, int mode) {
+  __shared__ T sh[kThreads / 64];
+  const int c = blockIdx.x;
+  T s = zero(T{});
+  for (int b = threadIdx.x; b < nblk; b += kThreads) s += part[(int64_t)c * nblk + b];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    if (h) h[c] = s;
+    if (mode == 1) hsum[c] = s;
+    if (mode == 2) hsum[c] += s;
+  }
+}
+
+// w[r] = ASSIGN ? sum_c V[r, c] h[c] : w[r] - sum_c V[r, c] h[c]; optional ||w||^2 partials
+template <typename T, bool ASSIGN, bool NORM>
+__global__ __launch_bounds__(kThreads) void update_k(int64_t n, int ncols, const T* __restrict__ V,
+                                                     int64_t ldv, const T* __restrict__ h,
+                                                     T* __restrict__ w,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[kThreads / 64];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * (kThreads * kRpt) + tid;
+  T acc[kRpt];
+#pragma unroll
+  for (int q = 0; q < kRpt; ++q) acc[q] = zero(T{});
+  if (r0 + (int64_t)(kRpt - 1) * kThreads < n) {  // full block of rows
+#pragma unroll 4
+    for (int c = 0; c < ncols; ++c) {
+      const T hc = h[c];
+      const T* col = V + (int64_t)c * ldv + r0;
+#pragma unroll
+      for (int q = 0; q < kRpt; ++q) acc[q] = mad(col[q * kThreads], hc, acc[q]);
+    }
+  } else {
+    for (int c = 0; c < ncols; ++c) {
+      const T hc = h[c];
+      const T* col = V + (int64_t)c * ldv;
+#pragma unroll
+      for (int q = 0; q < kRpt; ++q) {
+        const int64_t r = r0 + (int64_t)q * kThreads;
+        if (r < n) acc[q] = mad(col[r], hc, acc[q]);
+      }
+    }
+  }
+  double s2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < kRpt; ++q) {
+    const int64_t r = r0 + (int64_t)q * kThreads;
+    if (r < n) {
+      const T nw = ASSIGN ? acc[q] : w[r] - acc[q];
+      w[r] = nw;
+      if (NORM) s2 += abs2(nw);
+    }
+  }
+  if (NORM) {
+    s2 = block_sum(s2, sh);
+    if (tid == 0) part[blockIdx.x] = s2;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void normalize_k(int64_t n, const T* w,
+                                                        const double* __restrict__ nrm2,
+                                                        T* out, T* hout) {
+  const double nr = sqrt(nrm2[0]);
+  const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i == 0 && hout) {
+    T hv = zero(T{});
+    *reinterpret_cast<double*>(&hv) = nr;
+    *hout = hv;
+  }
+  if (i < n) out[i] = inv * w[i];
+}
+
+__device__ __forceinline__ double scale_val(double a_re, double, double x) { return a_re * x; }
+__device__ __forceinline__ cplx scale_val(double a_re, double a_im, cplx x) {
+  return cplx{a_re * x.x - a_im * x.y, a_re * x.y + a_im * x.x};
+}
+template <typename T>
+__global__ __launch_bounds__(kThreads) void scale_k(int64_t n, double a_re, double a_im,
+                                                    const T* x, T* y) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) y[i] = scale_val(a_re, a_im, x[i]);
+}
+
+// --------------------------------------------------------------------------
+template <typename T>
+static hipError_t project_t(int64_t n, int ncols, const T* V, int64_t ldv, const T* w, T* part,
+                            T* h, T* hsum, int mode, hipStream_t s) {
+  const RedPlan p = red_plan(n);
+  project_k<T><<<p.nblk, kThreads, 0, s>>>(n, ncols, V, ldv, w, part, p.nblk);
+  reduce_cols_k<T><<<ncols, kThreads, 0, s>>>(p.nblk, part, h, hsum, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(int dtype, int64_t n, int ncols, const void* V, int64_t ldv,
+                          const void* w, void* part, void* h, void* hsum, int hsum_mode,
+                          hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  if (dtype == FA_C128)
+    return project_t<cplx>(n, ncols, (const cplx*)V, ldv, (const cplx*)w, (cplx*)part,
+                           (cplx*)h, (cplx*)hsum, hsum_mode, s);
+  return project_t<double>(n, ncols, (const double*)V, ldv, (const double*)w, (double*)part,
+                           (double*)h, (double*)hsum, hsum_mode, s);
+}
+
+template <typename T>
+static hipError_t update_t(int64_t n, int ncols, const T* V, int64_t ldv, const T* h, T* w,
+                           void* part, double* nrm2, hipStream_t s) {
+  const RedPlan p = red_plan(n);
+  if (nrm2) {
+    update_k<T, false, true><<<p.nblk, kThreads, 0, s>>>(n, ncols, V, ldv, h, w, (double*)part);
+    reduce_cols_k<double><<<1, kThreads, 0, s>>>(p.nblk, (const double*)part, nrm2, nullptr, 0);
+  } else {
+    update_k<T, false, false><<<p.nblk, kThreads, 0, s>>>(n, ncols, V, ldv, h, w, nullptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_update(int dtype, int64_t n, int ncols, const void* V, int64_t ldv,
+                         const void* h, void* w, void* part, double* nrm2, hipStream_t s) {
+  if (dtype == FA_C128)
+    return update_t<cplx>(n, ncols, (const cplx*)V, ldv, (const cplx*)h, (cplx*)w, part, nrm2, s);
+  return update_t<double>(n, ncols, (const double*)V, ldv, (const double*)h, (double*)w, part,
+                          nrm2, s);
+}
+
+hipError_t launch_combine(int dtype, int64_t n, int ncols, const void* V, int64_t ldv,
+                          const void* z, void* x, hipStream_t s) {
+  const RedPlan p = red_plan(n);
+  if (dtype == FA_C128)
+    update_k<cplx, true, false><<<p.nblk, kThreads, 0, s>>>(n, ncols, (const cplx*)V, ldv,
+                                                            (const cplx*)z, (cplx*)x, nullptr);
+  else
+    update_k<double, true, false><<<p.nblk, kThreads, 0, s>>>(n, ncols, (const double*)V, ldv,
+                                                              (const double*)z, (double*)x,
+                                                              nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(int dtype, int64_t n, const void* w, const double* nrm2, void* out,
+                            void* hout, hipStream_t s) {
+  const int grid = (int)((n + kThreads - 1) / kThreads);
+  if (dtype == FA_C128)
+    normalize_k<cplx><<<grid, kThreads, 0, s>>>(n, (const cplx*)w, nrm2, (cplx*)out, (cplx*)hout);
+  else
+    normalize_k<double><<<grid, kThreads, 0, s>>>(n, (const double*)w, nrm2, (double*)out,
+                                                  (double*)hout);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(int dtype, int64_t n, cd a, const void* x, void* y, hipStream_t s) {
+  const int grid = (int)((n + kThreads - 1) / kThreads);
+  if (dtype == FA_C128)
+    scale_k<cplx><<<grid, kThreads, 0, s>>>(n, a.real(), a.imag(), (const cplx*)x, (cplx*)y);
+  else
+    scale_k<double><<<grid, kThreads, 0, s>>>(n, a.real(), a.imag(), (const double*)x, (double*)y);
+  return hipGetLastError();
+}
+
+}  // namespace fa

@@ -1,0 +1,27 @@
+// Host runtime entry points used by the C ABI layer.
+#pragma once
+#include "fa_internal.hpp"
+
+namespace fa {
+
+// device workspace layout of fa_apply for Krylov dimension m_max (offsets in
+// bytes, every region 256-byte aligned)
+struct Layout {
+  int64_t ldv = 0;  // leading dimension of the basis (elements)
+  int ldh = 0;      // leading dimension of H (elements)
+  size_t off_V = 0, off_U = 0, off_P = 0, off_Q = 0, off_part = 0, off_h = 0, off_H = 0,
+         off_nrm = 0, off_z = 0;
+  size_t bytes = 0;
+};
+Layout make_layout(const Op& op, int m_max);
+
+int op_apply(const Op& op, const void* x, void* y, hipStream_t s);
+int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_t s);
+int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double tol,
+          int check_every, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t s,
+          fa_stats* stats);
+size_t poly_workspace_bytes(const Op& op, int degree, int method);
+int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, size_t ws_bytes,
+               hipStream_t s, int64_t* mvms_setup);
+
+}  // namespace fa

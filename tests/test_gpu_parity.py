@@ -1,0 +1,311 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Tolerances (FP64 mode): one operator application or chain step 1e-13
+relative; q(A) x 1e-12; whole solves 1e-10 (the bar for all-FP64 results),
+both at a fixed Krylov dimension and at convergence.  Comparisons are element
+by element (max-norm relative to the reference's max-norm) and in 2-norm.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import exact, krylov as kr, operators as ops, polynomials as pl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2401_06684_amd as fa
+    fa.lib()  # the HIP library must load: no fallback
+
+
+def fa():
+    import paper_2401_06684_amd as m
+    return m
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def assert_close(x, ref, tol):
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    r2 = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+    rinf = np.max(np.abs(x - ref)) / np.max(np.abs(ref))
+    assert r2 <= tol and rinf <= 10 * tol, (r2, rinf)
+    return r2
+
+
+# --------------------------------------------------------------------------
+# operators: one application y = A x
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dims", [(70, 9, 11), (64, 4, 1), (37, 41, 23), (5, 3, 130), (1, 1, 7)])
+def test_stencil_apply(dims):
+    coeffs = wl.convdiff_stencil(max(dims), 50.0)
+    op = fa().Stencil7(dims, coeffs)
+    x = wl.rhs(int(np.prod(dims)), seed=1)
+    y = host(op.op_apply(dev(x)))
+    assert_close(y, ops.stencil_apply(coeffs, dims, x), 1e-14)
+
+
+@pytest.mark.parametrize("which", ["poisson32", "digraph", "complex"])
+def test_csr_apply(which):
+    if which == "poisson32":
+        rp, ci, va = wl.stencil_csr((32, 32, 1), wl.laplace_stencil(2))
+    elif which == "digraph":
+        rp, ci, va = wl.powerlaw_digraph_laplacian_csr(5000, 45000, seed=2)
+    else:
+        rp, ci, va = wl.stencil_csr((13, 11, 7), wl.convdiff_stencil(13, 50.0))
+        va = va * (1.0 + 0.3j)
+    n = len(rp) - 1
+    x = wl.rhs(n, seed=3, complex_=np.iscomplexobj(va))
+    op = fa().CSR(rp, ci, va)
+    y = host(op.op_apply(dev(x)))
+    assert_close(y, ops.csr_apply(rp, ci, va, x), 1e-14)
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4, 4), (6, 2, 4, 5)])
+def test_wilson_apply(shape):
+    Lt, Lz, Ly, Lx = shape
+    rng_links = wl.random_su3(4 * Lt * Lz * Ly * Lx, 0.8, np.random.default_rng(5))
+    U = rng_links.reshape(4, Lt, Lz, Ly, Lx, 3, 3)
+    m0 = 0.05
+    op = fa().Wilson(U, m0)
+    x = wl.rhs(op.n, seed=4, complex_=True)
+    y = host(op.op_apply(dev(x)))
+    assert_close(y, ops.wilson_apply(U, m0, x), 1e-14)
+
+
+# --------------------------------------------------------------------------
+# polynomial chain q(A) x
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("degree", [1, 2, 3, 4, 16, 32])
+def test_chebyshev_chain(degree):
+    dims = (70, 9, 11)
+    coeffs = wl.convdiff_stencil(70, 50.0)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(degree, "cheb")
+    a, b = ops.stencil_interval(coeffs, dims)
+    q = pl.chebyshev(a, b, degree)
+    x = wl.rhs(op.n, seed=2)
+    y = host(op.poly_apply(dev(x)))
+    ref, _ = q.apply(lambda v: ops.stencil_apply(coeffs, dims, v), x)
+    assert_close(y, ref, 1e-12)
+
+
+def test_ritz_setup_and_chain_wilson():
+    L = 4
+    U = wl.su3_links(L, eps=0.3, seed=1)
+    m0 = 0.05
+    op = fa().Wilson(U, m0)
+    start = wl.rhs(op.n, seed=11, complex_=True)
+    op.poly_setup(8, "ritz", start=dev(start))
+    p = op.poly()
+    apply_A = lambda v: ops.wilson_apply(U, m0, v)
+    q = pl.ritz(apply_A, start, 8, real_operator=False)
+    key = lambda z: (round(z.real, 6), round(z.imag, 6))
+    gt = np.array(sorted(p["theta"], key=key))
+    rt = np.array(sorted(q.theta, key=key))
+    assert p["degree"] == q.degree == 8
+    assert np.max(np.abs(gt - rt)) <= 1e-9 * np.max(np.abs(rt))
+    x = wl.rhs(op.n, seed=12, complex_=True)
+    y = host(op.poly_apply(dev(x)))
+    ref, _ = q.apply(apply_A, x)
+    assert_close(y, ref, 1e-8)
+
+
+# --------------------------------------------------------------------------
+# whole solves
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("degree,m", [(0, 40), (4, 10), (16, 5)])
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+def test_convdiff_fixed_m(degree, m, kind):
+    dims = (20, 18, 16)
+    coeffs = wl.convdiff_stencil(20, 50.0)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(degree, "cheb")
+    b = wl.rhs(op.n, seed=0)
+    x, st = op.apply(dev(b), kind=kind, m_max=m, tol=0.0)
+    a, bb = ops.stencil_interval(coeffs, dims)
+    ref = kr.fAb(lambda v: ops.stencil_apply(coeffs, dims, v), b, pl.chebyshev(a, bb, degree),
+                 kind, m_max=m, tol=0.0)
+    assert st["iters"] == ref.iters == m
+    assert st["mvms"] == ref.mvms
+    assert_close(host(x), ref.x, 1e-10)
+
+
+@pytest.mark.parametrize("degree", [0, 4, 16])
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+def test_convdiff_converged_against_closed_form(degree, kind):
+    N = 24
+    dims = (N, N, N)
+    coeffs = wl.convdiff_stencil(N, 10.0)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(degree, "cheb")
+    b = wl.rhs(op.n, seed=0)
+    x, st = op.apply(dev(b), kind=kind, m_max=400, tol=1e-12)
+    assert st["converged"] == 1
+    ref = exact.stencil_fAb_dst(coeffs, dims, b, kind)
+    assert_close(host(x), ref, 1e-10)
+    a, bb = ops.stencil_interval(coeffs, dims)
+    orc = kr.fAb(lambda v: ops.stencil_apply(coeffs, dims, v), b, pl.chebyshev(a, bb, degree),
+                 kind, m_max=400, tol=1e-12)
+    assert st["iters"] == orc.iters
+    assert_close(host(x), orc.x, 1e-10)
+
+
+@pytest.mark.parametrize("degree", [0, 8])
+def test_poisson2d_32_lanczos(degree):
+    """2D Poisson 32x32, CSR, Hermitian: Lanczos, tol 1e-10, m_max 200."""
+    N = 32
+    coeffs = wl.laplace_stencil(2)
+    rp, ci, va = wl.stencil_csr((N, N, 1), coeffs)
+    op = fa().CSR(rp, ci, va, hermitian=True)
+    lo, hi = ops.stencil_interval(coeffs, (N, N, 1))
+    op.set_spectral_interval(lo, hi)
+    op.poly_setup(degree, "cheb")
+    b = wl.rhs(N * N, seed=0)
+    x, st = op.apply(dev(b), kind="invsqrt", m_max=200, tol=1e-10)
+    assert st["converged"] == 1
+    assert st["inner_products"] == 2 * st["iters"]
+    orc = kr.fAb(lambda v: ops.csr_apply(rp, ci, va, v), b, pl.chebyshev(lo, hi, degree),
+                 "invsqrt", m_max=200, tol=1e-10, orth="lanczos")
+    assert st["iters"] == orc.iters
+    assert_close(host(x), orc.x, 1e-9)
+    assert_close(host(x), exact.stencil_fAb_dst(coeffs, (N, N, 1), b), 1e-9)
+
+
+@pytest.mark.parametrize("degree", [0, 8])
+def test_wilson_solve(degree):
+    L = 4
+    U = wl.su3_links(L, eps=0.3, seed=1)
+    m0 = 0.05
+    op = fa().Wilson(U, m0)
+    start = wl.rhs(op.n, seed=11, complex_=True)
+    op.poly_setup(degree, "ritz", start=dev(start))
+    b = wl.rhs(op.n, seed=0, complex_=True)
+    x, st = op.apply(dev(b), kind="invsqrt", m_max=400, tol=1e-12)
+    assert st["converged"] == 1
+    apply_A = lambda v: ops.wilson_apply(U, m0, v)
+    q = pl.ritz(apply_A, start, degree, real_operator=False)
+    orc = kr.fAb(apply_A, b, q, "invsqrt", m_max=400, tol=1e-12)
+    assert_close(host(x), orc.x, 1e-10)
+
+
+def test_wilson_free_field_closed_form():
+    L = 4
+    Ls = (L, L, L, L)
+    U = np.zeros((4, *Ls, 3, 3), dtype=complex)
+    U[...] = np.eye(3)
+    m0 = 0.1
+    op = fa().Wilson(U, m0)
+    op.poly_setup(6, "ritz", start=dev(wl.rhs(op.n, seed=1, complex_=True)))
+    b = wl.rhs(op.n, seed=0, complex_=True)
+    x, st = op.apply(dev(b), kind="invsqrt", m_max=400, tol=1e-12)
+    assert_close(host(x), exact.wilson_free_fAb(Ls, m0, b), 1e-10)
+
+
+# --------------------------------------------------------------------------
+# degenerate cases and error paths
+# --------------------------------------------------------------------------
+def test_zero_rhs_returns_zero():
+    op = fa().Stencil7((10, 10, 10), wl.convdiff_stencil(10, 50.0))
+    op.poly_setup(4, "cheb")
+    x, st = op.apply(torch.zeros(1000, dtype=torch.float64, device=DEV), m_max=20, tol=1e-10)
+    assert st["converged"] == 1 and st["iters"] == 0
+    assert torch.count_nonzero(x).item() == 0
+
+
+def test_nonfinite_rhs():
+    op = fa().Stencil7((10, 10, 10), wl.convdiff_stencil(10, 50.0))
+    op.poly_setup(4, "cheb")
+    b = wl.rhs(1000, seed=0)
+    b[17] = np.nan
+    with pytest.raises(fa().FAError) as e:
+        op.apply(dev(b), m_max=20, tol=1e-10)
+    assert e.value.status == -7
+
+
+def test_lucky_breakdown_diagonal():
+    a = np.repeat([0.5, 1.5, 4.0, 9.0], 300)
+    n = a.size
+    rp = np.arange(n + 1, dtype=np.int32)
+    op = fa().CSR(rp, np.arange(n, dtype=np.int32), a)
+    op.poly_setup(0)
+    b = wl.rhs(n, seed=3)
+    for kind, f in (("invsqrt", a ** -0.5), ("sqrt", a ** 0.5)):
+        x, st = op.apply(dev(b), kind=kind, m_max=50, tol=1e-12, check_every=5)
+        assert st["breakdown"] == 1 and st["iters"] == 4
+        assert_close(host(x), f * b, 1e-12)
+
+
+def test_branch_and_hessenberg_errors():
+    a = np.concatenate([[-1.0], np.linspace(1, 3, 99)])
+    n = a.size
+    rp = np.arange(n + 1, dtype=np.int32)
+    op = fa().CSR(rp, np.arange(n, dtype=np.int32), a)
+    with pytest.raises(fa().FAError) as e:
+        op.poly_setup(8, "ritz", start=dev(wl.rhs(n, seed=1)))
+    assert e.value.status == -3
+    op.poly_setup(0)
+    with pytest.raises(fa().FAError) as e:
+        op.apply(dev(wl.rhs(n, seed=2)), m_max=n, tol=1e-12, check_every=1)
+    assert e.value.status == -4
+
+
+def test_not_converged_warning():
+    op = fa().Stencil7((16, 16, 16), wl.convdiff_stencil(16, 50.0))
+    op.poly_setup(0)
+    x, st = op.apply(dev(wl.rhs(op.n, seed=0)), m_max=10, tol=1e-12)
+    assert st["status"] == 1 and st["converged"] == 0 and st["iters"] == 10
+
+
+def test_bitwise_deterministic_and_profile():
+    op = fa().Stencil7((40, 33, 29), wl.convdiff_stencil(40, 50.0))
+    op.poly_setup(8, "cheb")
+    b = dev(wl.rhs(op.n, seed=0))
+    x1, s1 = op.apply(b, m_max=60, tol=1e-10)
+    x2, s2 = op.apply(b, m_max=60, tol=1e-10, profile=True)
+    assert torch.equal(x1, x2)
+    assert s2["n_chain"] == s2["mvms"] and s2["ms_chain"] > 0 and s2["chain_bytes"] > 0
+
+
+# --------------------------------------------------------------------------
+# the 128^3 convection-diffusion workload at full size
+# --------------------------------------------------------------------------
+def test_convdiff_128_full_size():
+    N = 128
+    dims = (N, N, N)
+    coeffs = wl.convdiff_stencil(N, 50.0)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(16, "cheb")
+    b = wl.rhs(op.n, seed=0)
+    bd = dev(b)
+    # fixed m = 3 against the oracle (the oracle needs ~10^2 products with A)
+    x3, st = op.apply(bd, m_max=3, tol=0.0)
+    a, bb = ops.stencil_interval(coeffs, dims)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    ref = kr.fAb(A, b, pl.chebyshev(a, bb, 16), "invsqrt", m_max=3, tol=0.0)
+    assert_close(host(x3), ref.x, 1e-10)
+    # converged solves: invsqrt and sqrt related by A, degree 16 vs 32
+    xi, si = op.apply(bd, kind="invsqrt", m_max=200, tol=1e-10)
+    xs, ss = op.apply(bd, kind="sqrt", m_max=200, tol=1e-10)
+    assert si["converged"] and ss["converged"]
+    assert_close(A(host(xi)), host(xs), 1e-8)
+    op.poly_setup(32, "cheb")
+    x32, s32 = op.apply(bd, kind="invsqrt", m_max=200, tol=1e-10)
+    assert_close(host(x32), host(xi), 1e-8)
