@@ -8,9 +8,9 @@ stopping tolerance 1e-8 on the difference-of-iterates estimate.
 
 A step is one fa_apply solve (setup of the operator and polynomial excluded,
 inputs resident in HBM).  Printed as one JSON line with a roofline object for
-the dominant kernel (the fused stencil chain step: HIP events around every
-chain launch inside the timed region) and the CPU oracle timed on a bounded
-sample.  Extra fields report plain Arnoldi (degree 0), degrees 4 and 32 and the
+the dominant kernel (the fused stencil chain step: HIP events around the
+first 64 chain launches of every timed solve) and the CPU oracle timed on a
+bounded sample.  Extra fields report plain Arnoldi (degree 0), degrees 4 and 32 and the
 square root on the same GPU.
 """
 from __future__ import annotations
@@ -41,6 +41,10 @@ def main():
     ap.add_argument("--degree", type=int, default=16)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-Arnoldi leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--chain-only", type=int, default=0, metavar="R",
+                    help="only run R applications of q(A) (for hardware counters) and exit")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 2 GiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -54,6 +58,15 @@ def main():
     import workloads as wl
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        # a plain copy kernel of known size: 2^28 doubles (2 GiB) read + written
+        src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of 2 GiB done")
+        return
     N = args.N
     dims = (N, N, N)
     pe = 50.0
@@ -65,6 +78,15 @@ def main():
         op = fa.Stencil7(dims, coeffs, device=dev)
         op.poly_setup(degree, "cheb")
         return op
+
+    if args.chain_only:
+        op = make(args.degree)
+        y = torch.empty_like(b)
+        for _ in range(args.chain_only):
+            op.poly_apply(b, out=y)
+        torch.cuda.synchronize()
+        log(f"chain only: {args.chain_only} x q(A) b at degree {args.degree} done")
+        return
 
     # reference for the true error: degree 32, tight tolerance
     log("reference solve (degree 32, tol 1e-12)")

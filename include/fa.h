@@ -94,7 +94,7 @@ enum {
 enum {
   FA_HERMITIAN = 1u,     /* create: A is Hermitian; apply uses Lanczos (3-term)        */
   FA_FORCE_ARNOLDI = 4u, /* apply: Gram-Schmidt (CGS2) even for a Hermitian op          */
-  FA_PROFILE = 8u        /* apply: time every polynomial-chain launch with HIP events   */
+  FA_PROFILE = 8u        /* apply: time the first 64 chain launches with HIP events     */
 };
 
 typedef struct {
@@ -110,9 +110,11 @@ typedef struct {
   double h_last;          /* h_{m+1,m}                                                  */
   double ms_total;        /* wall time of fa_apply                                      */
   double ms_host_fH;      /* host time spent in H_j^{-1/2} e_1                          */
-  double ms_chain;        /* FA_PROFILE: summed device time of chain launches           */
-  int64_t n_chain;        /* FA_PROFILE: number of chain launches timed                 */
-  double chain_bytes;     /* algorithmic HBM bytes of one chain launch (see DESIGN)     */
+  double ms_chain;        /* FA_PROFILE: summed device time of the timed chain launches */
+  int64_t n_chain;        /* FA_PROFILE: number of chain launches timed (<= 64)         */
+  double chain_bytes;     /* FA_PROFILE: mean algorithmic bytes of a timed chain launch:
+                             x, each combined vector and the output once, plus the
+                             operator's own arrays (CSR arrays, Wilson links)            */
 } fa_stats;
 
 /*

@@ -49,12 +49,19 @@ Layout make_layout(const Op& op, int m_max) {
 namespace {
 thread_local std::vector<hipEvent_t> t_events;
 
+// Timing events serialize the stream (each timestamp waits for the previous
+// kernel and its cache write-back), so only the first kMaxTimed chain launches
+// of a solve are bracketed; the rest run undisturbed.
+constexpr size_t kMaxTimed = 64;
+
 struct Prof {
   bool on = false;
+  bool active = false;  // the current launch is being timed
   size_t used = 0;
-  double bytes = 0;  // bytes of the launches timed (first launch type)
+  double bytes = 0;     // algorithmic bytes of the timed launches
   hipError_t begin(hipStream_t s) {
-    if (!on) return hipSuccess;
+    active = on && used / 2 < kMaxTimed;
+    if (!active) return hipSuccess;
     if (used + 2 > t_events.size()) {
       for (int i = 0; i < 64; ++i) {
         hipEvent_t e;
@@ -66,7 +73,7 @@ struct Prof {
     return hipEventRecord(t_events[used], s);
   }
   hipError_t end(hipStream_t s) {
-    if (!on) return hipSuccess;
+    if (!active) return hipSuccess;
     hipError_t err = hipEventRecord(t_events[used + 1], s);
     used += 2;
     return err;
@@ -101,7 +108,7 @@ static int chain(const Op& op, const void* x, const void* y0, const void* y1, vo
                  const ChainCoef& k, hipStream_t s, Prof* prof) {
   if (prof) FA_HIP(prof->begin(s));
   FA_HIP(launch_chain(op, x, y0, y1, out, k, s));
-  if (prof) {
+  if (prof && prof->active) {
     FA_HIP(prof->end(s));
     prof->bytes += chain_bytes(op, y0 != nullptr, y1 != nullptr);
   }

@@ -281,7 +281,8 @@ def test_bitwise_deterministic_and_profile():
     x1, s1 = op.apply(b, m_max=60, tol=1e-10)
     x2, s2 = op.apply(b, m_max=60, tol=1e-10, profile=True)
     assert torch.equal(x1, x2)
-    assert s2["n_chain"] == s2["mvms"] and s2["ms_chain"] > 0 and s2["chain_bytes"] > 0
+    assert s2["n_chain"] == min(64, s2["mvms"]) and s2["ms_chain"] > 0
+    assert s2["chain_bytes"] > 3 * 8 * op.n
 
 
 # --------------------------------------------------------------------------
