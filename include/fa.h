@@ -94,7 +94,7 @@ enum {
 enum {
   FA_HERMITIAN = 1u,     /* create: A is Hermitian; apply uses Lanczos (3-term)        */
   FA_FORCE_ARNOLDI = 4u, /* apply: Gram-Schmidt (CGS2) even for a Hermitian op          */
-  FA_PROFILE = 8u        /* apply: time the first 64 chain launches with HIP events     */
+  FA_PROFILE = 8u        /* apply: time the middle terms of every q(A) application      */
 };
 
 typedef struct {
@@ -110,11 +110,15 @@ typedef struct {
   double h_last;          /* h_{m+1,m}                                                  */
   double ms_total;        /* wall time of fa_apply                                      */
   double ms_host_fH;      /* host time spent in H_j^{-1/2} e_1                          */
-  double ms_chain;        /* FA_PROFILE: summed device time of the timed chain launches */
-  int64_t n_chain;        /* FA_PROFILE: number of chain launches timed (<= 64)         */
-  double chain_bytes;     /* FA_PROFILE: mean algorithmic bytes of a timed chain launch:
-                             x, each combined vector and the output once, plus the
-                             operator's own arrays (CSR arrays, Wilson links)            */
+  double ms_chain;        /* FA_PROFILE: device time of the timed chain launches: HIP
+                             events bracket each run of consecutive middle terms of a
+                             q(A) recurrence (Clenshaw terms 1..K-3, Newton terms
+                             1..K-2), so the figure includes the short gaps between
+                             back-to-back launches                                     */
+  int64_t n_chain;        /* FA_PROFILE: number of chain launches timed                 */
+  double chain_bytes;     /* FA_PROFILE: algorithmic bytes of one timed launch: x, each
+                             combined vector and the output once, plus the operator's
+                             own arrays (Wilson links, CSR arrays)                      */
 } fa_stats;
 
 /*

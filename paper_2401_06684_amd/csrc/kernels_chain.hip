@@ -16,9 +16,14 @@ namespace fa {
 
 // --------------------------------------------------------------------------
 // 7-point / 5-point stencil, real FP64, zero Dirichlet boundary.
-// Threads tile the (x, y) plane, 64 along x (one wavefront per row segment,
-// coalesced), and march along z keeping the z-neighbours in registers, so x
-// is read from memory once per point; the x/y neighbours are hits in L1/L2.
+// A workgroup owns a 64 x 4 tile of the (x, y) plane (one wavefront per row
+// segment, coalesced along x) and marches through kz planes in z, keeping the
+// z-neighbours in registers, so x is read from memory about once per point;
+// x/y neighbours come from L1/L2.
+// The hardware deals consecutive workgroup ids round-robin to the eight XCDs,
+// each with its own L2.  The id is remapped so that every XCD gets one
+// contiguous slab of tiles: the halo rows and planes a tile shares with its
+// neighbours are then fetched once into that XCD's L2 instead of once per XCD.
 // --------------------------------------------------------------------------
 struct St7 {
   int nx, ny, nz;
@@ -26,17 +31,26 @@ struct St7 {
 };
 
 constexpr int ST_TX = 64, ST_TY = 4;
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_contiguous(int bid, int nwg) {
+  const int per = nwg / kXcds, rem = nwg % kXcds;
+  const int xcd = bid % kXcds, k = bid / kXcds;
+  return (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+}
 
 template <bool Y0, bool Y1>
-__global__ __launch_bounds__(ST_TX* ST_TY) void st7_chain(St7 s, int kz,
+__global__ __launch_bounds__(ST_TX* ST_TY) void st7_chain(St7 s, int kz, int gx, int gy, int nwg,
                                                           const double* __restrict__ x,
                                                           const double* __restrict__ y0,
                                                           const double* y1, double* out,
                                                           double al, double be, double g0,
                                                           double g1) {
-  const int i = blockIdx.x * ST_TX + threadIdx.x;
-  const int j = blockIdx.y * ST_TY + threadIdx.y;
-  const int k0 = blockIdx.z * kz;
+  const int lid = xcd_contiguous(blockIdx.x, nwg);
+  const int bx = lid % gx, by = (lid / gx) % gy, bz = lid / (gx * gy);
+  const int i = bx * ST_TX + (threadIdx.x & (ST_TX - 1));
+  const int j = by * ST_TY + (threadIdx.x / ST_TX);
+  const int k0 = bz * kz;
   const int k1 = min(k0 + kz, s.nz);
   if (i >= s.nx || j >= s.ny || k0 >= s.nz) return;
   const int64_t plane = (int64_t)s.nx * s.ny;
@@ -66,22 +80,23 @@ static hipError_t launch_st7(const Op& op, const double* x, const double* y0, co
                              double* out, const ChainCoef& k, hipStream_t st) {
   St7 s{op.dims[0], op.dims[1], op.dims[2], op.coef[0], op.coef[1], op.coef[2],
         op.coef[3], op.coef[4], op.coef[5], op.coef[6]};
-  const int bx = (s.nx + ST_TX - 1) / ST_TX, by = (s.ny + ST_TY - 1) / ST_TY;
+  const int gx = (s.nx + ST_TX - 1) / ST_TX, gy = (s.ny + ST_TY - 1) / ST_TY;
   // enough z-slabs for ~2048 workgroups, at least one plane per thread
   const int64_t want = 2048;
-  int nzb = (int)std::min<int64_t>(s.nz, std::max<int64_t>(1, want / ((int64_t)bx * by)));
-  const int kz = (s.nz + nzb - 1) / nzb;
-  nzb = (s.nz + kz - 1) / kz;
-  dim3 grid(bx, by, nzb), block(ST_TX, ST_TY, 1);
+  int gz = (int)std::min<int64_t>(s.nz, std::max<int64_t>(1, want / ((int64_t)gx * gy)));
+  const int kz = (s.nz + gz - 1) / gz;
+  gz = (s.nz + kz - 1) / kz;
+  const int nwg = gx * gy * gz;
   const double al = k.alpha.real(), be = k.beta.real(), g0 = k.g0.real(), g1 = k.g1.real();
+  const dim3 grid(nwg), block(ST_TX * ST_TY);
   if (y0 && y1)
-    st7_chain<true, true><<<grid, block, 0, st>>>(s, kz, x, y0, y1, out, al, be, g0, g1);
+    st7_chain<true, true><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
   else if (y0)
-    st7_chain<true, false><<<grid, block, 0, st>>>(s, kz, x, y0, y1, out, al, be, g0, g1);
+    st7_chain<true, false><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
   else if (y1)
-    st7_chain<false, true><<<grid, block, 0, st>>>(s, kz, x, y0, y1, out, al, be, g0, g1);
+    st7_chain<false, true><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
   else
-    st7_chain<false, false><<<grid, block, 0, st>>>(s, kz, x, y0, y1, out, al, be, g0, g1);
+    st7_chain<false, false><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
   return hipGetLastError();
 }
 

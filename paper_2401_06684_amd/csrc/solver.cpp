@@ -49,19 +49,18 @@ Layout make_layout(const Op& op, int m_max) {
 namespace {
 thread_local std::vector<hipEvent_t> t_events;
 
-// Timing events serialize the stream (each timestamp waits for the previous
-// kernel and its cache write-back), so only the first kMaxTimed chain launches
-// of a solve are bracketed; the rest run undisturbed.
-constexpr size_t kMaxTimed = 64;
-
+// Profiling: one pair of timing events around each run of consecutive middle
+// terms of a polynomial recurrence (the Clenshaw terms that read x, v and
+// b_{k+2}; the Newton terms that read r and v), all launches of the same
+// kernel on the same sizes.  Bracketing runs rather than single launches keeps
+// the events (each waits for the preceding kernel) from inflating the timing.
 struct Prof {
   bool on = false;
-  bool active = false;  // the current launch is being timed
   size_t used = 0;
-  double bytes = 0;     // algorithmic bytes of the timed launches
+  int64_t launches = 0;
+  double bytes = 0;  // algorithmic bytes of the timed launches
   hipError_t begin(hipStream_t s) {
-    active = on && used / 2 < kMaxTimed;
-    if (!active) return hipSuccess;
+    if (!on) return hipSuccess;
     if (used + 2 > t_events.size()) {
       for (int i = 0; i < 64; ++i) {
         hipEvent_t e;
@@ -72,10 +71,12 @@ struct Prof {
     }
     return hipEventRecord(t_events[used], s);
   }
-  hipError_t end(hipStream_t s) {
-    if (!active) return hipSuccess;
+  hipError_t end(hipStream_t s, int nlaunch, double bytes_each) {
+    if (!on) return hipSuccess;
     hipError_t err = hipEventRecord(t_events[used + 1], s);
     used += 2;
+    launches += nlaunch;
+    bytes += nlaunch * bytes_each;
     return err;
   }
   // after a stream sync: summed milliseconds
@@ -106,12 +107,8 @@ inline const char* col(const void* V, int64_t ldv, int j, size_t es) {
 // --------------------------------------------------------------------------
 static int chain(const Op& op, const void* x, const void* y0, const void* y1, void* out,
                  const ChainCoef& k, hipStream_t s, Prof* prof) {
-  if (prof) FA_HIP(prof->begin(s));
+  (void)prof;
   FA_HIP(launch_chain(op, x, y0, y1, out, k, s));
-  if (prof && prof->active) {
-    FA_HIP(prof->end(s));
-    prof->bytes += chain_bytes(op, y0 != nullptr, y1 != nullptr);
-  }
   return FA_OK;
 }
 
@@ -161,11 +158,13 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
     if (st) return st;
     void* bk1 = t2;  // b_{k+1}
     void* bk2 = t1;  // b_{k+2}, overwritten by b_k
+    if (prof && K >= 4) FA_HIP(prof->begin(s));
     for (int k = K - 3; k >= 1; --k) {
       st = chain(op, bk1, x, bk2, bk2, ChainCoef{2 * sig, 2 * tau, c[k], -1.0}, s, prof);
       if (st) return st;
       std::swap(bk1, bk2);
     }
+    if (prof && K >= 4) FA_HIP(prof->end(s, K - 3, chain_bytes(op, true, true)));
     st = chain(op, bk1, x, bk2, out, ChainCoef{sig, tau, c[0], -1.0}, s, prof);
     *res = out;
     return st;
@@ -184,12 +183,14 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
     if (st) return st;
     cur = dst;
   }
+  if (prof && K >= 3) FA_HIP(prof->begin(s));
   for (int j = K - 2; j >= 0; --j) {
     void* dst = (j == 0) ? out : (cur == t1 ? t2 : t1);
     int st = chain(op, cur, x, nullptr, dst, ChainCoef{1.0 / rho, -th[j] / rho, eta[j], 0}, s,
                    prof);
     if (st) return st;
     cur = dst;
+    if (prof && K >= 3 && j == 1) FA_HIP(prof->end(s, K - 2, chain_bytes(op, true, false)));
   }
   *res = cur;
   return FA_OK;
@@ -455,7 +456,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   S.ms_total = now_ms() - t0;
   if (prof.on) {
     S.ms_chain = prof.total_ms();
-    S.n_chain = (int64_t)(prof.used / 2);
+    S.n_chain = prof.launches;
     S.chain_bytes = S.n_chain ? prof.bytes / (double)S.n_chain : 0.0;
   }
   if (stats) *stats = S;

@@ -281,8 +281,9 @@ def test_bitwise_deterministic_and_profile():
     x1, s1 = op.apply(b, m_max=60, tol=1e-10)
     x2, s2 = op.apply(b, m_max=60, tol=1e-10, profile=True)
     assert torch.equal(x1, x2)
-    assert s2["n_chain"] == min(64, s2["mvms"]) and s2["ms_chain"] > 0
-    assert s2["chain_bytes"] > 3 * 8 * op.n
+    # Clenshaw degree 8: 5 middle terms per q(A), 2 q(A) per step plus c = q(A) b
+    assert s2["n_chain"] == 5 * (2 * s2["iters"] + 1) and s2["ms_chain"] > 0
+    assert s2["chain_bytes"] == 4 * 8 * op.n
 
 
 # --------------------------------------------------------------------------
