@@ -8,9 +8,9 @@ stopping tolerance 1e-8 on the difference-of-iterates estimate.
 
 A step is one fa_apply solve (setup of the operator and polynomial excluded,
 inputs resident in HBM).  Printed as one JSON line with a roofline object for
-the dominant kernel (the fused stencil chain step: HIP events around the
-first 64 chain launches of every timed solve) and the CPU oracle timed on a
-bounded sample.  Extra fields report plain Arnoldi (degree 0), degrees 4 and 32 and the
+the dominant kernel (the stencil chain launch that evaluates two Clenshaw
+terms: HIP events around each run of such launches in every timed solve) and
+the CPU oracle timed on a bounded sample.  Extra fields report plain Arnoldi (degree 0), degrees 4 and 32 and the
 square root on the same GPU.
 """
 from __future__ import annotations
@@ -99,15 +99,16 @@ def main():
     def rel_err(x):
         return float(torch.linalg.vector_norm(x - x_ref) / torch.linalg.vector_norm(x_ref))
 
-    def timed(op, steps, warmup, kind="invsqrt", m_max=200, profile=False):
+    def timed(op, steps, warmup, kind="invsqrt", m_max=200, profile=False, fuse=True):
         x = torch.empty_like(b)
         for _ in range(warmup):
-            op.apply(b, kind=kind, m_max=m_max, tol=tol, out=x)
+            op.apply(b, kind=kind, m_max=m_max, tol=tol, out=x, fuse=fuse)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         stats = []
         for _ in range(steps):
-            _, st = op.apply(b, kind=kind, m_max=m_max, tol=tol, out=x, profile=profile)
+            _, st = op.apply(b, kind=kind, m_max=m_max, tol=tol, out=x, profile=profile,
+                             fuse=fuse)
             stats.append(st)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -134,6 +135,19 @@ def main():
     extra = {"iters": st0["iters"], "mvms": st0["mvms"], "inner_products": st0["inner_products"],
              "rel_err_vs_ref": err, "est": st0["est_rel_change"],
              "ms_host_fH_per_solve": st0["ms_host_fH"]}
+
+    # ---- the same solve with one launch per recurrence term ---------------
+    o = make(K)
+    xu, dtu, stu = timed(o, 5, 1, profile=True, fuse=False)
+    nu = sum(s_["n_chain"] for s_ in stu)
+    avg_u = sum(s_["ms_chain"] for s_ in stu) / max(nu, 1)
+    extra["single_term_launches"] = {
+        "solves_per_s": 5 / dtu, "rel_err": rel_err(xu), "kernel": "st7_chain<true,true>",
+        "avg_launch_us": avg_u * 1e3, "bytes_per_launch": stu[-1]["chain_bytes"],
+        "achieved_GBs": stu[-1]["chain_bytes"] / (avg_u * 1e-3) / 1e9}
+    log(f"single-term launches: {5 / dtu:.2f} solves/s, chain launch {avg_u * 1e3:.1f} us")
+    o.release_workspace()
+    del o
 
     # ---- other degrees and the square root --------------------------------
     others = {}
@@ -188,7 +202,8 @@ def main():
         "config": {"workload": f"convdiff3d_{N}^3 Pe=50 invsqrt chebyshev degree {K} tol 1e-8",
                    "n": N ** 3, "degree": K, "tol": tol, "kind": "invsqrt",
                    "orthogonalization": "CGS2", "preconditioning": "left"},
-        "roofline": {"bound": "hbm", "kernel": "st7_chain (fused stencil chain step)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "st7_pair<true,true,true> (two Clenshaw terms per launch)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": bytes_avg, "avg_launch_us": avg_ms * 1e3,

@@ -94,7 +94,8 @@ enum {
 enum {
   FA_HERMITIAN = 1u,     /* create: A is Hermitian; apply uses Lanczos (3-term)        */
   FA_FORCE_ARNOLDI = 4u, /* apply: Gram-Schmidt (CGS2) even for a Hermitian op          */
-  FA_PROFILE = 8u        /* apply: time the middle terms of every q(A) application      */
+  FA_PROFILE = 8u,       /* apply: time the middle terms of every q(A) application      */
+  FA_NO_FUSION = 16u     /* apply: one launch per recurrence term (no two-term launches) */
 };
 
 typedef struct {
@@ -111,13 +112,14 @@ typedef struct {
   double ms_total;        /* wall time of fa_apply                                      */
   double ms_host_fH;      /* host time spent in H_j^{-1/2} e_1                          */
   double ms_chain;        /* FA_PROFILE: device time of the timed chain launches: HIP
-                             events bracket each run of consecutive middle terms of a
-                             q(A) recurrence (Clenshaw terms 1..K-3, Newton terms
-                             1..K-2), so the figure includes the short gaps between
-                             back-to-back launches                                     */
+                             events bracket each run of consecutive launches of the
+                             middle of a q(A) recurrence (the Clenshaw terms that read
+                             x, v, b_{k+2}, two per launch on a stencil; the Newton
+                             terms that read r, v), so the figure includes the short
+                             gaps between back-to-back launches                        */
   int64_t n_chain;        /* FA_PROFILE: number of chain launches timed                 */
   double chain_bytes;     /* FA_PROFILE: algorithmic bytes of one timed launch: x, each
-                             combined vector and the output once, plus the operator's
+                             combined vector and each output once, plus the operator's
                              own arrays (Wilson links, CSR arrays)                      */
 } fa_stats;
 
@@ -204,7 +206,7 @@ int fa_poly_get(fa_op op, int* degree, int* method, double* coef_re, double* coe
                 double* nodes_re, double* nodes_im, double* interval, double* rho);
 
 /* Bytes of device workspace fa_apply needs for Krylov dimension m_max:
- * (m_max + 1) basis vectors + 3 chain vectors + reduction scratch + H. */
+ * (m_max + 1) basis vectors + 5 chain vectors + reduction scratch + H. */
 size_t fa_workspace_bytes(fa_op op, int m_max, uint32_t flags);
 
 /*

@@ -205,7 +205,7 @@ int fa_apply(fa_op op, int kind, const void* d_b, void* d_x, int m_max, double t
              void* hip_stream, fa_stats* stats) {
   if (!op || !d_b || !d_x || d_b == d_x || m_max < 1 || check_every < 0 ||
       (kind != FA_INVSQRT && kind != FA_SQRT) || !std::isfinite(tol) ||
-      (flags & ~uint32_t(FA_FORCE_ARNOLDI | FA_PROFILE)))
+      (flags & ~uint32_t(FA_FORCE_ARNOLDI | FA_PROFILE | FA_NO_FUSION)))
     return FA_ERR_ARG;
   if (!op->op.poly_ready) return FA_ERR_NO_POLY;
   if ((int64_t)m_max > op->op.n) return FA_ERR_ARG;
@@ -263,14 +263,19 @@ const char* fa_status_string(int status) {
 int fa_dense_invsqrt_e1(int m, int dtype, const double* h_H, int ldh, double beta, double* h_z) {
   if (m < 1 || ldh < m || !h_H || !h_z || (dtype != FA_F64 && dtype != FA_C128)) return FA_ERR_ARG;
   return guarded([&] {
-    std::vector<cd> H((size_t)m * m), z(m);
-    for (int j = 0; j < m; ++j)
-      for (int i = 0; i < m; ++i) {
-        const size_t k = (size_t)j * ldh + i;
-        H[(size_t)j * m + i] =
-            (i > j + 1) ? cd(0.0) : (dtype == FA_C128 ? cd(h_H[2 * k], h_H[2 * k + 1]) : cd(h_H[k], 0.0));
-      }
-    const int st = hess_invsqrt_e1(m, H.data(), m, beta, z.data());
+    std::vector<cd> z(m);
+    int st;
+    if (dtype == FA_C128) {
+      std::vector<cd> H((size_t)m * m);
+      for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) {
+          const size_t k = (size_t)j * ldh + i;
+          H[(size_t)j * m + i] = (i > j + 1) ? cd(0.0) : cd(h_H[2 * k], h_H[2 * k + 1]);
+        }
+      st = hess_invsqrt_e1(m, H.data(), m, beta, z.data());
+    } else {
+      st = real_hess_invsqrt_e1(m, h_H, ldh, beta, z.data());
+    }
     if (st != DENSE_OK) return FA_ERR_HESSENBERG;
     for (int i = 0; i < m; ++i) {
       if (dtype == FA_C128) {

@@ -120,39 +120,223 @@ int hess_eigenvalues(int m, const cd* H, int ldh, cd* ev) {
   return DENSE_OK;
 }
 
-int hess_invsqrt_e1(int m, const cd* H, int ldh, double beta, cd* z) {
-  Schur S;
-  const int st = S.compute(m, H, ldh);
-  if (st != DENSE_OK) return st;
+// principal square root of a complex upper triangular T (Bjorck-Hammarling)
+// applied as z = Q R^{-1} Q^H (beta e_1); shared by both Schur variants
+template <typename S>
+static int triangular_invsqrt_e1(const S& sch, int m, double beta, cd* z) {
   double scale = 1.0;
-  for (int i = 0; i < m; ++i) scale = std::max(scale, std::abs(S.t(i, i)));
+  for (int i = 0; i < m; ++i) scale = std::max(scale, std::abs(sch.t(i, i)));
   for (int i = 0; i < m; ++i) {
-    const cd t = S.t(i, i);
+    const cd t = sch.t(i, i);
     if (t.real() <= 0.0 && std::fabs(t.imag()) <= 1e-12 * scale) return DENSE_BRANCH;
   }
-  // R = T^{1/2}: principal roots on the diagonal, then column by column
-  // R_ij (R_ii + R_jj) = T_ij - sum_{i<k<j} R_ik R_kj (Bjorck-Hammarling)
   std::vector<cd> R((size_t)m * m, cd(0.0));
   auto r = [&](int i, int j) -> cd& { return R[(size_t)j * m + i]; };
   for (int j = 0; j < m; ++j) {
-    r(j, j) = std::sqrt(S.t(j, j));
+    r(j, j) = std::sqrt(sch.t(j, j));
     for (int i = j - 1; i >= 0; --i) {
-      cd s = S.t(i, j);
+      cd s = sch.t(i, j);
       for (int k = i + 1; k < j; ++k) s -= r(i, k) * r(k, j);
       r(i, j) = s / (r(i, i) + r(j, j));
     }
   }
   std::vector<cd> u(m, cd(0.0));
   u[0] = beta;
-  S.apply_QH(u.data());
-  for (int i = m - 1; i >= 0; --i) {  // R y = u
+  sch.apply_QH(u.data());
+  for (int i = m - 1; i >= 0; --i) {
     cd s = u[i];
     for (int k = i + 1; k < m; ++k) s -= r(i, k) * u[k];
     u[i] = s / r(i, i);
   }
-  S.apply_Q(u.data());
+  sch.apply_Q(u.data());
   for (int i = 0; i < m; ++i) z[i] = u[i];
   return DENSE_OK;
+}
+
+int hess_invsqrt_e1(int m, const cd* H, int ldh, double beta, cd* z) {
+  Schur S;
+  const int st = S.compute(m, H, ldh);
+  if (st != DENSE_OK) return st;
+  return triangular_invsqrt_e1(S, m, beta, z);
+}
+
+// ---- real Francis double-shift QR ----------------------------------------
+namespace {
+// Householder reflector I - tau v v^T (v[0] = 1) with (I - tau v v^T) x = (beta, 0, ...)
+inline void house(int len, const double* x, double* v, double& tau) {
+  double sig = 0.0;
+  for (int i = 1; i < len; ++i) sig += x[i] * x[i];
+  v[0] = 1.0;
+  for (int i = 1; i < len; ++i) v[i] = x[i];
+  if (sig == 0.0) {
+    tau = 0.0;
+    return;
+  }
+  const double mu = std::sqrt(x[0] * x[0] + sig);
+  const double v0 = (x[0] <= 0.0) ? x[0] - mu : -sig / (x[0] + mu);
+  tau = 2.0 * v0 * v0 / (sig + v0 * v0);
+  for (int i = 1; i < len; ++i) v[i] /= v0;
+}
+}  // namespace
+
+int RealSchur::compute(int m_, const double* H, int ldh) {
+  m = m_;
+  Tr.assign((size_t)m * m, 0.0);
+  refl.clear();
+  rot.clear();
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i <= std::min(j + 1, m - 1); ++i) Tr[(size_t)j * m + i] = H[(size_t)j * ldh + i];
+  auto a = [&](int i, int j) -> double& { return Tr[(size_t)j * m + i]; };
+  double hnorm = 0.0;
+  for (double v : Tr) hnorm = std::max(hnorm, std::fabs(v));
+  if (hnorm == 0.0) hnorm = 1.0;
+
+  auto reflect = [&](int k, int len, const double* v, double tau, int ilo, int ihi) {
+    // left: rows k..k+len-1, columns from max(ilo, k-1) to m-1
+    for (int c = std::max(ilo, k - 1); c < m; ++c) {
+      double sdot = 0.0;
+      for (int r = 0; r < len; ++r) sdot += v[r] * a(k + r, c);
+      sdot *= tau;
+      for (int r = 0; r < len; ++r) a(k + r, c) -= sdot * v[r];
+    }
+    // right: columns k..k+len-1, rows 0..min(k+len, ihi)
+    const int rmax = std::min(k + len, ihi);
+    for (int r = 0; r <= rmax; ++r) {
+      double sdot = 0.0;
+      for (int c = 0; c < len; ++c) sdot += a(r, k + c) * v[c];
+      sdot *= tau;
+      for (int c = 0; c < len; ++c) a(r, k + c) -= sdot * v[c];
+    }
+    Refl R;
+    R.k = k;
+    R.len = len;
+    R.tau = tau;
+    for (int i = 0; i < 3; ++i) R.v[i] = (i < len) ? v[i] : 0.0;
+    refl.push_back(R);
+  };
+
+  int hi = m - 1, its = 0, total = 0;
+  while (hi >= 0) {
+    int l = hi;
+    for (; l > 0; --l) {
+      double sc = std::fabs(a(l, l)) + std::fabs(a(l - 1, l - 1));
+      if (sc == 0.0) sc = hnorm;
+      if (std::fabs(a(l, l - 1)) <= kEps * sc) {
+        a(l, l - 1) = 0.0;
+        break;
+      }
+    }
+    if (l >= hi - 1) {  // a 1x1 or 2x2 block has split off
+      hi = l - 1;
+      its = 0;
+      continue;
+    }
+    if (++its > 100 || ++total > 100 * m) return DENSE_NOCONV;
+    // double shift: the eigenvalues of the trailing 2x2 block (sum s, product t)
+    double sh, th;
+    if (its % 11 == 10) {  // exceptional shift
+      const double w = std::fabs(a(hi, hi - 1)) + std::fabs(a(hi - 1, hi - 2));
+      sh = 1.5 * w + a(hi, hi);
+      th = w * w;
+    } else {
+      sh = a(hi - 1, hi - 1) + a(hi, hi);
+      th = a(hi - 1, hi - 1) * a(hi, hi) - a(hi - 1, hi) * a(hi, hi - 1);
+    }
+    // first column of (H - mu1)(H - mu2) restricted to rows l..l+2
+    double x[3];
+    x[0] = a(l, l) * a(l, l) + a(l, l + 1) * a(l + 1, l) - sh * a(l, l) + th;
+    x[1] = a(l + 1, l) * (a(l, l) + a(l + 1, l + 1) - sh);
+    x[2] = a(l + 1, l) * a(l + 2, l + 1);
+    for (int k = l; k <= hi - 2; ++k) {
+      double v[3], tau;
+      house(3, x, v, tau);
+      if (tau != 0.0) reflect(k, 3, v, tau, l, hi);
+      x[0] = a(k + 1, k);
+      x[1] = a(k + 2, k);
+      if (k < hi - 2) x[2] = a(k + 3, k);
+      if (k > l) {  // the reflector annihilated the bulge in column k - 1
+        a(k + 1, k - 1) = 0.0;
+        a(k + 2, k - 1) = 0.0;
+      }
+    }
+    {
+      double v[3], tau;
+      house(2, x, v, tau);
+      if (tau != 0.0) reflect(hi - 1, 2, v, tau, l, hi);
+      if (hi - 2 >= l) a(hi, hi - 2) = 0.0;
+    }
+  }
+  // complex triangular T: triangularize each remaining 2x2 diagonal block
+  T.assign((size_t)m * m, cd(0.0));
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i <= std::min(j + 1, m - 1); ++i) T[(size_t)j * m + i] = a(i, j);
+  auto t_ = [&](int i, int j) -> cd& { return T[(size_t)j * m + i]; };
+  for (int i = 0; i + 1 < m; ++i) {
+    if (t_(i + 1, i) == 0.0) continue;
+    const cd A = t_(i, i), B = t_(i, i + 1), Cc = t_(i + 1, i), D = t_(i + 1, i + 1);
+    const cd half = 0.5 * (A + D);
+    const cd disc = std::sqrt(0.25 * (A - D) * (A - D) + B * Cc);
+    // eigenvector (lam - D, C) of the block for the eigenvalue farther from D
+    // (the nearer one makes lam - D a cancellation when C is small)
+    const cd l1 = half + disc, l2 = half - disc;
+    const cd lam = (std::abs(l1 - D) >= std::abs(l2 - D)) ? l1 : l2;
+    // normalized, it is the first column of G
+    cd g1 = lam - D, g2 = Cc;
+    const double nr = std::sqrt(std::norm(g1) + std::norm(g2));
+    g1 /= nr;
+    g2 /= nr;
+    // T <- G^H T G on rows / columns i, i+1;  G = [[g1, -conj g2], [g2, conj g1]]
+    for (int c = i; c < m; ++c) {
+      const cd r0 = t_(i, c), r1 = t_(i + 1, c);
+      t_(i, c) = std::conj(g1) * r0 + std::conj(g2) * r1;
+      t_(i + 1, c) = -g2 * r0 + g1 * r1;
+    }
+    for (int r = 0; r <= i + 1; ++r) {
+      const cd c0 = t_(r, i), c1 = t_(r, i + 1);
+      t_(r, i) = c0 * g1 + c1 * g2;
+      t_(r, i + 1) = -c0 * std::conj(g2) + c1 * std::conj(g1);
+    }
+    t_(i + 1, i) = 0.0;
+    rot.push_back({i, g1, g2});
+    ++i;  // the next block starts after this one
+  }
+  return DENSE_OK;
+}
+
+void RealSchur::apply_QH(cd* v) const {
+  // H = (P_1 ... P_N G_1 ... G_R) T (...)^H with symmetric reflectors P
+  for (const Refl& r : refl) {
+    cd sdot = 0.0;
+    for (int i = 0; i < r.len; ++i) sdot += r.v[i] * v[r.k + i];
+    sdot *= r.tau;
+    for (int i = 0; i < r.len; ++i) v[r.k + i] -= sdot * r.v[i];
+  }
+  for (const Rot2& g : rot) {
+    const cd a0 = v[g.k], a1 = v[g.k + 1];
+    v[g.k] = std::conj(g.g1) * a0 + std::conj(g.g2) * a1;
+    v[g.k + 1] = -g.g2 * a0 + g.g1 * a1;
+  }
+}
+
+void RealSchur::apply_Q(cd* v) const {
+  for (auto it = rot.rbegin(); it != rot.rend(); ++it) {
+    const cd a0 = v[it->k], a1 = v[it->k + 1];
+    v[it->k] = it->g1 * a0 - std::conj(it->g2) * a1;
+    v[it->k + 1] = it->g2 * a0 + std::conj(it->g1) * a1;
+  }
+  for (auto it = refl.rbegin(); it != refl.rend(); ++it) {
+    cd sdot = 0.0;
+    for (int i = 0; i < it->len; ++i) sdot += it->v[i] * v[it->k + i];
+    sdot *= it->tau;
+    for (int i = 0; i < it->len; ++i) v[it->k + i] -= sdot * it->v[i];
+  }
+}
+
+int real_hess_invsqrt_e1(int m, const double* H, int ldh, double beta, cd* z) {
+  RealSchur S;
+  const int st = S.compute(m, H, ldh);
+  if (st != DENSE_OK) return st;
+  return triangular_invsqrt_e1(S, m, beta, z);
 }
 
 int tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double beta,

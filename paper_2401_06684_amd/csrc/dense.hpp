@@ -35,6 +35,28 @@ struct Schur {
 // z = H^{-1/2} (beta e_1); H complex upper Hessenberg (column-major, ldh).
 int hess_invsqrt_e1(int m, const cd* H, int ldh, double beta, cd* z);
 
+// Real Schur form of a real upper Hessenberg matrix by the Francis
+// double-shift QR algorithm (3x3 Householder reflectors chasing the bulge),
+// then each 2x2 diagonal block triangularized by a unitary 2x2 transform, so
+// that H = Q T Q^H with T complex upper triangular.  About a quarter of the
+// arithmetic of the complex single-shift algorithm.
+struct RealSchur {
+  int m = 0;
+  std::vector<double> Tr;  // real quasi-triangular factor (column-major)
+  std::vector<cd> T;       // complex triangular factor (column-major)
+  struct Refl { int k, len; double v[3]; double tau; };  // I - tau v v^T on rows k..k+len-1
+  struct Rot2 { int k; cd g1, g2; };                    // columns (g1, g2), (-conj g2, conj g1)
+  std::vector<Refl> refl;
+  std::vector<Rot2> rot;
+  int compute(int m, const double* H, int ldh);
+  void apply_QH(cd* v) const;
+  void apply_Q(cd* v) const;
+  cd t(int i, int j) const { return T[(size_t)j * m + i]; }
+};
+
+// z = H^{-1/2} (beta e_1) for a real upper Hessenberg H (z real up to rounding)
+int real_hess_invsqrt_e1(int m, const double* H, int ldh, double beta, cd* z);
+
 // z = T^{-1/2} (beta e_1); T symmetric tridiagonal.
 int tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double beta,
                        double* z);

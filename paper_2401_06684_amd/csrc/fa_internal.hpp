@@ -28,6 +28,16 @@ struct Poly {
   std::vector<cd> theta;      // RITZ Leja-ordered nodes
   std::vector<cd> eta;        // RITZ scaled Newton coefficients
   double rho = 1.0;           // RITZ scaling
+  // Real operators whose Ritz values include conjugate pairs: the Newton form
+  // regrouped into real blocks (a real node, or a conjugate pair kept adjacent
+  // by the Leja order).  With w_B the real product of the factors of the
+  // blocks before B, q(z) = sum_B w_B(z) (a_B + b_B z).
+  struct Block {
+    bool pair;
+    double re, im;  // the node (pair: theta = re + i im, im > 0)
+    double a, b;    // real linear part a_B + b_B z
+  };
+  std::vector<Block> blocks;  // empty unless a real op has non-real nodes
 };
 
 struct Op {
@@ -61,9 +71,20 @@ struct ChainCoef {
   cd alpha, beta, g0, g1;
 };
 
+// Two consecutive terms in one launch (7-point stencil only):
+//   s = t1.alpha A x + t1.beta x + t1.g0 y0 + t1.g1 y1,  out1 = s (if out1),
+//   out2 = t2.alpha A s + t2.beta s + t2.g0 y0 + t2.g1 x.
+// out1 / out2 must not alias x, y0 or y1.
+hipError_t launch_chain_pair(const Op& op, const void* x, const void* y0, const void* y1,
+                             void* out1, void* out2, const ChainCoef& t1, const ChainCoef& t2,
+                             hipStream_t s);
+inline bool has_pair_kernel(const Op& op) { return op.kind == OP_STENCIL7; }
+
 // algorithmic bytes moved by one chain launch (x read once, y0, y1 read,
 // out written, plus the operator's own data)
 double chain_bytes(const Op& op, bool has_y0, bool has_y1);
+// algorithmic bytes of one two-term launch (x, y0, y1 read once; out1, out2 written)
+double chain_pair_bytes(const Op& op, bool has_y0, bool has_y1, bool has_out1);
 
 // ---- kernel launchers (kernels_*.hip) ----
 hipError_t launch_chain(const Op& op, const void* x, const void* y0, const void* y1, void* out,

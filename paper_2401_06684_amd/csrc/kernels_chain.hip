@@ -101,6 +101,251 @@ static hipError_t launch_st7(const Op& op, const double* x, const double* y0, co
 }
 
 // --------------------------------------------------------------------------
+// Two consecutive recurrence terms of the 7-point stencil in one launch:
+//     s    = a1 A x + b1 x + g01 y0 + g11 y1        (term t, on the tile + 1 halo)
+//     out2 = a2 A s + b2 s + g02 y0 + g12 x         (term t + 1, on the tile)
+// For the Clenshaw recurrence x = b_{k+1}, y0 = v, y1 = b_{k+2}, s = b_k and
+// out2 = b_{k-1}: a pair of terms reads x, v, b_{k+2} and writes b_k, b_{k-1}
+// (5 vector passes instead of 8 for two single-term launches).  s never leaves
+// the chip except for the tile written to out1 (skipped when nothing reads it).
+// A workgroup owns a 64 x 8 tile and marches through kz planes in z with three
+// LDS rings: x on the tile + 2 halo (three planes), s on the tile + 1 halo
+// (three planes).  The values outside the grid are zero (Dirichlet), so s is
+// zero there too.  out1 and out2 must not alias x, y0 or y1, which are read on
+// the halo of neighbouring tiles.
+// --------------------------------------------------------------------------
+#ifndef FA_PAIR_TY
+#define FA_PAIR_TY 8
+#endif
+#ifndef FA_PAIR_BLOCKS
+#define FA_PAIR_BLOCKS 512
+#endif
+constexpr int P_TX = 64, P_TY = FA_PAIR_TY;
+constexpr int P_XW = P_TX + 4, P_XH = P_TY + 4;  // x region (tile + 2)
+constexpr int P_SW = P_TX + 2, P_SH = P_TY + 2;  // s region (tile + 1)
+constexpr int P_THREADS = P_TX * P_TY;
+constexpr int P_XPT = (P_XW * P_XH + P_THREADS - 1) / P_THREADS;  // x points per thread
+constexpr int P_SPT = (P_SW * P_SH + P_THREADS - 1) / P_THREADS;  // s points per thread
+
+struct PairCoef {
+  double a1, b1, g01, g11, a2, b2, g02, g12;
+};
+
+// Software pipeline: the global loads for the next plane (x on the x region,
+// y0 / y1 on the s region, y0 on the tile) are issued into registers before
+// the current plane is computed from LDS, so their latency overlaps the work
+// of the current step instead of stalling at a barrier.  The x ring has four
+// planes so that the prefetched plane can be stored while the previous one is
+// still being read: two barriers per plane.
+__device__ __forceinline__ int xslot(int q) { return (q + 8) & 3; }
+__device__ __forceinline__ int sslot(int q) { return (q + 6) % 3; }
+
+template <bool Y0, bool Y1, bool W1>
+__global__ __launch_bounds__(P_THREADS) void st7_pair(St7 s, int kz, int gx, int gy, int nwg,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ y0,
+                                                      const double* __restrict__ y1,
+                                                      double* __restrict__ out1,
+                                                      double* __restrict__ out2, PairCoef c) {
+  __shared__ double xs[4][P_XH][P_XW];
+  __shared__ double ss[3][P_SH][P_SW];
+  const int lid = xcd_contiguous(blockIdx.x, nwg);
+  const int bx = lid % gx, by = (lid / gx) % gy, bz = lid / (gx * gy);
+  const int i0 = bx * P_TX, j0 = by * P_TY;
+  const int k0 = bz * kz, k1 = min(k0 + kz, s.nz);
+  const int tid = threadIdx.x;
+  const int tx = tid % P_TX, ty = tid / P_TX;
+  const int64_t plane = (int64_t)s.nx * s.ny;
+  auto in_grid = [&](int i, int j) { return i >= 0 && i < s.nx && j >= 0 && j < s.ny; };
+
+  // per-thread fixed points of the x region, the s region and the tile
+  int64_t xoff[P_XPT];
+  bool xok[P_XPT], xin[P_XPT];
+#pragma unroll
+  for (int u = 0; u < P_XPT; ++u) {
+    const int r = tid + u * P_THREADS;
+    const int rx = r % P_XW, ry = r / P_XW;
+    const int i = i0 - 2 + rx, j = j0 - 2 + ry;
+    xin[u] = r < P_XW * P_XH;
+    xok[u] = xin[u] && in_grid(i, j);
+    xoff[u] = (int64_t)j * s.nx + i;
+  }
+  int64_t soff[P_SPT];
+  bool sok[P_SPT], sin_[P_SPT], stile[P_SPT];
+  int sxx[P_SPT], syy[P_SPT];
+#pragma unroll
+  for (int u = 0; u < P_SPT; ++u) {
+    const int r = tid + u * P_THREADS;
+    const int sx = r % P_SW, sy = r / P_SW;
+    const int i = i0 - 1 + sx, j = j0 - 1 + sy;
+    sxx[u] = sx;
+    syy[u] = sy;
+    sin_[u] = r < P_SW * P_SH;
+    sok[u] = sin_[u] && in_grid(i, j);
+    stile[u] = sx >= 1 && sx <= P_TX && sy >= 1 && sy <= P_TY;
+    soff[u] = (int64_t)j * s.nx + i;
+  }
+  const bool tok = in_grid(i0 + tx, j0 + ty);
+  const int64_t toff = (int64_t)(j0 + ty) * s.nx + (i0 + tx);
+
+  auto fetch_x = [&](int q, double* reg) {
+    const bool zin = q >= 0 && q < s.nz;
+#pragma unroll
+    for (int u = 0; u < P_XPT; ++u)
+      reg[u] = (zin && xok[u]) ? x[(int64_t)q * plane + xoff[u]] : 0.0;
+  };
+  auto store_x = [&](int q, const double* reg) {
+    double* dst = &xs[xslot(q)][0][0];
+#pragma unroll
+    for (int u = 0; u < P_XPT; ++u)
+      if (xin[u]) dst[tid + u * P_THREADS] = reg[u];
+  };
+  auto fetch_y = [&](int q, double* r0, double* r1) {
+    const bool zin = q >= 0 && q < s.nz;
+#pragma unroll
+    for (int u = 0; u < P_SPT; ++u) {
+      const bool ok = zin && sok[u];
+      r0[u] = (Y0 && ok) ? y0[(int64_t)q * plane + soff[u]] : 0.0;
+      r1[u] = (Y1 && ok) ? y1[(int64_t)q * plane + soff[u]] : 0.0;
+    }
+  };
+  auto stage1 = [&](int q, const double* r0, const double* r1) {
+    double(*dst)[P_SW] = ss[sslot(q)];
+    const bool zin = q >= 0 && q < s.nz;
+    const double(*xm)[P_XW] = xs[xslot(q - 1)];
+    const double(*xc)[P_XW] = xs[xslot(q)];
+    const double(*xp)[P_XW] = xs[xslot(q + 1)];
+#pragma unroll
+    for (int u = 0; u < P_SPT; ++u) {
+      if (!sin_[u]) continue;
+      const int sx = sxx[u], sy = syy[u];
+      double v = 0.0;
+      if (zin && sok[u]) {
+        const int cx = sx + 1, cy = sy + 1;
+        const double xv = xc[cy][cx];
+        double ax = s.c0 * xv;
+        ax = fma(s.czm, xm[cy][cx], ax);
+        ax = fma(s.czp, xp[cy][cx], ax);
+        ax = fma(s.cxm, xc[cy][cx - 1], ax);
+        ax = fma(s.cxp, xc[cy][cx + 1], ax);
+        ax = fma(s.cym, xc[cy - 1][cx], ax);
+        ax = fma(s.cyp, xc[cy + 1][cx], ax);
+        v = fma(c.a1, ax, c.b1 * xv);
+        if (Y0) v = fma(c.g01, r0[u], v);
+        if (Y1) v = fma(c.g11, r1[u], v);
+        if (W1 && q >= k0 && q < k1 && stile[u]) out1[(int64_t)q * plane + soff[u]] = v;
+      }
+      dst[sy][sx] = v;
+    }
+  };
+  auto stage2 = [&](int z, double yt) {
+    if (!tok) return;
+    const double(*sm)[P_SW] = ss[sslot(z - 1)];
+    const double(*sc)[P_SW] = ss[sslot(z)];
+    const double(*sp)[P_SW] = ss[sslot(z + 1)];
+    const int cx = tx + 1, cy = ty + 1;
+    const double sv = sc[cy][cx];
+    double as = s.c0 * sv;
+    as = fma(s.czm, sm[cy][cx], as);
+    as = fma(s.czp, sp[cy][cx], as);
+    as = fma(s.cxm, sc[cy][cx - 1], as);
+    as = fma(s.cxp, sc[cy][cx + 1], as);
+    as = fma(s.cym, sc[cy - 1][cx], as);
+    as = fma(s.cyp, sc[cy + 1][cx], as);
+    double r = fma(c.a2, as, c.b2 * sv);
+    if (Y0) r = fma(c.g02, yt, r);
+    r = fma(c.g12, xs[xslot(z)][ty + 2][tx + 2], r);
+    out2[(int64_t)z * plane + toff] = r;
+  };
+
+  // s(q) needs x planes q-1..q+1; out2(z) needs s planes z-1..z+1.  Loads run
+  // two steps ahead: at step q the registers receive x plane q+3, y0 / y1 of
+  // plane q+2 and y0 of the tile at plane q+1.
+  {
+    double t[P_XPT];
+    fetch_x(k0 - 2, t);
+    store_x(k0 - 2, t);
+    fetch_x(k0 - 1, t);
+    store_x(k0 - 1, t);
+    fetch_x(k0, t);
+    store_x(k0, t);
+  }
+  double xa[P_XPT];  // x plane q + 2
+  fetch_x(k0 + 1, xa);
+  double y0c[P_SPT], y1c[P_SPT], y0n[P_SPT], y1n[P_SPT];  // y at planes q, q + 1
+  fetch_y(k0 - 1, y0c, y1c);
+  fetch_y(k0, y0n, y1n);
+  double ytc = 0.0;  // y0 on the tile at plane q - 1 (for stage2(q - 1))
+  double ytn = (Y0 && tok && k0 < k1) ? y0[(int64_t)k0 * plane + toff] : 0.0;  // plane q
+  __syncthreads();
+  for (int q = k0 - 1; q <= k1; ++q) {
+    double xb[P_XPT], y0m[P_SPT], y1m[P_SPT];
+    const bool fx = q + 3 <= k1 + 1, fy = q + 2 <= k1;
+    if (fx) fetch_x(q + 3, xb);
+    if (fy) fetch_y(q + 2, y0m, y1m);
+    double ytm = 0.0;
+    if (Y0 && tok && q + 1 >= k0 && q + 1 < k1) ytm = y0[(int64_t)(q + 1) * plane + toff];
+    stage1(q, y0c, y1c);
+    __syncthreads();  // s(q) complete
+    if (q - 1 >= k0) stage2(q - 1, ytc);
+    // the slot of plane q + 2 held plane q - 2, last read before the barrier above
+    if (q + 2 <= k1 + 1) store_x(q + 2, xa);
+    __syncthreads();  // x(q + 2) visible; stage2 done with s(q - 2)
+#pragma unroll
+    for (int u = 0; u < P_XPT; ++u) xa[u] = xb[u];
+#pragma unroll
+    for (int u = 0; u < P_SPT; ++u) {
+      y0c[u] = y0n[u];
+      y1c[u] = y1n[u];
+      y0n[u] = y0m[u];
+      y1n[u] = y1m[u];
+    }
+    ytc = ytn;
+    ytn = ytm;
+  }
+}
+
+static hipError_t launch_st7_pair(const Op& op, const double* x, const double* y0,
+                                  const double* y1, double* out1, double* out2,
+                                  const PairCoef& c, hipStream_t st) {
+  St7 s{op.dims[0], op.dims[1], op.dims[2], op.coef[0], op.coef[1], op.coef[2],
+        op.coef[3], op.coef[4], op.coef[5], op.coef[6]};
+  const int gx = (s.nx + P_TX - 1) / P_TX, gy = (s.ny + P_TY - 1) / P_TY;
+  // about FA_PAIR_BLOCKS workgroups, at least 2 planes each (the x ring reads
+  // 2 extra planes on each side of a workgroup's slab)
+  int gz = (int)std::max<int64_t>(
+      1, std::min<int64_t>(s.nz / 2, FA_PAIR_BLOCKS / ((int64_t)gx * gy)));
+  const int kz = (s.nz + gz - 1) / gz;
+  gz = (s.nz + kz - 1) / kz;
+  const int nwg = gx * gy * gz;
+  const bool w1 = out1 != nullptr;
+  const dim3 grid(nwg), block(P_THREADS);
+#define FA_PAIR(A, B, C) \
+  st7_pair<A, B, C><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out1, out2, c)
+  if (y0 && y1) {
+    if (w1) FA_PAIR(true, true, true); else FA_PAIR(true, true, false);
+  } else if (y0) {
+    if (w1) FA_PAIR(true, false, true); else FA_PAIR(true, false, false);
+  } else if (y1) {
+    if (w1) FA_PAIR(false, true, true); else FA_PAIR(false, true, false);
+  } else {
+    if (w1) FA_PAIR(false, false, true); else FA_PAIR(false, false, false);
+  }
+#undef FA_PAIR
+  return hipGetLastError();
+}
+
+hipError_t launch_chain_pair(const Op& op, const void* x, const void* y0, const void* y1,
+                             void* out1, void* out2, const ChainCoef& t1, const ChainCoef& t2,
+                             hipStream_t s) {
+  if (op.kind != OP_STENCIL7) return hipErrorInvalidValue;
+  const PairCoef c{t1.alpha.real(), t1.beta.real(), t1.g0.real(), t1.g1.real(),
+                   t2.alpha.real(), t2.beta.real(), t2.g0.real(), t2.g1.real()};
+  return launch_st7_pair(op, (const double*)x, (const double*)y0, (const double*)y1,
+                         (double*)out1, (double*)out2, c, s);
+}
+
+// --------------------------------------------------------------------------
 // CSR, real or complex values: G lanes per row (G = power of two <= 64 close
 // to the mean row length), row sums reduced with shuffles inside the group.
 // --------------------------------------------------------------------------
@@ -349,6 +594,11 @@ hipError_t launch_chain(const Op& op, const void* x, const void* y0, const void*
                            s);
   }
   return hipErrorInvalidValue;
+}
+
+double chain_pair_bytes(const Op& op, bool has_y0, bool has_y1, bool has_out1) {
+  const double vec = (double)op.n * elem_size(op.dtype);
+  return vec * (2.0 + (has_y0 ? 1.0 : 0.0) + (has_y1 ? 1.0 : 0.0) + (has_out1 ? 1.0 : 0.0));
 }
 
 double chain_bytes(const Op& op, bool has_y0, bool has_y1) {

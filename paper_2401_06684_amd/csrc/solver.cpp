@@ -34,6 +34,8 @@ Layout make_layout(const Op& op, int m_max) {
   L.off_U = take((size_t)L.ldv * es);
   L.off_P = take((size_t)L.ldv * es);
   L.off_Q = take((size_t)L.ldv * es);
+  L.off_R = take((size_t)L.ldv * es);
+  L.off_S = take((size_t)L.ldv * es);
   L.off_part = take((size_t)(m_max + 2) * rp.nblk * es + 64);
   L.off_h = take((size_t)(m_max + 2) * es);
   L.off_H = take((size_t)L.ldh * m_max * es);
@@ -71,13 +73,15 @@ struct Prof {
     }
     return hipEventRecord(t_events[used], s);
   }
-  hipError_t end(hipStream_t s, int nlaunch, double bytes_each) {
+  hipError_t end(hipStream_t s) {
     if (!on) return hipSuccess;
     hipError_t err = hipEventRecord(t_events[used + 1], s);
     used += 2;
+    return err;
+  }
+  void count(int nlaunch, double bytes_each) {
     launches += nlaunch;
     bytes += nlaunch * bytes_each;
-    return err;
   }
   // after a stream sync: summed milliseconds
   double total_ms() const {
@@ -117,92 +121,196 @@ int op_apply(const Op& op, const void* x, void* y, hipStream_t s) {
   return chain(op, x, nullptr, nullptr, y, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, nullptr);
 }
 
-// q(A) x by the recurrence of the polynomial (K products with A).  The result
-// is written to `out` unless K == 1 and out == x (the single step reads x with
-// neighbours), in which case it goes to t1.  out may equal x for K >= 2 (the
-// last step reads x pointwise only).  t1, t2 must differ from x and out.
-// Returns the buffer holding q(A) x through *res.
-static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, void* t1, void* t2,
-                      const void** res, hipStream_t s, Prof* prof, int64_t* mvms) {
+// One term of a polynomial recurrence: out_i = alpha A x_i + beta x_i + g0 v
+// + g1 out_{i-2}, where x_i = out_{i-1} (x_0 = v, the vector q(A) acts on).
+struct Term {
+  ChainCoef k;
+  bool y0, y1;
+};
+
+// The terms of q(A) v (K products with A):
+//   Chebyshev, Clenshaw (Sec. 5.1) with Ahat = sig A + tau I,
+//     b_k = c_k v + 2 Ahat b_{k+1} - b_{k+2},  q(A) v = c_0 v + Ahat b_1 - b_2;
+//     b_K = c_K v and b_{K+1} = 0 are folded into the first two terms.
+//   Newton form on Leja points, Horner-type recurrence (Sec. 5.2),
+//     r_K = eta_K v,  r_j = (A - theta_j) r_{j+1} / rho + eta_j v.
+static std::vector<Term> poly_terms(const Poly& q) {
+  std::vector<Term> T;
   const int K = q.degree;
-  if (q.method < 0 || K == 0) {
-    // q == 1: the caller treats x itself as the result
-    *res = x;
-    return FA_OK;
-  }
-  *mvms += K;
-  if (K == 1 && out == x) out = t1;
   if (q.method == FA_POLY_CHEB) {
-    // Clenshaw (Sec. 5.1) with Ahat = sig A + tau I:
-    //   b_k = c_k x + 2 Ahat b_{k+1} - b_{k+2},  q(A) x = c_0 x + Ahat b_1 - b_2,
-    // b_K = c_K x and b_{K+1} = 0 are folded into the first launches.
     const std::vector<double>& c = q.c;
     const double sig = 2.0 / (q.b - q.a), tau = -(q.a + q.b) / (q.b - q.a);
     if (K == 1) {
-      int st = chain(op, x, nullptr, nullptr, out, ChainCoef{sig * c[1], tau * c[1] + c[0], 0, 0},
-                     s, prof);
-      *res = out;
-      return st;
+      T.push_back({ChainCoef{sig * c[1], tau * c[1] + c[0], 0, 0}, false, false});
+      return T;
     }
-    // b_{K-1} = 2 Ahat (c_K x) + c_{K-1} x
-    int st = chain(op, x, nullptr, nullptr, t1,
-                   ChainCoef{2 * sig * c[K], 2 * tau * c[K] + c[K - 1], 0, 0}, s, prof);
-    if (st) return st;
-    if (K == 2) {  // q(A) x = c_0 x + Ahat b_1 - b_2, b_2 = c_2 x
-      st = chain(op, t1, x, nullptr, out, ChainCoef{sig, tau, c[0] - c[2], 0}, s, prof);
-      *res = out;
-      return st;
+    T.push_back({ChainCoef{2 * sig * c[K], 2 * tau * c[K] + c[K - 1], 0, 0}, false, false});
+    for (int i = 1; i < K; ++i) {
+      const int k = K - 1 - i;  // the term produces b_k (k = 0: q(A) v)
+      const double a = (k == 0) ? sig : 2 * sig, b = (k == 0) ? tau : 2 * tau;
+      const double g0 = c[k] - (i == 1 ? c[K] : 0.0);
+      T.push_back({ChainCoef{a, b, g0, i >= 2 ? -1.0 : 0.0}, true, i >= 2});
     }
-    // b_{K-2} = 2 Ahat b_{K-1} + c_{K-2} x - c_K x
-    st = chain(op, t1, x, nullptr, t2, ChainCoef{2 * sig, 2 * tau, c[K - 2] - c[K], 0}, s, prof);
-    if (st) return st;
-    void* bk1 = t2;  // b_{k+1}
-    void* bk2 = t1;  // b_{k+2}, overwritten by b_k
-    if (prof && K >= 4) FA_HIP(prof->begin(s));
-    for (int k = K - 3; k >= 1; --k) {
-      st = chain(op, bk1, x, bk2, bk2, ChainCoef{2 * sig, 2 * tau, c[k], -1.0}, s, prof);
-      if (st) return st;
-      std::swap(bk1, bk2);
-    }
-    if (prof && K >= 4) FA_HIP(prof->end(s, K - 3, chain_bytes(op, true, true)));
-    st = chain(op, bk1, x, bk2, out, ChainCoef{sig, tau, c[0], -1.0}, s, prof);
-    *res = out;
-    return st;
+    return T;
   }
-  // Newton form on Leja points, Horner-type recurrence (Sec. 5.2):
-  //   r_K = eta_K x,  r_j = (A - theta_j) r_{j+1} / rho + eta_j x
   const std::vector<cd>& th = q.theta;
   const std::vector<cd>& eta = q.eta;
   const double rho = q.rho;
-  void* cur = nullptr;
-  {
-    void* dst = (K == 1) ? out : t1;
-    const cd a = eta[K] / rho;
-    int st = chain(op, x, nullptr, nullptr, dst, ChainCoef{a, eta[K - 1] - th[K - 1] * a, 0, 0},
-                   s, prof);
-    if (st) return st;
-    cur = dst;
+  const cd a = eta[K] / rho;
+  T.push_back({ChainCoef{a, eta[K - 1] - th[K - 1] * a, 0, 0}, false, false});
+  for (int j = K - 2; j >= 0; --j)
+    T.push_back({ChainCoef{1.0 / rho, -th[j] / rho, eta[j], 0}, true, false});
+  return T;
+}
+
+// q(A) x for a Ritz polynomial of a real operator in real blocks (Horner over
+// the blocks, last to first):  R = a_L v + b_L u  (u = A v);  then for each
+// block B:
+//   real node theta:  R <- (A - theta) R / rho + a_B v
+//   pair theta, conj(theta), c = Re theta, s = Im theta:
+//     t  = (A - c) R / rho + d v,               d = -a_B rho / c
+//     R <- (A - c) t / rho + (s/rho)^2 R + f u, f = b_B + a_B / c
+// which adds ((A - c)^2 + s^2) R / rho^2 + a_B v + b_B u, two launches with at
+// most two extra vectors each.
+static int poly_apply_blocks(const Op& op, const Poly& q, const void* x, void* out,
+                             void* const tmp[4], const void** res, hipStream_t s, int64_t* mvms) {
+  const std::vector<Poly::Block>& B = q.blocks;
+  const int L = (int)B.size();
+  const double rho = q.rho;
+  bool need_u = false;
+  for (const auto& b : B) need_u |= b.pair;
+  void* u = tmp[3];
+  if (need_u) {
+    FA_HIP(launch_chain(op, x, nullptr, nullptr, u, ChainCoef{1.0, 0.0, 0.0, 0.0}, s));
+    *mvms += 1;
   }
-  if (prof && K >= 3) FA_HIP(prof->begin(s));
-  for (int j = K - 2; j >= 0; --j) {
-    void* dst = (j == 0) ? out : (cur == t1 ? t2 : t1);
-    int st = chain(op, cur, x, nullptr, dst, ChainCoef{1.0 / rho, -th[j] / rho, eta[j], 0}, s,
-                   prof);
-    if (st) return st;
-    cur = dst;
-    if (prof && K >= 3 && j == 1) FA_HIP(prof->end(s, K - 2, chain_bytes(op, true, false)));
+  // R = a_L v + b_L u (no product with A: alpha = 0)
+  void* R = tmp[0];
+  FA_HIP(launch_chain(op, x, nullptr, need_u ? u : nullptr, R,
+                      ChainCoef{0.0, B[L - 1].a, 0.0, B[L - 1].b}, s));
+  void* spare[2] = {tmp[1], tmp[2]};
+  for (int k = L - 2; k >= 0; --k) {
+    const auto& b = B[k];
+    const bool last = k == 0;
+    void* dst = spare[0];
+    if (!b.pair) {
+      if (last && out != R) dst = out;
+      FA_HIP(launch_chain(op, R, x, nullptr, dst, ChainCoef{1.0 / rho, -b.re / rho, b.a, 0.0}, s));
+      *mvms += 1;
+      spare[0] = R;
+      R = dst;
+    } else {
+      const double c = b.re, e = (b.im / rho) * (b.im / rho);
+      const double d = -b.a * rho / c, f = b.b + b.a / c;
+      void* t = spare[0];
+      FA_HIP(launch_chain(op, R, x, nullptr, t, ChainCoef{1.0 / rho, -c / rho, d, 0.0}, s));
+      // R' may overwrite R (read pointwise) or go to out (never read here)
+      void* d2 = (last && out != t) ? out : R;
+      FA_HIP(launch_chain(op, t, R, u, d2, ChainCoef{1.0 / rho, -c / rho, e, f}, s));
+      *mvms += 2;
+      R = d2;
+    }
   }
-  *res = cur;
+  *res = R;
+  return FA_OK;
+}
+
+// q(A) x.  tmp holds 4 scratch vectors distinct from x and out.  The result
+// goes to `out` when that is safe and to a scratch vector otherwise (a
+// single-term launch may write over x pointwise, a two-term launch may not);
+// *res names the buffer that holds q(A) x.  With `fuse`, consecutive terms
+// of the 7-point stencil run two per launch.
+static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, void* const tmp[4],
+                      const void** res, hipStream_t s, Prof* prof, int64_t* mvms, bool fuse) {
+  const int K = q.degree;
+  if (q.method < 0 || K == 0) {
+    *res = x;  // q == 1
+    return FA_OK;
+  }
+  if (!q.blocks.empty()) return poly_apply_blocks(op, q, x, out, tmp, res, s, mvms);
+  *mvms += K;
+  const std::vector<Term> T = poly_terms(q);
+  const int nT = (int)T.size();
+  const bool pairs = fuse && has_pair_kernel(op) && nT >= 2;
+  if (!pairs) {
+    // one launch per term; out_i may overwrite out_{i-2} in place (read pointwise)
+    const void* xm1 = x;       // out_{i-1}
+    const void* xm2 = nullptr; // out_{i-2}
+    void* slot[2] = {tmp[0], tmp[1]};
+    bool timing = false;
+    for (int i = 0; i < nT; ++i) {
+      const bool last = i == nT - 1;
+      void* dst;
+      if (last)
+        dst = (out == xm1) ? (xm2 && xm2 != x ? (void*)xm2 : slot[i & 1]) : out;
+      else
+        dst = (i >= 2 && T[i].y1) ? (void*)xm2 : slot[i & 1];
+      if (dst == xm1) dst = slot[(i + 1) & 1];
+      const bool middle = !last && T[i].y0 && (q.method == FA_POLY_RITZ || T[i].y1);
+      if (prof && middle && !timing) {
+        FA_HIP(prof->begin(s));
+        timing = true;
+      }
+      if (prof && timing && !middle) {
+        FA_HIP(prof->end(s));
+        timing = false;
+      }
+      FA_HIP(launch_chain(op, xm1, T[i].y0 ? x : nullptr, T[i].y1 ? xm2 : nullptr, dst, T[i].k, s));
+      if (prof && timing) prof->count(1, chain_bytes(op, T[i].y0, T[i].y1));
+      xm2 = xm1;
+      xm1 = dst;
+    }
+    if (prof && timing) FA_HIP(prof->end(s));
+    *res = xm1;
+    return FA_OK;
+  }
+  // two terms per launch: pair p = (T[2p], T[2p+1]) reads out_{2p-1}, out_{2p-2},
+  // x and writes out_{2p}, out_{2p+1} into the buffer set not holding its inputs
+  const void* xm1 = x;
+  const void* xm2 = nullptr;
+  int set = 0;
+  bool timing = false;
+  int i = 0;
+  for (; i + 1 < nT; i += 2) {
+    const bool has_next = i + 2 < nT;  // someone reads out_{2p} later
+    const bool last_pair = i + 2 >= nT;
+    void* o1 = has_next ? tmp[2 * set] : nullptr;
+    void* o2 = tmp[2 * set + 1];
+    if (last_pair && out != x && out != xm1 && out != xm2) o2 = out;
+    const bool middle = T[i].y0 && T[i].y1 && T[i + 1].y1 && has_next;
+    if (prof && middle && !timing) {
+      FA_HIP(prof->begin(s));
+      timing = true;
+    }
+    if (prof && timing && !middle) {
+      FA_HIP(prof->end(s));
+      timing = false;
+    }
+    ChainCoef k2 = T[i + 1].k;
+    if (!T[i + 1].y1) k2.g1 = 0.0;
+    FA_HIP(launch_chain_pair(op, xm1, (T[i].y0 || T[i + 1].y0) ? x : nullptr,
+                             T[i].y1 ? xm2 : nullptr, o1, o2, T[i].k, k2, s));
+    if (prof && timing) prof->count(1, chain_pair_bytes(op, true, true, o1 != nullptr));
+    xm2 = o1;
+    xm1 = o2;
+    set ^= 1;
+  }
+  if (prof && timing) FA_HIP(prof->end(s));
+  if (i < nT) {  // odd number of terms: the last one alone (pointwise in out)
+    void* dst = (out == xm1) ? tmp[2 * set] : out;
+    FA_HIP(launch_chain(op, xm1, T[i].y0 ? x : nullptr, T[i].y1 ? xm2 : nullptr, dst, T[i].k, s));
+    xm1 = dst;
+  }
+  *res = xm1;
   return FA_OK;
 }
 
 int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_t s) {
   const Layout L = make_layout(op, 1);
-  void* t1 = at(ws, L.off_P);
-  void* t2 = at(ws, L.off_Q);
+  void* const tmp[4] = {at(ws, L.off_P), at(ws, L.off_Q), at(ws, L.off_R), at(ws, L.off_S)};
   const void* res = nullptr;
   int64_t mv = 0;
-  int st = poly_apply(op, op.poly, x, y, t1, t2, &res, s, nullptr, &mv);
+  int st = poly_apply(op, op.poly, x, y, tmp, &res, s, nullptr, &mv, true);
   if (st) return st;
   if (res != y) FA_HIP(hipMemcpyAsync(y, res, op.n * elem_size(op.dtype), hipMemcpyDeviceToDevice, s));
   return FA_OK;
@@ -234,10 +342,15 @@ int host_coeffs(const HostH& H, int m, bool lanczos, double beta, std::vector<cd
     for (int i = 0; i < m; ++i) z[i] = zr[i];
     return FA_OK;
   }
-  std::vector<cd> Hc((size_t)m * m);
-  for (int j = 0; j < m; ++j)
-    for (int i = 0; i < m; ++i) Hc[(size_t)j * m + i] = (i <= j + 1) ? H.get(i, j) : cd(0.0);
-  const int st = hess_invsqrt_e1(m, Hc.data(), m, beta, z.data());
+  int st;
+  if (H.dtype == FA_F64) {  // real Francis double-shift QR on the host copy
+    st = real_hess_invsqrt_e1(m, H.buf.data(), H.ldh, beta, z.data());
+  } else {
+    std::vector<cd> Hc((size_t)m * m);
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) Hc[(size_t)j * m + i] = (i <= j + 1) ? H.get(i, j) : cd(0.0);
+    st = hess_invsqrt_e1(m, Hc.data(), m, beta, z.data());
+  }
   if (st != DENSE_OK) return FA_ERR_HESSENBERG;
   if (H.dtype == FA_F64)
     for (auto& v : z) v = cd(v.real(), 0.0);
@@ -267,8 +380,8 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
 
   char* V = at(ws, L.off_V);
   void* U = at(ws, L.off_U);
-  void* P = at(ws, L.off_P);
-  void* Qb = at(ws, L.off_Q);
+  void* const tmp[4] = {at(ws, L.off_P), at(ws, L.off_Q), at(ws, L.off_R), at(ws, L.off_S)};
+  const bool fuse = !(flags & FA_NO_FUSION);
   void* part = at(ws, L.off_part);
   char* hcur = at(ws, L.off_h);
   char* Hd = at(ws, L.off_H);
@@ -294,9 +407,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   // Algorithm 1: c = q(A) b', beta = ||c||, v_1 = c / beta
   {
     const void* res = nullptr;
-    void* t1 = (bsrc == U) ? P : U;
-    void* t2 = (bsrc == U) ? Qb : P;
-    st = poly_apply(op, q, bsrc, Vc(0), t1, t2, &res, s, pp, &mvms);
+    st = poly_apply(op, q, bsrc, Vc(0), tmp, &res, s, pp, &mvms, fuse);
     if (st) return st;
     if (res != Vc(0)) FA_HIP(launch_scale(op.dtype, n, cd(1.0), res, Vc(0), s));
     FA_HIP(launch_update(op.dtype, n, 0, V, L.ldv, hcur, Vc(0), part, nrm, s));
@@ -342,11 +453,17 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       if (st) return st;
       ++mvms;
       const void* y = nullptr;
-      st = poly_apply(op, q, U, U, P, Qb, &y, s, pp, &mvms);
+      st = poly_apply(op, q, U, U, tmp, &y, s, pp, &mvms, fuse);
       if (st) return st;
-      void* t1 = (y == P) ? U : P;
+      void* tmp2[4];  // the scratch vectors other than the one holding y
+      {
+        void* all[5] = {U, tmp[0], tmp[1], tmp[2], tmp[3]};
+        int c = 0;
+        for (void* b : all)
+          if (b != y && c < 4) tmp2[c++] = b;
+      }
       const void* r2 = nullptr;
-      st = poly_apply(op, q, y, w, t1, Qb, &r2, s, pp, &mvms);
+      st = poly_apply(op, q, y, w, tmp2, &r2, s, pp, &mvms, fuse);
       if (st) return st;
       if (r2 != w) FA_HIP(launch_scale(op.dtype, n, cd(1.0), r2, w, s));
     }
@@ -466,6 +583,37 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
 // --------------------------------------------------------------------------
 // polynomial setup
 // --------------------------------------------------------------------------
+// Regroup the scaled Newton form of a real operator's Ritz polynomial into
+// real blocks.  q(z) = sum_j eta_j w_j(z), w_j = prod_{i<j} (z - theta_i)/rho,
+// with conjugate pairs adjacent.  At a block start the nodes before it form a
+// conjugate-closed set, so w_j has real coefficients; q itself is real, so q
+// equals the sum of w_{start(B)} times the real parts of the coefficients of
+// each block's linear factor l_B(z) = eta_s + eta_{s+1} (z - theta_s)/rho
+// (pair) or eta_s (real node).
+static int real_blocks(Poly& q) {
+  const std::vector<cd>& th = q.theta;
+  const std::vector<cd>& eta = q.eta;
+  const double rho = q.rho;
+  q.blocks.clear();
+  for (size_t j = 0; j < th.size();) {
+    if (th[j].imag() == 0.0) {
+      q.blocks.push_back({false, th[j].real(), 0.0, eta[j].real(), 0.0});
+      j += 1;
+      continue;
+    }
+    if (j + 1 >= th.size() || std::abs(th[j + 1] - std::conj(th[j])) > 1e-10 * std::abs(th[j]))
+      return FA_ERR_UNSUPPORTED;  // a non-real node without its conjugate next to it
+    // the evaluation divides by Re theta (see poly_apply): refuse nodes that
+    // are nearly imaginary
+    if (th[j].real() < 1e-3 * std::abs(th[j])) return FA_ERR_UNSUPPORTED;
+    const cd e0 = eta[j], e1 = eta[j + 1];
+    q.blocks.push_back({true, th[j].real(), std::fabs(th[j].imag()),
+                        (e0 - e1 * th[j] / rho).real(), (e1 / rho).real()});
+    j += 2;
+  }
+  return FA_OK;
+}
+
 size_t poly_workspace_bytes(const Op& op, int degree, int method) {
   if (method == FA_POLY_CHEB || degree == 0) return 0;
   return make_layout(op, degree + 1).bytes;
@@ -558,11 +706,13 @@ int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, si
     for (int i = 0; i < steps; ++i) Hc[(size_t)j * steps + i] = (i <= j + 1) ? H.get(i, j) : cd(0.0);
   if (hess_eigenvalues(steps, Hc.data(), steps, ev.data()) != DENSE_OK) return FA_ERR_HESSENBERG;
   const bool real_op = op.dtype == FA_F64;
+  bool any_complex = false;
   for (auto& t : ev) {
     if (!(t.real() > 0.0)) return FA_ERR_BRANCH;  // Ritz value outside the right half-plane
     if (real_op) {
-      if (std::fabs(t.imag()) > 1e-10 * std::abs(t)) return FA_ERR_UNSUPPORTED;
-      t = cd(t.real(), 0.0);
+      // eigenvalues of a real H are real or come in conjugate pairs
+      if (std::fabs(t.imag()) <= 1e-10 * std::abs(t)) t = cd(t.real(), 0.0);
+      else any_complex = true;
     }
   }
   q.method = FA_POLY_RITZ;
@@ -570,8 +720,10 @@ int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, si
   q.degree = (int)q.theta.size() - 1;
   q.rho = leja_capacity(q.theta);
   q.eta = newton_invsqrt(q.theta, q.rho);
-  if (real_op)
-    for (auto& e : q.eta) e = cd(e.real(), 0.0);
+  if (real_op && any_complex) {
+    const int st = real_blocks(q);
+    if (st) return st;
+  }
   op.poly = q;
   op.poly_ready = true;
   return FA_OK;

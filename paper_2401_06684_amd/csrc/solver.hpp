@@ -9,7 +9,7 @@ namespace fa {
 struct Layout {
   int64_t ldv = 0;  // leading dimension of the basis (elements)
   int ldh = 0;      // leading dimension of H (elements)
-  size_t off_V = 0, off_U = 0, off_P = 0, off_Q = 0, off_part = 0, off_h = 0, off_H = 0,
+  size_t off_V = 0, off_U = 0, off_P = 0, off_Q = 0, off_R = 0, off_S = 0, off_part = 0, off_h = 0, off_H = 0,
          off_nrm = 0, off_z = 0;
   size_t bytes = 0;
 };

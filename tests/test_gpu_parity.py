@@ -281,9 +281,35 @@ def test_bitwise_deterministic_and_profile():
     x1, s1 = op.apply(b, m_max=60, tol=1e-10)
     x2, s2 = op.apply(b, m_max=60, tol=1e-10, profile=True)
     assert torch.equal(x1, x2)
-    # Clenshaw degree 8: 5 middle terms per q(A), 2 q(A) per step plus c = q(A) b
-    assert s2["n_chain"] == 5 * (2 * s2["iters"] + 1) and s2["ms_chain"] > 0
-    assert s2["chain_bytes"] == 4 * 8 * op.n
+    # Clenshaw degree 8 = 8 terms = 4 two-term launches per q(A), of which the
+    # 2nd and 3rd read x, v, b_{k+2} and write both terms (5 vectors); 2 q(A)
+    # per step plus c = q(A) b
+    assert s2["n_chain"] == 2 * (2 * s2["iters"] + 1) and s2["ms_chain"] > 0
+    assert s2["chain_bytes"] == 5 * 8 * op.n
+    x3, s3 = op.apply(b, m_max=60, tol=1e-10, fuse=False, profile=True)
+    assert s3["n_chain"] == 5 * (2 * s3["iters"] + 1)
+    assert s3["chain_bytes"] == 4 * 8 * op.n
+    assert_close(host(x3), host(x1), 1e-13)
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 4, 5, 16, 17])
+@pytest.mark.parametrize("dims", [(70, 9, 11), (128, 16, 24), (33, 65, 5), (20, 20, 1)])
+def test_two_term_launches_match_single_terms(degree, dims):
+    """q(A) x and whole solves with two recurrence terms per launch equal the
+    single-term path and the oracle (ragged tiles in x, y and z)."""
+    coeffs = wl.convdiff_stencil(max(dims), 50.0)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(degree, "cheb")
+    a, b = ops.stencil_interval(coeffs, dims)
+    q = pl.chebyshev(a, b, degree)
+    x = wl.rhs(op.n, seed=2)
+    ref, _ = q.apply(lambda v: ops.stencil_apply(coeffs, dims, v), x)
+    assert_close(host(op.poly_apply(dev(x))), ref, 1e-12)
+    bd = dev(wl.rhs(op.n, seed=0))
+    m = min(6, op.n)
+    x1, _ = op.apply(bd, m_max=m, tol=0.0)
+    x2, _ = op.apply(bd, m_max=m, tol=0.0, fuse=False)
+    assert_close(host(x1), host(x2), 1e-12)
 
 
 # --------------------------------------------------------------------------
@@ -311,3 +337,99 @@ def test_convdiff_128_full_size():
     op.poly_setup(32, "cheb")
     x32, s32 = op.apply(bd, kind="invsqrt", m_max=200, tol=1e-10)
     assert_close(host(x32), host(xi), 1e-8)
+
+
+# --------------------------------------------------------------------------
+# the 16^4 Wilson-like workload at full size
+# --------------------------------------------------------------------------
+def test_wilson_16_full_size():
+    """16^4 lattice, links exp(0.3 i H), m0 = 0.05, Ritz degree 16, tol 1e-8.
+
+    At this size the oracle is too slow for a whole solve; the checks are
+    properties that hold at any size: agreement with the plain method and
+    with another degree, and A^{1/2} (A^{-1/2} b) = b."""
+    L = 16
+    U = wl.su3_links(L, eps=0.3, seed=1)
+    m0 = 0.05
+    op = fa().Wilson(U, m0)
+    assert op.n == 786432
+    start = dev(wl.rhs(op.n, seed=11, complex_=True))
+    b = dev(wl.rhs(op.n, seed=0, complex_=True))
+    # one operator application against the oracle on the full lattice
+    xv = wl.rhs(op.n, seed=4, complex_=True)
+    assert_close(host(op.op_apply(dev(xv))), ops.wilson_apply(U, m0, xv), 1e-14)
+    op.poly_setup(16, "ritz", start=start)
+    p = op.poly()
+    assert min(z.real for z in p["theta"]) > 0
+    x16, s16 = op.apply(b, kind="invsqrt", m_max=200, tol=1e-10)
+    assert s16["converged"]
+    op.poly_setup(8, "ritz", start=start)
+    x8, s8 = op.apply(b, kind="invsqrt", m_max=300, tol=1e-10)
+    assert s8["converged"] and s8["iters"] > s16["iters"]
+    assert_close(host(x16), host(x8), 1e-8)
+    op.poly_setup(16, "ritz", start=start)
+    y, sy = op.apply(x16, kind="sqrt", m_max=200, tol=1e-10)
+    assert_close(host(y), host(b), 1e-8)
+
+
+def test_powerlaw_csr_apply_full_size():
+    """SpMV with a directed power-law graph Laplacian of the shape of
+    Example 3 (n = 281,903, ~2.58M stored entries, rows up to ~34k entries)."""
+    rp, ci, va = wl.powerlaw_digraph_laplacian_csr(281903, 2594228, seed=5)
+    op = fa().CSR(rp, ci, va)
+    xv = wl.rhs(op.n, seed=3)
+    assert_close(host(op.op_apply(dev(xv))), ops.csr_apply(rp, ci, va, xv), 1e-14)
+
+
+@pytest.mark.parametrize("degree", [0, 4, 8])
+def test_singular_digraph_laplacian_sqrt(degree):
+    """Sec. 4 (implicit desingularization): L^{1/2} b as L^{-1/2}(L b) for the
+    singular in-degree Laplacian of a random digraph; reference from the
+    eigendecomposition with sqrt(0) = 0, and the oracle."""
+    n = 300
+    rp, ci, va = wl.digraph_laplacian_csr(n, p=0.03, seed=3)
+    Ld = np.zeros((n, n))
+    for i in range(n):
+        Ld[i, ci[rp[i]:rp[i + 1]]] = va[rp[i]:rp[i + 1]]
+    lam, X = np.linalg.eig(Ld)
+    b = wl.rhs(n, seed=6)
+    ref = (X @ (np.sqrt(np.where(np.abs(lam) < 1e-10, 0, lam)) * np.linalg.solve(X, b))).real
+    op = fa().CSR(rp, ci, va)
+    start = wl.rhs(n, seed=8)
+    op.poly_setup(degree, "ritz", start=dev(start))
+    x, st = op.apply(dev(b), kind="sqrt", m_max=n, tol=1e-10, check_every=2)
+    assert st["converged"] and not st["breakdown"]
+    assert_close(host(x), ref, 1e-9)
+    A = lambda v: ops.csr_apply(rp, ci, va, v)
+    q = pl.ritz(A, start, degree, real_operator=True)
+    orc = kr.fAb(A, b, q, "sqrt", m_max=n, tol=1e-10, check_every=2)
+    assert_close(host(x), orc.x, 1e-9)
+
+
+@pytest.mark.parametrize("degree", [4, 8])
+def test_real_operator_complex_ritz_values(degree):
+    """Ritz polynomial of a strongly non-normal real operator whose Ritz values
+    include conjugate pairs: evaluated in real arithmetic (real linear and
+    quadratic factors) on the GPU, in complex arithmetic by the oracle."""
+    N = 12
+    dims = (N, N, N)
+    coeffs = wl.convdiff_stencil(N, 400.0)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    start = wl.rhs(N ** 3, seed=4)
+    q = pl.ritz(A, start, degree, real_operator=True)
+    assert np.max(np.abs(q.theta.imag)) > 0.1       # really complex nodes
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(degree, "ritz", start=dev(start))
+    p = op.poly()
+    key = lambda z: (round(z.real, 6), round(z.imag, 6))
+    gt = np.array(sorted(p["theta"], key=key))
+    rt = np.array(sorted(q.theta, key=key))
+    assert np.max(np.abs(gt - rt)) <= 1e-8 * np.max(np.abs(rt))
+    x = wl.rhs(N ** 3, seed=5)
+    ref, _ = q.apply(A, x)
+    assert_close(host(op.poly_apply(dev(x))), ref, 1e-7)
+    b = wl.rhs(N ** 3, seed=0)
+    xs, st = op.apply(dev(b), m_max=400, tol=1e-12)
+    orc = kr.fAb(A, b, q, "invsqrt", m_max=400, tol=1e-12)
+    assert st["converged"]
+    assert_close(host(xs), orc.x, 1e-10)
