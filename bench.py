@@ -99,16 +99,18 @@ def main():
     def rel_err(x):
         return float(torch.linalg.vector_norm(x - x_ref) / torch.linalg.vector_norm(x_ref))
 
-    def timed(op, steps, warmup, kind="invsqrt", m_max=200, profile=False, fuse=True):
+    def timed(op, steps, warmup, kind="invsqrt", m_max=200, profile=False, fuse=True,
+              mixed=False, tol_=None):
+        t_ = tol if tol_ is None else tol_
         x = torch.empty_like(b)
         for _ in range(warmup):
-            op.apply(b, kind=kind, m_max=m_max, tol=tol, out=x, fuse=fuse)
+            op.apply(b, kind=kind, m_max=m_max, tol=t_, out=x, fuse=fuse, mixed=mixed)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         stats = []
         for _ in range(steps):
-            _, st = op.apply(b, kind=kind, m_max=m_max, tol=tol, out=x, profile=profile,
-                             fuse=fuse)
+            _, st = op.apply(b, kind=kind, m_max=m_max, tol=t_, out=x, profile=profile,
+                             fuse=fuse, mixed=mixed)
             stats.append(st)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -146,6 +148,21 @@ def main():
         "avg_launch_us": avg_u * 1e3, "bytes_per_launch": stu[-1]["chain_bytes"],
         "achieved_GBs": stu[-1]["chain_bytes"] / (avg_u * 1e-3) / 1e9}
     log(f"single-term launches: {5 / dtu:.2f} solves/s, chain launch {avg_u * 1e3:.1f} us")
+    o.release_workspace()
+    del o
+
+    # ---- mixed precision: the chain in FP32 (tolerance 1e-7) ---------------
+    o = make(K)
+    xm, dtm, stm = timed(o, 5, 1, profile=True, mixed=True, tol_=1e-7)
+    nm = sum(s_["n_chain"] for s_ in stm)
+    avg_m = sum(s_["ms_chain"] for s_ in stm) / max(nm, 1)
+    extra["mixed_fp32_chain"] = {
+        "solves_per_s": 5 / dtm, "iters": stm[-1]["iters"], "rel_err": rel_err(xm),
+        "tol": 1e-7, "kernel": "st7_pair<float,float,true,true,true>",
+        "avg_launch_us": avg_m * 1e3, "bytes_per_launch": stm[-1]["chain_bytes"],
+        "achieved_GBs": stm[-1]["chain_bytes"] / (avg_m * 1e-3) / 1e9}
+    log(f"mixed precision: {5 / dtm:.2f} solves/s, m = {stm[-1]['iters']}, "
+        f"err {rel_err(xm):.2e}, chain launch {avg_m * 1e3:.1f} us")
     o.release_workspace()
     del o
 

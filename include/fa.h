@@ -95,7 +95,13 @@ enum {
   FA_HERMITIAN = 1u,     /* create: A is Hermitian; apply uses Lanczos (3-term)        */
   FA_FORCE_ARNOLDI = 4u, /* apply: Gram-Schmidt (CGS2) even for a Hermitian op          */
   FA_PROFILE = 8u,       /* apply: time the middle terms of every q(A) application      */
-  FA_NO_FUSION = 16u     /* apply: one launch per recurrence term (no two-term launches) */
+  FA_NO_FUSION = 16u,    /* apply: one launch per recurrence term (no two-term launches) */
+  FA_MIXED = 32u         /* apply: the polynomial chain (A and q(A) in the three-stage
+                            product, and c = q(A) b) in FP32 storage with FP32
+                            accumulation; Gram-Schmidt, H, H^{-1/2} e_1, the basis and
+                            x = V z stay FP64.  7-point stencil with a Chebyshev q of
+                            degree >= 1 (degree 0: the flag is ignored); other
+                            operators or polynomials: FA_ERR_UNSUPPORTED             */
 };
 
 typedef struct {

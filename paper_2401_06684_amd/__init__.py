@@ -18,7 +18,7 @@ import torch
 
 from . import _lib
 from ._lib import (FA_C128, FA_F64, FA_FORCE_ARNOLDI, FA_HERMITIAN, FA_INVSQRT,  # noqa: F401
-                   FA_NO_FUSION, FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_RITZ, FA_PROFILE, FA_SQRT, FAError,
+                   FA_MIXED, FA_NO_FUSION, FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_RITZ, FA_PROFILE, FA_SQRT, FAError,
                    check, lib)
 
 __all__ = ["Stencil7", "CSR", "Wilson", "FAError", "lib", "dense_invsqrt_e1",
@@ -145,17 +145,19 @@ class Operator:
         self._ws.clear()
 
     def apply(self, b, kind="invsqrt", m_max=100, tol=1e-10, check_every=0, out=None,
-              force_arnoldi=False, profile=False, fuse=True, raise_not_converged=False):
+              force_arnoldi=False, profile=False, fuse=True, mixed=False,
+              raise_not_converged=False):
         """x ~ A^{-1/2} b or A^{1/2} b.  Returns (x, stats dict).
 
-        fuse=False runs one launch per recurrence term (no two-term launches).
+        fuse=False runs one launch per recurrence term (no two-term launches);
+        mixed=True runs the polynomial chain in FP32 (stencil, Chebyshev q).
         """
         b = self._vec(b, "b")
         x = out if out is not None else torch.empty_like(b)
         self._vec(x, "out")
         _, wsp, nbytes = self._workspace(m_max)
         flags = ((FA_FORCE_ARNOLDI if force_arnoldi else 0) | (FA_PROFILE if profile else 0)
-                 | (0 if fuse else FA_NO_FUSION))
+                 | (0 if fuse else FA_NO_FUSION) | (FA_MIXED if mixed else 0))
         stats = _lib.fa_stats()
         st = lib().fa_apply(self._h, _KIND[kind], _ptr(b), _ptr(x), m_max, float(tol),
                             check_every, wsp, nbytes, flags, _stream(self.device),

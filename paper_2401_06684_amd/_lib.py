@@ -23,7 +23,7 @@ FA_F64, FA_C128 = 0, 1
 FA_INVSQRT, FA_SQRT = 0, 1
 FA_STENCIL7, FA_WILSON4D = 0, 1
 FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_RITZ = 0, 1, 2
-FA_HERMITIAN, FA_FORCE_ARNOLDI, FA_PROFILE, FA_NO_FUSION = 1, 4, 8, 16
+FA_HERMITIAN, FA_FORCE_ARNOLDI, FA_PROFILE, FA_NO_FUSION, FA_MIXED = 1, 4, 8, 16, 32
 
 EXPORTS = [
     "fa_create_csr", "fa_create_stencil", "fa_set_spectral_interval",

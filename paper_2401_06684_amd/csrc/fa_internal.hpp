@@ -64,6 +64,9 @@ struct Op {
   bool poly_ready = false;
 };
 
+// storage precision of the vectors of one chain launch
+enum Prec { P64 = 0, P32 = 1 };
+
 // One fused chain launch: out = alpha A x + beta x + g0 y0 + g1 y1, with y0 /
 // y1 optional (nullptr).  out may alias y1 (each point reads its own y1 entry
 // before writing), never x.  Coefficients are complex; real ops use .real().
@@ -77,18 +80,22 @@ struct ChainCoef {
 // out1 / out2 must not alias x, y0 or y1.
 hipError_t launch_chain_pair(const Op& op, const void* x, const void* y0, const void* y1,
                              void* out1, void* out2, const ChainCoef& t1, const ChainCoef& t2,
-                             hipStream_t s);
+                             hipStream_t s, Prec pin = P64, Prec pout = P64);
 inline bool has_pair_kernel(const Op& op) { return op.kind == OP_STENCIL7; }
 
 // algorithmic bytes moved by one chain launch (x read once, y0, y1 read,
-// out written, plus the operator's own data)
-double chain_bytes(const Op& op, bool has_y0, bool has_y1);
+// out written, plus the operator's own data); p = storage of the vectors
+double chain_bytes(const Op& op, bool has_y0, bool has_y1, Prec p = P64);
 // algorithmic bytes of one two-term launch (x, y0, y1 read once; out1, out2 written)
-double chain_pair_bytes(const Op& op, bool has_y0, bool has_y1, bool has_out1);
+double chain_pair_bytes(const Op& op, bool has_y0, bool has_y1, bool has_out1, Prec p = P64);
+// y (FP32) = x (FP64), n entries
+hipError_t launch_to_f32(int64_t n, const double* x, float* y, hipStream_t s);
 
 // ---- kernel launchers (kernels_*.hip) ----
+// pin: storage of x, y0, y1; pout: storage of out.  FP32 storage (with FP32
+// arithmetic) is available for the 7-point stencil only.
 hipError_t launch_chain(const Op& op, const void* x, const void* y0, const void* y1, void* out,
-                        const ChainCoef& k, hipStream_t s);
+                        const ChainCoef& k, hipStream_t s, Prec pin = P64, Prec pout = P64);
 
 // Gram-Schmidt building blocks on a column-major basis V (ld = ldv elements).
 // Partial sums go to `part` (ncols x nblk), the second stage writes `h`.

@@ -9,6 +9,8 @@
 // vector and one write.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "devmath.hpp"
 #include "fa_internal.hpp"
 
@@ -39,13 +41,26 @@ __device__ __forceinline__ int xcd_contiguous(int bid, int nwg) {
   return (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
 }
 
-template <bool Y0, bool Y1>
+// Storage types: TX for every input vector (x, y0, y1), TO for the output.
+// Arithmetic is FP64 when both are double and FP32 otherwise (the mixed
+// precision mode keeps the polynomial chain in FP32 storage with FP32
+// accumulation; the first launch reads the FP64 basis vector, the last one
+// writes the FP64 result).
+template <typename TX, typename TO>
+using calc_t = typename std::conditional<std::is_same<TX, double>::value &&
+                                             std::is_same<TO, double>::value,
+                                         double, float>::type;
+
+template <typename TX, typename TO, bool Y0, bool Y1>
 __global__ __launch_bounds__(ST_TX* ST_TY) void st7_chain(St7 s, int kz, int gx, int gy, int nwg,
-                                                          const double* __restrict__ x,
-                                                          const double* __restrict__ y0,
-                                                          const double* y1, double* out,
-                                                          double al, double be, double g0,
-                                                          double g1) {
+                                                          const TX* __restrict__ x,
+                                                          const TX* __restrict__ y0,
+                                                          const TX* y1, TO* out, double al_,
+                                                          double be_, double g0_, double g1_) {
+  using T = calc_t<TX, TO>;
+  const T al = (T)al_, be = (T)be_, g0 = (T)g0_, g1 = (T)g1_;
+  const T c0 = (T)s.c0, cxm = (T)s.cxm, cxp = (T)s.cxp, cym = (T)s.cym, cyp = (T)s.cyp,
+          czm = (T)s.czm, czp = (T)s.czp;
   const int lid = xcd_contiguous(blockIdx.x, nwg);
   const int bx = lid % gx, by = (lid / gx) % gy, bz = lid / (gx * gy);
   const int i = bx * ST_TX + (threadIdx.x & (ST_TX - 1));
@@ -56,28 +71,33 @@ __global__ __launch_bounds__(ST_TX* ST_TY) void st7_chain(St7 s, int kz, int gx,
   const int64_t plane = (int64_t)s.nx * s.ny;
   int64_t p = (int64_t)k0 * plane + (int64_t)j * s.nx + i;
   const bool hx0 = i > 0, hx1 = i + 1 < s.nx, hy0 = j > 0, hy1 = j + 1 < s.ny;
-  double xz0 = (k0 > 0) ? x[p - plane] : 0.0;
-  double xc = x[p];
+  T xz0 = (k0 > 0) ? (T)x[p - plane] : T(0);
+  T xc = (T)x[p];
   for (int k = k0; k < k1; ++k, p += plane) {
-    const double xz1 = (k + 1 < s.nz) ? x[p + plane] : 0.0;
-    double ax = s.c0 * xc;
-    ax = fma(s.czm, xz0, ax);
-    ax = fma(s.czp, xz1, ax);
-    if (hx0) ax = fma(s.cxm, x[p - 1], ax);
-    if (hx1) ax = fma(s.cxp, x[p + 1], ax);
-    if (hy0) ax = fma(s.cym, x[p - s.nx], ax);
-    if (hy1) ax = fma(s.cyp, x[p + s.nx], ax);
-    double r = fma(al, ax, be * xc);
-    if (Y0) r = fma(g0, y0[p], r);
-    if (Y1) r = fma(g1, y1[p], r);
-    out[p] = r;
+    const T xz1 = (k + 1 < s.nz) ? (T)x[p + plane] : T(0);
+    T ax = c0 * xc;
+    ax = fma(czm, xz0, ax);
+    ax = fma(czp, xz1, ax);
+    if (hx0) ax = fma(cxm, (T)x[p - 1], ax);
+    if (hx1) ax = fma(cxp, (T)x[p + 1], ax);
+    if (hy0) ax = fma(cym, (T)x[p - s.nx], ax);
+    if (hy1) ax = fma(cyp, (T)x[p + s.nx], ax);
+    T r = fma(al, ax, be * xc);
+    if (Y0) r = fma(g0, (T)y0[p], r);
+    if (Y1) r = fma(g1, (T)y1[p], r);
+    out[p] = (TO)r;
     xz0 = xc;
     xc = xz1;
   }
 }
 
-static hipError_t launch_st7(const Op& op, const double* x, const double* y0, const double* y1,
-                             double* out, const ChainCoef& k, hipStream_t st) {
+template <typename TX, typename TO>
+static hipError_t launch_st7_t(const Op& op, const void* xv, const void* y0v, const void* y1v,
+                               void* outv, const ChainCoef& k, hipStream_t st) {
+  const TX* x = (const TX*)xv;
+  const TX* y0 = (const TX*)y0v;
+  const TX* y1 = (const TX*)y1v;
+  TO* out = (TO*)outv;
   St7 s{op.dims[0], op.dims[1], op.dims[2], op.coef[0], op.coef[1], op.coef[2],
         op.coef[3], op.coef[4], op.coef[5], op.coef[6]};
   const int gx = (s.nx + ST_TX - 1) / ST_TX, gy = (s.ny + ST_TY - 1) / ST_TY;
@@ -90,14 +110,22 @@ static hipError_t launch_st7(const Op& op, const double* x, const double* y0, co
   const double al = k.alpha.real(), be = k.beta.real(), g0 = k.g0.real(), g1 = k.g1.real();
   const dim3 grid(nwg), block(ST_TX * ST_TY);
   if (y0 && y1)
-    st7_chain<true, true><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
+    st7_chain<TX, TO, true, true><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
   else if (y0)
-    st7_chain<true, false><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
+    st7_chain<TX, TO, true, false><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
   else if (y1)
-    st7_chain<false, true><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
+    st7_chain<TX, TO, false, true><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
   else
-    st7_chain<false, false><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
+    st7_chain<TX, TO, false, false><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
   return hipGetLastError();
+}
+
+static hipError_t launch_st7(const Op& op, const void* x, const void* y0, const void* y1, void* out,
+                             const ChainCoef& k, hipStream_t st, Prec pin, Prec pout) {
+  if (pin == P64 && pout == P64) return launch_st7_t<double, double>(op, x, y0, y1, out, k, st);
+  if (pin == P64) return launch_st7_t<double, float>(op, x, y0, y1, out, k, st);
+  if (pout == P64) return launch_st7_t<float, double>(op, x, y0, y1, out, k, st);
+  return launch_st7_t<float, float>(op, x, y0, y1, out, k, st);
 }
 
 // --------------------------------------------------------------------------
@@ -140,15 +168,21 @@ struct PairCoef {
 __device__ __forceinline__ int xslot(int q) { return (q + 8) & 3; }
 __device__ __forceinline__ int sslot(int q) { return (q + 6) % 3; }
 
-template <bool Y0, bool Y1, bool W1>
+template <typename TX, typename TO, bool Y0, bool Y1, bool W1>
 __global__ __launch_bounds__(P_THREADS) void st7_pair(St7 s, int kz, int gx, int gy, int nwg,
-                                                      const double* __restrict__ x,
-                                                      const double* __restrict__ y0,
-                                                      const double* __restrict__ y1,
-                                                      double* __restrict__ out1,
-                                                      double* __restrict__ out2, PairCoef c) {
-  __shared__ double xs[4][P_XH][P_XW];
-  __shared__ double ss[3][P_SH][P_SW];
+                                                      const TX* __restrict__ x,
+                                                      const TX* __restrict__ y0,
+                                                      const TX* __restrict__ y1,
+                                                      TO* __restrict__ out1,
+                                                      TO* __restrict__ out2, PairCoef cd_) {
+  using T = calc_t<TX, TO>;
+  struct {
+    T a1, b1, g01, g11, a2, b2, g02, g12;
+  } c{(T)cd_.a1, (T)cd_.b1, (T)cd_.g01, (T)cd_.g11, (T)cd_.a2, (T)cd_.b2, (T)cd_.g02, (T)cd_.g12};
+  const T c0 = (T)s.c0, cxm = (T)s.cxm, cxp = (T)s.cxp, cym = (T)s.cym, cyp = (T)s.cyp,
+          czm = (T)s.czm, czp = (T)s.czp;
+  __shared__ T xs[4][P_XH][P_XW];
+  __shared__ T ss[3][P_SH][P_SW];
   const int lid = xcd_contiguous(blockIdx.x, nwg);
   const int bx = lid % gx, by = (lid / gx) % gy, bz = lid / (gx * gy);
   const int i0 = bx * P_TX, j0 = by * P_TY;
@@ -188,81 +222,81 @@ __global__ __launch_bounds__(P_THREADS) void st7_pair(St7 s, int kz, int gx, int
   const bool tok = in_grid(i0 + tx, j0 + ty);
   const int64_t toff = (int64_t)(j0 + ty) * s.nx + (i0 + tx);
 
-  auto fetch_x = [&](int q, double* reg) {
+  auto fetch_x = [&](int q, T* reg) {
     const bool zin = q >= 0 && q < s.nz;
 #pragma unroll
     for (int u = 0; u < P_XPT; ++u)
-      reg[u] = (zin && xok[u]) ? x[(int64_t)q * plane + xoff[u]] : 0.0;
+      reg[u] = (zin && xok[u]) ? (T)x[(int64_t)q * plane + xoff[u]] : T(0);
   };
-  auto store_x = [&](int q, const double* reg) {
-    double* dst = &xs[xslot(q)][0][0];
+  auto store_x = [&](int q, const T* reg) {
+    T* dst = &xs[xslot(q)][0][0];
 #pragma unroll
     for (int u = 0; u < P_XPT; ++u)
       if (xin[u]) dst[tid + u * P_THREADS] = reg[u];
   };
-  auto fetch_y = [&](int q, double* r0, double* r1) {
+  auto fetch_y = [&](int q, T* r0, T* r1) {
     const bool zin = q >= 0 && q < s.nz;
 #pragma unroll
     for (int u = 0; u < P_SPT; ++u) {
       const bool ok = zin && sok[u];
-      r0[u] = (Y0 && ok) ? y0[(int64_t)q * plane + soff[u]] : 0.0;
-      r1[u] = (Y1 && ok) ? y1[(int64_t)q * plane + soff[u]] : 0.0;
+      r0[u] = (Y0 && ok) ? (T)y0[(int64_t)q * plane + soff[u]] : T(0);
+      r1[u] = (Y1 && ok) ? (T)y1[(int64_t)q * plane + soff[u]] : T(0);
     }
   };
-  auto stage1 = [&](int q, const double* r0, const double* r1) {
-    double(*dst)[P_SW] = ss[sslot(q)];
+  auto stage1 = [&](int q, const T* r0, const T* r1) {
+    T(*dst)[P_SW] = ss[sslot(q)];
     const bool zin = q >= 0 && q < s.nz;
-    const double(*xm)[P_XW] = xs[xslot(q - 1)];
-    const double(*xc)[P_XW] = xs[xslot(q)];
-    const double(*xp)[P_XW] = xs[xslot(q + 1)];
+    const T(*xm)[P_XW] = xs[xslot(q - 1)];
+    const T(*xc)[P_XW] = xs[xslot(q)];
+    const T(*xp)[P_XW] = xs[xslot(q + 1)];
 #pragma unroll
     for (int u = 0; u < P_SPT; ++u) {
       if (!sin_[u]) continue;
       const int sx = sxx[u], sy = syy[u];
-      double v = 0.0;
+      T v = T(0);
       if (zin && sok[u]) {
         const int cx = sx + 1, cy = sy + 1;
-        const double xv = xc[cy][cx];
-        double ax = s.c0 * xv;
-        ax = fma(s.czm, xm[cy][cx], ax);
-        ax = fma(s.czp, xp[cy][cx], ax);
-        ax = fma(s.cxm, xc[cy][cx - 1], ax);
-        ax = fma(s.cxp, xc[cy][cx + 1], ax);
-        ax = fma(s.cym, xc[cy - 1][cx], ax);
-        ax = fma(s.cyp, xc[cy + 1][cx], ax);
+        const T xv = xc[cy][cx];
+        T ax = c0 * xv;
+        ax = fma(czm, xm[cy][cx], ax);
+        ax = fma(czp, xp[cy][cx], ax);
+        ax = fma(cxm, xc[cy][cx - 1], ax);
+        ax = fma(cxp, xc[cy][cx + 1], ax);
+        ax = fma(cym, xc[cy - 1][cx], ax);
+        ax = fma(cyp, xc[cy + 1][cx], ax);
         v = fma(c.a1, ax, c.b1 * xv);
         if (Y0) v = fma(c.g01, r0[u], v);
         if (Y1) v = fma(c.g11, r1[u], v);
-        if (W1 && q >= k0 && q < k1 && stile[u]) out1[(int64_t)q * plane + soff[u]] = v;
+        if (W1 && q >= k0 && q < k1 && stile[u]) out1[(int64_t)q * plane + soff[u]] = (TO)v;
       }
       dst[sy][sx] = v;
     }
   };
-  auto stage2 = [&](int z, double yt) {
+  auto stage2 = [&](int z, T yt) {
     if (!tok) return;
-    const double(*sm)[P_SW] = ss[sslot(z - 1)];
-    const double(*sc)[P_SW] = ss[sslot(z)];
-    const double(*sp)[P_SW] = ss[sslot(z + 1)];
+    const T(*sm)[P_SW] = ss[sslot(z - 1)];
+    const T(*sc)[P_SW] = ss[sslot(z)];
+    const T(*sp)[P_SW] = ss[sslot(z + 1)];
     const int cx = tx + 1, cy = ty + 1;
-    const double sv = sc[cy][cx];
-    double as = s.c0 * sv;
-    as = fma(s.czm, sm[cy][cx], as);
-    as = fma(s.czp, sp[cy][cx], as);
-    as = fma(s.cxm, sc[cy][cx - 1], as);
-    as = fma(s.cxp, sc[cy][cx + 1], as);
-    as = fma(s.cym, sc[cy - 1][cx], as);
-    as = fma(s.cyp, sc[cy + 1][cx], as);
-    double r = fma(c.a2, as, c.b2 * sv);
+    const T sv = sc[cy][cx];
+    T as = c0 * sv;
+    as = fma(czm, sm[cy][cx], as);
+    as = fma(czp, sp[cy][cx], as);
+    as = fma(cxm, sc[cy][cx - 1], as);
+    as = fma(cxp, sc[cy][cx + 1], as);
+    as = fma(cym, sc[cy - 1][cx], as);
+    as = fma(cyp, sc[cy + 1][cx], as);
+    T r = fma(c.a2, as, c.b2 * sv);
     if (Y0) r = fma(c.g02, yt, r);
     r = fma(c.g12, xs[xslot(z)][ty + 2][tx + 2], r);
-    out2[(int64_t)z * plane + toff] = r;
+    out2[(int64_t)z * plane + toff] = (TO)r;
   };
 
   // s(q) needs x planes q-1..q+1; out2(z) needs s planes z-1..z+1.  Loads run
   // two steps ahead: at step q the registers receive x plane q+3, y0 / y1 of
   // plane q+2 and y0 of the tile at plane q+1.
   {
-    double t[P_XPT];
+    T t[P_XPT];
     fetch_x(k0 - 2, t);
     store_x(k0 - 2, t);
     fetch_x(k0 - 1, t);
@@ -270,21 +304,21 @@ __global__ __launch_bounds__(P_THREADS) void st7_pair(St7 s, int kz, int gx, int
     fetch_x(k0, t);
     store_x(k0, t);
   }
-  double xa[P_XPT];  // x plane q + 2
+  T xa[P_XPT];  // x plane q + 2
   fetch_x(k0 + 1, xa);
-  double y0c[P_SPT], y1c[P_SPT], y0n[P_SPT], y1n[P_SPT];  // y at planes q, q + 1
+  T y0c[P_SPT], y1c[P_SPT], y0n[P_SPT], y1n[P_SPT];  // y at planes q, q + 1
   fetch_y(k0 - 1, y0c, y1c);
   fetch_y(k0, y0n, y1n);
-  double ytc = 0.0;  // y0 on the tile at plane q - 1 (for stage2(q - 1))
-  double ytn = (Y0 && tok && k0 < k1) ? y0[(int64_t)k0 * plane + toff] : 0.0;  // plane q
+  T ytc = T(0);  // y0 on the tile at plane q - 1 (for stage2(q - 1))
+  T ytn = (Y0 && tok && k0 < k1) ? (T)y0[(int64_t)k0 * plane + toff] : T(0);  // plane q
   __syncthreads();
   for (int q = k0 - 1; q <= k1; ++q) {
-    double xb[P_XPT], y0m[P_SPT], y1m[P_SPT];
+    T xb[P_XPT], y0m[P_SPT], y1m[P_SPT];
     const bool fx = q + 3 <= k1 + 1, fy = q + 2 <= k1;
     if (fx) fetch_x(q + 3, xb);
     if (fy) fetch_y(q + 2, y0m, y1m);
-    double ytm = 0.0;
-    if (Y0 && tok && q + 1 >= k0 && q + 1 < k1) ytm = y0[(int64_t)(q + 1) * plane + toff];
+    T ytm = T(0);
+    if (Y0 && tok && q + 1 >= k0 && q + 1 < k1) ytm = (T)y0[(int64_t)(q + 1) * plane + toff];
     stage1(q, y0c, y1c);
     __syncthreads();  // s(q) complete
     if (q - 1 >= k0) stage2(q - 1, ytc);
@@ -305,9 +339,15 @@ __global__ __launch_bounds__(P_THREADS) void st7_pair(St7 s, int kz, int gx, int
   }
 }
 
-static hipError_t launch_st7_pair(const Op& op, const double* x, const double* y0,
-                                  const double* y1, double* out1, double* out2,
-                                  const PairCoef& c, hipStream_t st) {
+template <typename TX, typename TO>
+static hipError_t launch_st7_pair_t(const Op& op, const void* xv, const void* y0v,
+                                    const void* y1v, void* out1v, void* out2v,
+                                    const PairCoef& c, hipStream_t st) {
+  const TX* x = (const TX*)xv;
+  const TX* y0 = (const TX*)y0v;
+  const TX* y1 = (const TX*)y1v;
+  TO* out1 = (TO*)out1v;
+  TO* out2 = (TO*)out2v;
   St7 s{op.dims[0], op.dims[1], op.dims[2], op.coef[0], op.coef[1], op.coef[2],
         op.coef[3], op.coef[4], op.coef[5], op.coef[6]};
   const int gx = (s.nx + P_TX - 1) / P_TX, gy = (s.ny + P_TY - 1) / P_TY;
@@ -321,7 +361,7 @@ static hipError_t launch_st7_pair(const Op& op, const double* x, const double* y
   const bool w1 = out1 != nullptr;
   const dim3 grid(nwg), block(P_THREADS);
 #define FA_PAIR(A, B, C) \
-  st7_pair<A, B, C><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out1, out2, c)
+  st7_pair<TX, TO, A, B, C><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out1, out2, c)
   if (y0 && y1) {
     if (w1) FA_PAIR(true, true, true); else FA_PAIR(true, true, false);
   } else if (y0) {
@@ -337,12 +377,17 @@ static hipError_t launch_st7_pair(const Op& op, const double* x, const double* y
 
 hipError_t launch_chain_pair(const Op& op, const void* x, const void* y0, const void* y1,
                              void* out1, void* out2, const ChainCoef& t1, const ChainCoef& t2,
-                             hipStream_t s) {
+                             hipStream_t s, Prec pin, Prec pout) {
   if (op.kind != OP_STENCIL7) return hipErrorInvalidValue;
   const PairCoef c{t1.alpha.real(), t1.beta.real(), t1.g0.real(), t1.g1.real(),
                    t2.alpha.real(), t2.beta.real(), t2.g0.real(), t2.g1.real()};
-  return launch_st7_pair(op, (const double*)x, (const double*)y0, (const double*)y1,
-                         (double*)out1, (double*)out2, c, s);
+  if (pin == P64 && pout == P64)
+    return launch_st7_pair_t<double, double>(op, x, y0, y1, out1, out2, c, s);
+  if (pin == P32 && pout == P32)
+    return launch_st7_pair_t<float, float>(op, x, y0, y1, out1, out2, c, s);
+  if (pin == P32 && pout == P64 && out1 == nullptr)
+    return launch_st7_pair_t<float, double>(op, x, y0, y1, out1, out2, c, s);
+  return hipErrorInvalidValue;
 }
 
 // --------------------------------------------------------------------------
@@ -578,11 +623,11 @@ static hipError_t launch_wilson(const Op& op, const cplx* x, const cplx* y0, con
 
 // --------------------------------------------------------------------------
 hipError_t launch_chain(const Op& op, const void* x, const void* y0, const void* y1, void* out,
-                        const ChainCoef& k, hipStream_t s) {
+                        const ChainCoef& k, hipStream_t s, Prec pin, Prec pout) {
+  if ((pin != P64 || pout != P64) && op.kind != OP_STENCIL7) return hipErrorInvalidValue;
   switch (op.kind) {
     case OP_STENCIL7:
-      return launch_st7(op, (const double*)x, (const double*)y0, (const double*)y1,
-                        (double*)out, k, s);
+      return launch_st7(op, x, y0, y1, out, k, s, pin, pout);
     case OP_CSR:
       if (op.dtype == FA_C128)
         return launch_csr<cplx>(op, (const cplx*)x, (const cplx*)y0, (const cplx*)y1,
@@ -596,13 +641,13 @@ hipError_t launch_chain(const Op& op, const void* x, const void* y0, const void*
   return hipErrorInvalidValue;
 }
 
-double chain_pair_bytes(const Op& op, bool has_y0, bool has_y1, bool has_out1) {
-  const double vec = (double)op.n * elem_size(op.dtype);
+double chain_pair_bytes(const Op& op, bool has_y0, bool has_y1, bool has_out1, Prec p) {
+  const double vec = (double)op.n * (p == P32 ? 4.0 : (double)elem_size(op.dtype));
   return vec * (2.0 + (has_y0 ? 1.0 : 0.0) + (has_y1 ? 1.0 : 0.0) + (has_out1 ? 1.0 : 0.0));
 }
 
-double chain_bytes(const Op& op, bool has_y0, bool has_y1) {
-  const double vec = (double)op.n * elem_size(op.dtype);
+double chain_bytes(const Op& op, bool has_y0, bool has_y1, Prec p) {
+  const double vec = (double)op.n * (p == P32 ? 4.0 : (double)elem_size(op.dtype));
   const double nvec = 2.0 + (has_y0 ? 1.0 : 0.0) + (has_y1 ? 1.0 : 0.0);
   double extra = 0.0;
   if (op.kind == OP_CSR)

@@ -245,6 +245,18 @@ hipError_t launch_normalize(int dtype, int64_t n, const void* w, const double* n
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kThreads) void to_f32_k(int64_t n, const double* __restrict__ x,
+                                                     float* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+
+hipError_t launch_to_f32(int64_t n, const double* x, float* y, hipStream_t s) {
+  const int grid = (int)((n + kThreads - 1) / kThreads);
+  to_f32_k<<<grid, kThreads, 0, s>>>(n, x, y);
+  return hipGetLastError();
+}
+
 hipError_t launch_scale(int dtype, int64_t n, cd a, const void* x, void* y, hipStream_t s) {
   const int grid = (int)((n + kThreads - 1) / kThreads);
   if (dtype == FA_C128)

@@ -220,14 +220,20 @@ static int poly_apply_blocks(const Op& op, const Poly& q, const void* x, void* o
 // single-term launch may write over x pointwise, a two-term launch may not);
 // *res names the buffer that holds q(A) x.  With `fuse`, consecutive terms
 // of the 7-point stencil run two per launch.
+// pm = P32 (mixed precision): x and every intermediate vector are FP32 and
+// the last launch writes `out` in precision pout; pm = P64: everything FP64.
 static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, void* const tmp[4],
-                      const void** res, hipStream_t s, Prof* prof, int64_t* mvms, bool fuse) {
+                      const void** res, hipStream_t s, Prof* prof, int64_t* mvms, bool fuse,
+                      Prec pm = P64, Prec pout = P64) {
   const int K = q.degree;
   if (q.method < 0 || K == 0) {
     *res = x;  // q == 1
     return FA_OK;
   }
-  if (!q.blocks.empty()) return poly_apply_blocks(op, q, x, out, tmp, res, s, mvms);
+  if (!q.blocks.empty()) {
+    if (pm != P64) return FA_ERR_UNSUPPORTED;
+    return poly_apply_blocks(op, q, x, out, tmp, res, s, mvms);
+  }
   *mvms += K;
   const std::vector<Term> T = poly_terms(q);
   const int nT = (int)T.size();
@@ -255,8 +261,9 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
         FA_HIP(prof->end(s));
         timing = false;
       }
-      FA_HIP(launch_chain(op, xm1, T[i].y0 ? x : nullptr, T[i].y1 ? xm2 : nullptr, dst, T[i].k, s));
-      if (prof && timing) prof->count(1, chain_bytes(op, T[i].y0, T[i].y1));
+      FA_HIP(launch_chain(op, xm1, T[i].y0 ? x : nullptr, T[i].y1 ? xm2 : nullptr, dst, T[i].k, s,
+                          pm, last ? pout : pm));
+      if (prof && timing) prof->count(1, chain_bytes(op, T[i].y0, T[i].y1, pm));
       xm2 = xm1;
       xm1 = dst;
     }
@@ -289,8 +296,9 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
     ChainCoef k2 = T[i + 1].k;
     if (!T[i + 1].y1) k2.g1 = 0.0;
     FA_HIP(launch_chain_pair(op, xm1, (T[i].y0 || T[i + 1].y0) ? x : nullptr,
-                             T[i].y1 ? xm2 : nullptr, o1, o2, T[i].k, k2, s));
-    if (prof && timing) prof->count(1, chain_pair_bytes(op, true, true, o1 != nullptr));
+                             T[i].y1 ? xm2 : nullptr, o1, o2, T[i].k, k2, s, pm,
+                             last_pair && i + 2 >= nT ? pout : pm));
+    if (prof && timing) prof->count(1, chain_pair_bytes(op, true, true, o1 != nullptr, pm));
     xm2 = o1;
     xm1 = o2;
     set ^= 1;
@@ -298,7 +306,8 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
   if (prof && timing) FA_HIP(prof->end(s));
   if (i < nT) {  // odd number of terms: the last one alone (pointwise in out)
     void* dst = (out == xm1) ? tmp[2 * set] : out;
-    FA_HIP(launch_chain(op, xm1, T[i].y0 ? x : nullptr, T[i].y1 ? xm2 : nullptr, dst, T[i].k, s));
+    FA_HIP(launch_chain(op, xm1, T[i].y0 ? x : nullptr, T[i].y1 ? xm2 : nullptr, dst, T[i].k, s,
+                        pm, pout));
     xm1 = dst;
   }
   *res = xm1;
@@ -382,6 +391,10 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   void* U = at(ws, L.off_U);
   void* const tmp[4] = {at(ws, L.off_P), at(ws, L.off_Q), at(ws, L.off_R), at(ws, L.off_S)};
   const bool fuse = !(flags & FA_NO_FUSION);
+  // mixed precision: the polynomial chain in FP32 (stencil, Chebyshev q, K >= 1)
+  const bool mixed = (flags & FA_MIXED) && op.poly.method >= 0 && op.poly.degree > 0;
+  if (mixed && (op.kind != OP_STENCIL7 || op.poly.method != FA_POLY_CHEB)) return FA_ERR_UNSUPPORTED;
+  const Prec pm = mixed ? P32 : P64;
   void* part = at(ws, L.off_part);
   char* hcur = at(ws, L.off_h);
   char* Hd = at(ws, L.off_H);
@@ -407,7 +420,14 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   // Algorithm 1: c = q(A) b', beta = ||c||, v_1 = c / beta
   {
     const void* res = nullptr;
-    st = poly_apply(op, q, bsrc, Vc(0), tmp, &res, s, pp, &mvms, fuse);
+    if (mixed) {  // b' to FP32 in the fifth scratch vector, then the FP32 chain
+      void* b32 = tmp[3];
+      FA_HIP(launch_to_f32(n, (const double*)bsrc, (float*)b32, s));
+      void* const tmpm[4] = {tmp[0], tmp[1], tmp[2], U};
+      st = poly_apply(op, q, b32, Vc(0), tmpm, &res, s, pp, &mvms, fuse, P32, P64);
+    } else {
+      st = poly_apply(op, q, bsrc, Vc(0), tmp, &res, s, pp, &mvms, fuse);
+    }
     if (st) return st;
     if (res != Vc(0)) FA_HIP(launch_scale(op.dtype, n, cd(1.0), res, Vc(0), s));
     FA_HIP(launch_update(op.dtype, n, 0, V, L.ldv, hcur, Vc(0), part, nrm, s));
@@ -449,11 +469,10 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       if (st) return st;
       ++mvms;
     } else {
-      st = chain(op, vj, nullptr, nullptr, U, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, pp);
-      if (st) return st;
+      FA_HIP(launch_chain(op, vj, nullptr, nullptr, U, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, P64, pm));
       ++mvms;
       const void* y = nullptr;
-      st = poly_apply(op, q, U, U, tmp, &y, s, pp, &mvms, fuse);
+      st = poly_apply(op, q, U, U, tmp, &y, s, pp, &mvms, fuse, pm, pm);
       if (st) return st;
       void* tmp2[4];  // the scratch vectors other than the one holding y
       {
@@ -463,7 +482,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
           if (b != y && c < 4) tmp2[c++] = b;
       }
       const void* r2 = nullptr;
-      st = poly_apply(op, q, y, w, tmp2, &r2, s, pp, &mvms, fuse);
+      st = poly_apply(op, q, y, w, tmp2, &r2, s, pp, &mvms, fuse, pm, P64);
       if (st) return st;
       if (r2 != w) FA_HIP(launch_scale(op.dtype, n, cd(1.0), r2, w, s));
     }

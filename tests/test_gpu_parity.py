@@ -433,3 +433,53 @@ def test_real_operator_complex_ritz_values(degree):
     orc = kr.fAb(A, b, q, "invsqrt", m_max=400, tol=1e-12)
     assert st["converged"]
     assert_close(host(xs), orc.x, 1e-10)
+
+
+# --------------------------------------------------------------------------
+# mixed precision: the polynomial chain in FP32, the rest FP64
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("degree", [1, 2, 3, 8, 16])
+@pytest.mark.parametrize("fuse", [True, False])
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+def test_mixed_precision_against_fp64_oracle(degree, fuse, kind):
+    """Per-result error of the mixed mode against the FP64 oracle: <= 1e-6."""
+    dims = (40, 33, 29)
+    coeffs = wl.convdiff_stencil(40, 50.0)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(degree, "cheb")
+    b = wl.rhs(op.n, seed=0)
+    x, st = op.apply(dev(b), kind=kind, m_max=300, tol=1e-7, mixed=True, fuse=fuse)
+    assert st["converged"]
+    a, bb = ops.stencil_interval(coeffs, dims)
+    orc = kr.fAb(lambda v: ops.stencil_apply(coeffs, dims, v), b, pl.chebyshev(a, bb, degree),
+                 kind, m_max=300, tol=1e-12)
+    assert_close(host(x), orc.x, 1e-6)
+
+
+def test_mixed_precision_unsupported_and_degree0():
+    rp, ci, va = wl.stencil_csr((8, 8, 8), wl.laplace_stencil(3))
+    op = fa().CSR(rp, ci, va)
+    op.set_spectral_interval(*ops.stencil_interval(wl.laplace_stencil(3), (8, 8, 8)))
+    op.poly_setup(4, "cheb")
+    with pytest.raises(fa().FAError) as e:
+        op.apply(dev(wl.rhs(512, seed=0)), m_max=50, tol=1e-8, mixed=True)
+    assert e.value.status == -9
+    st7 = fa().Stencil7((8, 8, 8), wl.laplace_stencil(3))
+    st7.poly_setup(0)
+    b = dev(wl.rhs(512, seed=0))
+    x1, _ = st7.apply(b, m_max=100, tol=1e-10, mixed=True)
+    x2, _ = st7.apply(b, m_max=100, tol=1e-10)
+    assert torch.equal(x1, x2)
+
+
+def test_mixed_precision_128_full_size():
+    N = 128
+    dims = (N, N, N)
+    coeffs = wl.convdiff_stencil(N, 50.0)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(16, "cheb")
+    b = dev(wl.rhs(op.n, seed=0))
+    x64, _ = op.apply(b, m_max=200, tol=1e-10)
+    x32, st = op.apply(b, m_max=200, tol=1e-7, mixed=True)
+    assert st["converged"]
+    assert_close(host(x32), host(x64), 1e-6)
