@@ -104,7 +104,8 @@ def tridiagonal_invsqrt_e1(alpha, beta_off, beta):
 # the preconditioned Krylov method
 # --------------------------------------------------------------------------
 def fAb(apply_A, b, poly: Poly | None = None, kind="invsqrt", m_max=100, tol=1e-10,
-        check_every=0, orth="cgs2", side="left", x_true=None, keep_basis=False):
+        check_every=0, orth="cgs2", side="left", x_true=None, keep_basis=False,
+        two_pass=False):
     """Approximate A^{-1/2} b (kind "invsqrt") or A^{1/2} b (kind "sqrt").
 
     apply_A: callable x -> A x.  poly: preconditioning polynomial (None: q == 1).
@@ -113,7 +114,14 @@ def fAb(apply_A, b, poly: Poly | None = None, kind="invsqrt", m_max=100, tol=1e-
     difference-of-iterates estimate; with x_true given the true relative error
     ||f_j - x_true|| / ||x_true|| is tested instead (as in Example 1's tables).
     tol <= 0 runs exactly m_max steps.
+    two_pass (Lanczos, left): the first pass keeps only the three-term
+    coefficients (and the two latest vectors); after it stops, a second pass
+    regenerates the basis with the same coefficients and accumulates
+    x = V_m z_m, so no basis is stored and the products with A double (the
+    two-pass Lanczos of Sec. 6, Example 1).
     """
+    if two_pass:
+        return _two_pass_lanczos(apply_A, b, poly or one(), kind, m_max, tol, check_every)
     poly = poly or one()
     b = np.asarray(b)
     dt = np.result_type(b, 1.0)
@@ -239,3 +247,79 @@ def fAb(apply_A, b, poly: Poly | None = None, kind="invsqrt", m_max=100, tol=1e-
                   inner_products=ips, est=est, checks=checks,
                   H=H[:m + 1, :m].copy() if keep_basis else None,
                   V=V[:, :m + 1].copy() if keep_basis else None, history=history)
+
+
+def _two_pass_lanczos(apply_A, b, poly, kind, m_max, tol, check_every):
+    """Two-pass Lanczos for Hermitian A q(A)^2 (Sec. 6, Example 1)."""
+    b = np.asarray(b)
+    dt = np.result_type(b, 1.0)
+    mvms = 0
+
+    def A(x):
+        nonlocal mvms
+        mvms += 1
+        return apply_A(x)
+
+    def Q(x):
+        nonlocal mvms
+        y, k = poly.apply(apply_A, x)
+        mvms += k
+        return y.astype(dt, copy=False)
+
+    if kind == "sqrt":
+        b = A(b).astype(dt, copy=False)
+    c = Q(b)
+    beta = float(np.linalg.norm(c))
+    n = b.size
+    if beta == 0.0:
+        return Result(x=np.zeros(n, dtype=dt), iters=0, converged=True, breakdown=False,
+                      mvms=mvms, inner_products=0, est=0.0, checks=0)
+    k = check_every if check_every > 0 else default_check_every(poly.degree)
+    alpha = np.zeros(m_max)
+    off = np.zeros(m_max)   # off[j] = beta_{j+1} = h_{j+1,j}
+    # pass 1: coefficients only
+    v_prev = np.zeros(n, dtype=dt)
+    v = c / beta
+    z_prev = np.zeros(0)
+    m, est, checks, converged, breakdown = m_max, 1.0, 0, False, False
+    colmax = 0.0
+    ips = 0
+    for j in range(m_max):
+        w = Q(Q(A(v)))
+        if j > 0:
+            w = w - off[j - 1] * v_prev
+        alpha[j] = np.real(np.vdot(v, w))
+        w = w - alpha[j] * v
+        off[j] = float(np.linalg.norm(w))
+        ips += 2
+        colmax = max(colmax, math.sqrt(alpha[j] ** 2 + off[j] ** 2 + (off[j - 1] ** 2 if j else 0)))
+        if off[j] <= 1e-12 * colmax:
+            m, breakdown, converged = j + 1, True, True
+            break
+        v_prev, v = v, w / off[j]
+        jj = j + 1
+        if tol > 0.0 and (jj % k == 0 or jj == m_max):
+            z = tridiagonal_invsqrt_e1(alpha[:jj], off[:jj - 1], beta)
+            checks += 1
+            zp = np.zeros_like(z)
+            zp[:z_prev.size] = z_prev
+            est = float(np.linalg.norm(z - zp) / np.linalg.norm(z))
+            z_prev = z
+            if est <= tol:
+                m, converged = jj, True
+                break
+    z = tridiagonal_invsqrt_e1(alpha[:m], off[:m - 1], beta)
+    # pass 2: regenerate v_1..v_m with the stored coefficients and combine
+    c = Q(b)
+    v_prev = np.zeros(n, dtype=dt)
+    v = c / beta
+    x = z[0] * v
+    for j in range(m - 1):
+        w = Q(Q(A(v)))
+        if j > 0:
+            w = w - off[j - 1] * v_prev
+        w = w - alpha[j] * v
+        v_prev, v = v, w / off[j]
+        x = x + z[j + 1] * v
+    return Result(x=x, iters=m, converged=converged, breakdown=breakdown, mvms=mvms,
+                  inner_products=ips, est=est, checks=checks)

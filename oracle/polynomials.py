@@ -181,12 +181,13 @@ def chebyshev(a, b, degree, check_points=10000, check_interval=None):
 # --------------------------------------------------------------------------
 # Sec. 5.2: interpolation at Ritz values, Newton form on Leja points
 # --------------------------------------------------------------------------
-def arnoldi_hessenberg(apply_A, start, steps):
+def arnoldi_hessenberg(apply_A, start, steps, with_next=False):
     """H_d from `steps` Arnoldi steps on A (classical Gram-Schmidt, twice).
 
     Returns the square Hessenberg H (j x j) where j <= steps is the number of
     steps completed before a (lucky) breakdown, declared with the same rule as
     in the Krylov solver (h_{j+1,j} <= 1e-12 times the largest column norm).
+    With with_next, returns (H, h_{j+1,j}) (0 after a breakdown).
     """
     v = np.asarray(start)
     dt = np.result_type(v, 1.0)
@@ -207,9 +208,21 @@ def arnoldi_hessenberg(apply_A, start, steps):
         H[j + 1, j] = hn
         colmax = max(colmax, math.sqrt(np.linalg.norm(h) ** 2 + hn ** 2))
         if hn <= 1e-12 * colmax:
-            return H[:j + 1, :j + 1]
+            return (H[:j + 1, :j + 1], 0.0) if with_next else H[:j + 1, :j + 1]
         V[:, j + 1] = w / hn
-    return H[:steps, :steps]
+    return (H[:steps, :steps], float(H[steps, steps - 1])) if with_next else H[:steps, :steps]
+
+
+def harmonic_ritz_values(H, h_next):
+    """Harmonic Ritz values (Sec. 5.2): eigenvalues of
+    H_d + h_{d+1,d}^2 H_d^{-*} e_d e_d^*."""
+    d = H.shape[0]
+    ed = np.zeros(d)
+    ed[-1] = 1.0
+    y = np.linalg.solve(np.asarray(H).conj().T, ed)
+    Ht = np.array(H, dtype=np.result_type(H, y, 1.0), copy=True)
+    Ht[:, -1] += h_next ** 2 * y
+    return np.linalg.eigvals(Ht)
 
 
 def leja_order(theta, pair_conjugates):
@@ -295,18 +308,18 @@ def horner_apply(apply_A, theta, eta, rho, v):
     return r, nmv
 
 
-def ritz(apply_A, start, degree, real_operator):
+def ritz(apply_A, start, degree, real_operator, harmonic=False):
     """Sec. 5.2 polynomial of the given degree from Ritz values of A.
 
     d = degree + 1 Arnoldi steps from `start`; the Ritz values are the
-    eigenvalues of H_d.  If Arnoldi breaks down after j < d steps, the j Ritz
-    values found are used (degree j - 1).  Raises BranchError if a Ritz value
-    has Re <= 0.
+    eigenvalues of H_d (harmonic: of H_d + h_{d+1,d}^2 H_d^{-*} e_d e_d^*).  If
+    Arnoldi breaks down after j < d steps, the j Ritz values found are used
+    (degree j - 1).  Raises BranchError if a Ritz value has Re <= 0.
     """
     if degree == 0:
         return one()
-    H = arnoldi_hessenberg(apply_A, start, degree + 1)
-    theta = np.linalg.eigvals(H)
+    H, h_next = arnoldi_hessenberg(apply_A, start, degree + 1, with_next=True)
+    theta = harmonic_ritz_values(H, h_next) if harmonic else np.linalg.eigvals(H)
     if np.min(theta.real) <= 0.0:
         raise BranchError("a Ritz value lies outside the open right half-plane")
     if real_operator:

@@ -308,3 +308,23 @@ def test_table1_printed_rows_follow_the_count_rule():
     for r in g["rows"]:
         assert r["mvms"] == r["iterations"] * (2 * r["d"] - 1)
         assert r["inner_products"] == 2 * r["iterations"]
+
+
+@pytest.mark.parametrize("degree", [0, 4])
+def test_two_pass_lanczos_equals_one_pass(degree):
+    """Two-pass Lanczos (Sec. 6, Example 1): the same iterate as one pass,
+    without storing the basis, at twice the products with A."""
+    N = 20
+    dims = (N, N, N)
+    coeffs = wl.laplace_stencil(3)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    a, bb = ops.stencil_interval(coeffs, dims)
+    q = pl.chebyshev(a, bb, degree)
+    b = wl.rhs(N ** 3, seed=0)
+    one = kr.fAb(A, b, q, "invsqrt", m_max=300, tol=1e-10, orth="lanczos")
+    two = kr.fAb(A, b, q, "invsqrt", m_max=300, tol=1e-10, orth="lanczos", two_pass=True)
+    assert two.iters == one.iters and two.converged
+    assert rel(two.x, one.x) < 1e-13
+    # pass 2 repeats c = q(A) b and m - 1 steps of the three-stage product
+    assert two.mvms == 2 * one.mvms - (2 * degree + 1)
+    assert rel(two.x, exact.stencil_fAb_dst(coeffs, dims, b)) < 1e-9

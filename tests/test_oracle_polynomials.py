@@ -161,3 +161,45 @@ def test_ritz_polynomial_preconditions_wilson():
     y, _ = q.apply(op, v)
     ref = exact.wilson_free_fAb(L, m0, v)
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 0.5
+
+
+def test_harmonic_ritz_values_solve_the_petrov_galerkin_problem():
+    """Harmonic Ritz values (Sec. 5.2) against the generalized eigenproblem
+    (A V)^H (A V) y = theta (A V)^H V y that defines them, via the Arnoldi
+    relation A V_d = V_{d+1} Hbar_d, solved by scipy.linalg.eig."""
+    import scipy.linalg as sla
+    dims = (6, 5, 4)
+    coeffs = wl.convdiff_stencil(6, 80.0)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    start = wl.rhs(120, seed=3)
+    d = 7
+    H, h = pl.arnoldi_hessenberg(A, start, d, with_next=True)
+    Hbar = np.vstack([H, np.zeros((1, d))])
+    Hbar[d, d - 1] = h
+    ref = sla.eig(Hbar.conj().T @ Hbar, H.conj().T, right=False)
+    got = pl.harmonic_ritz_values(H, h)
+    key = lambda z: (round(z.real, 8), round(z.imag, 8))
+    assert np.allclose(sorted(got, key=key), sorted(ref, key=key), rtol=1e-10)
+
+
+def test_harmonic_ritz_values_spd_lie_in_the_spectral_interval():
+    # for SPD A the harmonic Ritz values are real and inside [lmin, lmax]
+    dims = (9, 8, 7)
+    coeffs = wl.laplace_stencil(3)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    lo, hi = ops.stencil_interval(coeffs, dims)
+    H, h = pl.arnoldi_hessenberg(A, wl.rhs(504, seed=1), 10, with_next=True)
+    th = pl.harmonic_ritz_values(H, h)
+    assert np.max(np.abs(th.imag)) < 1e-10
+    assert th.real.min() >= lo - 1e-10 and th.real.max() <= hi + 1e-10
+    # and they are at least the standard Ritz values' lower end (bounded away from 0)
+    assert th.real.min() >= np.linalg.eigvalsh((H + H.T) / 2).min() - 1e-10
+
+
+def test_harmonic_ritz_polynomial_preconditions():
+    N = 10
+    dims = (N, N, N)
+    coeffs = wl.convdiff_stencil(N, 20.0)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    q = pl.ritz(A, wl.rhs(N ** 3, seed=2), 6, real_operator=True, harmonic=True)
+    assert np.allclose(q.scalar(q.theta), q.theta ** -0.5, rtol=1e-8)
