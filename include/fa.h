@@ -87,7 +87,9 @@ enum {
 enum {
   FA_POLY_AUTO = 0, /* CHEB when the op has a real spectral interval, else RITZ     */
   FA_POLY_CHEB = 1, /* Chebyshev interpolant of z^{-1/2} on [lo, hi], Sec. 5.1      */
-  FA_POLY_RITZ = 2  /* interpolant at Ritz values, Newton form, Leja order, Sec. 5.2 */
+  FA_POLY_RITZ = 2, /* interpolant at Ritz values, Newton form, Leja order, Sec. 5.2 */
+  FA_POLY_HARMONIC = 3 /* as RITZ at the harmonic Ritz values (the eigenvalues of
+                          H_d + h_{d+1,d}^2 H_d^{-H} e_d e_d^T), Sec. 5.2           */
 };
 
 /* flags */
@@ -96,6 +98,18 @@ enum {
   FA_FORCE_ARNOLDI = 4u, /* apply: Gram-Schmidt (CGS2) even for a Hermitian op          */
   FA_PROFILE = 8u,       /* apply: time the middle terms of every q(A) application      */
   FA_NO_FUSION = 16u,    /* apply: one launch per recurrence term (no two-term launches) */
+  FA_TWO_PASS = 64u,     /* apply: two-pass Lanczos (Hermitian op, not with
+                            FA_FORCE_ARNOLDI or FA_RIGHT_PREC, else
+                            FA_ERR_UNSUPPORTED): pass 1 keeps three basis vectors
+                            and computes H_m and z_m = H_m^{-1/2} e_1 ||c||; pass 2
+                            regenerates v_1..v_m with the same kernels and
+                            accumulates x = sum_i z_i v_i.  Workspace O(n), about
+                            twice the products with A.                            */
+  FA_RIGHT_PREC = 128u,  /* apply: right preconditioning (Algorithm 2): the basis of
+                            K_m(A q(A)^2, b), y_j = q(A) v_j stored, x = Y_m z_m with
+                            z_m = H_m^{-1/2} e_1 ||b||.  The stopping estimate is
+                            ||Y_j (z_j - [z_{j-k}; 0])|| / ||Y_j z_j||.  Not with
+                            FA_MIXED.  With q == 1 it is the plain method.         */
   FA_MIXED = 32u         /* apply: the polynomial chain (A and q(A) in the three-stage
                             product, and c = q(A) b) in FP32 storage with FP32
                             accumulation; Gram-Schmidt, H, H^{-1/2} e_1, the basis and

@@ -210,7 +210,7 @@ def arnoldi_hessenberg(apply_A, start, steps, with_next=False):
         if hn <= 1e-12 * colmax:
             return (H[:j + 1, :j + 1], 0.0) if with_next else H[:j + 1, :j + 1]
         V[:, j + 1] = w / hn
-    return (H[:steps, :steps], float(H[steps, steps - 1])) if with_next else H[:steps, :steps]
+    return (H[:steps, :steps], float(np.real(H[steps, steps - 1]))) if with_next else H[:steps, :steps]
 
 
 def harmonic_ritz_values(H, h_next):

@@ -18,14 +18,16 @@ import torch
 
 from . import _lib
 from ._lib import (FA_C128, FA_F64, FA_FORCE_ARNOLDI, FA_HERMITIAN, FA_INVSQRT,  # noqa: F401
-                   FA_MIXED, FA_NO_FUSION, FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_RITZ, FA_PROFILE, FA_SQRT, FAError,
+                   FA_MIXED, FA_NO_FUSION, FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_HARMONIC,
+                   FA_POLY_RITZ, FA_PROFILE, FA_RIGHT_PREC, FA_SQRT, FA_TWO_PASS, FAError,
                    check, lib)
 
 __all__ = ["Stencil7", "CSR", "Wilson", "FAError", "lib", "dense_invsqrt_e1",
            "dense_tridiag_invsqrt_e1"]
 
 _KIND = {"invsqrt": FA_INVSQRT, "sqrt": FA_SQRT}
-_METHOD = {"auto": FA_POLY_AUTO, "cheb": FA_POLY_CHEB, "ritz": FA_POLY_RITZ}
+_METHOD = {"auto": FA_POLY_AUTO, "cheb": FA_POLY_CHEB, "ritz": FA_POLY_RITZ,
+           "harmonic": FA_POLY_HARMONIC}
 
 
 def _stream(device):
@@ -81,9 +83,10 @@ class Operator:
         return lo.value, hi.value
 
     def poly_setup(self, degree, method="auto", start=None):
-        """Choose q of the given degree (0: plain method).  method: auto|cheb|ritz.
+        """Choose q of the given degree (0: plain method).
+        method: auto|cheb|ritz|harmonic.
 
-        For Ritz polynomials `start` is the start vector of the setup Arnoldi
+        For (harmonic) Ritz polynomials `start` is the start vector of the setup Arnoldi
         run (a device tensor of length n).
         """
         m = _METHOD[method]
@@ -112,11 +115,12 @@ class Operator:
         rho = C.c_double()
         check(lib().fa_poly_get(self._h, None, None, cr, ci, nr, ni, iv, C.byref(rho)),
               "fa_poly_get")
-        meth_name = {-1: "one", FA_POLY_CHEB: "cheb", FA_POLY_RITZ: "ritz"}[meth.value]
+        meth_name = {-1: "one", FA_POLY_CHEB: "cheb", FA_POLY_RITZ: "ritz",
+                     FA_POLY_HARMONIC: "harmonic"}[meth.value]
         out = {"method": meth_name, "degree": K}
         if meth_name == "cheb":
             out.update(c=list(cr), interval=(iv[0], iv[1]))
-        elif meth_name == "ritz":
+        elif meth_name in ("ritz", "harmonic"):
             out.update(eta=[complex(a, b) for a, b in zip(cr, ci)],
                        theta=[complex(a, b) for a, b in zip(nr, ni)], rho=rho.value)
         return out
@@ -129,11 +133,11 @@ class Operator:
             raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of {self.n} entries")
         return v
 
-    def workspace_bytes(self, m_max):
-        return lib().fa_workspace_bytes(self._h, m_max, 0)
+    def workspace_bytes(self, m_max, flags=0):
+        return lib().fa_workspace_bytes(self._h, m_max, flags)
 
-    def _workspace(self, m_max):
-        nbytes = self.workspace_bytes(m_max)
+    def _workspace(self, m_max, flags=0):
+        nbytes = self.workspace_bytes(m_max, flags)
         ws = self._ws.get("apply")
         if ws is None or ws[2] < nbytes:
             self._ws.pop("apply", None)
@@ -145,19 +149,22 @@ class Operator:
         self._ws.clear()
 
     def apply(self, b, kind="invsqrt", m_max=100, tol=1e-10, check_every=0, out=None,
-              force_arnoldi=False, profile=False, fuse=True, mixed=False,
-              raise_not_converged=False):
+              force_arnoldi=False, profile=False, fuse=True, mixed=False, two_pass=False,
+              right=False, raise_not_converged=False):
         """x ~ A^{-1/2} b or A^{1/2} b.  Returns (x, stats dict).
 
         fuse=False runs one launch per recurrence term (no two-term launches);
-        mixed=True runs the polynomial chain in FP32 (stencil, Chebyshev q).
+        mixed=True runs the polynomial chain in FP32 (stencil, Chebyshev q);
+        two_pass=True runs two-pass Lanczos (O(n) basis storage);
+        right=True runs the right-preconditioned variant (Algorithm 2).
         """
         b = self._vec(b, "b")
         x = out if out is not None else torch.empty_like(b)
         self._vec(x, "out")
-        _, wsp, nbytes = self._workspace(m_max)
         flags = ((FA_FORCE_ARNOLDI if force_arnoldi else 0) | (FA_PROFILE if profile else 0)
-                 | (0 if fuse else FA_NO_FUSION) | (FA_MIXED if mixed else 0))
+                 | (0 if fuse else FA_NO_FUSION) | (FA_MIXED if mixed else 0)
+                 | (FA_TWO_PASS if two_pass else 0) | (FA_RIGHT_PREC if right else 0))
+        _, wsp, nbytes = self._workspace(m_max, flags)
         stats = _lib.fa_stats()
         st = lib().fa_apply(self._h, _KIND[kind], _ptr(b), _ptr(x), m_max, float(tol),
                             check_every, wsp, nbytes, flags, _stream(self.device),

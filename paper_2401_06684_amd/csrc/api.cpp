@@ -158,7 +158,7 @@ size_t fa_poly_workspace_bytes(fa_op op, int degree, int method) {
 
 int fa_poly_setup(fa_op op, int degree, int method, const void* d_start, void* d_workspace,
                   size_t ws_bytes, void* hip_stream) {
-  if (!op || degree < 0 || method < FA_POLY_AUTO || method > FA_POLY_RITZ) return FA_ERR_ARG;
+  if (!op || degree < 0 || method < FA_POLY_AUTO || method > FA_POLY_HARMONIC) return FA_ERR_ARG;
   return guarded([&] {
     int64_t mv = 0;
     return poly_setup(op->op, degree, method, d_start, d_workspace, ws_bytes,
@@ -172,7 +172,7 @@ int fa_poly_get(fa_op op, int* degree, int* method, double* coef_re, double* coe
   if (!op->op.poly_ready) return FA_ERR_NO_POLY;
   const Poly& q = op->op.poly;
   if (degree) *degree = q.degree;
-  if (method) *method = q.method;
+  if (method) *method = q.harmonic ? FA_POLY_HARMONIC : q.method;
   if (q.method == FA_POLY_CHEB) {
     for (int i = 0; i <= q.degree; ++i) {
       if (coef_re) coef_re[i] = q.c[i];
@@ -195,9 +195,8 @@ int fa_poly_get(fa_op op, int* degree, int* method, double* coef_re, double* coe
 }
 
 size_t fa_workspace_bytes(fa_op op, int m_max, uint32_t flags) {
-  (void)flags;
   if (!op || m_max < 1) return 0;
-  return make_layout(op->op, m_max).bytes;
+  return make_layout(op->op, m_max, flags).bytes;
 }
 
 int fa_apply(fa_op op, int kind, const void* d_b, void* d_x, int m_max, double tol,
@@ -205,7 +204,8 @@ int fa_apply(fa_op op, int kind, const void* d_b, void* d_x, int m_max, double t
              void* hip_stream, fa_stats* stats) {
   if (!op || !d_b || !d_x || d_b == d_x || m_max < 1 || check_every < 0 ||
       (kind != FA_INVSQRT && kind != FA_SQRT) || !std::isfinite(tol) ||
-      (flags & ~uint32_t(FA_FORCE_ARNOLDI | FA_PROFILE | FA_NO_FUSION | FA_MIXED)))
+      (flags & ~uint32_t(FA_FORCE_ARNOLDI | FA_PROFILE | FA_NO_FUSION | FA_MIXED | FA_TWO_PASS |
+                         FA_RIGHT_PREC)))
     return FA_ERR_ARG;
   if (!op->op.poly_ready) return FA_ERR_NO_POLY;
   if ((int64_t)m_max > op->op.n) return FA_ERR_ARG;
@@ -224,7 +224,7 @@ int fa_poly_apply(fa_op op, const void* d_x, void* d_y, void* d_workspace, size_
                   void* hip_stream) {
   if (!op || !d_x || !d_y || d_x == d_y) return FA_ERR_ARG;
   if (!op->op.poly_ready) return FA_ERR_NO_POLY;
-  const Layout L = make_layout(op->op, 1);
+  const Layout L = make_layout(op->op, 1, 0);
   if (!d_workspace || ws_bytes < L.bytes || ((uintptr_t)d_workspace & 255)) return FA_ERR_WORKSPACE;
   return guarded([&] {
     return poly_apply_public(op->op, d_x, d_y, d_workspace, stream_of(hip_stream));

@@ -153,6 +153,32 @@ static int triangular_invsqrt_e1(const S& sch, int m, double beta, cd* z) {
   return DENSE_OK;
 }
 
+int lu_solve(int m, cd* A, cd* x) {
+  auto a = [&](int i, int j) -> cd& { return A[(size_t)j * m + i]; };
+  for (int k = 0; k < m; ++k) {
+    int p = k;
+    for (int i = k + 1; i < m; ++i)
+      if (std::abs(a(i, k)) > std::abs(a(p, k))) p = i;
+    if (a(p, k) == cd(0.0)) return DENSE_NOCONV;
+    if (p != k) {
+      for (int j = 0; j < m; ++j) std::swap(a(k, j), a(p, j));
+      std::swap(x[k], x[p]);
+    }
+    for (int i = k + 1; i < m; ++i) {
+      const cd l = a(i, k) / a(k, k);
+      a(i, k) = l;
+      for (int j = k + 1; j < m; ++j) a(i, j) -= l * a(k, j);
+      x[i] -= l * x[k];
+    }
+  }
+  for (int k = m - 1; k >= 0; --k) {
+    cd t = x[k];
+    for (int j = k + 1; j < m; ++j) t -= a(k, j) * x[j];
+    x[k] = t / a(k, k);
+  }
+  return DENSE_OK;
+}
+
 int hess_invsqrt_e1(int m, const cd* H, int ldh, double beta, cd* z) {
   Schur S;
   const int st = S.compute(m, H, ldh);

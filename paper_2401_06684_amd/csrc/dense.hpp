@@ -64,6 +64,11 @@ int tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double be
 // eigenvalues of an upper Hessenberg matrix
 int hess_eigenvalues(int m, const cd* H, int ldh, cd* ev);
 
+// x = A^{-1} x for a general complex m x m matrix (column-major, ld m; A is
+// overwritten by its LU factors).  Gaussian elimination with partial
+// pivoting; DENSE_NOCONV if a pivot vanishes.
+int lu_solve(int m, cd* A, cd* x);
+
 // c_0..c_K of the Chebyshev interpolant of z^{-1/2} on [a, b] at K+1
 // first-kind Chebyshev points.
 void cheb_coefficients(double a, double b, int K, double* c);

@@ -21,7 +21,8 @@ enum OpKind { OP_CSR = 0, OP_STENCIL7 = 1, OP_WILSON = 2 };
 
 // the preconditioning polynomial, in the representation the chain kernels use
 struct Poly {
-  int method = -1;  // -1: q == 1; FA_POLY_CHEB; FA_POLY_RITZ
+  int method = -1;  // -1: q == 1; FA_POLY_CHEB; FA_POLY_RITZ (Newton form)
+  bool harmonic = false;  // RITZ nodes are harmonic Ritz values
   int degree = 0;   // K
   double a = 0, b = 0;        // CHEB interval
   std::vector<double> c;      // CHEB coefficients c_0..c_K

@@ -18,11 +18,14 @@ namespace fa {
 // --------------------------------------------------------------------------
 // workspace layout (every region 256-byte aligned)
 // --------------------------------------------------------------------------
-Layout make_layout(const Op& op, int m_max) {
+Layout make_layout(const Op& op, int m_max, uint32_t flags) {
   Layout L;
   const size_t es = elem_size(op.dtype);
   L.ldv = round_up(op.n, 32);
-  L.ldh = m_max + 1;
+  // Lanczos keeps only the diagonal and subdiagonal of H: column j holds
+  // (H(j, j), H(j + 1, j)); Arnoldi keeps full columns of m_max + 1 rows
+  L.band = (op.flags & FA_HERMITIAN) && !(flags & FA_FORCE_ARNOLDI);
+  L.ldh = L.band ? 2 : m_max + 1;
   const RedPlan rp = red_plan(op.n);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -30,13 +33,18 @@ Layout make_layout(const Op& op, int m_max) {
     off += (size_t)round_up((int64_t)bytes, 256);
     return o;
   };
-  L.off_V = take((size_t)(m_max + 1) * L.ldv * es);
+  // two-pass Lanczos keeps a ring of three basis vectors; right
+  // preconditioning also stores y_j = q(A) v_j
+  const int nbasis = (flags & FA_TWO_PASS) ? 3 : m_max + 1;
+  L.off_V = take((size_t)nbasis * L.ldv * es);
+  L.off_Y = (flags & FA_RIGHT_PREC) ? take((size_t)m_max * L.ldv * es) : 0;
   L.off_U = take((size_t)L.ldv * es);
   L.off_P = take((size_t)L.ldv * es);
   L.off_Q = take((size_t)L.ldv * es);
   L.off_R = take((size_t)L.ldv * es);
   L.off_S = take((size_t)L.ldv * es);
-  L.off_part = take((size_t)(m_max + 2) * rp.nblk * es + 64);
+  // per-block partial sums of one projection (Lanczos projects on one vector)
+  L.off_part = take((size_t)((L.band ? 1 : m_max) + 2) * rp.nblk * es + 64);
   L.off_h = take((size_t)(m_max + 2) * es);
   L.off_H = take((size_t)L.ldh * m_max * es);
   L.off_nrm = take(8 * sizeof(double));
@@ -315,7 +323,7 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
 }
 
 int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_t s) {
-  const Layout L = make_layout(op, 1);
+  const Layout L = make_layout(op, 1, FA_FORCE_ARNOLDI);
   void* const tmp[4] = {at(ws, L.off_P), at(ws, L.off_Q), at(ws, L.off_R), at(ws, L.off_S)};
   const void* res = nullptr;
   int64_t mv = 0;
@@ -331,11 +339,13 @@ int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_
 namespace {
 struct HostH {
   int ldh = 0;
+  bool band = false;        // Lanczos: column j holds rows j and j + 1 only
   int dtype = FA_F64;
   std::vector<double> buf;  // column-major, ldh rows, (complex interleaved)
   cd get(int i, int j) const {
-    if (dtype == FA_C128) return cd(buf[2 * ((size_t)j * ldh + i)], buf[2 * ((size_t)j * ldh + i) + 1]);
-    return cd(buf[(size_t)j * ldh + i], 0.0);
+    const size_t o = (size_t)j * ldh + (band ? i - j : i);
+    if (dtype == FA_C128) return cd(buf[2 * o], buf[2 * o + 1]);
+    return cd(buf[o], 0.0);
   }
 };
 
@@ -378,7 +388,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   const double t0 = now_ms();
   fa_stats S;
   std::memset(&S, 0, sizeof(S));
-  const Layout L = make_layout(op, m_max);
+  const Layout L = make_layout(op, m_max, flags);
   if (!ws || ws_bytes < L.bytes || ((uintptr_t)ws & 255)) return FA_ERR_WORKSPACE;
   const size_t es = elem_size(op.dtype);
   const int64_t n = op.n;
@@ -386,22 +396,33 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   const Poly& q = op.poly;
   const int K = (q.method < 0) ? 0 : q.degree;
   const int k_chk = check_every > 0 ? check_every : std::max(1, 64 / (K + 1));
+  const bool two_pass = (flags & FA_TWO_PASS) != 0;
+  // Algorithm 2 (right preconditioning); with q == 1 it is Algorithm 1
+  const bool right = (flags & FA_RIGHT_PREC) && K > 0;
+  if (two_pass && (!lanczos || (flags & FA_RIGHT_PREC))) return FA_ERR_UNSUPPORTED;
 
   char* V = at(ws, L.off_V);
+  char* Y = right ? at(ws, L.off_Y) : nullptr;
   void* U = at(ws, L.off_U);
   void* const tmp[4] = {at(ws, L.off_P), at(ws, L.off_Q), at(ws, L.off_R), at(ws, L.off_S)};
   const bool fuse = !(flags & FA_NO_FUSION);
   // mixed precision: the polynomial chain in FP32 (stencil, Chebyshev q, K >= 1)
-  const bool mixed = (flags & FA_MIXED) && op.poly.method >= 0 && op.poly.degree > 0;
-  if (mixed && (op.kind != OP_STENCIL7 || op.poly.method != FA_POLY_CHEB)) return FA_ERR_UNSUPPORTED;
+  const bool mixed = (flags & FA_MIXED) && K > 0;
+  if (mixed && (op.kind != OP_STENCIL7 || q.method != FA_POLY_CHEB || right))
+    return FA_ERR_UNSUPPORTED;
   const Prec pm = mixed ? P32 : P64;
   void* part = at(ws, L.off_part);
   char* hcur = at(ws, L.off_h);
   char* Hd = at(ws, L.off_H);
   double* nrm = (double*)at(ws, L.off_nrm);
   void* zd = at(ws, L.off_z);
-  auto Vc = [&](int j) -> char* { return V + (size_t)j * L.ldv * es; };
+  auto Vc = [&](int j) -> char* { return V + (size_t)(two_pass ? j % 3 : j) * L.ldv * es; };
+  auto Yc = [&](int j) -> char* { return Y + (size_t)j * L.ldv * es; };
   auto Hcol = [&](int j) -> char* { return Hd + (size_t)j * L.ldh * es; };
+  // entry H(i, j) (Lanczos: i in {j, j + 1})
+  auto Hent = [&](int i, int j) -> char* {
+    return Hcol(j) + (size_t)(L.band ? i - j : i) * es;
+  };
 
   Prof prof;
   prof.on = (flags & FA_PROFILE) != 0;
@@ -410,29 +431,114 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   int st = FA_OK;
 
   // Sec. 4: square root through the inverse square root, b' = A b
+  // (two-pass: b' is kept in the output vector, which pass 1 does not touch
+  // and which never aliases b)
   const void* bsrc = d_b;
   if (kind == FA_SQRT) {
-    st = chain(op, d_b, nullptr, nullptr, U, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, pp);
+    void* dst = two_pass ? d_x : U;
+    st = chain(op, d_b, nullptr, nullptr, dst, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, pp);
     if (st) return st;
     ++mvms;
-    bsrc = U;
+    bsrc = dst;
   }
-  // Algorithm 1: c = q(A) b', beta = ||c||, v_1 = c / beta
-  {
+  // the first basis vector: Algorithm 1 c = q(A) b', v_1 = c / ||c||;
+  // Algorithm 2 v_1 = b' / ||b'||
+  auto start_vector = [&]() -> int {
     const void* res = nullptr;
-    if (mixed) {  // b' to FP32 in the fifth scratch vector, then the FP32 chain
+    if (right) {
+      res = bsrc;
+    } else if (mixed) {  // b' to FP32 in the fifth scratch vector, then the FP32 chain
       void* b32 = tmp[3];
       FA_HIP(launch_to_f32(n, (const double*)bsrc, (float*)b32, s));
       void* const tmpm[4] = {tmp[0], tmp[1], tmp[2], U};
-      st = poly_apply(op, q, b32, Vc(0), tmpm, &res, s, pp, &mvms, fuse, P32, P64);
+      const int r = poly_apply(op, q, b32, Vc(0), tmpm, &res, s, pp, &mvms, fuse, P32, P64);
+      if (r) return r;
     } else {
-      st = poly_apply(op, q, bsrc, Vc(0), tmp, &res, s, pp, &mvms, fuse);
+      const int r = poly_apply(op, q, bsrc, Vc(0), tmp, &res, s, pp, &mvms, fuse);
+      if (r) return r;
     }
-    if (st) return st;
     if (res != Vc(0)) FA_HIP(launch_scale(op.dtype, n, cd(1.0), res, Vc(0), s));
     FA_HIP(launch_update(op.dtype, n, 0, V, L.ldv, hcur, Vc(0), part, nrm, s));
     FA_HIP(launch_normalize(op.dtype, n, Vc(0), nrm, Vc(0), nullptr, s));
-  }
+    return FA_OK;
+  };
+  // one Krylov step: w = A q(A)^2 v_j in three stages, orthogonalized against
+  // the basis (CGS2) or the two latest vectors (Lanczos), normalized into v_{j+1}
+  int64_t ips = 0;
+  auto step = [&](int j) -> int {
+    char* vj = Vc(j);
+    char* w = Vc(j + 1);
+    if (K == 0) {
+      const int r = chain(op, vj, nullptr, nullptr, w, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, pp);
+      if (r) return r;
+      ++mvms;
+    } else if (right) {  // Algorithm 2: y_j = q(A) v_j (stored), u = q(A) y_j, w = A u
+      const void* y = nullptr;
+      int r = poly_apply(op, q, vj, Yc(j), tmp, &y, s, pp, &mvms, fuse);
+      if (r) return r;
+      if (y != Yc(j)) FA_HIP(launch_scale(op.dtype, n, cd(1.0), y, Yc(j), s));
+      const void* u = nullptr;
+      r = poly_apply(op, q, Yc(j), U, tmp, &u, s, pp, &mvms, fuse);
+      if (r) return r;
+      r = chain(op, u, nullptr, nullptr, w, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, pp);
+      if (r) return r;
+      ++mvms;
+    } else {  // Algorithm 1: u = A v_j, y = q(A) u, w = q(A) y
+      FA_HIP(launch_chain(op, vj, nullptr, nullptr, U, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, P64, pm));
+      ++mvms;
+      const void* y = nullptr;
+      int r = poly_apply(op, q, U, U, tmp, &y, s, pp, &mvms, fuse, pm, pm);
+      if (r) return r;
+      void* tmp2[4];  // the scratch vectors other than the one holding y
+      {
+        void* all[5] = {U, tmp[0], tmp[1], tmp[2], tmp[3]};
+        int c = 0;
+        for (void* b : all)
+          if (b != y && c < 4) tmp2[c++] = b;
+      }
+      const void* r2 = nullptr;
+      r = poly_apply(op, q, y, w, tmp2, &r2, s, pp, &mvms, fuse, pm, P64);
+      if (r) return r;
+      if (r2 != w) FA_HIP(launch_scale(op.dtype, n, cd(1.0), r2, w, s));
+    }
+    // orthogonalization against v_1..v_j (h_ij = v_i^H w)
+    if (lanczos) {
+      if (j > 0)  // w -= beta_{j-1} v_{j-1}, beta_{j-1} = H(j, j-1)
+        FA_HIP(launch_update(op.dtype, n, 1, Vc(j - 1), L.ldv, Hent(j, j - 1), w, part, nullptr,
+                             s));
+      FA_HIP(launch_project(op.dtype, n, 1, vj, L.ldv, w, part, hcur, Hent(j, j), 1, s));
+      FA_HIP(launch_update(op.dtype, n, 1, vj, L.ldv, hcur, w, part, nrm, s));
+      ips += 2;
+    } else {  // classical Gram-Schmidt, twice
+      FA_HIP(launch_project(op.dtype, n, j + 1, V, L.ldv, w, part, hcur, Hcol(j), 1, s));
+      FA_HIP(launch_update(op.dtype, n, j + 1, V, L.ldv, hcur, w, part, nullptr, s));
+      FA_HIP(launch_project(op.dtype, n, j + 1, V, L.ldv, w, part, hcur, Hcol(j), 2, s));
+      FA_HIP(launch_update(op.dtype, n, j + 1, V, L.ldv, hcur, w, part, nrm, s));
+      ips += 2 * (j + 1) + 1;
+    }
+    // h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}
+    FA_HIP(launch_normalize(op.dtype, n, w, nrm, w, Hent(j + 1, j), s));
+    return FA_OK;
+  };
+  // coefficient vector z to the device (negated with `neg`)
+  auto z_to_device = [&](const std::vector<cd>& zz, int len, bool neg, void* dst) -> int {
+    std::vector<double> zh((size_t)len * (es / 8));
+    const double sg = neg ? -1.0 : 1.0;
+    for (int i = 0; i < len; ++i) {
+      if (op.dtype == FA_C128) {
+        zh[2 * i] = sg * zz[i].real();
+        zh[2 * i + 1] = sg * zz[i].imag();
+      } else {
+        zh[i] = sg * zz[i].real();
+      }
+    }
+    FA_HIP(hipMemcpyAsync(dst, zh.data(), zh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    FA_HIP(hipStreamSynchronize(s));  // zh is a local buffer
+    return FA_OK;
+  };
+
+  st = start_vector();
+  if (st) return st;
   double beta2 = 0.0;
   FA_HIP(hipMemcpyAsync(&beta2, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
   FA_HIP(hipStreamSynchronize(s));
@@ -450,6 +556,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
 
   HostH H;
   H.ldh = L.ldh;
+  H.band = L.band;
   H.dtype = op.dtype;
   H.buf.assign((size_t)L.ldh * m_max * (op.dtype == FA_C128 ? 2 : 1), 0.0);
   int copied = 0;          // columns of H already on the host
@@ -458,53 +565,10 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   int m = m_max;
   bool converged = false, breakdown = false;
   double est = 1.0;
-  int64_t ips = 0;
 
   for (int j = 0; j < m_max; ++j) {
-    char* vj = Vc(j);
-    char* w = Vc(j + 1);
-    // three-stage preconditioned product w = q(A) q(A) A v_j (Algorithm 1)
-    if (K == 0) {
-      st = chain(op, vj, nullptr, nullptr, w, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, pp);
-      if (st) return st;
-      ++mvms;
-    } else {
-      FA_HIP(launch_chain(op, vj, nullptr, nullptr, U, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, P64, pm));
-      ++mvms;
-      const void* y = nullptr;
-      st = poly_apply(op, q, U, U, tmp, &y, s, pp, &mvms, fuse, pm, pm);
-      if (st) return st;
-      void* tmp2[4];  // the scratch vectors other than the one holding y
-      {
-        void* all[5] = {U, tmp[0], tmp[1], tmp[2], tmp[3]};
-        int c = 0;
-        for (void* b : all)
-          if (b != y && c < 4) tmp2[c++] = b;
-      }
-      const void* r2 = nullptr;
-      st = poly_apply(op, q, y, w, tmp2, &r2, s, pp, &mvms, fuse, pm, P64);
-      if (st) return st;
-      if (r2 != w) FA_HIP(launch_scale(op.dtype, n, cd(1.0), r2, w, s));
-    }
-    // orthogonalization against v_1..v_j (h_ij = v_i^H w)
-    if (lanczos) {
-      if (j > 0)  // w -= beta_{j-1} v_{j-1}, beta_{j-1} = H(j, j-1)
-        FA_HIP(launch_update(op.dtype, n, 1, Vc(j - 1), L.ldv, Hcol(j - 1) + (size_t)j * es, w,
-                             part, nullptr, s));
-      FA_HIP(launch_project(op.dtype, n, 1, vj, L.ldv, w, part, hcur, Hcol(j) + (size_t)j * es, 1,
-                            s));
-      FA_HIP(launch_update(op.dtype, n, 1, vj, L.ldv, hcur, w, part, nrm, s));
-      ips += 2;
-    } else {  // classical Gram-Schmidt, twice
-      FA_HIP(launch_project(op.dtype, n, j + 1, V, L.ldv, w, part, hcur, Hcol(j), 1, s));
-      FA_HIP(launch_update(op.dtype, n, j + 1, V, L.ldv, hcur, w, part, nullptr, s));
-      FA_HIP(launch_project(op.dtype, n, j + 1, V, L.ldv, w, part, hcur, Hcol(j), 2, s));
-      FA_HIP(launch_update(op.dtype, n, j + 1, V, L.ldv, hcur, w, part, nrm, s));
-      ips += 2 * (j + 1) + 1;
-    }
-    // h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}
-    FA_HIP(launch_normalize(op.dtype, n, w, nrm, w, Hcol(j) + (size_t)(j + 1) * es, s));
-
+    st = step(j);
+    if (st) return st;
     const int jj = j + 1;
     const bool check = (tol > 0.0) ? (jj % k_chk == 0 || jj == m_max) : (jj == m_max);
     if (!check) continue;
@@ -542,13 +606,32 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     S.ms_host_fH += now_ms() - th;
     ++S.checks;
     if (st) return st;
-    double dn = 0.0, zn = 0.0;
-    for (int i = 0; i < jj; ++i) {
-      const cd zp = (i < (int)zprev.size()) ? zprev[i] : cd(0.0);
-      dn += std::norm(z[i] - zp);
-      zn += std::norm(z[i]);
+    if (right) {
+      // Y is not orthonormal: est = ||Y_j (z_j - [z_{j-k}; 0])|| / ||Y_j z_j||
+      std::vector<cd> dz(jj);
+      for (int i = 0; i < jj; ++i) dz[i] = z[i] - ((i < (int)zprev.size()) ? zprev[i] : cd(0.0));
+      st = z_to_device(dz, jj, false, zd);
+      if (st) return st;
+      FA_HIP(launch_combine(op.dtype, n, jj, Y, L.ldv, zd, tmp[0], s));
+      FA_HIP(launch_update(op.dtype, n, 0, V, L.ldv, hcur, tmp[0], part, nrm, s));
+      double dn2 = 0.0, zn2 = 0.0;
+      FA_HIP(hipMemcpyAsync(&dn2, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+      st = z_to_device(z, jj, false, zd);
+      if (st) return st;
+      FA_HIP(launch_combine(op.dtype, n, jj, Y, L.ldv, zd, tmp[0], s));
+      FA_HIP(launch_update(op.dtype, n, 0, V, L.ldv, hcur, tmp[0], part, nrm, s));
+      FA_HIP(hipMemcpyAsync(&zn2, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+      FA_HIP(hipStreamSynchronize(s));
+      est = std::sqrt(dn2 / zn2);
+    } else {  // V orthonormal: the iterates' difference from the coefficients
+      double dn = 0.0, zn = 0.0;
+      for (int i = 0; i < jj; ++i) {
+        const cd zp = (i < (int)zprev.size()) ? zprev[i] : cd(0.0);
+        dn += std::norm(z[i] - zp);
+        zn += std::norm(z[i]);
+      }
+      est = std::sqrt(dn / zn);
     }
-    est = std::sqrt(dn / zn);
     zprev = z;
     if (est <= tol) {
       m = jj;
@@ -568,18 +651,27 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     S.ms_host_fH += now_ms() - th;
     if (st) return st;
   }
-  // f_m = V_m z_m
-  std::vector<double> zh((size_t)m * (es / 8));
-  for (int i = 0; i < m; ++i) {
-    if (op.dtype == FA_C128) {
-      zh[2 * i] = z[i].real();
-      zh[2 * i + 1] = z[i].imag();
-    } else {
-      zh[i] = z[i].real();
+  if (two_pass) {
+    // second pass: regenerate v_1..v_m with the same (deterministic) kernels
+    // and accumulate x = sum_i z_i v_i, the basis never stored
+    st = z_to_device(z, m, true, zd);
+    if (st) return st;
+    st = start_vector();
+    if (st) return st;
+    FA_HIP(launch_scale(op.dtype, n, z[0], Vc(0), d_x, s));
+    for (int j = 0; j + 1 < m; ++j) {
+      st = step(j);
+      if (st) return st;
+      FA_HIP(launch_update(op.dtype, n, 1, Vc(j + 1), L.ldv, (char*)zd + (size_t)(j + 1) * es,
+                           d_x, part, nullptr, s));
     }
+  } else {
+    // f_m = V_m z_m (Algorithm 1) or Y_m z_m (Algorithm 2)
+    st = z_to_device(z, m, false, zd);
+    if (st) return st;
+    FA_HIP(launch_combine(op.dtype, n, m, right ? (const void*)Y : (const void*)V, L.ldv, zd, d_x,
+                          s));
   }
-  FA_HIP(hipMemcpyAsync(zd, zh.data(), zh.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  FA_HIP(launch_combine(op.dtype, n, m, V, L.ldv, zd, d_x, s));
   FA_HIP(hipStreamSynchronize(s));
 
   S.iters = m;
@@ -635,7 +727,7 @@ static int real_blocks(Poly& q) {
 
 size_t poly_workspace_bytes(const Op& op, int degree, int method) {
   if (method == FA_POLY_CHEB || degree == 0) return 0;
-  return make_layout(op, degree + 1).bytes;
+  return make_layout(op, degree + 1, FA_FORCE_ARNOLDI).bytes;  // RITZ and HARMONIC
 }
 
 int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, size_t ws_bytes,
@@ -673,11 +765,11 @@ int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, si
     op.poly_ready = true;
     return FA_OK;
   }
-  if (method != FA_POLY_RITZ) return FA_ERR_ARG;
+  if (method != FA_POLY_RITZ && method != FA_POLY_HARMONIC) return FA_ERR_ARG;
   if (!d_start) return FA_ERR_ARG;
   // d = degree + 1 Arnoldi steps on A itself (CGS2) from the given start vector
   const int d = degree + 1;
-  const Layout L = make_layout(op, d);
+  const Layout L = make_layout(op, d, FA_FORCE_ARNOLDI);
   if (!ws || ws_bytes < L.bytes || ((uintptr_t)ws & 255)) return FA_ERR_WORKSPACE;
   const size_t es = elem_size(op.dtype);
   const int64_t n = op.n;
@@ -723,6 +815,17 @@ int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, si
   std::vector<cd> Hc((size_t)steps * steps), ev(steps);
   for (int j = 0; j < steps; ++j)
     for (int i = 0; i < steps; ++i) Hc[(size_t)j * steps + i] = (i <= j + 1) ? H.get(i, j) : cd(0.0);
+  if (method == FA_POLY_HARMONIC) {
+    // harmonic Ritz values: eigenvalues of H_d + h_{d+1,d}^2 f e_d^T with
+    // H_d^H f = e_d (Sec. 5.2); after a lucky breakdown h_{d+1,d} = 0
+    const double hn = std::abs(H.get(steps, steps - 1));
+    std::vector<cd> A((size_t)steps * steps), f(steps, cd(0.0));
+    for (int j = 0; j < steps; ++j)
+      for (int i = 0; i < steps; ++i) A[(size_t)j * steps + i] = std::conj(Hc[(size_t)i * steps + j]);
+    f[steps - 1] = 1.0;
+    if (lu_solve(steps, A.data(), f.data()) != DENSE_OK) return FA_ERR_HESSENBERG;
+    for (int i = 0; i < steps; ++i) Hc[(size_t)(steps - 1) * steps + i] += hn * hn * f[i];
+  }
   if (hess_eigenvalues(steps, Hc.data(), steps, ev.data()) != DENSE_OK) return FA_ERR_HESSENBERG;
   const bool real_op = op.dtype == FA_F64;
   bool any_complex = false;
@@ -735,6 +838,7 @@ int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, si
     }
   }
   q.method = FA_POLY_RITZ;
+  q.harmonic = method == FA_POLY_HARMONIC;
   q.theta = leja_order(ev, real_op);
   q.degree = (int)q.theta.size() - 1;
   q.rho = leja_capacity(q.theta);

@@ -9,11 +9,12 @@ namespace fa {
 struct Layout {
   int64_t ldv = 0;  // leading dimension of the basis (elements)
   int ldh = 0;      // leading dimension of H (elements)
-  size_t off_V = 0, off_U = 0, off_P = 0, off_Q = 0, off_R = 0, off_S = 0, off_part = 0, off_h = 0, off_H = 0,
+  bool band = false;  // H stored as (diagonal, subdiagonal) pairs (Lanczos)
+  size_t off_V = 0, off_Y = 0, off_U = 0, off_P = 0, off_Q = 0, off_R = 0, off_S = 0, off_part = 0, off_h = 0, off_H = 0,
          off_nrm = 0, off_z = 0;
   size_t bytes = 0;
 };
-Layout make_layout(const Op& op, int m_max);
+Layout make_layout(const Op& op, int m_max, uint32_t flags);
 
 int op_apply(const Op& op, const void* x, void* y, hipStream_t s);
 int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_t s);

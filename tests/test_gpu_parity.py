@@ -483,3 +483,178 @@ def test_mixed_precision_128_full_size():
     x32, st = op.apply(b, m_max=200, tol=1e-7, mixed=True)
     assert st["converged"]
     assert_close(host(x32), host(x64), 1e-6)
+
+
+# --------------------------------------------------------------------------
+# variants of Sec. 5.2 and Sec. 6: harmonic Ritz values, right
+# preconditioning (Algorithm 2), two-pass Lanczos
+# --------------------------------------------------------------------------
+def _sorted_nodes(t):
+    key = lambda z: (round(z.real, 6), round(z.imag, 6))
+    return np.array(sorted(t, key=key))
+
+
+def test_harmonic_ritz_wilson():
+    L = 4
+    U = wl.su3_links(L, eps=0.3, seed=1)
+    m0 = 0.05
+    op = fa().Wilson(U, m0)
+    start = wl.rhs(op.n, seed=11, complex_=True)
+    op.poly_setup(8, "harmonic", start=dev(start))
+    p = op.poly()
+    assert p["method"] == "harmonic" and p["degree"] == 8
+    apply_A = lambda v: ops.wilson_apply(U, m0, v)
+    q = pl.ritz(apply_A, start, 8, real_operator=False, harmonic=True)
+    gt, rt = _sorted_nodes(p["theta"]), _sorted_nodes(q.theta)
+    assert np.max(np.abs(gt - rt)) <= 1e-9 * np.max(np.abs(rt))
+    # not the plain Ritz values
+    q0 = pl.ritz(apply_A, start, 8, real_operator=False)
+    assert np.max(np.abs(rt - _sorted_nodes(q0.theta))) > 1e-3
+    x = wl.rhs(op.n, seed=12, complex_=True)
+    ref, _ = q.apply(apply_A, x)
+    assert_close(host(op.poly_apply(dev(x))), ref, 1e-8)
+    b = wl.rhs(op.n, seed=0, complex_=True)
+    xs, st = op.apply(dev(b), m_max=400, tol=1e-12)
+    orc = kr.fAb(apply_A, b, q, "invsqrt", m_max=400, tol=1e-12)
+    assert st["converged"] and st["iters"] == orc.iters
+    assert_close(host(xs), orc.x, 1e-10)
+
+
+@pytest.mark.parametrize("degree", [4, 8])
+def test_harmonic_ritz_real_nonnormal(degree):
+    N = 12
+    dims = (N, N, N)
+    coeffs = wl.convdiff_stencil(N, 100.0)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    start = wl.rhs(N ** 3, seed=4)
+    q = pl.ritz(A, start, degree, real_operator=True, harmonic=True)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(degree, "harmonic", start=dev(start))
+    p = op.poly()
+    gt, rt = _sorted_nodes(p["theta"]), _sorted_nodes(q.theta)
+    assert np.max(np.abs(gt - rt)) <= 1e-8 * np.max(np.abs(rt))
+    b = wl.rhs(N ** 3, seed=0)
+    xs, st = op.apply(dev(b), m_max=400, tol=1e-12)
+    orc = kr.fAb(A, b, q, "invsqrt", m_max=400, tol=1e-12)
+    assert st["converged"]
+    assert_close(host(xs), orc.x, 1e-10)
+
+
+@pytest.mark.parametrize("degree,m", [(0, 30), (3, 12), (8, 6)])
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+def test_right_preconditioning_fixed_m(degree, m, kind):
+    """Algorithm 2 with Arnoldi (CGS2) on a non-normal operator, fixed m."""
+    dims = (20, 18, 16)
+    coeffs = wl.convdiff_stencil(20, 50.0)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(degree, "cheb")
+    a, bb = ops.stencil_interval(coeffs, dims)
+    b = wl.rhs(op.n, seed=0)
+    x, st = op.apply(dev(b), kind=kind, m_max=m, tol=0.0, right=True)
+    ref = kr.fAb(A, b, pl.chebyshev(a, bb, degree), kind, m_max=m, tol=0.0, side="right")
+    assert st["iters"] == ref.iters == m
+    assert st["mvms"] == ref.mvms
+    assert_close(host(x), ref.x, 1e-10)
+
+
+@pytest.mark.parametrize("degree", [4, 15])
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+def test_right_preconditioning_lanczos_converged(degree, kind):
+    """Algorithm 2 with Lanczos: the stopping estimate over the stored y_j and
+    the iteration count agree with the oracle; the result with the closed form."""
+    N = 24
+    dims = (N, N, N)
+    coeffs = wl.laplace_stencil(3)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    op = fa().Stencil7(dims, coeffs, hermitian=True)
+    op.poly_setup(degree, "cheb")
+    a, bb = ops.stencil_interval(coeffs, dims)
+    b = wl.rhs(op.n, seed=0)
+    x, st = op.apply(dev(b), kind=kind, m_max=300, tol=1e-11, right=True)
+    orc = kr.fAb(A, b, pl.chebyshev(a, bb, degree), kind, m_max=300, tol=1e-11,
+                 orth="lanczos", side="right")
+    assert st["converged"] and st["iters"] == orc.iters
+    assert st["mvms"] == orc.mvms and st["inner_products"] == orc.inner_products
+    # the estimate is a ratio of small differences: equal up to rounding noise
+    assert abs(st["est_rel_change"] - orc.est) <= 0.1 * orc.est + 1e-13
+    assert_close(host(x), orc.x, 1e-10)
+    assert_close(host(x), exact.stencil_fAb_dst(coeffs, dims, b, kind), 1e-9)
+
+
+@pytest.mark.parametrize("d", [8, 16])
+def test_table1_right_lanczos_100cubed(d):
+    """Sec. 6, Example 1, Table 1 at its size (100^3 Laplacian, Chebyshev q
+    with d coefficients, right-preconditioned Lanczos): at the printed
+    iteration count the true relative error is below 1e-12 and one check
+    interval earlier it is not; the operation counts follow the printed rule."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "table1_laplace3d.json")))
+    row = next(r for r in g["rows"] if r["d"] == d)
+    N = g["N"]
+    dims = (N, N, N)
+    coeffs = wl.laplace_stencil(3)
+    op = fa().Stencil7(dims, coeffs, hermitian=True)
+    op.poly_setup(d - 1, "cheb")
+    b = wl.rhs(N ** 3, seed=0)
+    b = b / np.linalg.norm(b)
+    xs = exact.stencil_fAb_dst(coeffs, dims, b, "invsqrt")
+    k = 64 // d
+    m = row["iterations"]
+    errs = {}
+    for mm in (m - k, m):
+        x, st = op.apply(dev(b), m_max=mm, tol=0.0, right=True)
+        errs[mm] = np.linalg.norm(host(x) - xs) / np.linalg.norm(xs)
+        assert st["mvms"] == mm * (2 * d - 1)
+        assert st["inner_products"] == 2 * mm
+    assert errs[m] < g["tol_true_error"] < errs[m - k], errs
+    assert st["mvms"] == row["mvms"] and st["inner_products"] == row["inner_products"]
+
+
+@pytest.mark.parametrize("degree", [0, 4])
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+def test_two_pass_lanczos(degree, kind):
+    """Two-pass Lanczos: the same iterate as one pass (same iteration count),
+    the basis regenerated instead of stored, and the oracle's counts."""
+    N = 20
+    dims = (N, N, N)
+    coeffs = wl.laplace_stencil(3)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    op = fa().Stencil7(dims, coeffs, hermitian=True)
+    op.poly_setup(degree, "cheb")
+    a, bb = ops.stencil_interval(coeffs, dims)
+    q = pl.chebyshev(a, bb, degree)
+    b = wl.rhs(op.n, seed=0)
+    x1, s1 = op.apply(dev(b), kind=kind, m_max=300, tol=1e-10)
+    x2, s2 = op.apply(dev(b), kind=kind, m_max=300, tol=1e-10, two_pass=True)
+    assert s2["converged"] and s2["iters"] == s1["iters"]
+    assert_close(host(x2), host(x1), 1e-13)
+    orc = kr.fAb(A, b, q, kind, m_max=300, tol=1e-10, orth="lanczos", two_pass=True)
+    assert s2["iters"] == orc.iters and s2["mvms"] == orc.mvms
+    assert_close(host(x2), orc.x, 1e-10)
+    # three basis vectors instead of m_max + 1 (plus the fixed scratch vectors)
+    tp = fa().FA_TWO_PASS
+    assert op.workspace_bytes(300, tp) < op.workspace_bytes(300) / 10
+    # ... and a few scalars per step (H's two diagonals, coefficients)
+    assert op.workspace_bytes(3000, tp) - op.workspace_bytes(300, tp) < 64 * (3000 - 300)
+
+
+def test_variant_flag_errors():
+    dims = (8, 8, 8)
+    coeffs = wl.convdiff_stencil(8, 10.0)
+    op = fa().Stencil7(dims, coeffs)          # not Hermitian
+    op.poly_setup(4, "cheb")
+    b = dev(wl.rhs(op.n, seed=0))
+    with pytest.raises(fa().FAError) as e:
+        op.apply(b, two_pass=True)
+    assert e.value.status == fa()._lib.FA_ERR_UNSUPPORTED
+    with pytest.raises(fa().FAError):
+        op.apply(b, right=True, mixed=True)
+    oph = fa().Stencil7(dims, wl.laplace_stencil(3), hermitian=True)
+    oph.poly_setup(4, "cheb")
+    with pytest.raises(fa().FAError):
+        oph.apply(b, two_pass=True, right=True)
+    with pytest.raises(fa().FAError):
+        oph.apply(b, two_pass=True, force_arnoldi=True)
