@@ -15,7 +15,8 @@ It is written to be read against the paper, not to be fast:
 * ``polynomials``  -- the preconditioning polynomial q ~ z^{-1/2}: Chebyshev
                       interpolant + Clenshaw recurrence (Sec. 5.1), and Ritz-value
                       interpolation in Newton form with Leja ordering + Horner
-                      evaluation (Sec. 5.2);
+                      evaluation (Sec. 5.2), harmonic Ritz values, and the
+                      least-squares polynomial on a contour (Sec. 5.3);
 * ``krylov``       -- left / right polynomially preconditioned Arnoldi and
                       Lanczos (Algorithms 1 and 2), the dense H^{-1/2} e_1 step,
                       the difference-of-iterates stopping rule (Sec. 3.1, Sec. 6)

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from oracle import exact, operators as ops, polynomials as pl
+from oracle import exact, krylov as kr, operators as ops, polynomials as pl
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -203,3 +203,114 @@ def test_harmonic_ritz_polynomial_preconditions():
     A = lambda v: ops.stencil_apply(coeffs, dims, v)
     q = pl.ritz(A, wl.rhs(N ** 3, seed=2), 6, real_operator=True, harmonic=True)
     assert np.allclose(q.scalar(q.theta), q.theta ** -0.5, rtol=1e-8)
+
+
+# --------------------------------------------------------------------------
+# Sec. 5.3: least-squares polynomials on a contour
+# --------------------------------------------------------------------------
+def test_ls_on_a_circle_is_the_truncated_taylor_series():
+    """On N equispaced points of a circle |z - c| = r the monomials (z - c)^j,
+    j < N, are orthogonal, so the discrete least-squares fit of degree K is the
+    degree-K Taylor polynomial of z^{-1/2} at c up to aliasing of order
+    (r / c)^(N - K)."""
+    from scipy.special import binom
+    c, r, N = 2.0, 1.0, 400
+    pts = c + r * np.exp(2j * np.pi * np.arange(N) / N)
+    zt = np.array([1.5, 2.3 + 0.4j, 2.0 - 0.7j, 2.9])
+    for K in (1, 5, 12):
+        q = pl.ls_polynomial(pts, K)
+        taylor = sum(binom(-0.5, j) * c ** (-0.5 - j) * (zt - c) ** j for j in range(K + 1))
+        assert np.max(np.abs(q.scalar(zt) - taylor)) < 1e-13
+
+
+def test_ls_fit_equals_lstsq_on_a_scaled_vandermonde():
+    """The fitted values P_d alpha are the orthogonal projection of f onto the
+    polynomials of degree <= K on the points: compare with numpy's least
+    squares on a scaled Vandermonde basis (independent of the Arnoldi basis)."""
+    th = np.array([0.3 + 1j, 0.3 - 1j, 6 + 2j, 6 - 2j, 9.0, 2 + 0.1j, 2 - 0.1j])
+    pts = pl.ls_contour(th, 0.1, 0.05, symmetric=True)
+    f = pl.inv_sqrt(pts)
+    cen, sc = 5.0, 6.0
+    for K in (2, 5, 8):
+        q = pl.ls_polynomial(pts, K, real_operator=True)
+        Vd = np.vander((pts - cen) / sc, K + 1, increasing=True)
+        coef, *_ = np.linalg.lstsq(Vd, f, rcond=None)
+        assert np.max(np.abs(q.scalar(pts) - Vd @ coef)) < 1e-10 * np.max(np.abs(f))
+        # real recurrence and coefficients for a conjugate-symmetric point set
+        assert not np.iscomplexobj(q.hls) and not np.iscomplexobj(q.alpha)
+
+
+def test_ls_matrix_recurrence_on_a_diagonal_matrix():
+    th = np.array([0.5 + 0.5j, 0.5 - 0.5j, 4.0 + 1j, 4.0 - 1j])
+    q = pl.ls_polynomial(pl.ls_contour(th, 0.1, 0.02, symmetric=True), 6, real_operator=True)
+    lam = np.linspace(0.6, 3.9, 50)
+    v = np.cos(np.arange(50.0))
+    y, nmv = q.apply(lambda x: lam * x, v)
+    assert nmv == 6
+    assert np.max(np.abs(y - q.scalar(lam) * v)) < 1e-13 * np.max(np.abs(y))
+    # complex operator, complex point set
+    lamc = lam + 0.3j
+    qc = pl.ls_polynomial(pl.ls_contour(th + 0.3j, 0.1, 0.02, symmetric=False), 6)
+    yc, _ = qc.apply(lambda x: lamc * x, v.astype(complex))
+    assert np.max(np.abs(yc - qc.scalar(lamc) * v)) < 1e-13 * np.max(np.abs(yc))
+
+
+def test_ls_contour_geometry_rectangle_with_min_radius():
+    """Hull = rectangle [0.05, 10] x [-1, 1]; the disk |z| < 0.1 cuts its left
+    edge, which is replaced by the arc |z| = 0.1 through z = 0.1."""
+    th = np.array([0.05 + 1j, 0.05 - 1j, 10 + 1j, 10 - 1j, 3 + 0.2j, 3 - 0.2j])
+    step, r = 0.005, 0.1
+    pts = pl.ls_contour(th, r, step, symmetric=False)
+    chord = 2 * math.sqrt(r * r - 0.05 ** 2)
+    length = 2 * 9.95 + 2 * 2.0 - chord + r * 2 * math.acos(0.05 / r)
+    N = math.ceil(length / step)
+    assert len(pts) == N
+    gaps = np.abs(np.diff(np.concatenate([pts, pts[:1]])))
+    assert np.max(gaps) <= length / N * (1 + 1e-12)
+    assert np.min(np.abs(pts)) >= r * (1 - 1e-14)
+    on_arc = np.abs(np.abs(pts) - r) < 1e-12
+    assert on_arc.sum() >= 2 and np.min(pts[on_arc].real) >= 0.05 - 1e-15
+    assert np.all(pts.real >= 0.05 - 1e-15) and np.all(pts.real <= 10 + 1e-15)
+    assert np.all(np.abs(pts.imag) <= 1 + 1e-15)
+    on_edges = ((np.abs(pts.real - 0.05) < 1e-12) | (np.abs(pts.real - 10) < 1e-12)
+                | (np.abs(np.abs(pts.imag) - 1) < 1e-12) | on_arc)
+    assert np.all(on_edges)
+    sym = pl.ls_contour(th, r, step, symmetric=True)
+    assert len(sym) == 2 * N and np.allclose(np.sort_complex(sym), np.sort_complex(sym.conj()))
+
+
+def test_ls_contour_of_real_ritz_values_is_a_segment():
+    th = np.array([0.05, 0.7, 2.0, 5.0])
+    pts = pl.ls_contour(th, 0.1, 0.01, symmetric=True)
+    assert np.all(pts.imag == 0.0)
+    assert abs(np.min(pts.real) - 0.1) < 1e-12 and np.max(pts.real) <= 5.0
+    # forth and back: 2 * 4.9 / 0.01 points, doubled by the symmetric union
+    assert len(pts) == 2 * math.ceil(2 * 4.9 / 0.01)
+
+
+def test_ls_branch_check():
+    """A low degree on points reaching close to the branch point cannot stay
+    in the right half-plane: the fit is refused."""
+    z = np.linspace(1e-4, 1.0, 500).astype(complex)
+    with pytest.raises(pl.BranchError):
+        pl.ls_polynomial(z, 1)
+    assert np.min(pl.ls_polynomial(z, 2).scalar(z).real) > 0
+
+
+def test_ls_preconditioned_solve_matches_closed_form():
+    """Sec. 5.3 polynomial (Ritz values from 60 Arnoldi steps, contour with
+    minimum radius 0.1) preconditioning a non-normal conv-diff operator."""
+    N = 12
+    dims = (N, N, N)
+    coeffs = wl.convdiff_stencil(N, 50.0)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    start = wl.rhs(N ** 3, seed=4)
+    q = pl.least_squares(A, start, 6, real_operator=True, ritz_steps=30, step=0.01)
+    assert q.kind == "ls" and q.degree == 6
+    b = wl.rhs(N ** 3, seed=0)
+    res = kr.fAb(A, b, q, "invsqrt", m_max=300, tol=1e-12)
+    assert res.converged
+    ref = exact.stencil_fAb_dst(coeffs, dims, b, "invsqrt")
+    assert np.linalg.norm(res.x - ref) / np.linalg.norm(ref) < 1e-10
+    plain = kr.fAb(A, b, None, "invsqrt", m_max=300, tol=1e-12)
+    assert res.iters < plain.iters
