@@ -88,8 +88,10 @@ enum {
   FA_POLY_AUTO = 0, /* CHEB when the op has a real spectral interval, else RITZ     */
   FA_POLY_CHEB = 1, /* Chebyshev interpolant of z^{-1/2} on [lo, hi], Sec. 5.1      */
   FA_POLY_RITZ = 2, /* interpolant at Ritz values, Newton form, Leja order, Sec. 5.2 */
-  FA_POLY_HARMONIC = 3 /* as RITZ at the harmonic Ritz values (the eigenvalues of
+  FA_POLY_HARMONIC = 3, /* as RITZ at the harmonic Ritz values (the eigenvalues of
                           H_d + h_{d+1,d}^2 H_d^{-H} e_d e_d^T), Sec. 5.2           */
+  FA_POLY_LS = 4       /* least-squares fit of z^{-1/2} on a contour around the Ritz
+                          values, Sec. 5.3 (fa_poly_setup_ls)                     */
 };
 
 /* flags */
@@ -191,7 +193,10 @@ int fa_set_spectral_interval(fa_op op, double lo, double hi);
 /* Query the interval; returns FA_ERR_NO_INTERVAL if the op has none. */
 int fa_get_spectral_interval(fa_op op, double* lo, double* hi);
 
-/* Bytes of device workspace fa_poly_setup needs for `degree` (0 for CHEB). */
+/* Bytes of device workspace fa_poly_setup needs for `degree` (0 for CHEB;
+ * for FA_POLY_LS: its default 60 setup Arnoldi steps, whatever the degree;
+ * with ritz_steps s given to fa_poly_setup_ls, the figure for degree s - 1
+ * and FA_POLY_RITZ). */
 size_t fa_poly_workspace_bytes(fa_op op, int degree, int method);
 
 /*
@@ -205,9 +210,14 @@ size_t fa_poly_workspace_bytes(fa_op op, int degree, int method);
  *     internally and not modified); the Ritz values (eigenvalues of H_{K+1})
  *     are the interpolation nodes of z^{-1/2}, stored in Newton form on the
  *     Leja ordering with capacity scaling.  A Ritz value with Re <= 0 gives
- *     FA_ERR_BRANCH.  Real operators whose Ritz values are not all real give
- *     FA_ERR_UNSUPPORTED.  If Arnoldi breaks down after j < K + 1 steps the
- *     degree becomes j - 1.  Needs d_workspace of fa_poly_workspace_bytes.
+ *     FA_ERR_BRANCH.  For real operators, conjugate pairs of Ritz values are
+ *     evaluated in real arithmetic (quadratic factors); a pair with
+ *     Re theta < 1e-3 |theta| gives FA_ERR_UNSUPPORTED.  If Arnoldi breaks down
+ *     after j < K + 1 steps the degree becomes j - 1.  Needs d_workspace of
+ *     fa_poly_workspace_bytes.
+ *   FA_POLY_HARMONIC (Sec. 5.2): as RITZ with the harmonic Ritz values.
+ *   FA_POLY_LS (Sec. 5.3): as fa_poly_setup_ls with ritz_steps 60, r_min 0.1
+ *     and step 0.005 (the choices of Sec. 6, Example 3).
  * Runs on hip_stream and synchronizes it.  Errors: FA_ERR_ARG, FA_ERR_BRANCH,
  * FA_ERR_NO_INTERVAL, FA_ERR_WORKSPACE, FA_ERR_UNSUPPORTED, FA_ERR_HIP.
  */
@@ -215,15 +225,49 @@ int fa_poly_setup(fa_op op, int degree, int method, const void* d_start, void* d
                   size_t ws_bytes, void* hip_stream);
 
 /*
+ * fa_poly_setup_ls -- the least-squares polynomial of Sec. 5.3, degree K
+ * (1 <= K <= 63):
+ *   1. ritz_steps (>= 2) Arnoldi steps on A from d_start give Ritz values
+ *      (any with Re <= 0: FA_ERR_BRANCH);
+ *   2. the contour is the boundary of their convex hull minus the disk
+ *      |z| < r_min (the part of the hull boundary inside the disk replaced by
+ *      the arc |z| = r_min), discretized at equal arc length with spacing at
+ *      most `step`; for real operators the mirror images are added, so the
+ *      point set is conjugate-symmetric and q has real coefficients;
+ *   3. Arnoldi on diag(z_1..z_N) from [1..1]/sqrt(N) gives the orthonormal
+ *      polynomials p_j of the discrete inner product and their recurrence;
+ *      alpha = P^H z^{-1/2} (the least-squares solution); Re q(z_i) <= 0 at a
+ *      point gives FA_ERR_BRANCH.
+ *   q(A) v is then evaluated by the recurrence with A in place of z (K
+ *   products with A, O(K^2) vector updates, no inner products); fa_apply's
+ *   workspace then also holds K + 1 vectors for it (query fa_workspace_bytes
+ *   after the setup).  Not with FA_MIXED.
+ *   d_workspace: fa_poly_workspace_bytes(op, ritz_steps - 1, FA_POLY_RITZ)
+ *   bytes.  Errors: FA_ERR_ARG, FA_ERR_BRANCH, FA_ERR_HESSENBERG (degenerate
+ *   contour), FA_ERR_WORKSPACE, FA_ERR_HIP.
+ */
+int fa_poly_setup_ls(fa_op op, int degree, int ritz_steps, double r_min, double step,
+                     const void* d_start, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/*
  * fa_poly_get -- read back the polynomial (host arrays of at least degree + 1
  * entries each; any pointer may be NULL).
- *   method: FA_POLY_CHEB / FA_POLY_RITZ, or -1 for q == 1.
+ *   method: FA_POLY_CHEB / FA_POLY_RITZ / FA_POLY_HARMONIC / FA_POLY_LS, or -1
+ *   for q == 1.
  *   CHEB: coef[i] = c_i, interval = {lo, hi}.
  *   RITZ: nodes_re/im = Leja-ordered Ritz values, coef_re/im = scaled Newton
  *         coefficients eta_j, *rho = scaling: q(z) = sum_j eta_j prod_{i<j} (z - theta_i)/rho.
  */
 int fa_poly_get(fa_op op, int* degree, int* method, double* coef_re, double* coef_im,
                 double* nodes_re, double* nodes_im, double* interval, double* rho);
+/*   LS:   coef_re/im = alpha_j, *rho = N (number of contour points); the
+ *         recurrence through fa_poly_get_ls. */
+
+/* fa_poly_get_ls -- the recurrence of an FA_POLY_LS polynomial: *npts = N and
+ * h_re/h_im (host, (K + 1) x K, column-major) = the Hessenberg matrix with
+ * z p_{j-1} = sum_{i<=j} h_{i,j-1} p_i, p_0 = N^{-1/2}.  Errors: FA_ERR_ARG
+ * (another kind of polynomial), FA_ERR_NO_POLY. */
+int fa_poly_get_ls(fa_op op, int64_t* npts, double* h_re, double* h_im);
 
 /* Bytes of device workspace fa_apply needs for Krylov dimension m_max:
  * (m_max + 1) basis vectors + 5 chain vectors + reduction scratch + H. */

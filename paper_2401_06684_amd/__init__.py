@@ -19,7 +19,7 @@ import torch
 from . import _lib
 from ._lib import (FA_C128, FA_F64, FA_FORCE_ARNOLDI, FA_HERMITIAN, FA_INVSQRT,  # noqa: F401
                    FA_MIXED, FA_NO_FUSION, FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_HARMONIC,
-                   FA_POLY_RITZ, FA_PROFILE, FA_RIGHT_PREC, FA_SQRT, FA_TWO_PASS, FAError,
+                   FA_POLY_LS, FA_POLY_RITZ, FA_PROFILE, FA_RIGHT_PREC, FA_SQRT, FA_TWO_PASS, FAError,
                    check, lib)
 
 __all__ = ["Stencil7", "CSR", "Wilson", "FAError", "lib", "dense_invsqrt_e1",
@@ -27,7 +27,7 @@ __all__ = ["Stencil7", "CSR", "Wilson", "FAError", "lib", "dense_invsqrt_e1",
 
 _KIND = {"invsqrt": FA_INVSQRT, "sqrt": FA_SQRT}
 _METHOD = {"auto": FA_POLY_AUTO, "cheb": FA_POLY_CHEB, "ritz": FA_POLY_RITZ,
-           "harmonic": FA_POLY_HARMONIC}
+           "harmonic": FA_POLY_HARMONIC, "ls": FA_POLY_LS}
 
 
 def _stream(device):
@@ -82,15 +82,20 @@ class Operator:
         check(st, "fa_get_spectral_interval")
         return lo.value, hi.value
 
-    def poly_setup(self, degree, method="auto", start=None):
+    def poly_setup(self, degree, method="auto", start=None, ritz_steps=60, r_min=0.1,
+                   step=0.005):
         """Choose q of the given degree (0: plain method).
-        method: auto|cheb|ritz|harmonic.
+        method: auto|cheb|ritz|harmonic|ls.
 
-        For (harmonic) Ritz polynomials `start` is the start vector of the setup Arnoldi
-        run (a device tensor of length n).
+        For (harmonic) Ritz and least-squares polynomials `start` is the start
+        vector of the setup Arnoldi run (a device tensor of length n); ls uses
+        ritz_steps Arnoldi steps and the contour parameters r_min and step.
         """
         m = _METHOD[method]
-        nbytes = lib().fa_poly_workspace_bytes(self._h, degree, m)
+        if m == FA_POLY_LS:
+            nbytes = lib().fa_poly_workspace_bytes(self._h, ritz_steps - 1, FA_POLY_RITZ)
+        else:
+            nbytes = lib().fa_poly_workspace_bytes(self._h, degree, m)
         keep = None
         wsp = C.c_void_p(0)
         if nbytes:
@@ -99,7 +104,11 @@ class Operator:
         if start is not None:
             start = self._vec(start, "start")
             sp = _ptr(start)
-        st = lib().fa_poly_setup(self._h, degree, m, sp, wsp, nbytes, _stream(self.device))
+        if m == FA_POLY_LS and degree > 0:
+            st = lib().fa_poly_setup_ls(self._h, degree, ritz_steps, float(r_min), float(step),
+                                        sp, wsp, nbytes, _stream(self.device))
+        else:
+            st = lib().fa_poly_setup(self._h, degree, m, sp, wsp, nbytes, _stream(self.device))
         check(st, "fa_poly_setup")
         del keep
 
@@ -116,13 +125,20 @@ class Operator:
         check(lib().fa_poly_get(self._h, None, None, cr, ci, nr, ni, iv, C.byref(rho)),
               "fa_poly_get")
         meth_name = {-1: "one", FA_POLY_CHEB: "cheb", FA_POLY_RITZ: "ritz",
-                     FA_POLY_HARMONIC: "harmonic"}[meth.value]
+                     FA_POLY_HARMONIC: "harmonic", FA_POLY_LS: "ls"}[meth.value]
         out = {"method": meth_name, "degree": K}
         if meth_name == "cheb":
             out.update(c=list(cr), interval=(iv[0], iv[1]))
         elif meth_name in ("ritz", "harmonic"):
             out.update(eta=[complex(a, b) for a, b in zip(cr, ci)],
                        theta=[complex(a, b) for a, b in zip(nr, ni)], rho=rho.value)
+        elif meth_name == "ls":
+            npts = C.c_int64()
+            hr, hi = (C.c_double * ((K + 1) * K))(), (C.c_double * ((K + 1) * K))()
+            check(lib().fa_poly_get_ls(self._h, C.byref(npts), hr, hi), "fa_poly_get_ls")
+            h = [[complex(hr[j * (K + 1) + i], hi[j * (K + 1) + i]) for j in range(K)]
+                 for i in range(K + 1)]
+            out.update(alpha=[complex(a, b) for a, b in zip(cr, ci)], npts=npts.value, h=h)
         return out
 
     # ---- application -------------------------------------------------------

@@ -22,13 +22,14 @@ FA_ERR_UNSUPPORTED = -9
 FA_F64, FA_C128 = 0, 1
 FA_INVSQRT, FA_SQRT = 0, 1
 FA_STENCIL7, FA_WILSON4D = 0, 1
-FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_RITZ, FA_POLY_HARMONIC = 0, 1, 2, 3
+FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_RITZ, FA_POLY_HARMONIC, FA_POLY_LS = 0, 1, 2, 3, 4
 FA_HERMITIAN, FA_FORCE_ARNOLDI, FA_PROFILE, FA_NO_FUSION, FA_MIXED = 1, 4, 8, 16, 32
 FA_TWO_PASS, FA_RIGHT_PREC = 64, 128
 
 EXPORTS = [
     "fa_create_csr", "fa_create_stencil", "fa_set_spectral_interval",
-    "fa_get_spectral_interval", "fa_poly_workspace_bytes", "fa_poly_setup", "fa_poly_get",
+    "fa_get_spectral_interval", "fa_poly_workspace_bytes", "fa_poly_setup", "fa_poly_setup_ls",
+    "fa_poly_get", "fa_poly_get_ls",
     "fa_workspace_bytes", "fa_apply", "fa_op_apply", "fa_poly_apply", "fa_op_info",
     "fa_destroy", "fa_status_string", "fa_dense_invsqrt_e1", "fa_dense_tridiag_invsqrt_e1",
 ]
@@ -75,7 +76,9 @@ def lib():
         "fa_get_spectral_interval": (i32, [vp, dp, dp]),
         "fa_poly_workspace_bytes": (sz, [vp, i32, i32]),
         "fa_poly_setup": (i32, [vp, i32, i32, vp, vp, sz, vp]),
+        "fa_poly_setup_ls": (i32, [vp, i32, i32, dbl, dbl, vp, vp, sz, vp]),
         "fa_poly_get": (i32, [vp, ip, ip, dp, dp, dp, dp, dp, dp]),
+        "fa_poly_get_ls": (i32, [vp, C.POINTER(C.c_int64), dp, dp]),
         "fa_workspace_bytes": (sz, [vp, i32, u32]),
         "fa_apply": (i32, [vp, i32, vp, vp, i32, dbl, i32, vp, sz, u32, vp, C.POINTER(fa_stats)]),
         "fa_op_apply": (i32, [vp, vp, vp, vp]),

@@ -158,11 +158,27 @@ size_t fa_poly_workspace_bytes(fa_op op, int degree, int method) {
 
 int fa_poly_setup(fa_op op, int degree, int method, const void* d_start, void* d_workspace,
                   size_t ws_bytes, void* hip_stream) {
-  if (!op || degree < 0 || method < FA_POLY_AUTO || method > FA_POLY_HARMONIC) return FA_ERR_ARG;
+  if (!op || degree < 0 || method < FA_POLY_AUTO || method > FA_POLY_LS) return FA_ERR_ARG;
   return guarded([&] {
     int64_t mv = 0;
     return poly_setup(op->op, degree, method, d_start, d_workspace, ws_bytes,
                       stream_of(hip_stream), &mv);
+  });
+}
+
+int fa_poly_setup_ls(fa_op op, int degree, int ritz_steps, double r_min, double step,
+                     const void* d_start, void* d_workspace, size_t ws_bytes, void* hip_stream) {
+  if (!op || degree < 1 || degree >= kLsMax || ritz_steps < 2 || !(r_min >= 0.0) ||
+      !(step > 0.0) || !std::isfinite(r_min) || !std::isfinite(step))
+    return FA_ERR_ARG;
+  LsParams ls;
+  ls.ritz_steps = ritz_steps;
+  ls.r_min = r_min;
+  ls.step = step;
+  return guarded([&] {
+    int64_t mv = 0;
+    return poly_setup(op->op, degree, FA_POLY_LS, d_start, d_workspace, ws_bytes,
+                      stream_of(hip_stream), &mv, ls);
   });
 }
 
@@ -190,6 +206,25 @@ int fa_poly_get(fa_op op, int* degree, int* method, double* coef_re, double* coe
       if (nodes_im) nodes_im[i] = q.theta[i].imag();
     }
     if (rho) *rho = q.rho;
+  } else if (q.method == FA_POLY_LS) {
+    for (int i = 0; i <= q.degree; ++i) {
+      if (coef_re) coef_re[i] = q.alpha[i].real();
+      if (coef_im) coef_im[i] = q.alpha[i].imag();
+    }
+    if (rho) *rho = (double)q.npts;
+  }
+  return FA_OK;
+}
+
+int fa_poly_get_ls(fa_op op, int64_t* npts, double* h_re, double* h_im) {
+  if (!op) return FA_ERR_ARG;
+  if (!op->op.poly_ready) return FA_ERR_NO_POLY;
+  const Poly& q = op->op.poly;
+  if (q.method != FA_POLY_LS) return FA_ERR_ARG;
+  if (npts) *npts = q.npts;
+  for (size_t i = 0; i < q.hls.size(); ++i) {
+    if (h_re) h_re[i] = q.hls[i].real();
+    if (h_im) h_im[i] = q.hls[i].imag();
   }
   return FA_OK;
 }
@@ -224,7 +259,7 @@ int fa_poly_apply(fa_op op, const void* d_x, void* d_y, void* d_workspace, size_
                   void* hip_stream) {
   if (!op || !d_x || !d_y || d_x == d_y) return FA_ERR_ARG;
   if (!op->op.poly_ready) return FA_ERR_NO_POLY;
-  const Layout L = make_layout(op->op, 1, 0);
+  const Layout L = make_layout(op->op, 1, 0);  // includes the least-squares q's vectors
   if (!d_workspace || ws_bytes < L.bytes || ((uintptr_t)d_workspace & 255)) return FA_ERR_WORKSPACE;
   return guarded([&] {
     return poly_apply_public(op->op, d_x, d_y, d_workspace, stream_of(hip_stream));

@@ -83,4 +83,20 @@ double leja_capacity(const std::vector<cd>& t);
 // scaled Newton divided differences of z^{-1/2}: eta_j = f[t_0..t_j] rho^j
 std::vector<cd> newton_invsqrt(const std::vector<cd>& t, double rho);
 
+// Sec. 5.3 least-squares polynomial (lspoly.cpp).
+// Convex hull of the points, counter-clockwise, collinear points dropped.
+std::vector<cd> convex_hull(const std::vector<cd>& pts);
+// Discretized boundary of (convex hull of theta) minus the disk |z| < r_min,
+// equal arc-length spacing <= step; with `symmetric` the mirror images are
+// appended.  DENSE_BRANCH if a hull vertex has Re <= 0; DENSE_NOCONV for a
+// degenerate hull or one within r_min of 0.
+int ls_contour(const std::vector<cd>& theta, double r_min, double step, bool symmetric,
+               std::vector<cd>& out);
+// Least-squares fit of z^{-1/2} of the given degree on the points: recurrence
+// hls (d x (d - 1), column-major, ld d) of the orthonormal polynomials and
+// their coefficients alpha (d = degree + 1).  DENSE_BRANCH if Re q <= 0 at a
+// point; real_op: hls and alpha made real (the point set conjugate-symmetric).
+int ls_fit_invsqrt(const std::vector<cd>& z, int degree, bool real_op, std::vector<cd>& hls,
+                   std::vector<cd>& alpha);
+
 }  // namespace fa

@@ -21,8 +21,12 @@ enum OpKind { OP_CSR = 0, OP_STENCIL7 = 1, OP_WILSON = 2 };
 
 // the preconditioning polynomial, in the representation the chain kernels use
 struct Poly {
-  int method = -1;  // -1: q == 1; FA_POLY_CHEB; FA_POLY_RITZ (Newton form)
+  int method = -1;  // -1: q == 1; FA_POLY_CHEB; FA_POLY_RITZ (Newton form); FA_POLY_LS
   bool harmonic = false;  // RITZ nodes are harmonic Ritz values
+  // LS (Sec. 5.3): recurrence of the orthonormal polynomials (d x (d - 1),
+  // column-major), coefficients alpha (d), number of contour points
+  std::vector<cd> hls, alpha;
+  long npts = 0;
   int degree = 0;   // K
   double a = 0, b = 0;        // CHEB interval
   std::vector<double> c;      // CHEB coefficients c_0..c_K
@@ -121,6 +125,15 @@ hipError_t launch_normalize(int dtype, int64_t n, const void* w, const double* n
                             void* out, void* hout, hipStream_t s);
 // y = a * x for a scalar on the host
 hipError_t launch_scale(int dtype, int64_t n, cd a, const void* x, void* y, hipStream_t s);
+
+// least-squares polynomial step (kernel arguments by value; degree <= kLsMax)
+constexpr int kLsMax = 64;
+struct LsCoef {
+  double re[kLsMax], im[kLsMax];  // g_i, i < k - 1
+  double a0_re, a0_im, ak_re, ak_im;
+};
+hipError_t launch_ls_step(int dtype, int64_t n, int k, void* W, int64_t ldv, const LsCoef& g,
+                          bool keep, void* out, hipStream_t s);
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline size_t elem_size(int dtype) { return dtype == FA_C128 ? 16 : 8; }

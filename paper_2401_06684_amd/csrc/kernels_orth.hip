@@ -179,6 +179,46 @@ __global__ __launch_bounds__(kThreads) void scale_k(int64_t n, double a_re, doub
   if (i < n) y[i] = scale_val(a_re, a_im, x[i]);
 }
 
+// One step of the recurrence of the least-squares polynomial (Sec. 5.3),
+// after the chain launch has formed t = (A w_{k-1} - h_{k-1,k-1} w_{k-1}) / h_{k,k-1}
+// in column k of W:
+//   w_k = t + sum_{i < k-1} g_i w_i        (g_i = -h_{i,k-1} / h_{k,k-1})
+//   out = (k == 1 ? a_0 w_0 : out) + a_k w_k
+// w_k is stored back only if a later step reads it.
+__device__ __forceinline__ double coef_of(const LsCoef& g, int i, double) { return g.re[i]; }
+__device__ __forceinline__ cplx coef_of(const LsCoef& g, int i, cplx) { return cplx{g.re[i], g.im[i]}; }
+__device__ __forceinline__ double cval(double re, double, double) { return re; }
+__device__ __forceinline__ cplx cval(double re, double im, cplx) { return cplx{re, im}; }
+
+template <typename T, bool FIRST, bool KEEP>
+__global__ __launch_bounds__(kThreads) void ls_step_k(int64_t n, int k, T* __restrict__ W,
+                                                      int64_t ldv, LsCoef g, T* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (r >= n) return;
+  T w = W[(int64_t)k * ldv + r];
+  for (int i = 0; i + 1 < k; ++i) w = mad(coef_of(g, i, T{}), W[(int64_t)i * ldv + r], w);
+  if (KEEP) W[(int64_t)k * ldv + r] = w;
+  const T o = FIRST ? cval(g.a0_re, g.a0_im, T{}) * W[r] : out[r];
+  out[r] = mad(cval(g.ak_re, g.ak_im, T{}), w, o);
+}
+
+hipError_t launch_ls_step(int dtype, int64_t n, int k, void* W, int64_t ldv, const LsCoef& g,
+                          bool keep, void* out, hipStream_t s) {
+  const int grid = (int)((n + kThreads - 1) / kThreads);
+  const bool first = k == 1;
+#define FA_LS(T, F, K)                                                                      \
+  ls_step_k<T, F, K><<<grid, kThreads, 0, s>>>(n, k, (T*)W, ldv, g, (T*)out)
+  if (dtype == FA_C128) {
+    if (first) { if (keep) FA_LS(cplx, true, true); else FA_LS(cplx, true, false); }
+    else { if (keep) FA_LS(cplx, false, true); else FA_LS(cplx, false, false); }
+  } else {
+    if (first) { if (keep) FA_LS(double, true, true); else FA_LS(double, true, false); }
+    else { if (keep) FA_LS(double, false, true); else FA_LS(double, false, false); }
+  }
+#undef FA_LS
+  return hipGetLastError();
+}
+
 // --------------------------------------------------------------------------
 template <typename T>
 static hipError_t project_t(int64_t n, int ncols, const T* V, int64_t ldv, const T* w, T* part,

@@ -18,7 +18,7 @@ namespace fa {
 // --------------------------------------------------------------------------
 // workspace layout (every region 256-byte aligned)
 // --------------------------------------------------------------------------
-Layout make_layout(const Op& op, int m_max, uint32_t flags) {
+Layout make_layout(const Op& op, int m_max, uint32_t flags, bool with_poly) {
   Layout L;
   const size_t es = elem_size(op.dtype);
   L.ldv = round_up(op.n, 32);
@@ -49,6 +49,8 @@ Layout make_layout(const Op& op, int m_max, uint32_t flags) {
   L.off_H = take((size_t)L.ldh * m_max * es);
   L.off_nrm = take(8 * sizeof(double));
   L.off_z = take((size_t)(m_max + 1) * es);
+  if (with_poly && op.poly_ready && op.poly.method == FA_POLY_LS)
+    L.off_W = take((size_t)(op.poly.degree + 1) * L.ldv * es);
   L.bytes = off;
   return L;
 }
@@ -223,6 +225,44 @@ static int poly_apply_blocks(const Op& op, const Poly& q, const void* x, void* o
   return FA_OK;
 }
 
+// q(A) x for the least-squares polynomial (Sec. 5.3) by the recurrence of
+// its orthonormal basis polynomials with A in place of z:
+//   w_0 = x / sqrt(N),
+//   w_k = (A w_{k-1} - sum_{i<k} h_{i,k-1} w_i) / h_{k,k-1},  k = 1..K,
+//   q(A) x = sum_k alpha_k w_k,
+// K products with A and no inner products.  W holds the K + 1 vectors w_k
+// (leading dimension round_up(n, 32), as the basis); the result goes to out
+// (which may alias x: x is read only by the first launch).
+static int poly_apply_ls(const Op& op, const Poly& q, const void* x, void* out, void* W,
+                         const void** res, hipStream_t s, int64_t* mvms) {
+  if (!W) return FA_ERR_WORKSPACE;
+  const int K = q.degree, d = K + 1;
+  const size_t es = elem_size(op.dtype);
+  const int64_t ldv = round_up(op.n, 32);
+  auto Wc = [&](int j) -> void* { return (char*)W + (size_t)j * ldv * es; };
+  auto h = [&](int i, int j) { return q.hls[(size_t)j * d + i]; };
+  FA_HIP(launch_scale(op.dtype, op.n, cd(1.0 / std::sqrt((double)q.npts)), x, Wc(0), s));
+  for (int k = 1; k <= K; ++k) {
+    const cd hk = h(k, k - 1);
+    FA_HIP(launch_chain(op, Wc(k - 1), nullptr, nullptr, Wc(k),
+                        ChainCoef{1.0 / hk, -h(k - 1, k - 1) / hk, 0.0, 0.0}, s));
+    LsCoef g;
+    for (int i = 0; i + 1 < k; ++i) {
+      const cd gi = -h(i, k - 1) / hk;
+      g.re[i] = gi.real();
+      g.im[i] = gi.imag();
+    }
+    g.a0_re = q.alpha[0].real();
+    g.a0_im = q.alpha[0].imag();
+    g.ak_re = q.alpha[k].real();
+    g.ak_im = q.alpha[k].imag();
+    FA_HIP(launch_ls_step(op.dtype, op.n, k, W, ldv, g, k < K, out, s));
+  }
+  *mvms += K;
+  *res = out;
+  return FA_OK;
+}
+
 // q(A) x.  tmp holds 4 scratch vectors distinct from x and out.  The result
 // goes to `out` when that is safe and to a scratch vector otherwise (a
 // single-term launch may write over x pointwise, a two-term launch may not);
@@ -232,11 +272,15 @@ static int poly_apply_blocks(const Op& op, const Poly& q, const void* x, void* o
 // the last launch writes `out` in precision pout; pm = P64: everything FP64.
 static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, void* const tmp[4],
                       const void** res, hipStream_t s, Prof* prof, int64_t* mvms, bool fuse,
-                      Prec pm = P64, Prec pout = P64) {
+                      Prec pm = P64, Prec pout = P64, void* wls = nullptr) {
   const int K = q.degree;
   if (q.method < 0 || K == 0) {
     *res = x;  // q == 1
     return FA_OK;
+  }
+  if (q.method == FA_POLY_LS) {
+    if (pm != P64 || pout != P64) return FA_ERR_UNSUPPORTED;
+    return poly_apply_ls(op, q, x, out, wls, res, s, mvms);
   }
   if (!q.blocks.empty()) {
     if (pm != P64) return FA_ERR_UNSUPPORTED;
@@ -323,11 +367,12 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
 }
 
 int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_t s) {
-  const Layout L = make_layout(op, 1, FA_FORCE_ARNOLDI);
+  const Layout L = make_layout(op, 1, 0);
   void* const tmp[4] = {at(ws, L.off_P), at(ws, L.off_Q), at(ws, L.off_R), at(ws, L.off_S)};
   const void* res = nullptr;
   int64_t mv = 0;
-  int st = poly_apply(op, op.poly, x, y, tmp, &res, s, nullptr, &mv, true);
+  int st = poly_apply(op, op.poly, x, y, tmp, &res, s, nullptr, &mv, true, P64, P64,
+                      L.off_W ? at(ws, L.off_W) : nullptr);
   if (st) return st;
   if (res != y) FA_HIP(hipMemcpyAsync(y, res, op.n * elem_size(op.dtype), hipMemcpyDeviceToDevice, s));
   return FA_OK;
@@ -406,6 +451,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   void* U = at(ws, L.off_U);
   void* const tmp[4] = {at(ws, L.off_P), at(ws, L.off_Q), at(ws, L.off_R), at(ws, L.off_S)};
   const bool fuse = !(flags & FA_NO_FUSION);
+  void* const wls = L.off_W ? at(ws, L.off_W) : nullptr;  // least-squares q
   // mixed precision: the polynomial chain in FP32 (stencil, Chebyshev q, K >= 1)
   const bool mixed = (flags & FA_MIXED) && K > 0;
   if (mixed && (op.kind != OP_STENCIL7 || q.method != FA_POLY_CHEB || right))
@@ -454,7 +500,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       const int r = poly_apply(op, q, b32, Vc(0), tmpm, &res, s, pp, &mvms, fuse, P32, P64);
       if (r) return r;
     } else {
-      const int r = poly_apply(op, q, bsrc, Vc(0), tmp, &res, s, pp, &mvms, fuse);
+      const int r = poly_apply(op, q, bsrc, Vc(0), tmp, &res, s, pp, &mvms, fuse, P64, P64, wls);
       if (r) return r;
     }
     if (res != Vc(0)) FA_HIP(launch_scale(op.dtype, n, cd(1.0), res, Vc(0), s));
@@ -474,11 +520,11 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       ++mvms;
     } else if (right) {  // Algorithm 2: y_j = q(A) v_j (stored), u = q(A) y_j, w = A u
       const void* y = nullptr;
-      int r = poly_apply(op, q, vj, Yc(j), tmp, &y, s, pp, &mvms, fuse);
+      int r = poly_apply(op, q, vj, Yc(j), tmp, &y, s, pp, &mvms, fuse, P64, P64, wls);
       if (r) return r;
       if (y != Yc(j)) FA_HIP(launch_scale(op.dtype, n, cd(1.0), y, Yc(j), s));
       const void* u = nullptr;
-      r = poly_apply(op, q, Yc(j), U, tmp, &u, s, pp, &mvms, fuse);
+      r = poly_apply(op, q, Yc(j), U, tmp, &u, s, pp, &mvms, fuse, P64, P64, wls);
       if (r) return r;
       r = chain(op, u, nullptr, nullptr, w, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, pp);
       if (r) return r;
@@ -487,7 +533,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       FA_HIP(launch_chain(op, vj, nullptr, nullptr, U, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, P64, pm));
       ++mvms;
       const void* y = nullptr;
-      int r = poly_apply(op, q, U, U, tmp, &y, s, pp, &mvms, fuse, pm, pm);
+      int r = poly_apply(op, q, U, U, tmp, &y, s, pp, &mvms, fuse, pm, pm, wls);
       if (r) return r;
       void* tmp2[4];  // the scratch vectors other than the one holding y
       {
@@ -497,7 +543,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
           if (b != y && c < 4) tmp2[c++] = b;
       }
       const void* r2 = nullptr;
-      r = poly_apply(op, q, y, w, tmp2, &r2, s, pp, &mvms, fuse, pm, P64);
+      r = poly_apply(op, q, y, w, tmp2, &r2, s, pp, &mvms, fuse, pm, P64, wls);
       if (r) return r;
       if (r2 != w) FA_HIP(launch_scale(op.dtype, n, cd(1.0), r2, w, s));
     }
@@ -727,11 +773,90 @@ static int real_blocks(Poly& q) {
 
 size_t poly_workspace_bytes(const Op& op, int degree, int method) {
   if (method == FA_POLY_CHEB || degree == 0) return 0;
-  return make_layout(op, degree + 1, FA_FORCE_ARNOLDI).bytes;  // RITZ and HARMONIC
+  // RITZ and HARMONIC: degree + 1 setup Arnoldi steps; LS: the default number
+  const int steps = (method == FA_POLY_LS) ? LsParams().ritz_steps : degree + 1;
+  return make_layout(op, steps, FA_FORCE_ARNOLDI, false).bytes;
 }
 
+namespace {
+// `steps` Arnoldi steps on A (CGS2) from d_start; the eigenvalues of H (Ritz
+// values) or of H + h^2 H^{-H} e e^T (harmonic Ritz values), fewer after a
+// lucky breakdown.  Real operators: conjugate pairs made exact, real values
+// made real.
+int setup_ritz_values(const Op& op, int steps, bool harmonic, const void* d_start, void* ws,
+                      size_t ws_bytes, hipStream_t s, int64_t* mvms_setup, std::vector<cd>& ev) {
+  if (!d_start) return FA_ERR_ARG;
+  const int d = steps;
+  const Layout L = make_layout(op, d, FA_FORCE_ARNOLDI, false);
+  if (!ws || ws_bytes < L.bytes || ((uintptr_t)ws & 255)) return FA_ERR_WORKSPACE;
+  const size_t es = elem_size(op.dtype);
+  const int64_t n = op.n;
+  char* V = at(ws, L.off_V);
+  void* part = at(ws, L.off_part);
+  char* hcur = at(ws, L.off_h);
+  char* Hd = at(ws, L.off_H);
+  double* nrm = (double*)at(ws, L.off_nrm);
+  auto Vc = [&](int j) -> char* { return V + (size_t)j * L.ldv * es; };
+  auto Hcol = [&](int j) -> char* { return Hd + (size_t)j * L.ldh * es; };
+  FA_HIP(launch_update(op.dtype, n, 0, V, L.ldv, hcur, (void*)d_start, part, nrm, s));
+  FA_HIP(launch_normalize(op.dtype, n, d_start, nrm, Vc(0), nullptr, s));
+  for (int j = 0; j < d; ++j) {
+    char* w = Vc(j + 1);
+    int st = op_apply(op, Vc(j), w, s);
+    if (st) return st;
+    ++*mvms_setup;
+    FA_HIP(launch_project(op.dtype, n, j + 1, V, L.ldv, w, part, hcur, Hcol(j), 1, s));
+    FA_HIP(launch_update(op.dtype, n, j + 1, V, L.ldv, hcur, w, part, nullptr, s));
+    FA_HIP(launch_project(op.dtype, n, j + 1, V, L.ldv, w, part, hcur, Hcol(j), 2, s));
+    FA_HIP(launch_update(op.dtype, n, j + 1, V, L.ldv, hcur, w, part, nrm, s));
+    FA_HIP(launch_normalize(op.dtype, n, w, nrm, w, Hcol(j) + (size_t)(j + 1) * es, s));
+  }
+  HostH H;
+  H.ldh = L.ldh;
+  H.dtype = op.dtype;
+  H.buf.assign((size_t)L.ldh * d * (es / 8), 0.0);
+  FA_HIP(hipMemcpyAsync(H.buf.data(), Hd, (size_t)L.ldh * d * es, hipMemcpyDeviceToHost, s));
+  FA_HIP(hipStreamSynchronize(s));
+  // steps completed before a lucky breakdown (same rule as in fa_apply)
+  int m = d;
+  double colmax = 0.0;
+  for (int c = 0; c < d; ++c) {
+    double cn = 0.0;
+    for (int i = 0; i <= c + 1; ++i) cn += std::norm(H.get(i, c));
+    if (!std::isfinite(cn)) return FA_ERR_NONFINITE;
+    colmax = std::max(colmax, std::sqrt(cn));
+    if (std::abs(H.get(c + 1, c)) <= 1e-12 * colmax) {
+      m = c + 1;
+      break;
+    }
+  }
+  std::vector<cd> Hc((size_t)m * m);
+  ev.assign(m, cd(0.0));
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) Hc[(size_t)j * m + i] = (i <= j + 1) ? H.get(i, j) : cd(0.0);
+  if (harmonic) {
+    // harmonic Ritz values: eigenvalues of H_m + h_{m+1,m}^2 f e_m^T with
+    // H_m^H f = e_m (Sec. 5.2); after a lucky breakdown h_{m+1,m} = 0
+    const double hn = std::abs(H.get(m, m - 1));
+    std::vector<cd> A((size_t)m * m), f(m, cd(0.0));
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) A[(size_t)j * m + i] = std::conj(Hc[(size_t)i * m + j]);
+    f[m - 1] = 1.0;
+    if (lu_solve(m, A.data(), f.data()) != DENSE_OK) return FA_ERR_HESSENBERG;
+    for (int i = 0; i < m; ++i) Hc[(size_t)(m - 1) * m + i] += hn * hn * f[i];
+  }
+  if (hess_eigenvalues(m, Hc.data(), m, ev.data()) != DENSE_OK) return FA_ERR_HESSENBERG;
+  for (auto& t : ev) {
+    if (!(t.real() > 0.0)) return FA_ERR_BRANCH;  // outside the right half-plane
+    // eigenvalues of a real H are real or come in conjugate pairs
+    if (op.dtype == FA_F64 && std::fabs(t.imag()) <= 1e-10 * std::abs(t)) t = cd(t.real(), 0.0);
+  }
+  return FA_OK;
+}
+}  // namespace
+
 int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, size_t ws_bytes,
-               hipStream_t s, int64_t* mvms_setup) {
+               hipStream_t s, int64_t* mvms_setup, const LsParams& ls) {
   if (degree < 0 || degree > 512) return FA_ERR_ARG;
   if (method == FA_POLY_AUTO) method = op.has_interval ? FA_POLY_CHEB : FA_POLY_RITZ;
   Poly q;
@@ -765,78 +890,37 @@ int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, si
     op.poly_ready = true;
     return FA_OK;
   }
-  if (method != FA_POLY_RITZ && method != FA_POLY_HARMONIC) return FA_ERR_ARG;
-  if (!d_start) return FA_ERR_ARG;
-  // d = degree + 1 Arnoldi steps on A itself (CGS2) from the given start vector
-  const int d = degree + 1;
-  const Layout L = make_layout(op, d, FA_FORCE_ARNOLDI);
-  if (!ws || ws_bytes < L.bytes || ((uintptr_t)ws & 255)) return FA_ERR_WORKSPACE;
-  const size_t es = elem_size(op.dtype);
-  const int64_t n = op.n;
-  char* V = at(ws, L.off_V);
-  void* part = at(ws, L.off_part);
-  char* hcur = at(ws, L.off_h);
-  char* Hd = at(ws, L.off_H);
-  double* nrm = (double*)at(ws, L.off_nrm);
-  auto Vc = [&](int j) -> char* { return V + (size_t)j * L.ldv * es; };
-  auto Hcol = [&](int j) -> char* { return Hd + (size_t)j * L.ldh * es; };
-  FA_HIP(launch_update(op.dtype, n, 0, V, L.ldv, hcur, (void*)d_start, part, nrm, s));
-  FA_HIP(launch_normalize(op.dtype, n, d_start, nrm, Vc(0), nullptr, s));
-  for (int j = 0; j < d; ++j) {
-    char* w = Vc(j + 1);
-    int st = op_apply(op, Vc(j), w, s);
-    if (st) return st;
-    ++*mvms_setup;
-    FA_HIP(launch_project(op.dtype, n, j + 1, V, L.ldv, w, part, hcur, Hcol(j), 1, s));
-    FA_HIP(launch_update(op.dtype, n, j + 1, V, L.ldv, hcur, w, part, nullptr, s));
-    FA_HIP(launch_project(op.dtype, n, j + 1, V, L.ldv, w, part, hcur, Hcol(j), 2, s));
-    FA_HIP(launch_update(op.dtype, n, j + 1, V, L.ldv, hcur, w, part, nrm, s));
-    FA_HIP(launch_normalize(op.dtype, n, w, nrm, w, Hcol(j) + (size_t)(j + 1) * es, s));
-  }
-  HostH H;
-  H.ldh = L.ldh;
-  H.dtype = op.dtype;
-  H.buf.assign((size_t)L.ldh * d * (es / 8), 0.0);
-  FA_HIP(hipMemcpyAsync(H.buf.data(), Hd, (size_t)L.ldh * d * es, hipMemcpyDeviceToHost, s));
-  FA_HIP(hipStreamSynchronize(s));
-  // steps completed before a lucky breakdown (same rule as in fa_apply)
-  int steps = d;
-  double colmax = 0.0;
-  for (int c = 0; c < d; ++c) {
-    double cn = 0.0;
-    for (int i = 0; i <= c + 1; ++i) cn += std::norm(H.get(i, c));
-    if (!std::isfinite(cn)) return FA_ERR_NONFINITE;
-    colmax = std::max(colmax, std::sqrt(cn));
-    if (std::abs(H.get(c + 1, c)) <= 1e-12 * colmax) {
-      steps = c + 1;
-      break;
-    }
-  }
-  std::vector<cd> Hc((size_t)steps * steps), ev(steps);
-  for (int j = 0; j < steps; ++j)
-    for (int i = 0; i < steps; ++i) Hc[(size_t)j * steps + i] = (i <= j + 1) ? H.get(i, j) : cd(0.0);
-  if (method == FA_POLY_HARMONIC) {
-    // harmonic Ritz values: eigenvalues of H_d + h_{d+1,d}^2 f e_d^T with
-    // H_d^H f = e_d (Sec. 5.2); after a lucky breakdown h_{d+1,d} = 0
-    const double hn = std::abs(H.get(steps, steps - 1));
-    std::vector<cd> A((size_t)steps * steps), f(steps, cd(0.0));
-    for (int j = 0; j < steps; ++j)
-      for (int i = 0; i < steps; ++i) A[(size_t)j * steps + i] = std::conj(Hc[(size_t)i * steps + j]);
-    f[steps - 1] = 1.0;
-    if (lu_solve(steps, A.data(), f.data()) != DENSE_OK) return FA_ERR_HESSENBERG;
-    for (int i = 0; i < steps; ++i) Hc[(size_t)(steps - 1) * steps + i] += hn * hn * f[i];
-  }
-  if (hess_eigenvalues(steps, Hc.data(), steps, ev.data()) != DENSE_OK) return FA_ERR_HESSENBERG;
   const bool real_op = op.dtype == FA_F64;
-  bool any_complex = false;
-  for (auto& t : ev) {
-    if (!(t.real() > 0.0)) return FA_ERR_BRANCH;  // Ritz value outside the right half-plane
-    if (real_op) {
-      // eigenvalues of a real H are real or come in conjugate pairs
-      if (std::fabs(t.imag()) <= 1e-10 * std::abs(t)) t = cd(t.real(), 0.0);
-      else any_complex = true;
-    }
+  if (method == FA_POLY_LS) {
+    // Sec. 5.3: Ritz values from ls.ritz_steps Arnoldi steps, the contour
+    // around them, the least-squares fit of z^{-1/2} on its points
+    if (degree >= kLsMax || ls.ritz_steps < 2 || !(ls.r_min >= 0.0) || !(ls.step > 0.0))
+      return FA_ERR_ARG;
+    std::vector<cd> ev, pts;
+    int st = setup_ritz_values(op, ls.ritz_steps, false, d_start, ws, ws_bytes, s, mvms_setup, ev);
+    if (st) return st;
+    st = ls_contour(ev, ls.r_min, ls.step, real_op, pts);
+    if (st == DENSE_BRANCH) return FA_ERR_BRANCH;
+    if (st != DENSE_OK) return FA_ERR_HESSENBERG;
+    if ((long)pts.size() <= degree) return FA_ERR_ARG;
+    st = ls_fit_invsqrt(pts, degree, real_op, q.hls, q.alpha);
+    if (st == DENSE_BRANCH) return FA_ERR_BRANCH;
+    if (st != DENSE_OK) return FA_ERR_HESSENBERG;
+    q.method = FA_POLY_LS;
+    q.degree = degree;
+    q.npts = (long)pts.size();
+    op.poly = q;
+    op.poly_ready = true;
+    return FA_OK;
   }
+  if (method != FA_POLY_RITZ && method != FA_POLY_HARMONIC) return FA_ERR_ARG;
+  // d = degree + 1 Arnoldi steps on A itself (CGS2) from the given start vector
+  std::vector<cd> ev;
+  int st = setup_ritz_values(op, degree + 1, method == FA_POLY_HARMONIC, d_start, ws, ws_bytes, s,
+                             mvms_setup, ev);
+  if (st) return st;
+  bool any_complex = false;
+  for (const auto& t : ev) any_complex |= real_op && t.imag() != 0.0;
   q.method = FA_POLY_RITZ;
   q.harmonic = method == FA_POLY_HARMONIC;
   q.theta = leja_order(ev, real_op);
@@ -844,8 +928,8 @@ int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, si
   q.rho = leja_capacity(q.theta);
   q.eta = newton_invsqrt(q.theta, q.rho);
   if (real_op && any_complex) {
-    const int st = real_blocks(q);
-    if (st) return st;
+    const int st2 = real_blocks(q);
+    if (st2) return st2;
   }
   op.poly = q;
   op.poly_ready = true;

@@ -12,17 +12,26 @@ struct Layout {
   bool band = false;  // H stored as (diagonal, subdiagonal) pairs (Lanczos)
   size_t off_V = 0, off_Y = 0, off_U = 0, off_P = 0, off_Q = 0, off_R = 0, off_S = 0, off_part = 0, off_h = 0, off_H = 0,
          off_nrm = 0, off_z = 0;
+  size_t off_W = 0;  // least-squares polynomial: its d basis vectors (0: none)
   size_t bytes = 0;
 };
-Layout make_layout(const Op& op, int m_max, uint32_t flags);
+// with_poly: include the storage the op's polynomial needs (least squares)
+Layout make_layout(const Op& op, int m_max, uint32_t flags, bool with_poly = true);
 
 int op_apply(const Op& op, const void* x, void* y, hipStream_t s);
 int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_t s);
 int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double tol,
           int check_every, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t s,
           fa_stats* stats);
+// parameters of the Sec. 5.3 least-squares polynomial (defaults: the choices
+// of Sec. 6, Example 3)
+struct LsParams {
+  int ritz_steps = 60;
+  double r_min = 0.1;
+  double step = 0.005;
+};
 size_t poly_workspace_bytes(const Op& op, int degree, int method);
 int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, size_t ws_bytes,
-               hipStream_t s, int64_t* mvms_setup);
+               hipStream_t s, int64_t* mvms_setup, const LsParams& ls = LsParams());
 
 }  // namespace fa

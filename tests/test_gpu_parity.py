@@ -658,3 +658,75 @@ def test_variant_flag_errors():
         oph.apply(b, two_pass=True, right=True)
     with pytest.raises(fa().FAError):
         oph.apply(b, two_pass=True, force_arnoldi=True)
+
+
+# --------------------------------------------------------------------------
+# Sec. 5.3: least-squares polynomials on a contour around the Ritz values
+# --------------------------------------------------------------------------
+def _ls_compare(op, q, p, tol_coef):
+    assert p["method"] == "ls" and p["degree"] == q.degree and p["npts"] == q.npts
+    assert np.max(np.abs(np.array(p["alpha"]) - q.alpha)) <= tol_coef * np.max(np.abs(q.alpha))
+    assert np.max(np.abs(np.array(p["h"]) - q.hls)) <= tol_coef * np.max(np.abs(q.hls))
+
+
+def test_ls_polynomial_real_nonnormal():
+    N = 12
+    dims = (N, N, N)
+    coeffs = wl.convdiff_stencil(N, 50.0)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    start = wl.rhs(N ** 3, seed=4)
+    q = pl.least_squares(A, start, 6, real_operator=True, ritz_steps=30, step=0.01)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(6, "ls", start=dev(start), ritz_steps=30, step=0.01)
+    _ls_compare(op, q, op.poly(), 1e-9)
+    x = wl.rhs(N ** 3, seed=5)
+    ref, _ = q.apply(A, x)
+    assert_close(host(op.poly_apply(dev(x))), ref, 1e-9)
+    b = wl.rhs(N ** 3, seed=0)
+    for kind in ("invsqrt", "sqrt"):
+        xs, st = op.apply(dev(b), kind=kind, m_max=300, tol=1e-12)
+        orc = kr.fAb(A, b, q, kind, m_max=300, tol=1e-12)
+        assert st["converged"] and st["iters"] == orc.iters and st["mvms"] == orc.mvms
+        assert_close(host(xs), orc.x, 1e-10)
+        assert_close(host(xs), exact.stencil_fAb_dst(coeffs, dims, b, kind), 1e-9)
+    # right preconditioning and a fixed Krylov dimension with the same q
+    xr, sr = op.apply(dev(b), m_max=8, tol=0.0, right=True)
+    orr = kr.fAb(A, b, q, "invsqrt", m_max=8, tol=0.0, side="right")
+    assert_close(host(xr), orr.x, 1e-10)
+
+
+def test_ls_polynomial_wilson_complex():
+    L = 4
+    U = wl.su3_links(L, eps=0.3, seed=1)
+    m0 = 0.05
+    apply_A = lambda v: ops.wilson_apply(U, m0, v)
+    op = fa().Wilson(U, m0)
+    start = wl.rhs(op.n, seed=11, complex_=True)
+    q = pl.least_squares(apply_A, start, 5, real_operator=False, ritz_steps=24, step=0.01)
+    op.poly_setup(5, "ls", start=dev(start), ritz_steps=24, step=0.01)
+    _ls_compare(op, q, op.poly(), 1e-8)
+    x = wl.rhs(op.n, seed=12, complex_=True)
+    ref, _ = q.apply(apply_A, x)
+    assert_close(host(op.poly_apply(dev(x))), ref, 1e-8)
+    b = wl.rhs(op.n, seed=0, complex_=True)
+    xs, st = op.apply(dev(b), m_max=400, tol=1e-12)
+    orc = kr.fAb(apply_A, b, q, "invsqrt", m_max=400, tol=1e-12)
+    assert st["converged"] and st["iters"] == orc.iters
+    assert_close(host(xs), orc.x, 1e-10)
+
+
+def test_ls_polynomial_errors():
+    N = 8
+    dims = (N, N, N)
+    coeffs = wl.convdiff_stencil(N, 10.0)
+    op = fa().Stencil7(dims, coeffs)
+    start = dev(wl.rhs(N ** 3, seed=4))
+    with pytest.raises(fa().FAError):
+        op.poly_setup(64, "ls", start=start, ritz_steps=30, step=0.01)
+    op.poly_setup(4, "ls", start=start, ritz_steps=30, step=0.01)
+    b = dev(wl.rhs(N ** 3, seed=0))
+    with pytest.raises(fa().FAError) as e:
+        op.apply(b, mixed=True)
+    assert e.value.status == fa()._lib.FA_ERR_UNSUPPORTED
+    x, st = op.apply(b, m_max=100, tol=1e-10)
+    assert st["converged"]
