@@ -10,8 +10,12 @@ A step is one fa_apply solve (setup of the operator and polynomial excluded,
 inputs resident in HBM).  Printed as one JSON line with a roofline object for
 the dominant kernel (the stencil chain launch that evaluates two Clenshaw
 terms: HIP events around each run of such launches in every timed solve) and
-the CPU oracle timed on a bounded sample.  Extra fields report plain Arnoldi (degree 0), degrees 4 and 32 and the
-square root on the same GPU.
+the CPU oracle timed on a bounded sample.  Extra fields report plain Arnoldi
+(degree 0), degrees 4 and 32 and the square root on the same GPU, and the
+serving workload: Poisson arrivals of a request mix (2D Laplacian 256^2,
+convection-diffusion 64^3 / 96^3 / 128^3, Wilson 16^4; f in {sqrt, invsqrt},
+tol in {1e-6, 1e-10}) through the library's request loop, with solves/s and
+p50/p99 latency from submission to completion.
 """
 from __future__ import annotations
 
@@ -45,6 +49,12 @@ def main():
                     help="only run R applications of q(A) (for hardware counters) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 2 GiB (counter calibration) and exit")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-only", action="store_true", help="only run the serving leg")
+    ap.add_argument("--qps", type=float, default=2000.0, help="serving arrival rate")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--serve-pool-gb", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -66,6 +76,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of 2 GiB done")
+        return
+    if args.serve_only:
+        print(json.dumps({"serving": serving_leg(args, fa, torch, wl, dev)}), flush=True)
         return
     N = args.N
     dims = (N, N, N)
@@ -198,6 +211,10 @@ def main():
         op0.release_workspace()
         del op0
 
+    # ---- serving: Poisson arrivals of a request mix ------------------------
+    if not args.no_serve:
+        extra["serving"] = serving_leg(args, fa, torch, wl, dev)
+
     # ---- CPU oracle on a bounded sample -----------------------------------
     cpu = None
     if not args.no_cpu:
@@ -229,6 +246,113 @@ def main():
         **extra,
     }
     print(json.dumps(line), flush=True)
+
+
+def serving_leg(args, fa, torch, wl, dev):
+    """Requests through the library's server (fa_server_*): operators and
+    polynomials set up once and kept on the device; each request gets its
+    own output vector; latency = completion - submission (server clock)."""
+    import threading
+    import queue
+
+    import numpy as np
+
+    log("serving: building the operators of the mix")
+    ops, bs = {}, {}
+    for name, _ in wl.SERVING_TYPES:
+        if name == "laplace2d_256":
+            op = fa.Stencil7((256, 256, 1), wl.laplace_stencil(2), hermitian=True, device=dev)
+            op.poly_setup(8, "cheb")
+            m_max = 300
+        elif name.startswith("convdiff3d_"):
+            n1 = int(name.split("_")[1])
+            op = fa.Stencil7((n1, n1, n1), wl.convdiff_stencil(n1, 50.0), device=dev)
+            op.poly_setup(16, "cheb")
+            m_max = 100
+        else:
+            op = fa.Wilson(wl.su3_links(16, eps=0.3, seed=1), 0.05, device=dev)
+            st = torch.from_numpy(wl.rhs(op.n, seed=11, complex_=True)).to(dev)
+            op.poly_setup(16, "ritz", start=st)
+            m_max = 150
+        cplx = op.dtype == torch.complex128
+        ops[name] = (op, m_max)
+        bs[name] = [torch.from_numpy(wl.rhs(op.n, seed=s, complex_=cplx)).to(dev)
+                    for s in range(4)]
+    torch.cuda.synchronize()
+    pool = int(args.serve_pool_gb * (1 << 30))
+    srv = fa.Server(pool, n_workers=args.serve_workers, device=dev)
+
+    def run(reqs, arrivals):
+        out = []
+        q = queue.Queue()
+
+        def waiter():
+            while True:
+                item = q.get()
+                if item is None:
+                    return
+                t, r = item
+                x, info = srv.wait(t, raise_errors=False)
+                out.append((r, info))
+                del x
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            if arrivals is not None:
+                delay = t0 + arrivals[i] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            op, m_max = ops[r["type"]]
+            t = srv.submit(op, bs[r["type"]][r["seed"] % 4], kind=r["kind"], m_max=m_max,
+                           tol=r["tol"])
+            q.put((t, r))
+        q.put(None)
+        th.join()
+        sub = min(info["t_submit_ms"] for _, info in out)
+        end = max(info["t_done_ms"] for _, info in out)
+        lat = np.array([info["t_done_ms"] - info["t_submit_ms"] for _, info in out])
+        wait = np.array([info["t_start_ms"] - info["t_submit_ms"] for _, info in out])
+        return {"requests": len(out), "solves_per_s": len(out) / ((end - sub) * 1e-3),
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_queue_wait_ms": float(wait.mean()),
+                "errors": sum(1 for _, i in out if i["status"] < 0),
+                "not_converged": sum(1 for _, i in out if i["status"] == 1),
+                "mean_iters": float(np.mean([i["stats"]["iters"] for _, i in out]))}
+
+    # each type alone (invsqrt, tol 1e-10) for reference, after one warm-up
+    solo = {}
+    for name, (op, m_max) in ops.items():
+        for rep in range(2):
+            t = srv.submit(op, bs[name][0], m_max=m_max, tol=1e-10)
+            _, info = srv.wait(t)
+        solo[name] = {"ms": info["t_done_ms"] - info["t_start_ms"],
+                      "iters": info["stats"]["iters"]}
+    log("serving: solo " + ", ".join(f"{k} {v['ms']:.1f} ms (m={v['iters']})"
+                                     for k, v in solo.items()))
+    mix = wl.serving_mix(args.serve_requests)
+    cap = run(mix[: max(1, args.serve_requests // 2)], None)
+    log(f"serving: saturated ({cap['requests']} requests submitted at once): "
+        f"{cap['solves_per_s']:.1f} solves/s, p50 {cap['p50_ms']:.0f} ms, p99 {cap['p99_ms']:.0f} ms")
+    arr = wl.poisson_arrivals(args.qps, args.serve_requests)
+    poi = run(mix, arr)
+    poi["offered_qps"] = args.qps
+    log(f"serving: Poisson {args.qps:.0f} QPS ({poi['requests']} requests): "
+        f"{poi['solves_per_s']:.1f} solves/s, p50 {poi['p50_ms']:.1f} ms, p99 {poi['p99_ms']:.1f} ms")
+    half = 0.5 * cap["solves_per_s"]
+    nh = max(20, min(args.serve_requests // 2, int(half * 3)))
+    low = run(wl.serving_mix(nh, seed=13), wl.poisson_arrivals(half, nh, seed=14))
+    low["offered_qps"] = half
+    log(f"serving: Poisson {half:.0f} QPS (half the saturated rate, {nh} requests): "
+        f"{low['solves_per_s']:.1f} solves/s, p50 {low['p50_ms']:.1f} ms, p99 {low['p99_ms']:.1f} ms")
+    stt = srv.status()
+    srv.close()
+    return {"workers": args.serve_workers, "pool_GB": args.serve_pool_gb,
+            "mix": {k: w for k, w in wl.SERVING_TYPES}, "solo": solo,
+            "saturated": cap, f"poisson_{args.qps:.0f}qps": poi, "poisson_half_saturated": low,
+            "peak_inflight": stt["peak_inflight"],
+            "peak_pool_GB_in_flight": stt["peak_bytes_inflight"] / (1 << 30)}
 
 
 def cpu_baseline(coeffs, dims, degree, m_gpu):

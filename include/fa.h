@@ -326,6 +326,68 @@ int fa_dense_invsqrt_e1(int m, int dtype, const double* h_H, int ldh, double bet
 int fa_dense_tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double beta,
                                 double* z);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop of f(A)b solves with continuous admission.
+ *
+ * Requests (fa_apply arguments) are queued in arrival order.  The oldest
+ * request is admitted as soon as a worker is idle and the device pool has
+ * room for its workspace (fa_workspace_bytes(op, m_max, flags): the Krylov
+ * basis of m_max + 1 vectors of n entries plus scratch), so basis memory
+ * bounds the solves in flight.  Each worker owns a HIP stream (default
+ * priority); admitted solves run concurrently on the device and a finished
+ * solve frees its memory and worker at once, whatever step the others are
+ * at.  Operators and polynomials stay on the device between requests (the
+ * caller creates and sets them up once).  Results do not depend on what else
+ * runs (the kernels are deterministic): a solve gives the same bits alone
+ * and in the mix.
+ * ------------------------------------------------------------------------ */
+typedef struct fa_server_s* fa_server;
+
+typedef struct {
+  int32_t status;       /* fa_apply's return value                          */
+  int32_t worker;       /* index of the worker that ran it                  */
+  fa_stats stats;       /* fa_apply's statistics                            */
+  double t_submit_ms;   /* host steady clock at submit, admission, and end  */
+  double t_start_ms;
+  double t_done_ms;
+  size_t ws_bytes;      /* pool bytes the request held                      */
+} fa_request_info;
+
+typedef struct {
+  int32_t pending, inflight, peak_inflight;
+  uint64_t completed;
+  size_t pool_bytes, bytes_inflight, peak_bytes_inflight, largest_free;
+} fa_server_info;
+
+/* Create a server on the current device.  d_pool: device memory of
+ * pool_bytes (256-byte aligned), borrowed for the server's lifetime, from
+ * which request workspaces are carved.  n_workers (1..64): concurrent solves
+ * at most (HIP maps the streams onto the device's hardware queues).
+ * Errors: FA_ERR_ARG, FA_ERR_HIP. */
+int fa_server_create(fa_server* out, void* d_pool, size_t pool_bytes, int n_workers);
+
+/* Queue one solve (arguments as fa_apply; FA_PROFILE not allowed).  d_b and
+ * d_x must stay valid and untouched until the request is done; op must
+ * outlive it.  Returns at once with *ticket.  Errors: FA_ERR_ARG,
+ * FA_ERR_WORKSPACE (the workspace exceeds the whole pool). */
+int fa_server_submit(fa_server srv, fa_op op, int kind, const void* d_b, void* d_x, int m_max,
+                     double tol, int check_every, uint32_t flags, uint64_t* ticket);
+
+/* *done = 1 once the request finished (its x is complete on the device). */
+int fa_server_poll(fa_server srv, uint64_t ticket, int* done);
+
+/* Block until the request finished, fill *info (may be NULL), forget the
+ * ticket and return the request's fa_apply status.  One wait per ticket.
+ * FA_ERR_ARG for an unknown ticket. */
+int fa_server_wait(fa_server srv, uint64_t ticket, fa_request_info* info);
+
+/* Queue depth, solves in flight, completed count and pool occupancy. */
+int fa_server_status(fa_server srv, fa_server_info* info);
+
+/* Finish every queued request, stop the workers, destroy their streams.
+ * No fa_server_wait may be pending.  The pool stays the caller's. */
+int fa_server_destroy(fa_server srv);
+
 #ifdef __cplusplus
 }
 #endif

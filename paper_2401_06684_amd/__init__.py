@@ -22,7 +22,7 @@ from ._lib import (FA_C128, FA_F64, FA_FORCE_ARNOLDI, FA_HERMITIAN, FA_INVSQRT, 
                    FA_POLY_LS, FA_POLY_RITZ, FA_PROFILE, FA_RIGHT_PREC, FA_SQRT, FA_TWO_PASS, FAError,
                    check, lib)
 
-__all__ = ["Stencil7", "CSR", "Wilson", "FAError", "lib", "dense_invsqrt_e1",
+__all__ = ["Stencil7", "CSR", "Wilson", "Server", "FAError", "lib", "dense_invsqrt_e1",
            "dense_tridiag_invsqrt_e1"]
 
 _KIND = {"invsqrt": FA_INVSQRT, "sqrt": FA_SQRT}
@@ -268,6 +268,77 @@ class Wilson(Operator):
         check(st, "fa_create_stencil")
         super().__init__(h, dev, (U,))
         self.lattice = (Lt, Lz, Ly, Lx)
+
+
+class Server:
+    """Request loop of f(A)b solves with admission by workspace memory.
+
+    pool_bytes of device memory are carved into per-request workspaces (the
+    Krylov basis and scratch); up to n_workers solves run at once, each on its
+    own HIP stream.  submit() returns a ticket at once; wait(ticket) returns
+    (x, info) when the solve is done.
+    """
+
+    def __init__(self, pool_bytes, n_workers=4, device="cuda"):
+        self.device = torch.device(device)
+        self._pool, pp, nbytes = workspace(pool_bytes, self.device)
+        torch.cuda.synchronize(self.device)
+        h = C.c_void_p()
+        check(lib().fa_server_create(C.byref(h), pp, nbytes, int(n_workers)), "fa_server_create")
+        self._h = h
+        self._live = {}
+
+    def submit(self, op, b, kind="invsqrt", m_max=100, tol=1e-10, check_every=0, out=None,
+               force_arnoldi=False, fuse=True, mixed=False, two_pass=False, right=False):
+        """Queue one solve; b (and out) must stay untouched until it is done."""
+        b = op._vec(b, "b")
+        x = out if out is not None else torch.empty_like(b)
+        op._vec(x, "out")
+        flags = ((FA_FORCE_ARNOLDI if force_arnoldi else 0) | (0 if fuse else FA_NO_FUSION)
+                 | (FA_MIXED if mixed else 0) | (FA_TWO_PASS if two_pass else 0)
+                 | (FA_RIGHT_PREC if right else 0))
+        # b is produced on torch's stream; the server's streams do not wait for it
+        torch.cuda.current_stream(self.device).synchronize()
+        t = C.c_uint64()
+        check(lib().fa_server_submit(self._h, op._h, _KIND[kind], _ptr(b), _ptr(x), int(m_max),
+                                     float(tol), int(check_every), flags, C.byref(t)),
+              "fa_server_submit")
+        self._live[t.value] = (op, b, x)
+        return t.value
+
+    def poll(self, ticket):
+        d = C.c_int()
+        check(lib().fa_server_poll(self._h, ticket, C.byref(d)), "fa_server_poll")
+        return bool(d.value)
+
+    def wait(self, ticket, raise_errors=True):
+        """Block until the solve is done; returns (x, info dict)."""
+        info = _lib.fa_request_info()
+        st = lib().fa_server_wait(self._h, ticket, C.byref(info))
+        op, b, x = self._live.pop(ticket)
+        if raise_errors:
+            check(st, "fa_server_wait")
+        d = {"status": info.status, "worker": info.worker, "stats": info.stats.as_dict(),
+             "t_submit_ms": info.t_submit_ms, "t_start_ms": info.t_start_ms,
+             "t_done_ms": info.t_done_ms, "ws_bytes": info.ws_bytes}
+        return x, d
+
+    def status(self):
+        si = _lib.fa_server_info()
+        check(lib().fa_server_status(self._h, C.byref(si)), "fa_server_status")
+        return si.as_dict()
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().fa_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def dense_invsqrt_e1(H, beta):

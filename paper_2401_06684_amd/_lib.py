@@ -32,6 +32,8 @@ EXPORTS = [
     "fa_poly_get", "fa_poly_get_ls",
     "fa_workspace_bytes", "fa_apply", "fa_op_apply", "fa_poly_apply", "fa_op_info",
     "fa_destroy", "fa_status_string", "fa_dense_invsqrt_e1", "fa_dense_tridiag_invsqrt_e1",
+    "fa_server_create", "fa_server_submit", "fa_server_poll", "fa_server_wait",
+    "fa_server_status", "fa_server_destroy",
 ]
 
 
@@ -42,6 +44,25 @@ class fa_stats(C.Structure):
         ("inner_products", C.c_int64), ("est_rel_change", C.c_double), ("h_last", C.c_double),
         ("ms_total", C.c_double), ("ms_host_fH", C.c_double), ("ms_chain", C.c_double),
         ("n_chain", C.c_int64), ("chain_bytes", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class fa_request_info(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("worker", C.c_int32), ("stats", fa_stats),
+        ("t_submit_ms", C.c_double), ("t_start_ms", C.c_double), ("t_done_ms", C.c_double),
+        ("ws_bytes", C.c_size_t),
+    ]
+
+
+class fa_server_info(C.Structure):
+    _fields_ = [
+        ("pending", C.c_int32), ("inflight", C.c_int32), ("peak_inflight", C.c_int32),
+        ("completed", C.c_uint64), ("pool_bytes", C.c_size_t), ("bytes_inflight", C.c_size_t),
+        ("peak_bytes_inflight", C.c_size_t), ("largest_free", C.c_size_t),
     ]
 
     def as_dict(self):
@@ -88,6 +109,13 @@ def lib():
         "fa_status_string": (C.c_char_p, [i32]),
         "fa_dense_invsqrt_e1": (i32, [i32, i32, dp, i32, dbl, dp]),
         "fa_dense_tridiag_invsqrt_e1": (i32, [i32, dp, dp, dbl, dp]),
+        "fa_server_create": (i32, [C.POINTER(vp), vp, sz, i32]),
+        "fa_server_submit": (i32, [vp, vp, i32, vp, vp, i32, dbl, i32, u32,
+                                   C.POINTER(C.c_uint64)]),
+        "fa_server_poll": (i32, [vp, C.c_uint64, ip]),
+        "fa_server_wait": (i32, [vp, C.c_uint64, C.POINTER(fa_request_info)]),
+        "fa_server_status": (i32, [vp, C.POINTER(fa_server_info)]),
+        "fa_server_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

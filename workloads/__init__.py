@@ -265,3 +265,37 @@ CONFIGS = {
     "wilson4d_16": dict(kind="wilson4d", L=16, eps=0.3, m0=0.05, degrees=(0, 16),
                         tol=1e-8, f="invsqrt"),
 }
+
+
+# --------------------------------------------------------------------------
+# serving: a stream of requests (arrival times and request parameters only)
+# --------------------------------------------------------------------------
+SERVING_TYPES = (
+    # name, weight in the mix
+    ("laplace2d_256", 0.30),
+    ("convdiff3d_64", 0.25),
+    ("convdiff3d_96", 0.15),
+    ("convdiff3d_128", 0.10),
+    ("wilson4d_16", 0.20),
+)
+
+
+def poisson_arrivals(qps: float, count: int, seed: int = 11) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of rate qps:
+    cumulative sums of exponential gaps with mean 1/qps."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / qps, size=count))
+
+
+def serving_mix(count: int, seed: int = 12):
+    """Request parameters of the serving workload: operator type (by weight),
+    f in {sqrt, invsqrt} and tol in {1e-6, 1e-10}, each half and half, and the
+    seed of the request's right-hand side."""
+    rng = np.random.default_rng(seed)
+    names = [t[0] for t in SERVING_TYPES]
+    w = np.array([t[1] for t in SERVING_TYPES])
+    typ = rng.choice(len(names), size=count, p=w / w.sum())
+    kind = rng.integers(0, 2, size=count)
+    tol = rng.integers(0, 2, size=count)
+    return [dict(type=names[typ[i]], kind=("sqrt", "invsqrt")[kind[i]],
+                 tol=(1e-6, 1e-10)[tol[i]], seed=1000 + i) for i in range(count)]
