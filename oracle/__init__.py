@@ -21,6 +21,9 @@ It is written to be read against the paper, not to be fast:
                       Lanczos (Algorithms 1 and 2), the dense H^{-1/2} e_1 step,
                       the difference-of-iterates stopping rule (Sec. 3.1, Sec. 6)
                       and the square root through the inverse square root (Sec. 4);
+* ``block``        -- block Arnoldi for several right-hand sides sharing A (the
+                      block form of Algorithm 1; an extension, pinned against
+                      the single-vector method and closed forms);
 * ``exact``        -- exact references: DST closed forms for Laplace and
                       convection-diffusion, free-field and pure-gauge Wilson by
                       FFT, dense matrix functions for tiny n.
