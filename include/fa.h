@@ -327,6 +327,57 @@ int fa_dense_tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, 
                                 double* z);
 
 /* ------------------------------------------------------------------------
+ * Several right-hand sides sharing the operator: block Arnoldi.
+ *
+ * The block form of Algorithm 1 (an extension: the paper treats one
+ * right-hand side): C = q(A) B' = V_1 R_0 (B' = B, or A B for FA_SQRT);
+ * each step W = q(A) (q(A) (A V_j)) on the whole block (one stencil launch per
+ * recurrence term for all s columns), classical block Gram-Schmidt twice as
+ * FP64 matrix-core products (H(:, j) = [V_1..V_j]^T W summed over both
+ * passes), W = V_{j+1} H_{j+1,j} by Cholesky QR twice; every k steps
+ * Z_j = H_j^{-1/2} E_1 R_0 (coupled Newton-Schulz iteration on the device, FP64)
+ * and the per-column estimate ||Z_j e_c - [Z_{j-k} e_c; 0]|| / ||Z_j e_c||;
+ * stop when every column is <= tol; X = [V_1..V_m] Z_m.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t iters;       /* m: block steps                                     */
+  int32_t converged;   /* every column's estimate <= tol, or lucky breakdown  */
+  int32_t breakdown;   /* the new block vanished (invariant block space)      */
+  int32_t checks;
+  int32_t ns_iters;    /* Newton-Schulz iterations of the last H^{-1/2}       */
+  int32_t reserved;
+  int64_t mvms;        /* products of A with single vectors (s per block)    */
+  double est_max;      /* largest per-column estimate at the last check       */
+  double ms_total;
+  double ms_fH;        /* time in H^{-1/2} E_1 R_0 (device, incl. syncs)     */
+} fa_block_stats;
+
+/* Workspace of fa_block_apply: (m_max + 1) FP64 basis blocks of n x s, five
+ * chain blocks (FP32 with FA_MIXED), split-K partials, H ((m_max + 1) s x
+ * m_max s) and four (m_max s)^2 matrices for the Newton-Schulz iteration. */
+size_t fa_block_workspace_bytes(fa_op op, int s, int m_max, uint32_t flags);
+
+/*
+ * fa_block_apply -- X ~ A^{-1/2} B or A^{1/2} B for s right-hand sides.
+ *   op       : a real 7-point stencil (fa_create_stencil FA_STENCIL7) with a
+ *              Chebyshev q or q == 1; others: FA_ERR_UNSUPPORTED
+ *   s        : 16, 32 or 64
+ *   d_B, d_X : device, n x s FP64, ROW-MAJOR (entry (i, c) at i * s + c: the s
+ *              values of grid point i contiguous); d_X must not alias d_B
+ *   m_max    : maximal number of block steps; tol, check_every as fa_apply
+ *   flags    : FA_MIXED (the stencil chain in FP32 storage and arithmetic;
+ *              Gram-Schmidt, Cholesky QR, H^{-1/2} and X = V Z in FP64)
+ * Returns FA_OK, FA_WARN_NOT_CONVERGED, or FA_ERR_ARG, FA_ERR_NO_POLY,
+ * FA_ERR_WORKSPACE, FA_ERR_UNSUPPORTED, FA_ERR_HESSENBERG (a new block lost
+ * rank partially -- block Arnoldi without deflation cannot continue -- or the
+ * Newton-Schulz iteration did not converge), FA_ERR_NONFINITE, FA_ERR_HIP.
+ * Blocks the host at checks and at return.
+ */
+int fa_block_apply(fa_op op, int kind, int s, const void* d_B, void* d_X, int m_max, double tol,
+                   int check_every, void* d_workspace, size_t ws_bytes, uint32_t flags,
+                   void* hip_stream, fa_block_stats* stats);
+
+/* ------------------------------------------------------------------------
  * Serving: a request loop of f(A)b solves with continuous admission.
  *
  * Requests (fa_apply arguments) are queued in arrival order.  The oldest

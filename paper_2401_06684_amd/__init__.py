@@ -192,6 +192,38 @@ class Operator:
         d["status"] = st
         return x, d
 
+    def block_apply(self, B, kind="invsqrt", m_max=30, tol=1e-10, check_every=0, out=None,
+                    mixed=False, raise_not_converged=False):
+        """X ~ A^{-1/2} B or A^{1/2} B for the columns of B (n x s, s in
+        {16, 32, 64}, a contiguous row-major tensor) by block Arnoldi.
+        Returns (X, stats dict)."""
+        if not (isinstance(B, torch.Tensor) and B.is_cuda and B.dtype == torch.float64
+                and B.dim() == 2 and B.shape[0] == self.n and B.is_contiguous()):
+            raise ValueError(f"B must be a contiguous float64 CUDA tensor of shape ({self.n}, s)")
+        s = B.shape[1]
+        X = out if out is not None else torch.empty_like(B)
+        if X.shape != B.shape or not X.is_contiguous() or X.dtype != B.dtype:
+            raise ValueError("out must match B")
+        flags = FA_MIXED if mixed else 0
+        nbytes = lib().fa_block_workspace_bytes(self._h, s, m_max, flags)
+        if nbytes == 0:
+            raise ValueError("unsupported block size (s must be 16, 32 or 64)")
+        ws = self._ws.get("block")
+        if ws is None or ws[2] < nbytes:
+            self._ws.pop("block", None)
+            ws = workspace(nbytes, self.device)
+            self._ws["block"] = ws
+        stats = _lib.fa_block_stats()
+        st = lib().fa_block_apply(self._h, _KIND[kind], s, _ptr(B), _ptr(X), int(m_max),
+                                  float(tol), int(check_every), ws[1], ws[2], flags,
+                                  _stream(self.device), C.byref(stats))
+        check(st, "fa_block_apply")
+        if st == _lib.FA_WARN_NOT_CONVERGED and raise_not_converged:
+            raise FAError(st, "fa_block_apply")
+        d = stats.as_dict()
+        d["status"] = st
+        return X, d
+
     def op_apply(self, x, out=None):
         """y = A x (one operator application)."""
         x = self._vec(x, "x")

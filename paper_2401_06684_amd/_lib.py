@@ -32,6 +32,7 @@ EXPORTS = [
     "fa_poly_get", "fa_poly_get_ls",
     "fa_workspace_bytes", "fa_apply", "fa_op_apply", "fa_poly_apply", "fa_op_info",
     "fa_destroy", "fa_status_string", "fa_dense_invsqrt_e1", "fa_dense_tridiag_invsqrt_e1",
+    "fa_block_workspace_bytes", "fa_block_apply",
     "fa_server_create", "fa_server_submit", "fa_server_poll", "fa_server_wait",
     "fa_server_status", "fa_server_destroy",
 ]
@@ -48,6 +49,18 @@ class fa_stats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class fa_block_stats(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int32), ("converged", C.c_int32), ("breakdown", C.c_int32),
+        ("checks", C.c_int32), ("ns_iters", C.c_int32), ("reserved", C.c_int32),
+        ("mvms", C.c_int64), ("est_max", C.c_double), ("ms_total", C.c_double),
+        ("ms_fH", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class fa_request_info(C.Structure):
@@ -109,6 +122,9 @@ def lib():
         "fa_status_string": (C.c_char_p, [i32]),
         "fa_dense_invsqrt_e1": (i32, [i32, i32, dp, i32, dbl, dp]),
         "fa_dense_tridiag_invsqrt_e1": (i32, [i32, dp, dp, dbl, dp]),
+        "fa_block_workspace_bytes": (sz, [vp, i32, i32, u32]),
+        "fa_block_apply": (i32, [vp, i32, i32, vp, vp, i32, dbl, i32, vp, sz, u32, vp,
+                                 C.POINTER(fa_block_stats)]),
         "fa_server_create": (i32, [C.POINTER(vp), vp, sz, i32]),
         "fa_server_submit": (i32, [vp, vp, i32, vp, vp, i32, dbl, i32, u32,
                                    C.POINTER(C.c_uint64)]),

@@ -250,6 +250,25 @@ int fa_apply(fa_op op, int kind, const void* d_b, void* d_x, int m_max, double t
   });
 }
 
+size_t fa_block_workspace_bytes(fa_op op, int s, int m_max, uint32_t flags) {
+  if (!op || (s != 16 && s != 32 && s != 64) || m_max < 1) return 0;
+  return block_workspace_bytes(op->op, s, m_max, flags);
+}
+
+int fa_block_apply(fa_op op, int kind, int s, const void* d_B, void* d_X, int m_max, double tol,
+                   int check_every, void* d_workspace, size_t ws_bytes, uint32_t flags,
+                   void* hip_stream, fa_block_stats* stats) {
+  if (!op || !d_B || !d_X || d_B == d_X || (s != 16 && s != 32 && s != 64) || m_max < 1 ||
+      check_every < 0 || (kind != FA_INVSQRT && kind != FA_SQRT) || !(tol == tol) ||
+      (flags & ~uint32_t(FA_MIXED)))
+    return FA_ERR_ARG;
+  if (!op->op.poly_ready) return FA_ERR_NO_POLY;
+  return guarded([&] {
+    return block_apply(op->op, kind, s, d_B, d_X, m_max, tol, check_every, d_workspace, ws_bytes,
+                       flags, stream_of(hip_stream), stats);
+  });
+}
+
 int fa_op_apply(fa_op op, const void* d_x, void* d_y, void* hip_stream) {
   if (!op || !d_x || !d_y || d_x == d_y) return FA_ERR_ARG;
   return op_apply(op->op, d_x, d_y, stream_of(hip_stream));

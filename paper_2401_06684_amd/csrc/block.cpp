@@ -1,0 +1,375 @@
+// Block (several right-hand sides) form of Algorithm 1: s right-hand sides
+// sharing the operator run as one block Arnoldi process.
+//
+//   B' = B (or A B for the square root, Sec. 4);  C = q(A) B' = V_1 R_0
+//   for j = 1, 2, ...:
+//     W = q(A) (q(A) (A V_j))                     block stencil chain
+//     twice: P = [V_1..V_j]^T W, W -= [V_1..V_j] P   FP64 MFMA, H(:, j) += P
+//     W = V_{j+1} H_{j+1,j}                       CholQR2 (Gram matrix on MFMA,
+//                                                 Cholesky in one workgroup)
+//   every k steps: Z = H_j^{-1/2} E_1 R_0 by the coupled Newton-Schulz
+//   iteration on the device (dense FP64 MFMA products), per-column estimate
+//   ||Z_j e_c - [Z_{j-k} e_c; 0]|| / ||Z_j e_c||; stop when all <= tol
+//   X = [V_1..V_m] Z.
+//
+// Blocks are row-major n x s (the s values of a grid point contiguous), the
+// basis FP64; with FA_MIXED the stencil chain runs in FP32 storage with FP32
+// arithmetic and writes the FP64 block W, everything else stays FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fa_internal.hpp"
+#include "solver.hpp"
+
+namespace fa {
+
+namespace {
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr int kNsplitMax = 256;  // split-K chunks of the projections
+
+struct BlkLayout {
+  int64_t bstride = 0;  // elements per basis block (n * s rounded up)
+  int M = 0;            // m_max * s (the largest Hessenberg order)
+  int64_t ldh = 0;      // leading dimension of H (row-major)
+  size_t off_V = 0, off_C[5] = {0, 0, 0, 0, 0}, off_part = 0, off_H = 0, off_G = 0, off_R = 0,
+         off_Ri = 0, off_R0 = 0, off_Rt = 0, off_P2 = 0, off_NS[4] = {0, 0, 0, 0}, off_Zc = 0,
+         off_nrm = 0, off_flag = 0, off_rows = 0;
+  size_t bytes = 0;
+};
+
+BlkLayout blk_layout(const Op& op, int s, int m_max, bool mixed) {
+  BlkLayout L;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off += (size_t)round_up((int64_t)b, 256);
+    return o;
+  };
+  L.bstride = round_up(op.n * s, 32);
+  L.M = m_max * s;
+  L.ldh = L.M;
+  const size_t ce = mixed ? 4 : 8;
+  L.off_V = take((size_t)(m_max + 1) * L.bstride * 8);
+  for (int i = 0; i < 5; ++i) L.off_C[i] = take((size_t)L.bstride * ce);
+  L.off_part = take((size_t)kNsplitMax * (m_max + 1) * s * s * 8);
+  L.off_H = take((size_t)(L.M + s) * L.ldh * 8);
+  L.off_G = take((size_t)s * s * 8);
+  L.off_R = take((size_t)s * s * 8);
+  L.off_Ri = take((size_t)s * s * 8);
+  L.off_R0 = take((size_t)s * s * 8);
+  L.off_Rt = take((size_t)s * s * 8);
+  L.off_P2 = take((size_t)(L.M + s) * s * 8);
+  for (int i = 0; i < 4; ++i) L.off_NS[i] = take((size_t)L.M * L.M * 8);
+  L.off_Zc = take((size_t)L.M * s * 8);
+  L.off_nrm = take(8 * sizeof(double));
+  L.off_flag = take((size_t)(m_max + 2) * sizeof(int));
+  L.off_rows = take((size_t)2 * L.M * 8);
+  L.bytes = off;
+  return L;
+}
+
+char* at(void* ws, size_t off) { return (char*)ws + off; }
+
+#define BLK_HIP(x)                              \
+  do {                                          \
+    if ((x) != hipSuccess) return FA_ERR_HIP;   \
+  } while (0)
+
+// split-K chunk count: enough workgroups to fill the chip several times
+int nsplit_for(int64_t n, int nb) {
+  int ns = (int)std::min<int64_t>(kNsplitMax, std::max<int64_t>(8, 2048 / std::max(nb, 1)));
+  ns = (int)std::min<int64_t>(ns, std::max<int64_t>(1, n / 64));
+  return ns;
+}
+
+}  // namespace
+
+size_t block_workspace_bytes(const Op& op, int s, int m_max, uint32_t flags) {
+  return blk_layout(op, s, m_max, (flags & FA_MIXED) != 0).bytes;
+}
+
+int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m_max, double tol,
+                int check_every, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t st,
+                fa_block_stats* stats) {
+  const double t0 = now_ms();
+  fa_block_stats S;
+  std::memset(&S, 0, sizeof(S));
+  if (op.kind != OP_STENCIL7 || op.dtype != FA_F64) return FA_ERR_UNSUPPORTED;
+  const Poly& q = op.poly;
+  const int K = (q.method < 0) ? 0 : q.degree;
+  if (K > 0 && q.method != FA_POLY_CHEB) return FA_ERR_UNSUPPORTED;
+  const bool mixed = (flags & FA_MIXED) && K > 0;
+  const BlkLayout L = blk_layout(op, s, m_max, (flags & FA_MIXED) != 0);
+  if (!ws || ws_bytes < L.bytes || ((uintptr_t)ws & 255)) return FA_ERR_WORKSPACE;
+  const int k_chk = check_every > 0 ? check_every : std::max(1, 64 / (K + 1));
+  const Prec pc = mixed ? P32 : P64;
+  const int64_t n = op.n;
+
+  double* V = (double*)at(ws, L.off_V);
+  auto Vb = [&](int j) { return V + (size_t)j * L.bstride; };
+  void* C[5];
+  for (int i = 0; i < 5; ++i) C[i] = at(ws, L.off_C[i]);
+  double* part = (double*)at(ws, L.off_part);
+  double* H = (double*)at(ws, L.off_H);
+  double* G = (double*)at(ws, L.off_G);
+  double* R = (double*)at(ws, L.off_R);
+  double* Ri = (double*)at(ws, L.off_Ri);
+  double* R0 = (double*)at(ws, L.off_R0);
+  double* Rt = (double*)at(ws, L.off_Rt);
+  double* P2 = (double*)at(ws, L.off_P2);
+  double* NS[4];
+  for (int i = 0; i < 4; ++i) NS[i] = (double*)at(ws, L.off_NS[i]);
+  double* Zc = (double*)at(ws, L.off_Zc);
+  double* nrm = (double*)at(ws, L.off_nrm);
+  int* flag = (int*)at(ws, L.off_flag);
+  double* rowsc = (double*)at(ws, L.off_rows);
+  int64_t mvms = 0;
+
+  // H and the per-step flags start at zero (the projections add into H)
+  BLK_HIP(hipMemsetAsync(H, 0, (size_t)(L.M + s) * L.ldh * 8, st));
+  BLK_HIP(hipMemsetAsync(flag, 0, (size_t)(m_max + 2) * sizeof(int), st));
+
+  // q(A) applied to a block: x (precision px) -> out (precision pout) using
+  // the chain scratch blocks `tmp` (two of them); returns the buffer that
+  // holds the result.  Single term per launch; out_i may overwrite out_{i-2}.
+  const std::vector<Term> T = K > 0 ? poly_terms(q) : std::vector<Term>();
+  auto qblock = [&](const void* x, Prec px, void* out, Prec pout, void* tA, void* tB) -> int {
+    const int nT = (int)T.size();
+    const void* xm1 = x;
+    const void* xm2 = nullptr;
+    Prec pm1 = px;
+    void* slot[2] = {tA, tB};
+    for (int i = 0; i < nT; ++i) {
+      const bool last = i == nT - 1;
+      void* dst = last ? out : ((i >= 2 && T[i].y1) ? (void*)xm2 : slot[i & 1]);
+      if (dst == xm1) dst = slot[(i + 1) & 1];
+      const Prec po = last ? pout : pc;
+      // the first term reads x (precision px); later terms read the chain
+      // precision, and y0 = x must then be in the chain precision too
+      BLK_HIP(launch_blk_chain(op, s, xm1, T[i].y0 ? x : nullptr, T[i].y1 ? xm2 : nullptr, dst,
+                               T[i].k, pm1, px, po, st));
+      xm2 = xm1;
+      xm1 = dst;
+      pm1 = po;
+    }
+    mvms += (int64_t)K * s;
+    return FA_OK;
+  };
+
+  // CholQR2 of the block W in place; H_sub (ldsub) = R2 R1
+  auto cholqr2 = [&](double* W, double* Hsub, int64_t ldsub, int step) -> int {
+    const int nsp = nsplit_for(n, 1);
+    for (int pass = 0; pass < 2; ++pass) {
+      BLK_HIP(launch_blk_proj(n, s, 1, W, 0, W, part, nsp, G, s, false, st));
+      BLK_HIP(launch_chol(s, G, pass == 0 ? Rt : R, Ri, flag + step, st));
+      BLK_HIP(launch_gemm(n, s, s, 1.0, W, 0, s, s, Ri, s, 0.0, W, s, st));
+    }
+    // Hsub = R (second) * Rt (first)
+    BLK_HIP(launch_gemm(s, s, s, 1.0, R, 0, s, s, Rt, s, 0.0, Hsub, ldsub, st));
+    return FA_OK;
+  };
+
+  // Z = H_m^{-1/2} E_1 R_0 on the device (coupled Newton-Schulz), m blocks
+  auto invsqrt_E1R = [&](int m, int* iters) -> int {
+    const int Mm = m * s;
+    double hn[2] = {0.0, 0.0};
+    BLK_HIP(launch_mat_norms(Mm, H, L.ldh, nrm, rowsc, st));
+    BLK_HIP(hipMemcpyAsync(hn, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    BLK_HIP(hipStreamSynchronize(st));
+    const double c = hn[0];
+    if (!(c > 0.0) || !std::isfinite(c)) return FA_ERR_NONFINITE;
+    double *Y = NS[0], *Z = NS[1], *Tm = NS[2], *Tmp = NS[3];
+    BLK_HIP(launch_scale_mat(Mm, Mm, 1.0 / c, H, L.ldh, Y, Mm, st));
+    BLK_HIP(launch_set_diag(Mm, Mm, 1.0, Z, Mm, st));
+    int it = 0;
+    double prev = 1e300;
+    for (;; ++it) {
+      // T = (3 I - Z Y) / 2
+      BLK_HIP(launch_set_diag(Mm, Mm, 1.5, Tm, Mm, st));
+      BLK_HIP(launch_gemm(Mm, Mm, Mm, -0.5, Z, 0, Mm, Mm, Y, Mm, 1.0, Tm, Mm, st));
+      BLK_HIP(launch_mat_norms(Mm, Tm, Mm, nrm, rowsc, st));
+      BLK_HIP(hipMemcpyAsync(hn, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      BLK_HIP(hipStreamSynchronize(st));
+      const double dev = hn[1];  // max |T - I|
+      if (!std::isfinite(dev) || it > 200 || (it > 20 && dev > 4.0 * prev))
+        return FA_ERR_HESSENBERG;  // no convergence
+      prev = dev;
+      if (dev == 0.0) break;
+      // Y <- Y T, Z <- T Z
+      BLK_HIP(launch_gemm(Mm, Mm, Mm, 1.0, Y, 0, Mm, Mm, Tm, Mm, 0.0, Tmp, Mm, st));
+      std::swap(Y, Tmp);
+      BLK_HIP(launch_gemm(Mm, Mm, Mm, 1.0, Tm, 0, Mm, Mm, Z, Mm, 0.0, Tmp, Mm, st));
+      std::swap(Z, Tmp);
+      if (dev < 1e-14) {
+        ++it;
+        break;
+      }
+    }
+    *iters = it;
+    // Zc = (Z / sqrt(c))[:, 0:s] R_0
+    BLK_HIP(launch_gemm(Mm, s, s, 1.0 / std::sqrt(c), Z, 0, Mm, s, R0, s, 0.0, Zc, s, st));
+    return FA_OK;
+  };
+
+  // ---- start block -------------------------------------------------------
+  const double* Bp = (const double*)d_B;
+  if (kind == FA_SQRT) {  // B' = A B into the slot of V_2 (free until step 1)
+    BLK_HIP(launch_blk_chain(op, s, d_B, nullptr, nullptr, Vb(1), ChainCoef{1.0, 0.0, 0.0, 0.0},
+                             P64, P64, P64, st));
+    mvms += s;
+    Bp = Vb(1);
+  }
+  if (K == 0) {
+    BLK_HIP(hipMemcpyAsync(Vb(0), Bp, (size_t)n * s * 8, hipMemcpyDeviceToDevice, st));
+  } else if (mixed) {
+    BLK_HIP(launch_blk_to_f32(n * s, Bp, (float*)C[4], st));
+    int r = qblock(C[4], P32, Vb(0), P64, C[0], C[1]);
+    if (r) return r;
+  } else {
+    int r = qblock(Bp, P64, Vb(0), P64, C[0], C[1]);
+    if (r) return r;
+  }
+  {
+    int r = cholqr2(Vb(0), R0, s, m_max + 1);
+    if (r) return r;
+  }
+
+  // ---- block Arnoldi loop --------------------------------------------------
+  std::vector<double> Hh;      // host copy of H columns (row-major, ldh), for checks
+  std::vector<double> zprev, zcur((size_t)L.M * s);
+  int m = m_max;
+  bool converged = false, breakdown = false;
+  double colmax = 0.0, est_max = 1.0;
+  int ns_iters = 0;
+  for (int j = 0; j < m_max; ++j) {
+    double* W = Vb(j + 1);
+    if (K == 0) {
+      BLK_HIP(launch_blk_chain(op, s, Vb(j), nullptr, nullptr, W, ChainCoef{1.0, 0.0, 0.0, 0.0},
+                               P64, P64, P64, st));
+      mvms += s;
+    } else {
+      // U = A V_j (chain precision), then q twice, the last launch writes FP64 W
+      BLK_HIP(launch_blk_chain(op, s, Vb(j), nullptr, nullptr, C[0],
+                               ChainCoef{1.0, 0.0, 0.0, 0.0}, P64, P64, pc, st));
+      mvms += s;
+      int r = qblock(C[0], pc, C[1], pc, C[2], C[3]);
+      if (r) return r;
+      // q's result sits in C[1] unless the rotation moved it (single-term
+      // launches write `out` directly, so it is C[1])
+      r = qblock(C[1], pc, W, P64, C[2], C[3]);
+      if (r) return r;
+    }
+    // block CGS2: H(0:(j+1)s, js:(j+1)s) = P1 + P2
+    const int nb = j + 1;
+    const int nsp = nsplit_for(n, nb);
+    double* Hcol = H + (size_t)j * s;
+    BLK_HIP(launch_blk_proj(n, s, nb, V, L.bstride, W, part, nsp, Hcol, (int)L.ldh, false, st));
+    BLK_HIP(launch_gemm(n, s, nb * s, -1.0, V, L.bstride, s, s, Hcol, L.ldh, 1.0, W, s, st));
+    BLK_HIP(launch_blk_proj(n, s, nb, V, L.bstride, W, part, nsp, P2, s, false, st));
+    BLK_HIP(launch_gemm(n, s, nb * s, -1.0, V, L.bstride, s, s, P2, s, 1.0, W, s, st));
+    BLK_HIP(launch_add_mat(nb * s, s, P2, s, Hcol, L.ldh, st));
+    // W = V_{j+1} H_{j+1,j}
+    {
+      int r = cholqr2(W, H + (size_t)(j + 1) * s * L.ldh + (size_t)j * s, L.ldh, j);
+      if (r) return r;
+    }
+    const int jj = j + 1;
+    const bool check = (tol > 0.0) ? (jj % k_chk == 0 || jj == m_max) : (jj == m_max);
+    if (!check) continue;
+    // breakdown scan on the host copy of the new columns and the flags
+    const int rows = (jj + 1) * s;
+    Hh.assign((size_t)rows * L.ldh, 0.0);
+    std::vector<int> fl(m_max + 2, 0);
+    BLK_HIP(hipMemcpyAsync(Hh.data(), H, (size_t)rows * L.ldh * 8, hipMemcpyDeviceToHost, st));
+    BLK_HIP(hipMemcpyAsync(fl.data(), flag, (size_t)(m_max + 2) * sizeof(int),
+                           hipMemcpyDeviceToHost, st));
+    BLK_HIP(hipStreamSynchronize(st));
+    if (fl[m_max + 1]) return FA_ERR_HESSENBERG;  // rank-deficient start block
+    int mb = -1;
+    for (int c = 0; c < jj && mb < 0; ++c) {
+      for (int b = 0; b < s; ++b) {
+        double cn = 0.0;
+        for (int r = 0; r < (c + 2) * s; ++r) {
+          const double v = Hh[(size_t)r * L.ldh + c * s + b];
+          if (!std::isfinite(v)) return FA_ERR_NONFINITE;
+          cn += v * v;
+        }
+        colmax = std::max(colmax, std::sqrt(cn));
+      }
+      int small = 0;
+      for (int b = 0; b < s; ++b)
+        if (std::fabs(Hh[(size_t)((c + 1) * s + b) * L.ldh + c * s + b]) <= 1e-12 * colmax) ++small;
+      if (small == s) {
+        mb = c + 1;  // the block Krylov space is invariant
+      } else if (small > 0 || fl[c]) {
+        return FA_ERR_HESSENBERG;  // partial rank loss: would need deflation
+      }
+    }
+    if (mb > 0) {
+      m = mb;
+      breakdown = converged = true;
+      break;
+    }
+    if (tol <= 0.0) break;
+    const double th = now_ms();
+    int it = 0;
+    int r = invsqrt_E1R(jj, &it);
+    if (r) return r;
+    ns_iters = it;
+    ++S.checks;
+    BLK_HIP(hipMemcpyAsync(zcur.data(), Zc, (size_t)jj * s * s * 8, hipMemcpyDeviceToHost, st));
+    BLK_HIP(hipStreamSynchronize(st));
+    S.ms_fH += now_ms() - th;
+    // per-column relative change of the coefficient block
+    est_max = 0.0;
+    for (int b = 0; b < s; ++b) {
+      double dn = 0.0, zn = 0.0;
+      for (int i = 0; i < jj * s; ++i) {
+        const double z = zcur[(size_t)i * s + b];
+        const double zp = (i < (int)(zprev.size() / s)) ? zprev[(size_t)i * s + b] : 0.0;
+        dn += (z - zp) * (z - zp);
+        zn += z * z;
+      }
+      est_max = std::max(est_max, std::sqrt(dn / zn));
+    }
+    zprev.assign(zcur.begin(), zcur.begin() + (size_t)jj * s * s);
+    if (est_max <= tol) {
+      m = jj;
+      converged = true;
+      break;
+    }
+  }
+  // final coefficients unless the loop ended on a fresh check of size m
+  if ((int)(zprev.size() / s) != m * s || breakdown) {
+    const double th = now_ms();
+    int it = 0;
+    int r = invsqrt_E1R(m, &it);
+    if (r) return r;
+    ns_iters = it;
+    S.ms_fH += now_ms() - th;
+  }
+  // X = [V_1 .. V_m] Z
+  BLK_HIP(launch_gemm(n, s, m * s, 1.0, V, L.bstride, s, s, Zc, s, 0.0, (double*)d_X, s, st));
+  BLK_HIP(hipStreamSynchronize(st));
+  S.iters = m;
+  S.converged = converged ? 1 : 0;
+  S.breakdown = breakdown ? 1 : 0;
+  S.ns_iters = ns_iters;
+  S.mvms = mvms;
+  S.est_max = est_max;
+  S.ms_total = now_ms() - t0;
+  if (stats) *stats = S;
+  return converged ? FA_OK : FA_WARN_NOT_CONVERGED;
+}
+
+}  // namespace fa

@@ -51,6 +51,17 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Workgroup index remap for the 8 XCDs of the chip: the hardware hands
+// consecutive workgroups to the XCDs in turn, so logical tile
+// xcd_contiguous(b) gives each XCD one contiguous range of tiles (neighbouring
+// tiles share halos in that XCD's L2).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_contiguous(int bid, int nwg) {
+  const int per = nwg / kXcds, rem = nwg % kXcds;
+  const int xcd = bid % kXcds, k = bid / kXcds;
+  return (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+}
+
 template <typename T> struct host_to_dev;
 template <> struct host_to_dev<double> {
   static double conv(const cd& z) { return z.real(); }

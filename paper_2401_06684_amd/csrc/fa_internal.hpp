@@ -135,6 +135,37 @@ struct LsCoef {
 hipError_t launch_ls_step(int dtype, int64_t n, int k, void* W, int64_t ldv, const LsCoef& g,
                           bool keep, void* out, hipStream_t s);
 
+// ---- block (several right-hand sides) kernels, row-major n x s blocks ----
+// one recurrence term on a block, 7-point stencil; s in {16, 32, 64}; storage
+// of x (px), y0/y1 (py) and out (po): all FP64, all FP32, FP64 x -> FP32 out
+// (no y), or FP32 x, y -> FP64 out
+hipError_t launch_blk_chain(const Op& op, int s, const void* x, const void* y0, const void* y1,
+                            void* out, const ChainCoef& k, Prec px, Prec py, Prec po,
+                            hipStream_t st);
+hipError_t launch_blk_to_f32(int64_t count, const double* x, float* y, hipStream_t st);
+// P (row i*s + a, column b; leading dimension ldp) = (or +=) V_i^T W, i < nb,
+// V_i = V + i * v_blk; split-K over nsplit chunks of rows (part holds
+// nsplit * nb * s * s doubles)
+hipError_t launch_blk_proj(int64_t n, int s, int nb, const double* V, int64_t v_blk,
+                           const double* W, double* part, int nsplit, double* P, int ldp, bool acc,
+                           hipStream_t st);
+// C = alpha A B + beta C; A (r, k) at A[(k / kb) * a_blk + r * lda + k % kb]
+hipError_t launch_gemm(int64_t M, int N, int K, double alpha, const double* A, int64_t a_blk,
+                       int64_t lda, int kb, const double* B, int64_t ldb, double beta, double* C,
+                       int64_t ldc, hipStream_t st);
+// Cholesky G = R^T R and R^{-1} (s <= 64, row-major); *flag = 1 if G is not PD
+hipError_t launch_chol(int s, const double* G, double* R, double* Rinv, int* flag,
+                       hipStream_t st);
+hipError_t launch_set_diag(int M, int N, double d, double* C, int64_t ldc, hipStream_t st);
+hipError_t launch_scale_mat(int M, int N, double a, const double* X, int64_t ldx, double* Y,
+                            int64_t ldy, hipStream_t st);
+hipError_t launch_add_mat(int M, int N, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                          hipStream_t st);
+// out[0] = max row sum of |X|, out[1] = max |X - I| (X square M x M);
+// scratch holds 2 M doubles
+hipError_t launch_mat_norms(int M, const double* X, int64_t ldx, double* out, double* scratch,
+                            hipStream_t st);
+
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline size_t elem_size(int dtype) { return dtype == FA_C128 ? 16 : 8; }
 

@@ -33,13 +33,6 @@ struct St7 {
 };
 
 constexpr int ST_TX = 64, ST_TY = 4;
-constexpr int kXcds = 8;
-
-__device__ __forceinline__ int xcd_contiguous(int bid, int nwg) {
-  const int per = nwg / kXcds, rem = nwg % kXcds;
-  const int xcd = bid % kXcds, k = bid / kXcds;
-  return (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
-}
 
 // Storage types: TX for every input vector (x, y0, y1), TO for the output.
 // Arithmetic is FP64 when both are double and FP32 otherwise (the mixed

@@ -131,20 +131,13 @@ int op_apply(const Op& op, const void* x, void* y, hipStream_t s) {
   return chain(op, x, nullptr, nullptr, y, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, nullptr);
 }
 
-// One term of a polynomial recurrence: out_i = alpha A x_i + beta x_i + g0 v
-// + g1 out_{i-2}, where x_i = out_{i-1} (x_0 = v, the vector q(A) acts on).
-struct Term {
-  ChainCoef k;
-  bool y0, y1;
-};
-
 // The terms of q(A) v (K products with A):
 //   Chebyshev, Clenshaw (Sec. 5.1) with Ahat = sig A + tau I,
 //     b_k = c_k v + 2 Ahat b_{k+1} - b_{k+2},  q(A) v = c_0 v + Ahat b_1 - b_2;
 //     b_K = c_K v and b_{K+1} = 0 are folded into the first two terms.
 //   Newton form on Leja points, Horner-type recurrence (Sec. 5.2),
 //     r_K = eta_K v,  r_j = (A - theta_j) r_{j+1} / rho + eta_j v.
-static std::vector<Term> poly_terms(const Poly& q) {
+std::vector<Term> poly_terms(const Poly& q) {
   std::vector<Term> T;
   const int K = q.degree;
   if (q.method == FA_POLY_CHEB) {

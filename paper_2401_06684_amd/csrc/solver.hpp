@@ -1,5 +1,7 @@
 // Host runtime entry points used by the C ABI layer.
 #pragma once
+#include <vector>
+
 #include "fa_internal.hpp"
 
 namespace fa {
@@ -18,6 +20,15 @@ struct Layout {
 // with_poly: include the storage the op's polynomial needs (least squares)
 Layout make_layout(const Op& op, int m_max, uint32_t flags, bool with_poly = true);
 
+// One term of a polynomial recurrence: out_i = alpha A x_i + beta x_i + g0 v
+// + g1 out_{i-2}, where x_i = out_{i-1} (x_0 = v, the vector q(A) acts on).
+struct Term {
+  ChainCoef k;
+  bool y0, y1;
+};
+// the terms of q(A) v for a Chebyshev or (complex) Newton-form q (K terms)
+std::vector<Term> poly_terms(const Poly& q);
+
 int op_apply(const Op& op, const void* x, void* y, hipStream_t s);
 int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_t s);
 int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double tol,
@@ -30,6 +41,10 @@ struct LsParams {
   double r_min = 0.1;
   double step = 0.005;
 };
+size_t block_workspace_bytes(const Op& op, int s, int m_max, uint32_t flags);
+int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m_max, double tol,
+                int check_every, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t st,
+                fa_block_stats* stats);
 size_t poly_workspace_bytes(const Op& op, int degree, int method);
 int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, size_t ws_bytes,
                hipStream_t s, int64_t* mvms_setup, const LsParams& ls = LsParams());

@@ -1,0 +1,155 @@
+"""Block Arnoldi for several right-hand sides (fa_block_apply) against the
+block oracle, the single-vector oracle and the DST closed forms.
+
+Tolerances: FP64 mode 1e-10 relative per column (fixed m and at convergence);
+mixed mode (FP32 stencil chain) 1e-6 per column against the FP64 reference."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import block as bk, exact, krylov as kr, operators as ops, polynomials as pl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2401_06684_amd as fa
+    fa.lib()
+
+
+def fa():
+    import paper_2401_06684_amd as m
+    return m
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def col_err(X, R):
+    return np.linalg.norm(X - R, axis=0) / np.linalg.norm(R, axis=0)
+
+
+def _problem(dims, pe, s, seed0=0):
+    coeffs = wl.convdiff_stencil(max(dims), pe)
+    n = int(np.prod(dims))
+    B = np.stack([wl.rhs(n, seed=seed0 + c) for c in range(s)], 1)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    a, b = ops.stencil_interval(coeffs, dims)
+    return coeffs, B, A, a, b
+
+
+@pytest.mark.parametrize("degree,m", [(0, 6), (4, 4), (9, 3)])
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+def test_block_fixed_m_against_block_oracle(degree, m, kind):
+    dims = (13, 11, 9)
+    coeffs, B, A, a, b = _problem(dims, 50.0, 16)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(degree, "cheb")
+    X, st = op.block_apply(dev(B), kind=kind, m_max=m, tol=0.0)
+    ref = bk.block_fAB(A, B, pl.chebyshev(a, b, degree), kind, m_max=m, tol=0.0)
+    assert st["iters"] == ref.iters == m and st["mvms"] == ref.mvms
+    assert np.max(col_err(host(X), ref.X)) < 1e-10
+
+
+@pytest.mark.parametrize("s", [16, 32, 64])
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+def test_block_converged_against_closed_form(s, kind):
+    dims = (16, 15, 14)
+    coeffs, B, A, a, b = _problem(dims, 20.0, s, seed0=s)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(8, "cheb")
+    X, st = op.block_apply(dev(B), kind=kind, m_max=40, tol=1e-11)
+    assert st["converged"] == 1 and st["est_max"] <= 1e-11
+    Xh = host(X)
+    ref = np.stack([exact.stencil_fAb_dst(coeffs, dims, B[:, c], kind) for c in range(s)], 1)
+    assert np.max(col_err(Xh, ref)) < 1e-9
+    if s <= 32:  # the block oracle takes ~10 s of CPU at s = 64
+        orc = bk.block_fAB(A, B, pl.chebyshev(a, b, 8), kind, m_max=40, tol=1e-11)
+        assert st["iters"] == orc.iters
+        assert np.max(col_err(Xh, orc.X)) < 1e-10
+
+
+@pytest.mark.parametrize("degree", [4, 16])
+def test_block_mixed_precision_per_column(degree):
+    dims = (18, 17, 16)
+    coeffs, B, A, a, b = _problem(dims, 50.0, 32, seed0=7)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(degree, "cheb")
+    X, st = op.block_apply(dev(B), m_max=60, tol=1e-7, mixed=True)
+    assert st["converged"] == 1
+    ref = np.stack([exact.stencil_fAb_dst(coeffs, dims, B[:, c]) for c in range(32)], 1)
+    err = col_err(host(X), ref)
+    assert np.max(err) <= 1e-6, np.max(err)
+
+
+def test_block_96cubed_64_rhs_mixed_full_size():
+    """The batched configuration: 96^3 conv-diff (Pe = 50), 64 right-hand
+    sides N(0, 1), degree 16, FP32 chain, tol 1e-7.  Per column: error
+    against the FP64 oracle (columns 0 and 63, single-vector, tol 1e-10)
+    <= 1e-6, and against the FP64 single-vector GPU solve of every column
+    <= 1e-6.  (The DST closed form is no reference at this size: the
+    diagonal similarity of the upwind operator spans ~16 orders of
+    magnitude.)"""
+    N = 96
+    dims = (N, N, N)
+    coeffs = wl.convdiff_stencil(N, 50.0)
+    n = N ** 3
+    B = np.stack([wl.rhs(n, seed=c) for c in range(64)], 1)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(16, "cheb")
+    Bd = dev(B)
+    X, st = op.block_apply(Bd, m_max=30, tol=1e-7, mixed=True)
+    assert st["converged"] == 1
+    errs = []
+    for c in range(64):
+        xc, sc = op.apply(Bd[:, c].contiguous(), m_max=100, tol=1e-10)
+        assert sc["converged"]
+        errs.append(float(torch.linalg.vector_norm(X[:, c] - xc) / torch.linalg.vector_norm(xc)))
+    assert max(errs) <= 1e-6, max(errs)
+    Xh = host(X)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    a, b = ops.stencil_interval(coeffs, dims)
+    q = pl.chebyshev(a, b, 16)
+    for c in (0, 63):
+        orc = kr.fAb(A, B[:, c], q, "invsqrt", m_max=100, tol=1e-10)
+        e = np.linalg.norm(Xh[:, c] - orc.x) / np.linalg.norm(orc.x)
+        assert e <= 1e-6, (c, e)
+    op.release_workspace()
+
+
+def test_block_errors():
+    m = fa()
+    dims = (8, 8, 8)
+    coeffs = wl.convdiff_stencil(8, 10.0)
+    op = m.Stencil7(dims, coeffs)
+    op.poly_setup(4, "cheb")
+    B = dev(np.stack([wl.rhs(512, seed=c) for c in range(16)], 1))
+    with pytest.raises(ValueError):
+        op.block_apply(dev(np.zeros((512, 48))))
+    # two equal columns: the start block has rank 15
+    Bd = B.clone()
+    Bd[:, 5] = Bd[:, 3]
+    with pytest.raises(m.FAError) as e:
+        op.block_apply(Bd, m_max=10, tol=1e-10)
+    assert e.value.status == m._lib.FA_ERR_HESSENBERG
+    U = wl.su3_links(4, eps=0.3, seed=1)
+    wil = m.Wilson(U, 0.05)
+    wil.poly_setup(0)
+    with pytest.raises(m.FAError) as e:
+        wil.block_apply(dev(np.zeros((wil.n, 16))))
+    assert e.value.status == m._lib.FA_ERR_UNSUPPORTED
+    rp = m.Stencil7(dims, coeffs)
+    rp.poly_setup(4, "ritz", start=dev(wl.rhs(512, seed=9)))
+    with pytest.raises(m.FAError) as e:
+        rp.block_apply(B)
+    assert e.value.status == m._lib.FA_ERR_UNSUPPORTED
