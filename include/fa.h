@@ -345,11 +345,12 @@ typedef struct {
   int32_t breakdown;   /* the new block vanished (invariant block space)      */
   int32_t checks;
   int32_t ns_iters;    /* Newton-Schulz iterations of the last H^{-1/2}       */
-  int32_t reserved;
+  int32_t zc;          /* z-planes per workgroup of the stencil (autotuned)   */
   int64_t mvms;        /* products of A with single vectors (s per block)    */
   double est_max;      /* largest per-column estimate at the last check       */
   double ms_total;
   double ms_fH;        /* time in H^{-1/2} E_1 R_0 (device, incl. syncs)     */
+  double ms_tune;      /* autotuning in this call (first use of a shape)     */
 } fa_block_stats;
 
 /* Workspace of fa_block_apply: (m_max + 1) FP64 basis blocks of n x s, five
@@ -367,6 +368,10 @@ size_t fa_block_workspace_bytes(fa_op op, int s, int m_max, uint32_t flags);
  *   m_max    : maximal number of block steps; tol, check_every as fa_apply
  *   flags    : FA_MIXED (the stencil chain in FP32 storage and arithmetic;
  *              Gram-Schmidt, Cholesky QR, H^{-1/2} and X = V Z in FP64)
+ * d_B and d_X must be 32-byte aligned.  Launch parameters (the split-K chunk
+ * count of the projections per basis size, the z-march length of the
+ * stencil) are autotuned at the first use of a problem shape in the process
+ * (timed on hip_stream, then cached).
  * Returns FA_OK, FA_WARN_NOT_CONVERGED, or FA_ERR_ARG, FA_ERR_NO_POLY,
  * FA_ERR_WORKSPACE, FA_ERR_UNSUPPORTED, FA_ERR_HESSENBERG (a new block lost
  * rank partially -- block Arnoldi without deflation cannot continue -- or the

@@ -54,13 +54,13 @@ class fa_stats(C.Structure):
 class fa_block_stats(C.Structure):
     _fields_ = [
         ("iters", C.c_int32), ("converged", C.c_int32), ("breakdown", C.c_int32),
-        ("checks", C.c_int32), ("ns_iters", C.c_int32), ("reserved", C.c_int32),
+        ("checks", C.c_int32), ("ns_iters", C.c_int32), ("zc", C.c_int32),
         ("mvms", C.c_int64), ("est_max", C.c_double), ("ms_total", C.c_double),
-        ("ms_fH", C.c_double),
+        ("ms_fH", C.c_double), ("ms_tune", C.c_double),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class fa_request_info(C.Structure):

@@ -21,6 +21,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "fa_internal.hpp"
@@ -85,11 +87,66 @@ char* at(void* ws, size_t off) { return (char*)ws + off; }
     if ((x) != hipSuccess) return FA_ERR_HIP;   \
   } while (0)
 
-// split-K chunk count: enough workgroups to fill the chip several times
-int nsplit_for(int64_t n, int nb) {
-  int ns = (int)std::min<int64_t>(kNsplitMax, std::max<int64_t>(8, 2048 / std::max(nb, 1)));
-  ns = (int)std::min<int64_t>(ns, std::max<int64_t>(1, n / 64));
-  return ns;
+// Autotuner.  A launch parameter with several candidates is timed on the
+// caller's stream the first time its problem shape occurs in the process
+// (one warm-up and one timed run per candidate, HIP events); the fastest is
+// kept for every later launch of that shape, and run once more so that the
+// results of the current call are the chosen candidate's.  Only launches
+// that may be repeated without changing their result are tuned.
+struct Tuner {
+  std::mutex mu;
+  std::map<std::vector<int64_t>, int> best;
+};
+Tuner& tuner() {
+  static Tuner t;
+  return t;
+}
+
+template <class F>
+int tune_pick(const std::vector<int64_t>& key, const std::vector<int>& cands, hipStream_t st,
+              F&& run, int* chosen, double* ms_tune) {
+  {
+    std::lock_guard<std::mutex> g(tuner().mu);
+    auto it = tuner().best.find(key);
+    if (it != tuner().best.end()) {
+      *chosen = it->second;
+      BLK_HIP(run(*chosen));
+      return FA_OK;
+    }
+  }
+  const double t0 = now_ms();
+  hipEvent_t a, b;
+  BLK_HIP(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return FA_ERR_HIP;
+  }
+  float best_ms = 1e30f;
+  int best_c = cands[0];
+  int st_code = FA_OK;
+  for (int c : cands) {
+    float ms = 0.0f;
+    if (run(c) != hipSuccess || hipEventRecord(a, st) != hipSuccess || run(c) != hipSuccess ||
+        hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+      st_code = FA_ERR_HIP;
+      break;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_c = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st_code) return st_code;
+  {
+    std::lock_guard<std::mutex> g(tuner().mu);
+    *chosen = tuner().best.emplace(key, best_c).first->second;
+  }
+  BLK_HIP(run(*chosen));
+  *ms_tune += now_ms() - t0;
+  return FA_OK;
 }
 
 }  // namespace
@@ -143,6 +200,7 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
   // the chain scratch blocks `tmp` (two of them); returns the buffer that
   // holds the result.  Single term per launch; out_i may overwrite out_{i-2}.
   const std::vector<Term> T = K > 0 ? poly_terms(q) : std::vector<Term>();
+  int zc = 8;  // z-planes per workgroup of the block stencil (tuned below)
   auto qblock = [&](const void* x, Prec px, void* out, Prec pout, void* tA, void* tB) -> int {
     const int nT = (int)T.size();
     const void* xm1 = x;
@@ -157,7 +215,7 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
       // the first term reads x (precision px); later terms read the chain
       // precision, and y0 = x must then be in the chain precision too
       BLK_HIP(launch_blk_chain(op, s, xm1, T[i].y0 ? x : nullptr, T[i].y1 ? xm2 : nullptr, dst,
-                               T[i].k, pm1, px, po, st));
+                               T[i].k, pm1, px, po, st, zc));
       xm2 = xm1;
       xm1 = dst;
       pm1 = po;
@@ -166,11 +224,28 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
     return FA_OK;
   };
 
+  // P (ldp) = [V_1..V_nb]^T W with the split-K chunk count tuned per shape
+  auto proj = [&](int nb, const double* Vp, int64_t vb, const double* W, double* P,
+                  int ldp) -> int {
+    std::vector<int> cands;
+    for (int c : {64, 128, 256})
+      if (c <= kNsplitMax && c <= std::max<int64_t>(1, n / 64)) cands.push_back(c);
+    if (cands.empty()) cands.push_back(1);
+    int chosen = 0;
+    return tune_pick({0, n, s, nb}, cands, st,
+                     [&](int c) {
+                       return launch_blk_proj(n, s, nb, Vp, vb, W, part, c, P, ldp, false, st);
+                     },
+                     &chosen, &S.ms_tune);
+  };
+
   // CholQR2 of the block W in place; H_sub (ldsub) = R2 R1
   auto cholqr2 = [&](double* W, double* Hsub, int64_t ldsub, int step) -> int {
-    const int nsp = nsplit_for(n, 1);
     for (int pass = 0; pass < 2; ++pass) {
-      BLK_HIP(launch_blk_proj(n, s, 1, W, 0, W, part, nsp, G, s, false, st));
+      {
+        const int r = proj(1, W, 0, W, G, s);
+        if (r) return r;
+      }
       BLK_HIP(launch_chol(s, G, pass == 0 ? Rt : R, Ri, flag + step, st));
       BLK_HIP(launch_gemm(n, s, s, 1.0, W, 0, s, s, Ri, s, 0.0, W, s, st));
     }
@@ -258,9 +333,18 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
                                P64, P64, P64, st));
       mvms += s;
     } else {
-      // U = A V_j (chain precision), then q twice, the last launch writes FP64 W
-      BLK_HIP(launch_blk_chain(op, s, Vb(j), nullptr, nullptr, C[0],
-                               ChainCoef{1.0, 0.0, 0.0, 0.0}, P64, P64, pc, st));
+      // U = A V_j (chain precision; the z-march length is tuned on this
+      // launch), then q twice, the last launch writes FP64 W
+      {
+        const int r = tune_pick(
+            {1, op.dims[0], op.dims[1], op.dims[2], s, (int)pc}, {4, 8, 16}, st,
+            [&](int c) {
+              return launch_blk_chain(op, s, Vb(j), nullptr, nullptr, C[0],
+                                      ChainCoef{1.0, 0.0, 0.0, 0.0}, P64, P64, pc, st, c);
+            },
+            &zc, &S.ms_tune);
+        if (r) return r;
+      }
       mvms += s;
       int r = qblock(C[0], pc, C[1], pc, C[2], C[3]);
       if (r) return r;
@@ -271,11 +355,14 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
     }
     // block CGS2: H(0:(j+1)s, js:(j+1)s) = P1 + P2
     const int nb = j + 1;
-    const int nsp = nsplit_for(n, nb);
     double* Hcol = H + (size_t)j * s;
-    BLK_HIP(launch_blk_proj(n, s, nb, V, L.bstride, W, part, nsp, Hcol, (int)L.ldh, false, st));
-    BLK_HIP(launch_gemm(n, s, nb * s, -1.0, V, L.bstride, s, s, Hcol, L.ldh, 1.0, W, s, st));
-    BLK_HIP(launch_blk_proj(n, s, nb, V, L.bstride, W, part, nsp, P2, s, false, st));
+    {
+      int r = proj(nb, V, L.bstride, W, Hcol, (int)L.ldh);
+      if (r) return r;
+      BLK_HIP(launch_gemm(n, s, nb * s, -1.0, V, L.bstride, s, s, Hcol, L.ldh, 1.0, W, s, st));
+      r = proj(nb, V, L.bstride, W, P2, s);
+      if (r) return r;
+    }
     BLK_HIP(launch_gemm(n, s, nb * s, -1.0, V, L.bstride, s, s, P2, s, 1.0, W, s, st));
     BLK_HIP(launch_add_mat(nb * s, s, P2, s, Hcol, L.ldh, st));
     // W = V_{j+1} H_{j+1,j}
@@ -365,6 +452,7 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
   S.converged = converged ? 1 : 0;
   S.breakdown = breakdown ? 1 : 0;
   S.ns_iters = ns_iters;
+  S.zc = zc;
   S.mvms = mvms;
   S.est_max = est_max;
   S.ms_total = now_ms() - t0;

@@ -138,10 +138,10 @@ hipError_t launch_ls_step(int dtype, int64_t n, int k, void* W, int64_t ldv, con
 // ---- block (several right-hand sides) kernels, row-major n x s blocks ----
 // one recurrence term on a block, 7-point stencil; s in {16, 32, 64}; storage
 // of x (px), y0/y1 (py) and out (po): all FP64, all FP32, FP64 x -> FP32 out
-// (no y), or FP32 x, y -> FP64 out
+// (no y), or FP32 x, y -> FP64 out; zc: z-planes per workgroup
 hipError_t launch_blk_chain(const Op& op, int s, const void* x, const void* y0, const void* y1,
                             void* out, const ChainCoef& k, Prec px, Prec py, Prec po,
-                            hipStream_t st);
+                            hipStream_t st, int zc = 8);
 hipError_t launch_blk_to_f32(int64_t count, const double* x, float* y, hipStream_t st);
 // P (row i*s + a, column b; leading dimension ldp) = (or +=) V_i^T W, i < nb,
 // V_i = V + i * v_blk; split-K over nsplit chunks of rows (part holds

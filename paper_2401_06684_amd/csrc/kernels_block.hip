@@ -38,6 +38,7 @@ __device__ __forceinline__ dx4 mfma16(double a, double b, dx4 c) {
 // --------------------------------------------------------------------------
 struct BlkSt7 {
   int nx, ny, nz;
+  int zc;  // planes per workgroup (z-march length)
   double c0, cxm, cxp, cym, cyp, czm, czp;
 };
 
@@ -48,15 +49,13 @@ using blk_calc_t =
                               double, float>::type;
 
 // Workgroup tile: a segment of 1024 / S points of one x-line (fixed y) and
-// all S columns, marching along z through kZc planes.  Each thread owns four
+// all S columns, marching along z through zc planes.  Each thread owns four
 // consecutive columns of one point (16- or 32-byte vector loads and stores)
 // and keeps them at z - 1, z, z + 1 in registers, so the z-neighbours are
 // read once.  x-neighbours come from the neighbouring threads' fresh loads
 // (L1), the y-neighbour lines from the workgroups of the adjacent lines,
 // which run alongside (tiles ordered segment, y, z-chunk, each XCD owning a
 // contiguous range of tiles).
-constexpr int kZc = 8;
-
 __device__ __forceinline__ void ld4(const float* p, float (&v)[4]) {
   const float4 t = *reinterpret_cast<const float4*>(p);
   v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
@@ -92,8 +91,8 @@ __global__ __launch_bounds__(256) void st7_blk_k(BlkSt7 g, const TX* __restrict_
   const int lid = xcd_contiguous(blockIdx.x, gridDim.x);
   const int seg = lid % nseg;
   const int j = (lid / nseg) % g.ny;
-  const int k0 = (lid / (nseg * g.ny)) * kZc;
-  const int k1 = min(k0 + kZc, g.nz);
+  const int k0 = (lid / (nseg * g.ny)) * g.zc;
+  const int k1 = min(k0 + g.zc, g.nz);
   const int i = seg * PPW + (int)threadIdx.x / CG;
   if (i >= g.nx) return;
   const int c = 4 * ((int)threadIdx.x % CG);
@@ -163,7 +162,7 @@ template <typename TX, typename TY, typename TO, int S>
 static hipError_t st7_blk_s(const BlkSt7& g, const void* x, const void* y0, const void* y1,
                             void* out, double a, double b, double c0, double c1, hipStream_t st) {
   constexpr int PPW = 1024 / S;
-  const int grid = ((g.nx + PPW - 1) / PPW) * g.ny * ((g.nz + kZc - 1) / kZc);
+  const int grid = ((g.nx + PPW - 1) / PPW) * g.ny * ((g.nz + g.zc - 1) / g.zc);
   const TX* X = (const TX*)x;
   const TY *A0 = (const TY*)y0, *A1 = (const TY*)y1;
   TO* O = (TO*)out;
@@ -189,8 +188,9 @@ static hipError_t st7_blk_t(const BlkSt7& g, int lg_s, const void* x, const void
 
 hipError_t launch_blk_chain(const Op& op, int s, const void* x, const void* y0, const void* y1,
                             void* out, const ChainCoef& k, Prec px, Prec py, Prec po,
-                            hipStream_t st) {
-  BlkSt7 g{op.dims[0], op.dims[1], op.dims[2], op.coef[0], op.coef[1], op.coef[2],
+                            hipStream_t st, int zc) {
+  if (zc < 1) return hipErrorInvalidValue;
+  BlkSt7 g{op.dims[0], op.dims[1], op.dims[2], zc, op.coef[0], op.coef[1], op.coef[2],
            op.coef[3], op.coef[4], op.coef[5], op.coef[6]};
   const int lg_s = s == 16 ? 4 : s == 32 ? 5 : 6;
   const double a = k.alpha.real(), b = k.beta.real(), c0 = k.g0.real(), c1 = k.g1.real();
@@ -219,17 +219,45 @@ hipError_t launch_blk_to_f32(int64_t count, const double* x, float* y, hipStream
 // --------------------------------------------------------------------------
 // split-K projections: part[sp][i][a][b] = sum_{r in chunk sp} V_i[r][a] W[r][b]
 // --------------------------------------------------------------------------
-// grid (nsplit, nb), 256 threads.  Every wave takes every fourth group of 4
-// rows of the chunk and accumulates all (s/16)^2 output tiles; the four waves'
-// tiles are added in LDS in a fixed order.
+// nsplit * nb workgroups of 256 threads; workgroup (sp, i) multiplies chunk
+// sp of V_i and W.  The nb workgroups of one chunk are consecutive in a
+// range that one XCD owns, so they run together there and read the chunk of
+// W once from HBM (then from that XCD's L2).  Every wave takes every fourth
+// group of 4 rows of the chunk and accumulates all (s/16)^2 output tiles; the
+// four waves' tiles are added in LDS in a fixed order.
+// Output index permutation: in tile (t, u) the MFMA row i and column j stand
+// for a = T i + t and b = T j + u, so every lane reads its T values of a row
+// of V_i (and of W) as one vector load.
+template <int T> struct DVec;
+template <> struct DVec<1> {
+  double v[1];
+  __device__ static DVec load(const double* p) { return DVec{{p[0]}}; }
+};
+template <> struct DVec<2> {
+  double v[2];
+  __device__ static DVec load(const double* p) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    return DVec{{a.x, a.y}};
+  }
+};
+template <> struct DVec<4> {
+  double v[4];
+  __device__ static DVec load(const double* p) {
+    const dx4 a = *reinterpret_cast<const dx4*>(p);
+    return DVec{{a[0], a[1], a[2], a[3]}};
+  }
+};
+
 template <int T>
 __global__ __launch_bounds__(256) void blk_proj_k(int64_t n, const double* __restrict__ V,
                                                   int64_t v_blk, const double* __restrict__ W,
-                                                  double* __restrict__ part, int64_t chunk) {
+                                                  double* __restrict__ part, int64_t chunk,
+                                                  int nb) {
   constexpr int S = 16 * T;
   __shared__ double red[S * S];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int sp = blockIdx.x, i = blockIdx.y, nb = gridDim.y;
+  const int lid = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int sp = lid / nb, i = lid % nb;
   const double* Vi = V + (int64_t)i * v_blk;
   const int64_t r_beg = (int64_t)sp * chunk;
   const int64_t r_end = min(n, r_beg + chunk);
@@ -241,21 +269,18 @@ __global__ __launch_bounds__(256) void blk_proj_k(int64_t n, const double* __res
   const int rl = lane >> 4, cl = lane & 15;
   for (int64_t r0 = r_beg + 4 * wv; r0 < r_end; r0 += 16) {
     const int64_t r = r0 + rl;
-    double av[T], bv[T];
+    DVec<T> av, bv;
     if (r < r_end) {
-#pragma unroll
-      for (int t = 0; t < T; ++t) {
-        av[t] = Vi[r * S + 16 * t + cl];
-        bv[t] = W[r * S + 16 * t + cl];
-      }
+      av = DVec<T>::load(Vi + r * S + T * cl);
+      bv = DVec<T>::load(W + r * S + T * cl);
     } else {
 #pragma unroll
-      for (int t = 0; t < T; ++t) av[t] = bv[t] = 0.0;
+      for (int t = 0; t < T; ++t) av.v[t] = bv.v[t] = 0.0;
     }
 #pragma unroll
     for (int a = 0; a < T; ++a)
 #pragma unroll
-      for (int b = 0; b < T; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
+      for (int b = 0; b < T; ++b) acc[a][b] = mfma16(av.v[a], bv.v[b], acc[a][b]);
   }
   // wave w adds its tiles into red in turn (w = 0 stores)
   for (int w = 0; w < 4; ++w) {
@@ -266,7 +291,7 @@ __global__ __launch_bounds__(256) void blk_proj_k(int64_t n, const double* __res
         for (int b = 0; b < T; ++b)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int row = 16 * a + rl + 4 * q, col = 16 * b + cl;
+            const int row = T * (rl + 4 * q) + a, col = T * cl + b;
             if (w == 0) red[row * S + col] = acc[a][b][q];
             else red[row * S + col] += acc[a][b][q];
           }
@@ -297,13 +322,13 @@ hipError_t launch_blk_proj(int64_t n, int s, int nb, const double* V, int64_t v_
                            const double* W, double* part, int nsplit, double* P, int ldp, bool acc,
                            hipStream_t st) {
   const int64_t chunk = ((n + nsplit - 1) / nsplit + 15) / 16 * 16;
-  dim3 grid(nsplit, nb);
+  const int grid = nsplit * nb;
   if (s == 64)
-    blk_proj_k<4><<<grid, 256, 0, st>>>(n, V, v_blk, W, part, chunk);
+    blk_proj_k<4><<<grid, 256, 0, st>>>(n, V, v_blk, W, part, chunk, nb);
   else if (s == 32)
-    blk_proj_k<2><<<grid, 256, 0, st>>>(n, V, v_blk, W, part, chunk);
+    blk_proj_k<2><<<grid, 256, 0, st>>>(n, V, v_blk, W, part, chunk, nb);
   else if (s == 16)
-    blk_proj_k<1><<<grid, 256, 0, st>>>(n, V, v_blk, W, part, chunk);
+    blk_proj_k<1><<<grid, 256, 0, st>>>(n, V, v_blk, W, part, chunk, nb);
   else
     return hipErrorInvalidValue;
   const int64_t per = (int64_t)nb * s * s;
@@ -318,10 +343,12 @@ hipError_t launch_blk_proj(int64_t n, int s, int nb, const double* V, int64_t v_
 // matrix stored as column blocks of width kb, e.g. the basis blocks V_i, or a
 // plain row-major matrix with kb = K); B (K x N) row-major ldb; C (M x N)
 // row-major ldc.  Workgroup tile 64 rows x 16 T columns, one wave per 16
-// rows.  K and kb multiples of 16, A 32-byte aligned with lda a multiple of 4.
-// The reduction order inside a group of 16 k is permuted (MFMA step t of
-// lane group g takes k = 4 g + t), so that each lane reads its four A values
-// as one 32-byte load; B follows the same permutation.
+// rows.  K and kb multiples of 16, A 32-byte aligned with lda a multiple of
+// 4, B and C 8 T-byte aligned with ldb, ldc multiples of T.
+// Permutations that turn operand reads into vector loads: inside a group of
+// 16 k, MFMA step q of lane group g takes k = 4 g + q (one 32-byte load of A
+// per lane), and in column tile t the MFMA column j stands for column
+// T j + t (one T-wide load of B per k, and T-wide stores of C).
 template <int T>
 __global__ __launch_bounds__(256) void gemm_k(int64_t M, int K, double alpha,
                                               const double* __restrict__ A, int64_t a_blk,
@@ -338,29 +365,31 @@ __global__ __launch_bounds__(256) void gemm_k(int64_t M, int K, double alpha,
   const int64_t ra = r0 + cl;  // the A row this lane supplies
   const bool arow = ra < M;
   const double* Ab = A + ra * lda + 4 * rl;
-  const double* Bb = B + (int64_t)(4 * rl) * ldb + c0 + cl;
-  for (int kbase = 0; kbase < K; kbase += kb, Ab += a_blk) {
-    const int kend = min(kb, K - kbase);
-    for (int kk = 0; kk < kend; kk += 16) {
-      dx4 a4 = arow ? *reinterpret_cast<const dx4*>(Ab + kk) : dx4{0.0, 0.0, 0.0, 0.0};
-      const double* Bk = Bb + (int64_t)(kbase + kk) * ldb;
+  const double* Bb = B + (int64_t)(4 * rl) * ldb + c0 + T * cl;
+  const int per = kb / 16;  // groups of 16 k per column block of A
+  const int ng = K / 16;
+  for (int g = 0; g < ng; ++g) {
+    const int blk = g / per, kk = (g - blk * per) * 16;
+    const dx4 a4 = arow ? *reinterpret_cast<const dx4*>(Ab + (int64_t)blk * a_blk + kk)
+                        : dx4{0.0, 0.0, 0.0, 0.0};
+    const double* Bk = Bb + (int64_t)g * 16 * ldb;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 4; ++q) {
+      const DVec<T> bq = DVec<T>::load(Bk + (int64_t)q * ldb);
 #pragma unroll
-        for (int t = 0; t < T; ++t) acc[t] = mfma16(a4[q], Bk[(int64_t)q * ldb + 16 * t], acc[t]);
-      }
+      for (int t = 0; t < T; ++t) acc[t] = mfma16(a4[q], bq.v[t], acc[t]);
     }
   }
 #pragma unroll
-  for (int t = 0; t < T; ++t)
+  for (int q = 0; q < 4; ++q) {
+    const int64_t row = r0 + rl + 4 * q;
+    if (row < M) {
+      double* d = C + row * ldc + c0 + T * cl;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t row = r0 + rl + 4 * q;
-      if (row < M) {
-        double* d = C + row * ldc + c0 + 16 * t + cl;
-        *d = beta == 0.0 ? alpha * acc[t][q] : alpha * acc[t][q] + beta * *d;
-      }
+      for (int t = 0; t < T; ++t)
+        d[t] = beta == 0.0 ? alpha * acc[t][q] : alpha * acc[t][q] + beta * d[t];
     }
+  }
 }
 
 hipError_t launch_gemm(int64_t M, int N, int K, double alpha, const double* A, int64_t a_blk,
@@ -368,6 +397,9 @@ hipError_t launch_gemm(int64_t M, int N, int K, double alpha, const double* A, i
                        int64_t ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (N % 16 || K % 16 || kb % 16 || K <= 0 || lda % 4 || ((uintptr_t)A & 31))
+    return hipErrorInvalidValue;
+  const int T = N % 64 == 0 ? 4 : N % 32 == 0 ? 2 : 1;
+  if (ldb % T || ldc % T || ((uintptr_t)B & (8 * T - 1)) || ((uintptr_t)C & (8 * T - 1)))
     return hipErrorInvalidValue;
   const int gx = (int)((M + 63) / 64);
   if (N % 64 == 0) {

@@ -153,3 +153,21 @@ def test_block_errors():
     with pytest.raises(m.FAError) as e:
         rp.block_apply(B)
     assert e.value.status == m._lib.FA_ERR_UNSUPPORTED
+
+
+def test_block_autotuned_launches_are_reproducible():
+    """The first call of a shape times the launch candidates; the result is
+    the chosen candidate's, so it equals every later call bit for bit."""
+    dims = (40, 36, 33)   # a shape no other test uses: tuned in this call
+    coeffs, B, A, a, b = _problem(dims, 50.0, 16, seed0=3)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(6, "cheb")
+    Bd = dev(B)
+    X1, s1 = op.block_apply(Bd, m_max=12, tol=0.0, mixed=True)
+    X1 = X1.clone()
+    X2, s2 = op.block_apply(Bd, m_max=12, tol=0.0, mixed=True)
+    assert torch.equal(X1, X2)
+    assert s1["ms_tune"] > 0.0 and s2["ms_tune"] == 0.0
+    assert s1["zc"] in (4, 8, 16) and s2["zc"] == s1["zc"]
+    ref = bk.block_fAB(A, B, pl.chebyshev(a, b, 6), "invsqrt", m_max=12, tol=0.0)
+    assert np.max(col_err(host(X2), ref.X)) < 1e-6
