@@ -306,6 +306,31 @@ def batched_leg(fa, torch, wl, dev):
         op.apply(cols[c], m_max=100, tol=1e-7, mixed=True)
     torch.cuda.synchronize()
     dtm = time.perf_counter() - t3
+    # block steps replayed from HIP graphs (captured on the first graph call)
+    op.block_apply(B, m_max=30, tol=1e-7, mixed=True, graph=True)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for _ in range(reps):
+        Xg, stg = op.block_apply(B, m_max=30, tol=1e-7, mixed=True, graph=True)
+    torch.cuda.synchronize()
+    dtg = (time.perf_counter() - t4) / reps
+    same = bool(torch.equal(Xg, X))
+    # a small block (launch-bound): 32^3, 16 right-hand sides, eager vs graphs
+    Ns, ss = 32, 16
+    ops_ = fa.Stencil7((Ns, Ns, Ns), wl.convdiff_stencil(Ns, 50.0), device=dev)
+    ops_.poly_setup(K, "cheb")
+    Bs = torch.from_numpy(np.stack([wl.rhs(Ns ** 3, seed=c) for c in range(ss)], 1)).to(dev)
+    small = {}
+    for g in (False, True):
+        ops_.block_apply(Bs, m_max=30, tol=1e-7, mixed=True, graph=g)
+        ops_.block_apply(Bs, m_max=30, tol=1e-7, mixed=True, graph=g)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        for _ in range(10):
+            _, sts = ops_.block_apply(Bs, m_max=30, tol=1e-7, mixed=True, graph=g)
+        torch.cuda.synchronize()
+        small["graph" if g else "eager"] = (time.perf_counter() - t5) / 10 * 1e3
+    ops_.release_workspace()
     out = {"workload": "convdiff3d_96^3 Pe=50 invsqrt chebyshev degree 16, 64 rhs",
            "rhs_solves_per_s": s / dt, "ms_per_block_solve": dt * 1e3,
            "block_iters": st["iters"], "tol": 1e-7, "max_col_rel_err_vs_fp64": max(errs),
@@ -314,10 +339,17 @@ def batched_leg(fa, torch, wl, dev):
            "fp64_block": {"rhs_solves_per_s": s / dtf, "iters": stf["iters"], "tol": 1e-10},
            "single_vector_fp64_tol1e-10": {"rhs_solves_per_s": s / dts},
            "single_vector_mixed_tol1e-7": {"rhs_solves_per_s": s / dtm},
-           "speedup_vs_single_vector_same_mode": dtm / dt}
+           "speedup_vs_single_vector_same_mode": dtm / dt,
+           "hip_graph_steps": {"ms_per_block_solve": dtg * 1e3, "graph_steps": stg["graph_steps"],
+                               "same_result_as_eager": same,
+                               "small_32^3_x16_ms": {"eager": small["eager"],
+                                                     "graph": small["graph"],
+                                                     "block_iters": sts["iters"]}}}
     log(f"batched: {s / dt:.1f} rhs-solves/s ({dt * 1e3:.0f} ms per block of 64, m = {st['iters']}), "
         f"max col err {max(errs):.2e}; FP64 block {s / dtf:.1f}/s; one at a time: FP64 "
-        f"{s / dts:.1f}/s, mixed {s / dtm:.1f}/s")
+        f"{s / dts:.1f}/s, mixed {s / dtm:.1f}/s; steps from HIP graphs {dtg * 1e3:.0f} ms "
+        f"(same bits: {same}); 32^3 x 16: eager {small['eager']:.2f} ms, graphs "
+        f"{small['graph']:.2f} ms")
     op.release_workspace()
     return out
 

@@ -112,6 +112,11 @@ enum {
                             z_m = H_m^{-1/2} e_1 ||b||.  The stopping estimate is
                             ||Y_j (z_j - [z_{j-k}; 0])|| / ||Y_j z_j||.  Not with
                             FA_MIXED.  With q == 1 it is the plain method.         */
+  FA_GRAPH = 256u,       /* fa_block_apply: run each block step from a HIP graph,
+                            captured at the step's first use once its launch
+                            parameters are tuned and replayed afterwards (per op,
+                            polynomial, workspace address, block size, m_max,
+                            precision and step index; released by fa_destroy) */
   FA_MIXED = 32u         /* apply: the polynomial chain (A and q(A) in the three-stage
                             product, and c = q(A) b) in FP32 storage with FP32
                             accumulation; Gram-Schmidt, H, H^{-1/2} e_1, the basis and
@@ -346,6 +351,8 @@ typedef struct {
   int32_t checks;
   int32_t ns_iters;    /* Newton-Schulz iterations of the last H^{-1/2}       */
   int32_t zc;          /* z-planes per workgroup of the stencil (autotuned)   */
+  int32_t graph_steps; /* block steps replayed from (or captured into) graphs */
+  int32_t reserved;
   int64_t mvms;        /* products of A with single vectors (s per block)    */
   double est_max;      /* largest per-column estimate at the last check       */
   double ms_total;
@@ -367,7 +374,9 @@ size_t fa_block_workspace_bytes(fa_op op, int s, int m_max, uint32_t flags);
  *              values of grid point i contiguous); d_X must not alias d_B
  *   m_max    : maximal number of block steps; tol, check_every as fa_apply
  *   flags    : FA_MIXED (the stencil chain in FP32 storage and arithmetic;
- *              Gram-Schmidt, Cholesky QR, H^{-1/2} and X = V Z in FP64)
+ *              Gram-Schmidt, Cholesky QR, H^{-1/2} and X = V Z in FP64),
+ *              FA_GRAPH (block steps from captured HIP graphs; the same
+ *              launches, so the same results)
  * d_B and d_X must be 32-byte aligned.  Launch parameters (the split-K chunk
  * count of the projections per basis size, the z-march length of the
  * stencil) are autotuned at the first use of a problem shape in the process

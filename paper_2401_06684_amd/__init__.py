@@ -193,9 +193,10 @@ class Operator:
         return x, d
 
     def block_apply(self, B, kind="invsqrt", m_max=30, tol=1e-10, check_every=0, out=None,
-                    mixed=False, raise_not_converged=False):
+                    mixed=False, graph=False, raise_not_converged=False):
         """X ~ A^{-1/2} B or A^{1/2} B for the columns of B (n x s, s in
         {16, 32, 64}, a contiguous row-major tensor) by block Arnoldi.
+        graph=True replays the block steps from captured HIP graphs.
         Returns (X, stats dict)."""
         if not (isinstance(B, torch.Tensor) and B.is_cuda and B.dtype == torch.float64
                 and B.dim() == 2 and B.shape[0] == self.n and B.is_contiguous()):
@@ -204,7 +205,7 @@ class Operator:
         X = out if out is not None else torch.empty_like(B)
         if X.shape != B.shape or not X.is_contiguous() or X.dtype != B.dtype:
             raise ValueError("out must match B")
-        flags = FA_MIXED if mixed else 0
+        flags = (FA_MIXED if mixed else 0) | (_lib.FA_GRAPH if graph else 0)
         nbytes = lib().fa_block_workspace_bytes(self._h, s, m_max, flags)
         if nbytes == 0:
             raise ValueError("unsupported block size (s must be 16, 32 or 64)")

@@ -24,7 +24,7 @@ FA_INVSQRT, FA_SQRT = 0, 1
 FA_STENCIL7, FA_WILSON4D = 0, 1
 FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_RITZ, FA_POLY_HARMONIC, FA_POLY_LS = 0, 1, 2, 3, 4
 FA_HERMITIAN, FA_FORCE_ARNOLDI, FA_PROFILE, FA_NO_FUSION, FA_MIXED = 1, 4, 8, 16, 32
-FA_TWO_PASS, FA_RIGHT_PREC = 64, 128
+FA_TWO_PASS, FA_RIGHT_PREC, FA_GRAPH = 64, 128, 256
 
 EXPORTS = [
     "fa_create_csr", "fa_create_stencil", "fa_set_spectral_interval",
@@ -55,12 +55,12 @@ class fa_block_stats(C.Structure):
     _fields_ = [
         ("iters", C.c_int32), ("converged", C.c_int32), ("breakdown", C.c_int32),
         ("checks", C.c_int32), ("ns_iters", C.c_int32), ("zc", C.c_int32),
-        ("mvms", C.c_int64), ("est_max", C.c_double), ("ms_total", C.c_double),
+        ("graph_steps", C.c_int32), ("reserved", C.c_int32), ("mvms", C.c_int64), ("est_max", C.c_double), ("ms_total", C.c_double),
         ("ms_fH", C.c_double), ("ms_tune", C.c_double),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class fa_request_info(C.Structure):

@@ -62,6 +62,7 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
   return guarded([&] {
     fa_op h = new fa_op_s;
     Op& op = h->op;
+    op.uid = next_op_uid();
     op.kind = OP_CSR;
     op.dtype = dtype;
     op.n = n;
@@ -127,6 +128,7 @@ int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double*
       return FA_ERR_ARG;
     }
     op.flags = flags;
+    op.uid = next_op_uid();
     fa_op h = new fa_op_s;
     h->op = op;
     *out = h;
@@ -260,7 +262,7 @@ int fa_block_apply(fa_op op, int kind, int s, const void* d_B, void* d_X, int m_
                    void* hip_stream, fa_block_stats* stats) {
   if (!op || !d_B || !d_X || d_B == d_X || (s != 16 && s != 32 && s != 64) || m_max < 1 ||
       check_every < 0 || (kind != FA_INVSQRT && kind != FA_SQRT) || !(tol == tol) ||
-      (flags & ~uint32_t(FA_MIXED)))
+      (flags & ~uint32_t(FA_MIXED | FA_GRAPH)))
     return FA_ERR_ARG;
   if (!op->op.poly_ready) return FA_ERR_NO_POLY;
   return guarded([&] {
@@ -293,6 +295,7 @@ int fa_op_info(fa_op op, int64_t* n, int* dtype) {
 }
 
 int fa_destroy(fa_op op) {
+  if (op) release_op_graphs(op->op.uid);
   delete op;
   return FA_OK;
 }

@@ -149,7 +149,51 @@ int tune_pick(const std::vector<int64_t>& key, const std::vector<int>& cands, hi
   return FA_OK;
 }
 
+bool is_tuned(const std::vector<int64_t>& key) {
+  std::lock_guard<std::mutex> g(tuner().mu);
+  return tuner().best.count(key) != 0;
+}
+
+// Executable graphs of block steps, keyed by everything their kernel
+// arguments depend on (op identity and polynomial version, workspace address,
+// block size, Krylov dimension bound, precision mode, step index, tuned
+// parameters).  Freed with the op (release_op_graphs) or at process end.
+struct GraphCache {
+  std::mutex mu;
+  std::map<std::vector<int64_t>, hipGraphExec_t> execs;
+};
+GraphCache& graphs() {
+  static GraphCache c;
+  return c;
+}
+
+// A private stream per thread for stream capture (the caller's stream may be
+// the null stream, which cannot be captured).
+struct CaptureStream {
+  hipStream_t s = nullptr;
+  ~CaptureStream() {
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+hipStream_t capture_stream() {
+  thread_local CaptureStream cs;
+  if (!cs.s && hipStreamCreateWithFlags(&cs.s, hipStreamNonBlocking) != hipSuccess) cs.s = nullptr;
+  return cs.s;
+}
+
 }  // namespace
+
+void release_op_graphs(uint64_t uid) {
+  std::lock_guard<std::mutex> g(graphs().mu);
+  for (auto it = graphs().execs.begin(); it != graphs().execs.end();) {
+    if ((uint64_t)it->first[0] == uid) {
+      (void)hipGraphExecDestroy(it->second);
+      it = graphs().execs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
 
 size_t block_workspace_bytes(const Op& op, int s, int m_max, uint32_t flags) {
   return blk_layout(op, s, m_max, (flags & FA_MIXED) != 0).bytes;
@@ -200,7 +244,15 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
   // the chain scratch blocks `tmp` (two of them); returns the buffer that
   // holds the result.  Single term per launch; out_i may overwrite out_{i-2}.
   const std::vector<Term> T = K > 0 ? poly_terms(q) : std::vector<Term>();
-  int zc = 8;  // z-planes per workgroup of the block stencil (tuned below)
+  // z-planes per workgroup of the block stencil (tuned at the first A V_j)
+  const std::vector<int64_t> zc_key{1, op.dims[0], op.dims[1], op.dims[2], s, (int)pc};
+  int zc = 8;
+  {
+    std::lock_guard<std::mutex> g(tuner().mu);
+    auto it = tuner().best.find(zc_key);
+    if (it != tuner().best.end()) zc = it->second;
+  }
+  hipStream_t cur = st;  // the stream the step launches go to (capture: a private one)
   auto qblock = [&](const void* x, Prec px, void* out, Prec pout, void* tA, void* tB) -> int {
     const int nT = (int)T.size();
     const void* xm1 = x;
@@ -215,7 +267,7 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
       // the first term reads x (precision px); later terms read the chain
       // precision, and y0 = x must then be in the chain precision too
       BLK_HIP(launch_blk_chain(op, s, xm1, T[i].y0 ? x : nullptr, T[i].y1 ? xm2 : nullptr, dst,
-                               T[i].k, pm1, px, po, st, zc));
+                               T[i].k, pm1, px, po, cur, zc));
       xm2 = xm1;
       xm1 = dst;
       pm1 = po;
@@ -232,9 +284,9 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
       if (c <= kNsplitMax && c <= std::max<int64_t>(1, n / 64)) cands.push_back(c);
     if (cands.empty()) cands.push_back(1);
     int chosen = 0;
-    return tune_pick({0, n, s, nb}, cands, st,
+    return tune_pick({0, n, s, nb}, cands, cur,
                      [&](int c) {
-                       return launch_blk_proj(n, s, nb, Vp, vb, W, part, c, P, ldp, false, st);
+                       return launch_blk_proj(n, s, nb, Vp, vb, W, part, c, P, ldp, false, cur);
                      },
                      &chosen, &S.ms_tune);
   };
@@ -246,11 +298,11 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
         const int r = proj(1, W, 0, W, G, s);
         if (r) return r;
       }
-      BLK_HIP(launch_chol(s, G, pass == 0 ? Rt : R, Ri, flag + step, st));
-      BLK_HIP(launch_gemm(n, s, s, 1.0, W, 0, s, s, Ri, s, 0.0, W, s, st));
+      BLK_HIP(launch_chol(s, G, pass == 0 ? Rt : R, Ri, flag + step, cur));
+      BLK_HIP(launch_gemm(n, s, s, 1.0, W, 0, s, s, Ri, s, 0.0, W, s, cur));
     }
     // Hsub = R (second) * Rt (first)
-    BLK_HIP(launch_gemm(s, s, s, 1.0, R, 0, s, s, Rt, s, 0.0, Hsub, ldsub, st));
+    BLK_HIP(launch_gemm(s, s, s, 1.0, R, 0, s, s, Rt, s, 0.0, Hsub, ldsub, cur));
     return FA_OK;
   };
 
@@ -326,21 +378,22 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
   bool converged = false, breakdown = false;
   double colmax = 0.0, est_max = 1.0;
   int ns_iters = 0;
-  for (int j = 0; j < m_max; ++j) {
+  // one block step: W = A q(A)^2 V_j, block CGS2, CholQR2 (all launches on `cur`)
+  auto do_step = [&](int j) -> int {
     double* W = Vb(j + 1);
     if (K == 0) {
       BLK_HIP(launch_blk_chain(op, s, Vb(j), nullptr, nullptr, W, ChainCoef{1.0, 0.0, 0.0, 0.0},
-                               P64, P64, P64, st));
+                               P64, P64, P64, cur, zc));
       mvms += s;
     } else {
       // U = A V_j (chain precision; the z-march length is tuned on this
       // launch), then q twice, the last launch writes FP64 W
       {
         const int r = tune_pick(
-            {1, op.dims[0], op.dims[1], op.dims[2], s, (int)pc}, {4, 8, 16}, st,
+            zc_key, {4, 8, 16}, cur,
             [&](int c) {
               return launch_blk_chain(op, s, Vb(j), nullptr, nullptr, C[0],
-                                      ChainCoef{1.0, 0.0, 0.0, 0.0}, P64, P64, pc, st, c);
+                                      ChainCoef{1.0, 0.0, 0.0, 0.0}, P64, P64, pc, cur, c);
             },
             &zc, &S.ms_tune);
         if (r) return r;
@@ -359,15 +412,73 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
     {
       int r = proj(nb, V, L.bstride, W, Hcol, (int)L.ldh);
       if (r) return r;
-      BLK_HIP(launch_gemm(n, s, nb * s, -1.0, V, L.bstride, s, s, Hcol, L.ldh, 1.0, W, s, st));
+      BLK_HIP(launch_gemm(n, s, nb * s, -1.0, V, L.bstride, s, s, Hcol, L.ldh, 1.0, W, s, cur));
       r = proj(nb, V, L.bstride, W, P2, s);
       if (r) return r;
     }
-    BLK_HIP(launch_gemm(n, s, nb * s, -1.0, V, L.bstride, s, s, P2, s, 1.0, W, s, st));
-    BLK_HIP(launch_add_mat(nb * s, s, P2, s, Hcol, L.ldh, st));
+    BLK_HIP(launch_gemm(n, s, nb * s, -1.0, V, L.bstride, s, s, P2, s, 1.0, W, s, cur));
+    BLK_HIP(launch_add_mat(nb * s, s, P2, s, Hcol, L.ldh, cur));
     // W = V_{j+1} H_{j+1,j}
     {
       int r = cholqr2(W, H + (size_t)(j + 1) * s * L.ldh + (size_t)j * s, L.ldh, j);
+      if (r) return r;
+    }
+    return FA_OK;
+  };
+  const bool use_graph = (flags & FA_GRAPH) != 0;
+  const int64_t step_mvms = (int64_t)(K > 0 ? 2 * K + 1 : 1) * s;
+  // run step j: replayed from a captured graph when FA_GRAPH is set and its
+  // launch parameters are tuned already, else launched one by one
+  auto run_step = [&](int j) -> int {
+    const bool tuned = (K == 0 || is_tuned(zc_key)) && is_tuned({0, n, s, j + 1}) &&
+                       is_tuned({0, n, s, 1});
+    if (!use_graph || !tuned) return do_step(j);
+    const std::vector<int64_t> key{(int64_t)op.uid, (int64_t)op.poly_version, (int64_t)(uintptr_t)ws,
+                                   s, m_max, mixed ? 1 : 0, j, zc, n};
+    hipGraphExec_t exec = nullptr;
+    {
+      std::lock_guard<std::mutex> g(graphs().mu);
+      auto it = graphs().execs.find(key);
+      if (it != graphs().execs.end()) exec = it->second;
+    }
+    if (exec) {
+      mvms += step_mvms;
+      ++S.graph_steps;
+      BLK_HIP(hipGraphLaunch(exec, st));
+      return FA_OK;
+    }
+    hipStream_t cs = capture_stream();
+    if (!cs) return FA_ERR_HIP;
+    BLK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    cur = cs;
+    const int r = do_step(j);
+    cur = st;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (r) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return r;
+    }
+    if (e != hipSuccess) return FA_ERR_HIP;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return FA_ERR_HIP;
+    {
+      std::lock_guard<std::mutex> g(graphs().mu);
+      auto ins = graphs().execs.emplace(key, exec);
+      if (!ins.second) {  // another thread stored one meanwhile
+        (void)hipGraphExecDestroy(exec);
+        exec = ins.first->second;
+      }
+    }
+    ++S.graph_steps;
+    BLK_HIP(hipGraphLaunch(exec, st));
+    return FA_OK;
+  };
+
+  for (int j = 0; j < m_max; ++j) {
+    {
+      const int r = run_step(j);
       if (r) return r;
     }
     const int jj = j + 1;

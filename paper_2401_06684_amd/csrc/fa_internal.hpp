@@ -67,7 +67,13 @@ struct Op {
   double lo = 0, hi = 0;
   Poly poly;
   bool poly_ready = false;
+  // identity for caches that hold launch parameters of this op: a process-
+  // wide unique id set at creation, and a counter bumped by every setup of q
+  uint64_t uid = 0;
+  uint64_t poly_version = 0;
 };
+// a fresh process-wide unique id (thread-safe)
+uint64_t next_op_uid();
 
 // storage precision of the vectors of one chain launch
 enum Prec { P64 = 0, P32 = 1 };

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -14,6 +15,11 @@
 #include "solver.hpp"
 
 namespace fa {
+
+uint64_t next_op_uid() {
+  static std::atomic<uint64_t> counter{0};
+  return ++counter;
+}
 
 // --------------------------------------------------------------------------
 // workspace layout (every region 256-byte aligned)
@@ -859,6 +865,7 @@ int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, si
     q.degree = 0;
     op.poly = q;
     op.poly_ready = true;
+    ++op.poly_version;
     return FA_OK;
   }
   if (method == FA_POLY_CHEB) {
@@ -881,6 +888,7 @@ int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, si
     }
     op.poly = q;
     op.poly_ready = true;
+    ++op.poly_version;
     return FA_OK;
   }
   const bool real_op = op.dtype == FA_F64;
@@ -904,6 +912,7 @@ int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, si
     q.npts = (long)pts.size();
     op.poly = q;
     op.poly_ready = true;
+    ++op.poly_version;
     return FA_OK;
   }
   if (method != FA_POLY_RITZ && method != FA_POLY_HARMONIC) return FA_ERR_ARG;
@@ -926,6 +935,7 @@ int poly_setup(Op& op, int degree, int method, const void* d_start, void* ws, si
   }
   op.poly = q;
   op.poly_ready = true;
+  ++op.poly_version;
   return FA_OK;
 }
 

@@ -42,6 +42,8 @@ struct LsParams {
   double step = 0.005;
 };
 size_t block_workspace_bytes(const Op& op, int s, int m_max, uint32_t flags);
+// destroy the block-step graphs cached for an op (fa_destroy)
+void release_op_graphs(uint64_t uid);
 int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m_max, double tol,
                 int check_every, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t st,
                 fa_block_stats* stats);

@@ -171,3 +171,30 @@ def test_block_autotuned_launches_are_reproducible():
     assert s1["zc"] in (4, 8, 16) and s2["zc"] == s1["zc"]
     ref = bk.block_fAB(A, B, pl.chebyshev(a, b, 6), "invsqrt", m_max=12, tol=0.0)
     assert np.max(col_err(host(X2), ref.X)) < 1e-6
+
+
+def test_block_steps_from_hip_graphs_match_eager_launches():
+    """FA_GRAPH: the block steps are captured once (after their launch
+    parameters are tuned) and replayed.  Several replays, with eager solves
+    and synchronizations between them, each equal the eager result bit for
+    bit (graphs hold no memset nodes)."""
+    dims = (24, 22, 20)
+    coeffs, B, A, a, b = _problem(dims, 50.0, 32, seed0=5)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(8, "cheb")
+    Bd = dev(B)
+    ref, s0 = op.block_apply(Bd, m_max=20, tol=1e-9, mixed=True)   # eager; tunes
+    ref = ref.clone()
+    for rep in range(3):
+        Xg, sg = op.block_apply(Bd, m_max=20, tol=1e-9, mixed=True, graph=True)
+        torch.cuda.synchronize()
+        assert sg["graph_steps"] == sg["iters"] and sg["iters"] == s0["iters"]
+        assert torch.equal(Xg, ref), rep
+        Xe, _ = op.block_apply(Bd, m_max=20, tol=1e-9, mixed=True)   # eager in between
+        assert torch.equal(Xe, ref)
+    # FP64 mode, sqrt, also through graphs
+    r64, _ = op.block_apply(Bd, kind="sqrt", m_max=20, tol=1e-10)
+    r64 = r64.clone()
+    for rep in range(2):
+        g64, sg = op.block_apply(Bd, kind="sqrt", m_max=20, tol=1e-10, graph=True)
+        assert sg["graph_steps"] > 0 and torch.equal(g64, r64)
