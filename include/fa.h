@@ -112,6 +112,13 @@ enum {
                             z_m = H_m^{-1/2} e_1 ||b||.  The stopping estimate is
                             ||Y_j (z_j - [z_{j-k}; 0])|| / ||Y_j z_j||.  Not with
                             FA_MIXED.  With q == 1 it is the plain method.         */
+  FA_CGS2 = 512u,        /* apply: classical Gram-Schmidt applied twice in every
+                            Arnoldi step.  Default: the second pass of step j is
+                            delayed to step j + 1 and merged with its first
+                            (one sweep of projections on two vectors and one
+                            of updates per step instead of two of each); the
+                            same Arnoldi relation up to rounding.  Lanczos and
+                            FA_RIGHT_PREC always use their own scheme. */
   FA_GRAPH = 256u,       /* fa_block_apply: run each block step from a HIP graph,
                             captured at the step's first use once its launch
                             parameters are tuned and replayed afterwards (per op,
@@ -281,7 +288,8 @@ size_t fa_workspace_bytes(fa_op op, int m_max, uint32_t flags);
 /*
  * fa_apply -- x ~ A^{-1/2} b (kind FA_INVSQRT) or A^{1/2} b (FA_SQRT) by
  * left polynomially preconditioned Arnoldi (Algorithm 1) with classical
- * Gram-Schmidt applied twice, or Lanczos for FA_HERMITIAN ops.
+ * Gram-Schmidt applied twice (the second pass delayed by one step unless
+ * FA_CGS2), or Lanczos for FA_HERMITIAN ops.
  *   d_b, d_x     : device vectors of length n (d_x must not alias d_b)
  *   m_max        : maximal Krylov dimension (>= 1)
  *   tol          : stop when ||f_j - f_{j-k}|| / ||f_j|| <= tol; tol <= 0 runs

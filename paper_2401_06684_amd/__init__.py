@@ -166,20 +166,25 @@ class Operator:
 
     def apply(self, b, kind="invsqrt", m_max=100, tol=1e-10, check_every=0, out=None,
               force_arnoldi=False, profile=False, fuse=True, mixed=False, two_pass=False,
-              right=False, raise_not_converged=False):
+              right=False, orth="dcgs2", raise_not_converged=False):
         """x ~ A^{-1/2} b or A^{1/2} b.  Returns (x, stats dict).
 
         fuse=False runs one launch per recurrence term (no two-term launches);
         mixed=True runs the polynomial chain in FP32 (stencil, Chebyshev q);
         two_pass=True runs two-pass Lanczos (O(n) basis storage);
-        right=True runs the right-preconditioned variant (Algorithm 2).
+        right=True runs the right-preconditioned variant (Algorithm 2);
+        orth="cgs2" runs both Gram-Schmidt passes in every Arnoldi step
+        (default "dcgs2": the second pass delayed by one step).
         """
+        if orth not in ("dcgs2", "cgs2"):
+            raise ValueError("orth must be 'dcgs2' or 'cgs2'")
         b = self._vec(b, "b")
         x = out if out is not None else torch.empty_like(b)
         self._vec(x, "out")
         flags = ((FA_FORCE_ARNOLDI if force_arnoldi else 0) | (FA_PROFILE if profile else 0)
                  | (0 if fuse else FA_NO_FUSION) | (FA_MIXED if mixed else 0)
-                 | (FA_TWO_PASS if two_pass else 0) | (FA_RIGHT_PREC if right else 0))
+                 | (FA_TWO_PASS if two_pass else 0) | (FA_RIGHT_PREC if right else 0)
+                 | (_lib.FA_CGS2 if orth == "cgs2" else 0))
         _, wsp, nbytes = self._workspace(m_max, flags)
         stats = _lib.fa_stats()
         st = lib().fa_apply(self._h, _KIND[kind], _ptr(b), _ptr(x), m_max, float(tol),

@@ -129,6 +129,14 @@ hipError_t launch_combine(int dtype, int64_t n, int ncols, const void* V, int64_
 // out = w / sqrt(nrm2) (nrm2 on device); hout (if not null) = sqrt(nrm2) as a T
 hipError_t launch_normalize(int dtype, int64_t n, const void* w, const double* nrm2,
                             void* out, void* hout, hipStream_t s);
+// One step of CGS2 with delayed reorthogonalization, j >= 1: V columns
+// 0..j-1 hold q_0..q_{j-1}, column j the once-orthogonalized u_j and column
+// j + 1 the new z = Op u_j.  Finishes column j - 1 of H (column-major, ldh),
+// forms the first-pass column j, and leaves q_j in column j and u_{j+1} in
+// column j + 1.  part: 2 (j + 1) x nblk partials; S: 2 (j + 1) values;
+// coef: 2 j + 2 values.
+hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv, void* part,
+                        void* S, void* H, int64_t ldh, void* coef, hipStream_t s);
 // y = a * x for a scalar on the host
 hipError_t launch_scale(int dtype, int64_t n, cd a, const void* x, void* y, hipStream_t s);
 

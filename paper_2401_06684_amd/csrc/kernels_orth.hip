@@ -227,6 +227,197 @@ hipError_t launch_ls_step(int dtype, int64_t n, int k, void* W, int64_t ldv, con
 }
 
 // --------------------------------------------------------------------------
+// CGS2 with the reorthogonalization delayed by one step (one sweep of
+// projections and one sweep of updates per Arnoldi step):
+//   project2 : S[2c + r] = V_c^H w_r for c < ncols and the two vectors
+//              w_0 = u_j (the once-orthogonalized vector, also column j of V)
+//              and w_1 = z = Op u_j
+//   dcgs2_coef : finishes column j - 1 of H with the second-pass
+//              coefficients s = Q_j^H u_j and nu = ||u_j - Q_j s||, and forms
+//              the first-pass column j from p = Q_j^H z (one workgroup)
+//   update2  : q_j = (u_j - Q_j s) / nu (in place of u_j) and
+//              u_{j+1} = (z - Q_j p - q_j gamma) / nu (in place of z)
+// --------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void project2_k(int64_t n, int ncols,
+                                                       const T* __restrict__ V, int64_t ldv,
+                                                       const T* __restrict__ w0,
+                                                       const T* __restrict__ w1,
+                                                       T* __restrict__ part, int nblk) {
+  __shared__ T red[kThreads / 64][2 * kCb];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * (kThreads * kRpt) + tid;
+  T a0[kRpt], a1[kRpt];
+#pragma unroll
+  for (int q = 0; q < kRpt; ++q) {
+    const int64_t r = r0 + (int64_t)q * kThreads;
+    a0[q] = (r < n) ? w0[r] : zero(T{});
+    a1[q] = (r < n) ? w1[r] : zero(T{});
+  }
+  const bool full = r0 + (int64_t)(kRpt - 1) * kThreads < n;
+  for (int c0 = 0; c0 < ncols; c0 += kCb) {
+    T acc[2 * kCb];
+#pragma unroll
+    for (int cc = 0; cc < kCb; ++cc) {
+      acc[2 * cc] = acc[2 * cc + 1] = zero(T{});
+      if (c0 + cc < ncols) {
+        const T* col = V + (int64_t)(c0 + cc) * ldv + r0;
+#pragma unroll
+        for (int q = 0; q < kRpt; ++q) {
+          if (full || r0 + (int64_t)q * kThreads < n) {
+            const T v = col[q * kThreads];
+            acc[2 * cc] = cmad(v, a0[q], acc[2 * cc]);
+            acc[2 * cc + 1] = cmad(v, a1[q], acc[2 * cc + 1]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 2 * kCb; ++e) acc[e] = wave_sum(acc[e]);
+    if (lane == 0) {
+#pragma unroll
+      for (int e = 0; e < 2 * kCb; ++e) red[wv][e] = acc[e];
+    }
+    __syncthreads();
+    if (tid < 2 * kCb && c0 + tid / 2 < ncols) {
+      T t = red[0][tid];
+      t += red[1][tid];
+      t += red[2][tid];
+      t += red[3][tid];
+      part[(int64_t)(2 * c0 + tid) * nblk + blockIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ double re_of(double a) { return a; }
+__device__ __forceinline__ double re_of(cplx a) { return a.x; }
+__device__ __forceinline__ double mk_real(double a, double) { return a; }
+__device__ __forceinline__ cplx mk_real(double a, cplx) { return cplx{a, 0.0}; }
+__device__ __forceinline__ double div_real(double a, double d) { return a / d; }
+__device__ __forceinline__ cplx div_real(cplx a, double d) { return cplx{a.x / d, a.y / d}; }
+
+// S (2 (j + 1) entries, see project2), H column-major (ldh), j >= 1.
+// Writes cs = s, cp = p (j entries each), sc[0] = 1 / nu, sc[1] = gamma.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void dcgs2_coef_k(int j, const T* __restrict__ S, T* H,
+                                                         int64_t ldh, T* __restrict__ cs,
+                                                         T* __restrict__ cp,
+                                                         T* __restrict__ sc) {
+  __shared__ double shd[kThreads / 64];
+  __shared__ T sht[kThreads / 64];
+  __shared__ double s_nu;
+  __shared__ T s_gam;
+  const int tid = threadIdx.x;
+  // ||s||^2 and s^H p
+  double ss = 0.0;
+  T sp = zero(T{});
+  for (int i = tid; i < j; i += kThreads) {
+    ss += abs2(S[2 * i]);
+    sp = cmad(S[2 * i], S[2 * i + 1], sp);
+  }
+  ss = block_sum(ss, shd);
+  sp = block_sum(sp, sht);
+  if (tid == 0) {
+    const double alpha = re_of(S[2 * j]);
+    const double nu2 = alpha - ss;
+    const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+    s_nu = nu;
+    s_gam = div_real(S[2 * j + 1] - sp, nu);
+    sc[0] = mk_real(nu > 0.0 ? 1.0 / nu : 0.0, T{});
+    sc[1] = s_gam;
+  }
+  // finish column j - 1: H(0:j, j-1) += s, H(j, j-1) = nu
+  for (int i = tid; i < j; i += kThreads) {
+    H[(int64_t)(j - 1) * ldh + i] += S[2 * i];
+    cs[i] = S[2 * i];
+    cp[i] = S[2 * i + 1];
+  }
+  __syncthreads();
+  if (tid == 0) H[(int64_t)(j - 1) * ldh + j] = mk_real(s_nu, T{});
+  __syncthreads();
+  // first-pass column j: (Q_{j+1}^H z - Hbar s) / nu, Hbar = H(0:j, 0:j-1)
+  const double nu = s_nu;
+  for (int i = tid; i <= j; i += kThreads) {
+    T t = zero(T{});
+    for (int c = max(0, i - 1); c < j; ++c) t = mad(H[(int64_t)c * ldh + i], S[2 * c], t);
+    const T top = (i < j) ? S[2 * i + 1] : s_gam;
+    H[(int64_t)j * ldh + i] = div_real(top - t, nu);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void update2_k(int64_t n, int ncols, const T* __restrict__ V,
+                                                      int64_t ldv, const T* __restrict__ cs,
+                                                      const T* __restrict__ cp,
+                                                      const T* __restrict__ sc, T* u, T* z) {
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * (kThreads * kRpt) + tid;
+  T as[kRpt], ap[kRpt];
+#pragma unroll
+  for (int q = 0; q < kRpt; ++q) as[q] = ap[q] = zero(T{});
+  const bool full = r0 + (int64_t)(kRpt - 1) * kThreads < n;
+#pragma unroll 2
+  for (int c = 0; c < ncols; ++c) {
+    const T hs = cs[c], hp = cp[c];
+    const T* col = V + (int64_t)c * ldv + r0;
+#pragma unroll
+    for (int q = 0; q < kRpt; ++q) {
+      if (full || r0 + (int64_t)q * kThreads < n) {
+        const T v = col[q * kThreads];
+        as[q] = mad(v, hs, as[q]);
+        ap[q] = mad(v, hp, ap[q]);
+      }
+    }
+  }
+  const double inv = re_of(sc[0]);
+  const T gam = sc[1];
+#pragma unroll
+  for (int q = 0; q < kRpt; ++q) {
+    const int64_t r = r0 + (int64_t)q * kThreads;
+    if (r < n) {
+      const T qv = mk_real(inv, T{}) * (u[r] - as[q]);
+      u[r] = qv;
+      z[r] = mk_real(inv, T{}) * (z[r] - ap[q] - qv * gam);
+    }
+  }
+}
+
+hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv, void* part,
+                        void* S, void* H, int64_t ldh, void* coef, hipStream_t s) {
+  const RedPlan p = red_plan(n);
+  const size_t es = dtype == FA_C128 ? 16 : 8;
+  void* u = (char*)V + (size_t)j * ldv * es;
+  void* z = (char*)V + (size_t)(j + 1) * ldv * es;
+  char* cs = (char*)coef;
+  char* cp = cs + (size_t)j * es;
+  char* sc = cp + (size_t)j * es;
+  if (dtype == FA_C128) {
+    project2_k<cplx><<<p.nblk, kThreads, 0, s>>>(n, j + 1, (const cplx*)V, ldv, (const cplx*)u,
+                                                 (const cplx*)z, (cplx*)part, p.nblk);
+    reduce_cols_k<cplx><<<2 * (j + 1), kThreads, 0, s>>>(p.nblk, (const cplx*)part, (cplx*)S,
+                                                         nullptr, 0);
+    dcgs2_coef_k<cplx><<<1, kThreads, 0, s>>>(j, (const cplx*)S, (cplx*)H, ldh, (cplx*)cs,
+                                              (cplx*)cp, (cplx*)sc);
+    update2_k<cplx><<<p.nblk, kThreads, 0, s>>>(n, j, (const cplx*)V, ldv, (const cplx*)cs,
+                                                (const cplx*)cp, (const cplx*)sc, (cplx*)u,
+                                                (cplx*)z);
+  } else {
+    project2_k<double><<<p.nblk, kThreads, 0, s>>>(n, j + 1, (const double*)V, ldv,
+                                                   (const double*)u, (const double*)z,
+                                                   (double*)part, p.nblk);
+    reduce_cols_k<double><<<2 * (j + 1), kThreads, 0, s>>>(p.nblk, (const double*)part,
+                                                           (double*)S, nullptr, 0);
+    dcgs2_coef_k<double><<<1, kThreads, 0, s>>>(j, (const double*)S, (double*)H, ldh,
+                                                (double*)cs, (double*)cp, (double*)sc);
+    update2_k<double><<<p.nblk, kThreads, 0, s>>>(n, j, (const double*)V, ldv,
+                                                  (const double*)cs, (const double*)cp,
+                                                  (const double*)sc, (double*)u, (double*)z);
+  }
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
 template <typename T>
 static hipError_t project_t(int64_t n, int ncols, const T* V, int64_t ldv, const T* w, T* part,
                             T* h, T* hsum, int mode, hipStream_t s) {

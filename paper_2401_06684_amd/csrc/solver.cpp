@@ -49,9 +49,12 @@ Layout make_layout(const Op& op, int m_max, uint32_t flags, bool with_poly) {
   L.off_Q = take((size_t)L.ldv * es);
   L.off_R = take((size_t)L.ldv * es);
   L.off_S = take((size_t)L.ldv * es);
-  // per-block partial sums of one projection (Lanczos projects on one vector)
-  L.off_part = take((size_t)((L.band ? 1 : m_max) + 2) * rp.nblk * es + 64);
-  L.off_h = take((size_t)(m_max + 2) * es);
+  // per-block partial sums of one projection (Lanczos projects on one
+  // vector; the delayed-reorthogonalization step projects two vectors on
+  // m_max + 1 columns)
+  L.off_part = take((size_t)(L.band ? 3 : 2 * m_max + 4) * rp.nblk * es + 64);
+  L.off_h = take((size_t)(2 * m_max + 4) * es);
+  L.off_dc = take((size_t)(2 * m_max + 4) * es);
   L.off_H = take((size_t)L.ldh * m_max * es);
   L.off_nrm = take(8 * sizeof(double));
   L.off_z = take((size_t)(m_max + 1) * es);
@@ -386,10 +389,20 @@ struct HostH {
   bool band = false;        // Lanczos: column j holds rows j and j + 1 only
   int dtype = FA_F64;
   std::vector<double> buf;  // column-major, ldh rows, (complex interleaved)
+  size_t off(int i, int j) const { return (size_t)j * ldh + (band ? i - j : i); }
   cd get(int i, int j) const {
-    const size_t o = (size_t)j * ldh + (band ? i - j : i);
+    const size_t o = off(i, j);
     if (dtype == FA_C128) return cd(buf[2 * o], buf[2 * o + 1]);
     return cd(buf[o], 0.0);
+  }
+  void set(int i, int j, cd v) {
+    const size_t o = off(i, j);
+    if (dtype == FA_C128) {
+      buf[2 * o] = v.real();
+      buf[2 * o + 1] = v.imag();
+    } else {
+      buf[o] = v.real();
+    }
   }
 };
 
@@ -444,6 +457,12 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   // Algorithm 2 (right preconditioning); with q == 1 it is Algorithm 1
   const bool right = (flags & FA_RIGHT_PREC) && K > 0;
   if (two_pass && (!lanczos || (flags & FA_RIGHT_PREC))) return FA_ERR_UNSUPPORTED;
+  // Arnoldi: CGS2 with the reorthogonalization delayed by one step (one sweep
+  // of projections and one of updates per step), unless FA_CGS2 asks for the
+  // two classical passes in each step; the right-preconditioned variant keeps
+  // CGS2 (its stored y_j would need the same delayed correction)
+  const bool dcgs2 = !lanczos && !right && !(flags & FA_CGS2);
+  void* const dcoef = at(ws, L.off_dc);
 
   char* V = at(ws, L.off_V);
   char* Y = right ? at(ws, L.off_Y) : nullptr;
@@ -547,6 +566,18 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       if (r2 != w) FA_HIP(launch_scale(op.dtype, n, cd(1.0), r2, w, s));
     }
     // orthogonalization against v_1..v_j (h_ij = v_i^H w)
+    if (dcgs2) {
+      // column j + 1 stays unnormalized (u_{j+1}); step j also finishes q_j
+      if (j == 0) {
+        FA_HIP(launch_project(op.dtype, n, 1, V, L.ldv, w, part, hcur, Hcol(0), 1, s));
+        FA_HIP(launch_update(op.dtype, n, 1, V, L.ldv, hcur, w, part, nullptr, s));
+        ips += 1;
+      } else {
+        FA_HIP(launch_dcgs2(op.dtype, n, j, V, L.ldv, part, hcur, Hd, L.ldh, dcoef, s));
+        ips += 2 * (j + 1);
+      }
+      return FA_OK;
+    }
     if (lanczos) {
       if (j > 0)  // w -= beta_{j-1} v_{j-1}, beta_{j-1} = H(j, j-1)
         FA_HIP(launch_update(op.dtype, n, 1, Vc(j - 1), L.ldv, Hent(j, j - 1), w, part, nullptr,
@@ -604,7 +635,8 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   H.band = L.band;
   H.dtype = op.dtype;
   H.buf.assign((size_t)L.ldh * m_max * (op.dtype == FA_C128 ? 2 : 1), 0.0);
-  int copied = 0;          // columns of H already on the host
+  int copied = 0;          // columns of H final on the host
+  int refresh = 0;         // first column to copy again at the next check
   double colmax = 0.0;     // largest column norm of H seen (breakdown scale)
   std::vector<cd> z, zprev;
   int m = m_max;
@@ -618,9 +650,32 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     const bool check = (tol > 0.0) ? (jj % k_chk == 0 || jj == m_max) : (jj == m_max);
     if (!check) continue;
     // copy the new columns of H to the host
-    FA_HIP(hipMemcpyAsync(H.buf.data() + (size_t)copied * L.ldh * (es / 8), Hcol(copied),
-                          (size_t)(jj - copied) * L.ldh * es, hipMemcpyDeviceToHost, s));
-    FA_HIP(hipStreamSynchronize(s));
+    const int from = std::min(copied, refresh);
+    FA_HIP(hipMemcpyAsync(H.buf.data() + (size_t)from * L.ldh * (es / 8), Hcol(from),
+                          (size_t)(jj - from) * L.ldh * es, hipMemcpyDeviceToHost, s));
+    if (dcgs2) {
+      // column j still lacks its second pass (done on the device in the next
+      // step): project u_{j+1} on [q_0 .. q_j, u_{j+1}] and finish the host
+      // copy: H(0:j, j) += s', H(j+1, j) = (||u_{j+1}||^2 - ||s'||^2)^{1/2}
+      FA_HIP(launch_project(op.dtype, n, jj + 1, V, L.ldv, Vc(jj), part, hcur, nullptr, 0, s));
+      std::vector<double> sh((size_t)(jj + 1) * (es / 8));
+      FA_HIP(hipMemcpyAsync(sh.data(), hcur, sh.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            s));
+      FA_HIP(hipStreamSynchronize(s));
+      auto sv = [&](int i) {
+        return op.dtype == FA_C128 ? cd(sh[2 * i], sh[2 * i + 1]) : cd(sh[i], 0.0);
+      };
+      double ss = 0.0;
+      for (int i = 0; i <= j; ++i) {
+        H.set(i, j, H.get(i, j) + sv(i));
+        ss += std::norm(sv(i));
+      }
+      const double nu2 = sv(jj).real() - ss;
+      H.set(jj, j, cd(nu2 > 0.0 ? std::sqrt(nu2) : 0.0, 0.0));
+      ips += jj + 1;
+    } else {
+      FA_HIP(hipStreamSynchronize(s));
+    }
     // scan new columns for a lucky breakdown / nonfinite entries
     int mb = -1;
     for (int c = copied; c < jj; ++c) {
@@ -640,6 +695,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       }
     }
     copied = jj;
+    refresh = dcgs2 ? j : jj;
     if (mb > 0) {
       m = mb;
       breakdown = converged = true;

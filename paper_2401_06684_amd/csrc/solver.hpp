@@ -15,6 +15,7 @@ struct Layout {
   size_t off_V = 0, off_Y = 0, off_U = 0, off_P = 0, off_Q = 0, off_R = 0, off_S = 0, off_part = 0, off_h = 0, off_H = 0,
          off_nrm = 0, off_z = 0;
   size_t off_W = 0;  // least-squares polynomial: its d basis vectors (0: none)
+  size_t off_dc = 0; // coefficients of the delayed-reorthogonalization step
   size_t bytes = 0;
 };
 // with_poly: include the storage the op's polynomial needs (least squares)
