@@ -262,12 +262,21 @@ __global__ __launch_bounds__(kThreads) void project2_k(int64_t n, int ncols,
       acc[2 * cc] = acc[2 * cc + 1] = zero(T{});
       if (c0 + cc < ncols) {
         const T* col = V + (int64_t)(c0 + cc) * ldv + r0;
+        if (full) {  // no row checks: all loads of the round issue together
 #pragma unroll
-        for (int q = 0; q < kRpt; ++q) {
-          if (full || r0 + (int64_t)q * kThreads < n) {
+          for (int q = 0; q < kRpt; ++q) {
             const T v = col[q * kThreads];
             acc[2 * cc] = cmad(v, a0[q], acc[2 * cc]);
             acc[2 * cc + 1] = cmad(v, a1[q], acc[2 * cc + 1]);
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < kRpt; ++q) {
+            if (r0 + (int64_t)q * kThreads < n) {
+              const T v = col[q * kThreads];
+              acc[2 * cc] = cmad(v, a0[q], acc[2 * cc]);
+              acc[2 * cc + 1] = cmad(v, a1[q], acc[2 * cc + 1]);
+            }
           }
         }
       }
@@ -333,16 +342,34 @@ __global__ __launch_bounds__(kThreads) void dcgs2_coef_k(int j, const T* __restr
     cs[i] = S[2 * i];
     cp[i] = S[2 * i + 1];
   }
-  __syncthreads();
   if (tid == 0) H[(int64_t)(j - 1) * ldh + j] = mk_real(s_nu, T{});
+}
+
+// first-pass column j of H: (Q_{j+1}^H z - Hbar s) / nu with Hbar = H(0:j,
+// 0:j-1) (column j - 1 finished by dcgs2_coef_k).  64 rows per workgroup
+// (one per lane); the four waves take every fourth column and their partial
+// sums are added in LDS in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void dcgs2_col_k(int j, const T* __restrict__ S, T* H,
+                                                        int64_t ldh, const T* __restrict__ sc) {
+  __shared__ T part[kThreads / 64][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  T t = zero(T{});
+  if (i <= j) {
+#pragma unroll 4
+    for (int c = max(0, i - 1) + wv; c < j; c += 4) t = mad(H[(int64_t)c * ldh + i], S[2 * c], t);
+  }
+  part[wv][lane] = t;
   __syncthreads();
-  // first-pass column j: (Q_{j+1}^H z - Hbar s) / nu, Hbar = H(0:j, 0:j-1)
-  const double nu = s_nu;
-  for (int i = tid; i <= j; i += kThreads) {
-    T t = zero(T{});
-    for (int c = max(0, i - 1); c < j; ++c) t = mad(H[(int64_t)c * ldh + i], S[2 * c], t);
-    const T top = (i < j) ? S[2 * i + 1] : s_gam;
-    H[(int64_t)j * ldh + i] = div_real(top - t, nu);
+  if (wv == 0 && i <= j) {
+    T tt = part[0][lane];
+    tt += part[1][lane];
+    tt += part[2][lane];
+    tt += part[3][lane];
+    const double inv = re_of(sc[0]);
+    const T top = (i < j) ? S[2 * i + 1] : sc[1];
+    H[(int64_t)j * ldh + i] = mk_real(inv, T{}) * (top - tt);
   }
 }
 
@@ -356,17 +383,30 @@ __global__ __launch_bounds__(kThreads) void update2_k(int64_t n, int ncols, cons
   T as[kRpt], ap[kRpt];
 #pragma unroll
   for (int q = 0; q < kRpt; ++q) as[q] = ap[q] = zero(T{});
-  const bool full = r0 + (int64_t)(kRpt - 1) * kThreads < n;
-#pragma unroll 2
-  for (int c = 0; c < ncols; ++c) {
-    const T hs = cs[c], hp = cp[c];
-    const T* col = V + (int64_t)c * ldv + r0;
+  if (r0 + (int64_t)(kRpt - 1) * kThreads < n) {  // full block of rows
+#pragma unroll 4
+    for (int c = 0; c < ncols; ++c) {
+      const T hs = cs[c], hp = cp[c];
+      const T* col = V + (int64_t)c * ldv + r0;
 #pragma unroll
-    for (int q = 0; q < kRpt; ++q) {
-      if (full || r0 + (int64_t)q * kThreads < n) {
+      for (int q = 0; q < kRpt; ++q) {
         const T v = col[q * kThreads];
         as[q] = mad(v, hs, as[q]);
         ap[q] = mad(v, hp, ap[q]);
+      }
+    }
+  } else {
+    for (int c = 0; c < ncols; ++c) {
+      const T hs = cs[c], hp = cp[c];
+      const T* col = V + (int64_t)c * ldv;
+#pragma unroll
+      for (int q = 0; q < kRpt; ++q) {
+        const int64_t r = r0 + (int64_t)q * kThreads;
+        if (r < n) {
+          const T v = col[r];
+          as[q] = mad(v, hs, as[q]);
+          ap[q] = mad(v, hp, ap[q]);
+        }
       }
     }
   }
@@ -399,6 +439,8 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
                                                          nullptr, 0);
     dcgs2_coef_k<cplx><<<1, kThreads, 0, s>>>(j, (const cplx*)S, (cplx*)H, ldh, (cplx*)cs,
                                               (cplx*)cp, (cplx*)sc);
+    dcgs2_col_k<cplx><<<(j + 64) / 64, kThreads, 0, s>>>(j, (const cplx*)S, (cplx*)H, ldh,
+                                                         (const cplx*)sc);
     update2_k<cplx><<<p.nblk, kThreads, 0, s>>>(n, j, (const cplx*)V, ldv, (const cplx*)cs,
                                                 (const cplx*)cp, (const cplx*)sc, (cplx*)u,
                                                 (cplx*)z);
@@ -410,6 +452,8 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
                                                            (double*)S, nullptr, 0);
     dcgs2_coef_k<double><<<1, kThreads, 0, s>>>(j, (const double*)S, (double*)H, ldh,
                                                 (double*)cs, (double*)cp, (double*)sc);
+    dcgs2_col_k<double><<<(j + 64) / 64, kThreads, 0, s>>>(j, (const double*)S, (double*)H, ldh,
+                                                           (const double*)sc);
     update2_k<double><<<p.nblk, kThreads, 0, s>>>(n, j, (const double*)V, ldv,
                                                   (const double*)cs, (const double*)cp,
                                                   (const double*)sc, (double*)u, (double*)z);
