@@ -643,9 +643,23 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   bool converged = false, breakdown = false;
   double est = 1.0;
 
+  // When the host evaluation of H_j^{-1/2} e_1 at a check is expected to take
+  // longer than a step, the next steps (as many as that time covers, fewer
+  // than k) are enqueued before it, so the GPU works while the host does; if
+  // the iteration stops at the check, their output is not used and their
+  // counts are undone.  The host time is predicted from the previous check
+  // (cubic in the order of H), the step time from the wall time between
+  // checks.
+  int ahead_until = 0;        // steps below this index are already enqueued
+  double last_host_ms = 0.0;  // host time of the previous check's H^{-1/2} e_1
+  int last_host_m = 0;
+  double t_resume = now_ms();
+  int j_resume = 0;
   for (int j = 0; j < m_max; ++j) {
-    st = step(j);
-    if (st) return st;
+    if (j >= ahead_until) {
+      st = step(j);
+      if (st) return st;
+    }
     const int jj = j + 1;
     const bool check = (tol > 0.0) ? (jj % k_chk == 0 || jj == m_max) : (jj == m_max);
     if (!check) continue;
@@ -702,9 +716,25 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       break;
     }
     if (tol <= 0.0) break;
+    const int64_t mvms_here = mvms, ips_here = ips;
+    const Prof prof_here = prof;
+    {
+      const double step_ms = (now_ms() - t_resume) / std::max(1, jj - j_resume);
+      const double ratio = last_host_m > 0 ? (double)jj / last_host_m : 0.0;
+      const double host_est = last_host_ms * ratio * ratio * ratio;
+      int r = step_ms > 0.0 ? (int)(host_est / step_ms) : 0;
+      r = std::min(r, std::min(k_chk - 1, m_max - jj));
+      for (int a = 0; a < r; ++a) {
+        st = step(jj + a);
+        if (st) return st;
+      }
+      ahead_until = jj + std::max(r, 0);
+    }
     const double th = now_ms();
     st = host_coeffs(H, jj, lanczos, beta, z);
-    S.ms_host_fH += now_ms() - th;
+    last_host_ms = now_ms() - th;
+    last_host_m = jj;
+    S.ms_host_fH += last_host_ms;
     ++S.checks;
     if (st) return st;
     if (right) {
@@ -737,8 +767,13 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     if (est <= tol) {
       m = jj;
       converged = true;
+      mvms = mvms_here;  // steps enqueued ahead are not part of the result
+      ips = ips_here;
+      prof = prof_here;
       break;
     }
+    t_resume = now_ms();
+    j_resume = std::max(jj, ahead_until);
   }
   // final coefficients (if the loop did not end on a fresh check of size m)
   if ((int)z.size() != m || breakdown) {
