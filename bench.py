@@ -30,6 +30,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "f(A)b solves/s at rel err 1e-8, poly-precond vs plain Arnoldi; SpMV HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of st7_pair<true,true,true> at 128^3 (FETCH_SIZE x 2.00 +
+# WRITE_SIZE x 1.00, the factors of a 2 GiB copy), from the rocprofv3 counter
+# runs in profiles/st7_chain_convdiff128_deg16_hbm_counters.md
+PAIR_TRAFFIC_BYTES = (64540 + 32768) * 1024
 
 
 def log(msg):
@@ -248,7 +252,7 @@ def main():
         "roofline": {"bound": "hbm",
                      "kernel": "st7_pair<true,true,true> (two Clenshaw terms per launch)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": PAIR_TRAFFIC_BYTES,
                      "bytes_per_launch": bytes_avg, "avg_launch_us": avg_ms * 1e3,
                      "launches_timed": n_chain},
         "cpu_baseline": cpu,

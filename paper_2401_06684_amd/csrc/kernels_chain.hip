@@ -138,6 +138,9 @@ static hipError_t launch_st7(const Op& op, const void* x, const void* y0, const 
 #ifndef FA_PAIR_TY
 #define FA_PAIR_TY 8
 #endif
+#ifndef FA_PAIR_ZFIRST
+#define FA_PAIR_ZFIRST 0
+#endif
 #ifndef FA_PAIR_BLOCKS
 #define FA_PAIR_BLOCKS 512
 #endif
@@ -177,7 +180,12 @@ __global__ __launch_bounds__(P_THREADS) void st7_pair(St7 s, int kz, int gx, int
   __shared__ T xs[4][P_XH][P_XW];
   __shared__ T ss[3][P_SH][P_SW];
   const int lid = xcd_contiguous(blockIdx.x, nwg);
+#if FA_PAIR_ZFIRST
+  const int gz = nwg / (gx * gy);
+  const int bz = lid % gz, bx = (lid / gz) % gx, by = lid / (gz * gx);
+#else
   const int bx = lid % gx, by = (lid / gx) % gy, bz = lid / (gx * gy);
+#endif
   const int i0 = bx * P_TX, j0 = by * P_TY;
   const int k0 = bz * kz, k1 = min(k0 + kz, s.nz);
   const int tid = threadIdx.x;
