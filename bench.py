@@ -56,6 +56,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (block) leg")
     ap.add_argument("--batch-only", action="store_true", help="only run the batched leg")
+    ap.add_argument("--csr-only", action="store_true", help="only run the CSR SpMV leg")
     ap.add_argument("--serve-only", action="store_true", help="only run the serving leg")
     ap.add_argument("--qps", type=float, default=2000.0, help="serving arrival rate")
     ap.add_argument("--serve-requests", type=int, default=1000)
@@ -82,6 +83,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of 2 GiB done")
+        return
+    if args.csr_only:
+        print(json.dumps({"csr_spmv": csr_leg(fa, torch, wl, dev)}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"batched": batched_leg(fa, torch, wl, dev)}), flush=True)
@@ -227,6 +231,9 @@ def main():
         op0.release_workspace()
         del op0
 
+    # ---- CSR SpMV (the operator of the directed-graph example) ------------
+    extra["csr_spmv"] = csr_leg(fa, torch, wl, dev)
+
     # ---- batched: 64 right-hand sides as one block Arnoldi ------------------
     if not args.no_batch:
         extra["batched"] = batched_leg(fa, torch, wl, dev)
@@ -271,6 +278,35 @@ def main():
         **extra,
     }
     print(json.dumps(line), flush=True)
+
+
+def csr_leg(fa, torch, wl, dev):
+    """y = A x with the CSR kernel: a synthetic directed power-law graph
+    Laplacian of the shape of the paper's graph example (n = 281,903, about
+    2.59M stored entries) and the 2D Poisson 32 x 32 matrix.  GB/s counts
+    row pointers, column indices, values, x and y once."""
+    out = {}
+    for name, (rp, ci, va) in (
+            ("powerlaw_digraph_281903", wl.powerlaw_digraph_laplacian_csr(281903, 2594228, seed=5)),
+            ("poisson2d_32", wl.stencil_csr((32, 32, 1), wl.laplace_stencil(2)))):
+        op = fa.CSR(rp, ci, va, device=dev)
+        x = torch.from_numpy(wl.rhs(op.n, seed=1)).to(dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            op.op_apply(x, out=y)
+        torch.cuda.synchronize()
+        reps = 50
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            op.op_apply(x, out=y)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        n, nnz = op.n, len(ci)
+        nbytes = 4 * (n + 1) + 12 * nnz + 16 * n
+        out[name] = {"n": n, "nnz": nnz, "us_per_spmv": dt * 1e6,
+                     "GBs": nbytes / dt / 1e9, "bytes": nbytes}
+        log(f"CSR SpMV {name}: {dt * 1e6:.1f} us, {nbytes / dt / 1e9:.0f} GB/s")
+    return out
 
 
 def batched_leg(fa, torch, wl, dev):

@@ -166,10 +166,15 @@ typedef struct {
  *   d_vals       : double[nnz] (FA_F64) or double complex[nnz] (FA_C128)
  *   dtype        : FA_F64 or FA_C128 (vectors passed to fa_apply use the same type)
  *   flags        : FA_HERMITIAN to select Lanczos in fa_apply
- * The arrays are not copied or validated on the device; they must stay alive
- * and unchanged until fa_destroy.  A CSR op has no spectral interval until
- * fa_set_spectral_interval is called.
- * Errors: FA_ERR_ARG.
+ * The arrays are not copied; they must stay alive and unchanged until
+ * fa_destroy.  The row pointers are read once to the host (a synchronous
+ * copy) to check them and to pick the work split: rows up to 16 times the
+ * mean length (rounded to a power of two) are summed by lane groups, longer
+ * ones (at most 900; the threshold doubles until so) by one 1024-thread
+ * workgroup each.  Column indices are not validated.  A CSR op has no
+ * spectral interval until fa_set_spectral_interval is called.
+ * Errors: FA_ERR_ARG (including row pointers that do not start at 0, end at
+ * nnz and never decrease), FA_ERR_HIP.
  */
 int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
                   const int32_t* d_colind, const void* d_vals, int dtype, uint32_t flags,

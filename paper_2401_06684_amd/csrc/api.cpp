@@ -2,6 +2,7 @@
 // dispatch to the runtime.  No exception crosses the boundary.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -76,6 +77,37 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
     int g = 1;
     while (g < 64 && g < avg) g <<= 1;
     op.csr_group = g;
+    // rows longer than 16 groups' worth (the tail of a skewed distribution),
+    // at most kCsrLongMax of them, go to the one-workgroup-per-row kernel
+    std::vector<int32_t> rp((size_t)n + 1);
+    if (hipMemcpy(rp.data(), d_rowptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+        hipSuccess) {
+      delete h;
+      return FA_ERR_HIP;
+    }
+    // the row pointers must describe nnz entries in order (the kernels index
+    // with them unchecked)
+    if (rp[0] != 0 || rp[(size_t)n] != nnz) {
+      delete h;
+      return FA_ERR_ARG;
+    }
+    for (int64_t r = 0; r < n; ++r)
+      if (rp[r + 1] < rp[r]) {
+        delete h;
+        return FA_ERR_ARG;
+      }
+    int64_t thr = 16 * (int64_t)g;
+    for (;;) {
+      std::vector<int32_t> lr;
+      for (int64_t r = 0; r < n && (int)lr.size() <= kCsrLongMax; ++r)
+        if (rp[r + 1] - rp[r] > thr) lr.push_back((int32_t)r);
+      if ((int)lr.size() <= kCsrLongMax) {
+        op.csr_long_rows = lr;
+        op.csr_long_thr = (int)std::min<int64_t>(thr, 0x7fffffff);
+        break;
+      }
+      thr *= 2;
+    }
     *out = h;
     return FA_OK;
   });

@@ -56,6 +56,10 @@ struct Op {
   const void* vals = nullptr;
   int64_t nnz = 0;
   int csr_group = 1;  // lanes per row
+  // rows longer than csr_long_thr (at most kCsrLongMax of them, sorted) are
+  // left to a kernel with one 1024-thread workgroup per row
+  int csr_long_thr = 0x7fffffff;
+  std::vector<int32_t> csr_long_rows;
   // stencil
   int dims[4] = {1, 1, 1, 1};
   double coef[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -74,6 +78,8 @@ struct Op {
 };
 // a fresh process-wide unique id (thread-safe)
 uint64_t next_op_uid();
+
+constexpr int kCsrLongMax = 900;  // long rows passed by value to their kernel
 
 // storage precision of the vectors of one chain launch
 enum Prec { P64 = 0, P32 = 1 };

@@ -394,6 +394,9 @@ hipError_t launch_chain_pair(const Op& op, const void* x, const void* y0, const 
 // --------------------------------------------------------------------------
 // CSR, real or complex values: G lanes per row (G = power of two <= 64 close
 // to the mean row length), row sums reduced with shuffles inside the group.
+// Rows longer than `thr` (the long tail of a power-law degree distribution)
+// are skipped here and summed by csr_long, one 1024-thread workgroup each, so
+// that no lane group walks tens of thousands of entries alone.
 // --------------------------------------------------------------------------
 template <typename T, int G, bool Y0, bool Y1>
 __global__ __launch_bounds__(256) void csr_chain(int n, const int32_t* __restrict__ rowptr,
@@ -401,18 +404,53 @@ __global__ __launch_bounds__(256) void csr_chain(int n, const int32_t* __restric
                                                  const T* __restrict__ vals,
                                                  const T* __restrict__ x,
                                                  const T* __restrict__ y0, const T* y1, T* out,
-                                                 T al, T be, T g0, T g1) {
+                                                 T al, T be, T g0, T g1, int thr) {
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t row = gt / G;
   const int lane = (int)(gt % G);
   if (row >= n) return;  // whole groups leave together (G divides 64)
   T acc = zero(T{});
-  const int e1 = rowptr[row + 1];
-  for (int e = rowptr[row] + lane; e < e1; e += G) acc = mad(vals[e], x[colind[e]], acc);
+  const int e0 = rowptr[row], e1 = rowptr[row + 1];
+  if (e1 - e0 > thr) return;  // a long row: csr_long writes it
+  for (int e = e0 + lane; e < e1; e += G) acc = mad(vals[e], x[colind[e]], acc);
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) acc += shfl_down(acc, off, G);
   if (lane == 0) {
     T r = mad(al, acc, be * x[row]);
+    if (Y0) r = mad(g0, y0[row], r);
+    if (Y1) r = mad(g1, y1[row], r);
+    out[row] = r;
+  }
+}
+
+struct LongRows {
+  int count;
+  int idx[kCsrLongMax];
+};
+
+// one long row per workgroup of 1024 threads; the partial sums are added in a
+// fixed order (wavefront shuffles, then the 16 wavefront sums in LDS)
+template <typename T, bool Y0, bool Y1>
+__global__ __launch_bounds__(1024) void csr_long(const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ colind,
+                                                 const T* __restrict__ vals,
+                                                 const T* __restrict__ x,
+                                                 const T* __restrict__ y0, const T* y1, T* out,
+                                                 T al, T be, T g0, T g1, LongRows lr) {
+  __shared__ T ws[16];
+  const int row = lr.idx[blockIdx.x];
+  const int e0 = rowptr[row], e1 = rowptr[row + 1];
+  T acc = zero(T{});
+#pragma unroll 4
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += 1024) acc = mad(vals[e], x[colind[e]], acc);
+  acc = wave_sum(acc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) ws[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T t = ws[0];
+    for (int w = 1; w < 16; ++w) t += ws[w];
+    T r = mad(al, t, be * x[row]);
     if (Y0) r = mad(g0, y0[row], r);
     if (Y1) r = mad(g1, y1[row], r);
     out[row] = r;
@@ -428,14 +466,28 @@ static void launch_csr_g(const Op& op, const T* x, const T* y0, const T* y1, T* 
   auto rp = op.rowptr;
   auto ci = op.colind;
   auto va = (const T*)op.vals;
+  const int thr = op.csr_long_thr;
   if (y0 && y1)
-    csr_chain<T, G, true, true><<<grid, 256, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1);
+    csr_chain<T, G, true, true><<<grid, 256, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr);
   else if (y0)
-    csr_chain<T, G, true, false><<<grid, 256, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1);
+    csr_chain<T, G, true, false><<<grid, 256, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr);
   else if (y1)
-    csr_chain<T, G, false, true><<<grid, 256, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1);
+    csr_chain<T, G, false, true><<<grid, 256, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr);
   else
-    csr_chain<T, G, false, false><<<grid, 256, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1);
+    csr_chain<T, G, false, false><<<grid, 256, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr);
+  const int nl = (int)op.csr_long_rows.size();
+  if (nl == 0) return;
+  LongRows lr;
+  lr.count = nl;
+  for (int i = 0; i < nl; ++i) lr.idx[i] = op.csr_long_rows[i];
+  if (y0 && y1)
+    csr_long<T, true, true><<<nl, 1024, 0, st>>>(rp, ci, va, x, y0, y1, out, al, be, g0, g1, lr);
+  else if (y0)
+    csr_long<T, true, false><<<nl, 1024, 0, st>>>(rp, ci, va, x, y0, y1, out, al, be, g0, g1, lr);
+  else if (y1)
+    csr_long<T, false, true><<<nl, 1024, 0, st>>>(rp, ci, va, x, y0, y1, out, al, be, g0, g1, lr);
+  else
+    csr_long<T, false, false><<<nl, 1024, 0, st>>>(rp, ci, va, x, y0, y1, out, al, be, g0, g1, lr);
 }
 
 template <typename T>

@@ -730,3 +730,45 @@ def test_ls_polynomial_errors():
     assert e.value.status == fa()._lib.FA_ERR_UNSUPPORTED
     x, st = op.apply(b, m_max=100, tol=1e-10)
     assert st["converged"]
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_csr_long_rows(complex_):
+    """Rows far longer than the mean (a power-law tail) are summed by their own
+    one-workgroup-per-row kernel: A x and a Ritz q(A) x (whose Newton terms
+    combine A r with v) against the oracle."""
+    rng = np.random.default_rng(7)
+    n = 3000
+    rows, cols = [], []
+    for i in range(n):
+        k = 3000 if i % 97 == 0 else (1200 if i % 151 == 0 else 4)
+        c = rng.choice(n, size=min(k, n), replace=False)
+        rows += [i] * len(c)
+        cols += list(c)
+    rows, cols = np.array(rows), np.array(cols)
+    vals = rng.standard_normal(len(rows)) * 0.01
+    if complex_:
+        vals = vals + 0.01j * rng.standard_normal(len(rows))
+    import scipy.sparse as sp
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    A = A + sp.diags(np.asarray(abs(A).sum(axis=1)).ravel() + 1.0)
+    A = A.tocsr()
+    A.sort_indices()
+    rp, ci, va = A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data
+    op = fa().CSR(rp, ci, va)
+    x = wl.rhs(n, seed=3, complex_=complex_)
+    assert_close(host(op.op_apply(dev(x))), ops.csr_apply(rp, ci, va, x), 1e-14)
+    start = wl.rhs(n, seed=4, complex_=complex_)
+    op.poly_setup(6, "ritz", start=dev(start))
+    Aop = lambda v: ops.csr_apply(rp, ci, va, v)
+    q = pl.ritz(Aop, start, 6, real_operator=not complex_)
+    ref, _ = q.apply(Aop, x)
+    assert_close(host(op.poly_apply(dev(x))), ref, 1e-9)
+
+
+def test_csr_rejects_bad_row_pointers():
+    rp = np.array([0, 2, 1, 3], dtype=np.int32)
+    ci = np.array([0, 1, 2], dtype=np.int32)
+    va = np.ones(3)
+    with pytest.raises(fa().FAError):
+        fa().CSR(rp, ci, va)
