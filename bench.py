@@ -57,6 +57,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (block) leg")
     ap.add_argument("--batch-only", action="store_true", help="only run the batched leg")
     ap.add_argument("--csr-only", action="store_true", help="only run the CSR SpMV leg")
+    ap.add_argument("--wilson-only", action="store_true", help="only run the Wilson leg")
     ap.add_argument("--serve-only", action="store_true", help="only run the serving leg")
     ap.add_argument("--qps", type=float, default=2000.0, help="serving arrival rate")
     ap.add_argument("--serve-requests", type=int, default=1000)
@@ -83,6 +84,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of 2 GiB done")
+        return
+    if args.wilson_only:
+        print(json.dumps({"wilson4d_16": wilson_leg(fa, torch, wl, dev)}), flush=True)
         return
     if args.csr_only:
         print(json.dumps({"csr_spmv": csr_leg(fa, torch, wl, dev)}), flush=True)
@@ -231,6 +235,9 @@ def main():
         op0.release_workspace()
         del op0
 
+    # ---- Wilson 16^4 (the lattice operator) --------------------------------
+    extra["wilson4d_16"] = wilson_leg(fa, torch, wl, dev)
+
     # ---- CSR SpMV (the operator of the directed-graph example) ------------
     extra["csr_spmv"] = csr_leg(fa, torch, wl, dev)
 
@@ -278,6 +285,40 @@ def main():
         **extra,
     }
     print(json.dumps(line), flush=True)
+
+
+def wilson_leg(fa, torch, wl, dev):
+    """The 4D Wilson-Dirac-like operator on 16^4 (links exp(0.3 i H), m0 =
+    0.05), A^{-1/2} b with a Ritz polynomial of degree 16, tol 1e-8, and
+    the same with q == 1.  The Newton middle terms (read r with its 8
+    neighbours, the links, v; write r') are timed with HIP events: 4 spinor
+    fields + the links = 75.5 MB per launch."""
+    L = 16
+    op = fa.Wilson(wl.su3_links(L, eps=0.3, seed=1), 0.05, device=dev)
+    start = torch.from_numpy(wl.rhs(op.n, seed=11, complex_=True)).to(dev)
+    b = torch.from_numpy(wl.rhs(op.n, seed=0, complex_=True)).to(dev)
+    out = {}
+    for deg, m_max in ((16, 200), (0, 1000)):
+        op.poly_setup(deg, "ritz", start=start)
+        op.apply(b, m_max=m_max, tol=1e-8)
+        torch.cuda.synchronize()
+        reps = 3 if deg else 1
+        t0 = time.perf_counter()
+        sts = [op.apply(b, m_max=m_max, tol=1e-8, profile=deg > 0)[1] for _ in range(reps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        d = {"solves_per_s": 1.0 / dt, "iters": sts[-1]["iters"], "mvms": sts[-1]["mvms"]}
+        if deg:
+            nch = sum(s_["n_chain"] for s_ in sts)
+            ms = sum(s_["ms_chain"] for s_ in sts)
+            d["chain_launch_us"] = ms / nch * 1e3
+            d["chain_bytes"] = sts[-1]["chain_bytes"]
+            d["chain_GBs"] = sts[-1]["chain_bytes"] / (ms / nch * 1e-3) / 1e9
+        out[f"degree_{deg}"] = d
+        log(f"Wilson 16^4 degree {deg}: {1.0 / dt:.2f} solves/s, m = {sts[-1]['iters']}"
+            + (f", chain launch {d['chain_launch_us']:.1f} us, {d['chain_GBs']:.0f} GB/s" if deg else ""))
+    op.release_workspace()
+    return out
 
 
 def csr_leg(fa, torch, wl, dev):
