@@ -195,10 +195,14 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
  *     periodic, chiral-basis Euclidean gamma matrices; 12 complex per site,
  *     vectors [t][z][y][x][spin 4][colour 3] (FA_C128).  d_links: device
  *     double complex[4][Lt][Lz][Ly][Lx][3][3] (direction mu = x, y, z, t, row
- *     major 3x3), borrowed.  The Wilson-Dirac operator is the matrix of
- *     Sec. 6, Example 2 (without clover term and chemical potential).
+ *     major 3x3), read once on hip_stream (which is synchronized) into device
+ *     memory the op owns, reordered so that one link element of consecutive
+ *     sites is contiguous; the caller's array may be freed after the call
+ *     (36 V complex doubles stay allocated until fa_destroy).  The
+ *     Wilson-Dirac operator is the matrix of Sec. 6, Example 2 (without
+ *     clover term and chemical potential).
  *   flags: FA_HERMITIAN allowed only for symmetric stencils.
- * Errors: FA_ERR_ARG.
+ * Errors: FA_ERR_ARG, FA_ERR_HIP (Wilson: the link copy failed).
  */
 int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double* params,
                       int nparams, const void* d_links, uint32_t flags, void* hip_stream);

@@ -302,9 +302,11 @@ class Wilson(Operator):
         h = C.c_void_p()
         d4 = (C.c_int32 * 4)(Lx, Ly, Lz, Lt)
         p = (C.c_double * 1)(float(m0))
-        st = lib().fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1, _ptr(U), 0, None)
+        # the library copies the links (reordered) on this stream and waits
+        st = lib().fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1, _ptr(U), 0,
+                                     _stream(dev))
         check(st, "fa_create_stencil")
-        super().__init__(h, dev, (U,))
+        super().__init__(h, dev, ())
         self.lattice = (Lt, Lz, Ly, Lx)
 
 

@@ -115,7 +115,6 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
 
 int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double* params,
                       int nparams, const void* d_links, uint32_t flags, void* hip_stream) {
-  (void)hip_stream;
   if (!out || !dims || !params) return FA_ERR_ARG;
   if (flags & ~uint32_t(FA_HERMITIAN)) return FA_ERR_ARG;
   for (int d = 0; d < 4; ++d)
@@ -153,9 +152,17 @@ int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double*
       op.dtype = FA_C128;
       op.n = V * 12;
       for (int d = 0; d < 4; ++d) op.dims[d] = dims[d];
-      op.links = d_links;
       op.m0 = params[0];
       if (!std::isfinite(op.m0)) return FA_ERR_ARG;
+      // own structure-of-arrays copy of the links (coalesced link loads)
+      void* us = nullptr;
+      if (hipMalloc(&us, (size_t)V * 36 * 16) != hipSuccess) return FA_ERR_HIP;
+      op.links_owned = std::shared_ptr<void>(us, [](void* p) { (void)hipFree(p); });
+      op.links = us;
+      hipStream_t st = stream_of(hip_stream);
+      if (launch_wilson_links_soa(V, d_links, us, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return FA_ERR_HIP;
     } else {
       return FA_ERR_ARG;
     }

@@ -508,15 +508,33 @@ static hipError_t launch_csr(const Op& op, const T* x, const T* y0, const T* y1,
 }
 
 // --------------------------------------------------------------------------
-// Wilson-Dirac-like operator, complex FP64, one thread per lattice site.
+// Wilson-Dirac-like operator, complex FP64.
 //   (D x)(s) = (4 + m0) x(s) - 1/2 sum_mu [(1 - g_mu) U_mu(s) x(s + mu)
 //                                         + (1 + g_mu) U_mu(s - mu)^H x(s - mu)]
-// (1 -+ g_mu) has rank 2 in spin space: the hop projects the 4-spinor to a
-// 2-spinor h, multiplies h by the 3x3 link (6 colour matvecs instead of 12) and
-// rebuilds the lower two spins from h.  Chiral basis:
-//   g_k = [[0, -i s_k], [i s_k, 0]] (k = x, y, z), g_t = [[0, I], [I, 0]].
-// For (1 - g_k): h = u + i s_k d, lower = -i s_k h; for (1 + g_k): h = u - i s_k d,
-// lower = i s_k h; for g_t: h = u -+ d, lower = -+ h  (u, d = upper / lower spins).
+// Chiral basis: g_k = [[0, -i s_k], [i s_k, 0]] (k = x, y, z), g_t = [[0, I], [I, 0]].
+// (1 + sg g_mu), sg = -1 or +1, has rank 2 in spin space: with u, d the upper
+// and lower spin pairs, h = u + sg M_mu d and the lower pair of the result is
+// sg M_mu^{-1} h, where M_k = -i s_k and M_t = I.  A hop therefore projects the
+// 4-spinor to the 2-spinor h, multiplies h by the 3x3 link (6 colour matvecs
+// instead of 12) and rebuilds the lower pair from the transported h.
+//
+// Every M_mu is diagonal or anti-diagonal with entries in {+-1, +-i}, so the
+// projections are written branch-free from a few per-direction unit
+// coefficients; multiplying by a unit in {+-1, +-i} is exact, so each hop
+// rounds exactly as the direction-specialised formulas would.
+//
+// Work split: one wave per 16 consecutive sites, four lanes per site, one per
+// direction mu (lane = 4 site + mu).  A lane does the forward and the
+// backward hop of its direction; the quad then reduce-scatters the four
+// partial sums so that lane mu owns spin row mu of the result.
+// Memory access: a spinor is 192 contiguous bytes, so a lane that reads its
+// own neighbour's spinor makes every load instruction touch 64 cache lines.
+// Instead the 16 lanes of one direction read the 16 neighbour spinors as
+// consecutive 16-byte chunks (contiguous but for lattice wrap-around) into a
+// wave-private LDS slice, and each lane then takes its spinor from there; the
+// result goes out the same way.  The links are kept in a structure-of-arrays
+// copy Us[mu][e][s] (made once at creation), so that link element e of 16
+// consecutive sites is 256 contiguous bytes.
 // --------------------------------------------------------------------------
 struct Wil {
   int L0, L1, L2, L3;  // x, y, z, t extents
@@ -524,153 +542,219 @@ struct Wil {
   double diag;         // 4 + m0
 };
 
-// s_k applied with a factor i: returns i s_k [a; b]
-__device__ __forceinline__ void isig(int k, cplx a, cplx b, cplx& o0, cplx& o1) {
-  if (k == 0) {        // i s_x [a; b] = [i b; i a]
-    o0 = times_i(b);
-    o1 = times_i(a);
-  } else if (k == 1) { // i s_y [a; b] = [b; -a]
-    o0 = b;
-    o1 = cplx{-a.x, -a.y};
-  } else {             // i s_z [a; b] = [i a; -i b]
-    o0 = times_i(a);
-    o1 = times_mi(b);
-  }
+// p * a for a unit p = pr + i pi with pr, pi in {0, +-1}: exact
+__device__ __forceinline__ cplx unit_mul(double pr, double pi, cplx a) {
+  return {pr * a.x - pi * a.y, pr * a.y + pi * a.x};
 }
 
-// h (2 spins x 3 colours) = upper half of (1 + sgn g_mu) psi; sgn = -1 or +1
-__device__ __forceinline__ void spin_project(int mu, int sgn, const cplx* psi, cplx h[2][3]) {
+// value of lane (l ^ 1) or (l ^ 2) inside a quad (DPP quad permutation)
+template <int X>
+__device__ __forceinline__ double quad_xor(double v) {
+  constexpr int ctrl = X == 1 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] / [2,3,0,1]
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int X>
+__device__ __forceinline__ cplx quad_xor(cplx v) {
+  return {quad_xor<X>(v.x), quad_xor<X>(v.y)};
+}
+
+constexpr int kWilSites = 16;                      // sites per wave
+constexpr int kWilChunks = kWilSites * 12;         // 16-byte chunks of their spinors
+constexpr int kWilDirStride = kWilChunks + 1;      // LDS slice of one direction (+1:
+                                                   // spreads the 4 directions over banks)
+
+struct HopCoef {
+  double sg;  // -1: forward hop (1 - g_mu), +1: backward hop (1 + g_mu)
+  bool swap;  // M_mu anti-diagonal
+  double p0r, p0i, p1r, p1i;  // M_mu entries (rows 0, 1)
+  double q0r, q0i, q1r, q1i;  // M_mu^{-1} entries (rows 0, 1)
+};
+
+// one hop: acc += (1 + sg g_mu) W x(nb), W = U (forward) or U^H (backward).
+// xs: this lane's neighbour spinor in LDS; Ue: link element 0 of the site in
+// the structure-of-arrays copy, element e at Ue[e V].
+template <bool Adj>
+__device__ __forceinline__ void wilson_hop(const cplx* xs, const cplx* __restrict__ Ue,
+                                           int64_t V, const HopCoef& k, cplx acc[4][3]) {
+  cplx u[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = Ue[e * V];
+  cplx h[2][3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const cplx u0 = psi[0 * 3 + c], u1 = psi[1 * 3 + c], d0 = psi[2 * 3 + c], d1 = psi[3 * 3 + c];
-    if (mu == 3) {  // g_t: h = u + sgn d
-      h[0][c] = sgn > 0 ? u0 + d0 : u0 - d0;
-      h[1][c] = sgn > 0 ? u1 + d1 : u1 - d1;
-    } else {        // g_k: h = u - sgn i s_k d
-      cplx t0, t1;
-      isig(mu, d0, d1, t0, t1);
-      h[0][c] = sgn > 0 ? u0 - t0 : u0 + t0;
-      h[1][c] = sgn > 0 ? u1 - t1 : u1 + t1;
-    }
+    const cplx u0 = xs[0 * 3 + c], u1 = xs[1 * 3 + c], d0 = xs[2 * 3 + c], d1 = xs[3 * 3 + c];
+    const cplx e0 = k.swap ? d1 : d0, e1 = k.swap ? d0 : d1;
+    h[0][c] = u0 + k.sg * unit_mul(k.p0r, k.p0i, e0);
+    h[1][c] = u1 + k.sg * unit_mul(k.p1r, k.p1i, e1);
   }
-}
-
-// acc += full spinor rebuilt from the projected-and-transported h
-__device__ __forceinline__ void spin_accumulate(int mu, int sgn, const cplx g[2][3],
-                                                cplx acc[4][3]) {
+  cplx g[2][3];
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (Adj)  // (U^H h)_a = sum_b conj(U_ba) h_b
+        g[sp][a] = cmad(u[2 * 3 + a], h[sp][2],
+                        cmad(u[1 * 3 + a], h[sp][1], cmad(u[0 * 3 + a], h[sp][0], cplx{0.0, 0.0})));
+      else
+        g[sp][a] = mad(u[a * 3 + 2], h[sp][2], mad(u[a * 3 + 1], h[sp][1], u[a * 3 + 0] * h[sp][0]));
+    }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     acc[0][c] += g[0][c];
     acc[1][c] += g[1][c];
-    if (mu == 3) {  // lower = sgn h
-      if (sgn > 0) { acc[2][c] += g[0][c]; acc[3][c] += g[1][c]; }
-      else { acc[2][c] -= g[0][c]; acc[3][c] -= g[1][c]; }
-    } else {        // lower = sgn i s_k h
-      cplx t0, t1;
-      isig(mu, g[0][c], g[1][c], t0, t1);
-      if (sgn > 0) { acc[2][c] += t0; acc[3][c] += t1; }
-      else { acc[2][c] -= t0; acc[3][c] -= t1; }
-    }
+    const cplx f0 = k.swap ? g[1][c] : g[0][c], f1 = k.swap ? g[0][c] : g[1][c];
+    acc[2][c] += k.sg * unit_mul(k.q0r, k.q0i, f0);
+    acc[3][c] += k.sg * unit_mul(k.q1r, k.q1i, f1);
   }
 }
 
+// the 16 neighbour spinors of this lane's direction into the wave's LDS slice
+// (chunk q of the slice = element q % 12 of the spinor of site q / 12); nb is
+// this lane's neighbour site, lanes 4 j + mu hold those of site j
+__device__ __forceinline__ void wilson_stage(const cplx* __restrict__ x, int nb, int sl, int mu,
+                                             cplx* slice) {
+  cplx v[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const int q = k * kWilSites + sl, j = q / 12;
+    const int nbj = __shfl(nb, 4 * j + mu, 64);
+    v[k] = x[(int64_t)nbj * 12 + (q - 12 * j)];
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) slice[k * kWilSites + sl] = v[k];
+}
+
 template <bool Y0, bool Y1>
-__global__ __launch_bounds__(128) void wilson_chain(Wil w, const cplx* __restrict__ U,
-                                                    const cplx* __restrict__ x,
-                                                    const cplx* __restrict__ y0,
-                                                    const cplx* y1, cplx* out, cplx al,
-                                                    cplx be, cplx g0, cplx g1) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= w.V) return;
-  int co[4];
+__global__ __launch_bounds__(64) void wilson_chain(Wil w, const cplx* __restrict__ Us,
+                                                   const cplx* __restrict__ x,
+                                                   const cplx* __restrict__ y0,
+                                                   const cplx* y1, cplx* out, cplx al,
+                                                   cplx be, cplx g0, cplx g1) {
+  __shared__ cplx lds[4 * kWilDirStride];
+  const int lane = threadIdx.x;
+  const int sl = lane >> 2, mu = lane & 3;
+  // each XCD takes one contiguous range of sites, so that the neighbours
+  // in x, y and z (and most in t) are fetched into the same L2
+  const int s0 = xcd_contiguous(blockIdx.x, gridDim.x) * kWilSites;
+  const int nsite = min(kWilSites, w.V - s0);
+  // lanes past the last site work on site V - 1 (all addresses stay in
+  // bounds) and store nothing
+  const int s = min(s0 + sl, w.V - 1);
+  int c0, c1, c2, c3;
   {
     int r = s;
-    co[0] = r % w.L0; r /= w.L0;
-    co[1] = r % w.L1; r /= w.L1;
-    co[2] = r % w.L2; r /= w.L2;
-    co[3] = r;
+    c0 = r % w.L0; r /= w.L0;
+    c1 = r % w.L1; r /= w.L1;
+    c2 = r % w.L2;
+    c3 = r / w.L2;
   }
-  const int Ls[4] = {w.L0, w.L1, w.L2, w.L3};
-  const int stride[4] = {1, w.L0, w.L0 * w.L1, w.L0 * w.L1 * w.L2};
+  const int L = mu == 0 ? w.L0 : mu == 1 ? w.L1 : mu == 2 ? w.L2 : w.L3;
+  const int co = mu == 0 ? c0 : mu == 1 ? c1 : mu == 2 ? c2 : c3;
+  const int st = mu == 0 ? 1 : mu == 1 ? w.L0 : mu == 2 ? w.L0 * w.L1 : w.L0 * w.L1 * w.L2;
+  const int sf = (co + 1 < L) ? s + st : s - (L - 1) * st;
+  const int sb = (co > 0) ? s - st : s + (L - 1) * st;
+  // M_mu: x, y anti-diagonal (-i, -i), (-1, 1); z diagonal (-i, i); t identity.
+  // M_mu^{-1}: x (i, i), y (1, -1), z (i, -i), t identity.
+  HopCoef k;
+  k.swap = mu < 2;
+  k.p0r = mu == 1 ? -1.0 : mu == 3 ? 1.0 : 0.0;
+  k.p0i = mu == 1 || mu == 3 ? 0.0 : -1.0;
+  k.p1r = mu == 1 || mu == 3 ? 1.0 : 0.0;
+  k.p1i = mu == 0 ? -1.0 : mu == 2 ? 1.0 : 0.0;
+  k.q0r = mu == 1 || mu == 3 ? 1.0 : 0.0;
+  k.q0i = mu == 1 || mu == 3 ? 0.0 : 1.0;
+  k.q1r = mu == 1 ? -1.0 : mu == 3 ? 1.0 : 0.0;
+  k.q1i = mu == 0 ? 1.0 : mu == 2 ? -1.0 : 0.0;
+
+  cplx* slice = lds + mu * kWilDirStride;
+  const cplx* mine = slice + sl * 12;
+  const int64_t V = w.V;
   cplx acc[4][3];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[a][c] = cplx{0.0, 0.0};
+  // forward hop: (1 - g_mu) U_mu(s) x(s + mu)
+  wilson_stage(x, sf, sl, mu, slice);
+  __builtin_amdgcn_wave_barrier();
+  k.sg = -1.0;
+  wilson_hop<false>(mine, Us + (int64_t)mu * 9 * V + s, V, k, acc);
+  __builtin_amdgcn_wave_barrier();
+  // backward hop: (1 + g_mu) U_mu(s - mu)^H x(s - mu)
+  wilson_stage(x, sb, sl, mu, slice);
+  __builtin_amdgcn_wave_barrier();
+  k.sg = 1.0;
+  wilson_hop<true>(mine, Us + (int64_t)mu * 9 * V + sb, V, k, acc);
+  __builtin_amdgcn_wave_barrier();
 
+  // quad reduce-scatter: after the xor-2 step a lane holds rows {0,1} or
+  // {2,3} summed over its pair, after the xor-1 step row mu over the quad
+  const bool hi2 = (mu & 2) != 0, hi1 = (mu & 1) != 0;
+  cplx k2[2][3];
 #pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
-    // forward hop: (1 - g_mu) U_mu(s) x(s + mu)
-    {
-      const int sf = (co[mu] + 1 < Ls[mu]) ? s + stride[mu] : s - (Ls[mu] - 1) * stride[mu];
-      cplx psi[12];
-#pragma unroll
-      for (int e = 0; e < 12; ++e) psi[e] = x[(int64_t)sf * 12 + e];
-      cplx h[2][3], g[2][3];
-      spin_project(mu, -1, psi, h);
-      const cplx* Um = U + ((int64_t)mu * w.V + s) * 9;
-      cplx u[9];
-#pragma unroll
-      for (int e = 0; e < 9; ++e) u[e] = Um[e];
-#pragma unroll
-      for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-          g[sp][a] = mad(u[a * 3 + 2], h[sp][2], mad(u[a * 3 + 1], h[sp][1], u[a * 3 + 0] * h[sp][0]));
-      spin_accumulate(mu, -1, g, acc);
-    }
-    // backward hop: (1 + g_mu) U_mu(s - mu)^H x(s - mu)
-    {
-      const int sb = (co[mu] > 0) ? s - stride[mu] : s + (Ls[mu] - 1) * stride[mu];
-      cplx psi[12];
-#pragma unroll
-      for (int e = 0; e < 12; ++e) psi[e] = x[(int64_t)sb * 12 + e];
-      cplx h[2][3], g[2][3];
-      spin_project(mu, +1, psi, h);
-      const cplx* Um = U + ((int64_t)mu * w.V + sb) * 9;
-      cplx u[9];
-#pragma unroll
-      for (int e = 0; e < 9; ++e) u[e] = Um[e];
-#pragma unroll
-      for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-        for (int a = 0; a < 3; ++a)  // (U^H h)_a = sum_b conj(U_ba) h_b
-          g[sp][a] = cmad(u[2 * 3 + a], h[sp][2], cmad(u[1 * 3 + a], h[sp][1],
-                          cmad(u[0 * 3 + a], h[sp][0], cplx{0.0, 0.0})));
-      spin_accumulate(mu, +1, g, acc);
-    }
-  }
-  const int64_t base = (int64_t)s * 12;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const int e = a * 3 + c;
-      const cplx xc = x[base + e];
-      const cplx dx = w.diag * xc - 0.5 * acc[a][c];
-      cplx r = mad(al, dx, be * xc);
-      if (Y0) r = mad(g0, y0[base + e], r);
-      if (Y1) r = mad(g1, y1[base + e], r);
-      out[base + e] = r;
+      const cplx keep = hi2 ? acc[r + 2][c] : acc[r][c];
+      const cplx send = hi2 ? acc[r][c] : acc[r + 2][c];
+      k2[r][c] = keep + quad_xor<2>(send);
     }
+  // row mu of site sl -> chunks 12 sl + 3 mu + c of the first slice
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cplx keep = hi1 ? k2[1][c] : k2[0][c];
+    const cplx send = hi1 ? k2[0][c] : k2[1][c];
+    lds[sl * 12 + mu * 3 + c] = keep + quad_xor<1>(send);
+  }
+  __builtin_amdgcn_wave_barrier();
+  // out = al (diag x - sum / 2) + be x + g0 y0 + g1 y1, chunk by chunk
+  const int64_t base = (int64_t)s0 * 12;
+#pragma unroll
+  for (int i = 0; i < kWilChunks / 64; ++i) {
+    const int q = lane + 64 * i;
+    if (q < nsite * 12) {
+      const cplx xc = x[base + q];
+      const cplx dx = w.diag * xc - 0.5 * lds[q];
+      cplx r = mad(al, dx, be * xc);
+      if (Y0) r = mad(g0, y0[base + q], r);
+      if (Y1) r = mad(g1, y1[base + q], r);
+      out[base + q] = r;
+    }
+  }
 }
 
 static hipError_t launch_wilson(const Op& op, const cplx* x, const cplx* y0, const cplx* y1,
                                 cplx* out, const ChainCoef& k, hipStream_t st) {
   Wil w{op.dims[0], op.dims[1], op.dims[2], op.dims[3],
         op.dims[0] * op.dims[1] * op.dims[2] * op.dims[3], 4.0 + op.m0};
-  const int grid = (w.V + 127) / 128;
+  const int grid = (w.V + kWilSites - 1) / kWilSites;
   const cplx al = host_to_dev<cplx>::conv(k.alpha), be = host_to_dev<cplx>::conv(k.beta),
              g0 = host_to_dev<cplx>::conv(k.g0), g1 = host_to_dev<cplx>::conv(k.g1);
   const cplx* U = (const cplx*)op.links;
   if (y0 && y1)
-    wilson_chain<true, true><<<grid, 128, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1);
+    wilson_chain<true, true><<<grid, 64, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1);
   else if (y0)
-    wilson_chain<true, false><<<grid, 128, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1);
+    wilson_chain<true, false><<<grid, 64, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1);
   else if (y1)
-    wilson_chain<false, true><<<grid, 128, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1);
+    wilson_chain<false, true><<<grid, 64, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1);
   else
-    wilson_chain<false, false><<<grid, 128, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1);
+    wilson_chain<false, false><<<grid, 64, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1);
+  return hipGetLastError();
+}
+
+// Us[mu][e][s] = U[mu][s][e] for the 4 directions, 9 link elements, V sites
+__global__ void wilson_links_soa_k(int64_t V, const cplx* __restrict__ U, cplx* __restrict__ Us) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // over Us
+  if (i >= 36 * V) return;
+  const int64_t s = i % V, me = i / V, mu = me / 9, e = me - 9 * mu;
+  Us[i] = U[(mu * V + s) * 9 + e];
+}
+
+hipError_t launch_wilson_links_soa(int64_t V, const void* U, void* Us, hipStream_t st) {
+  const int64_t n = 36 * V;
+  wilson_links_soa_k<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(V, (const cplx*)U, (cplx*)Us);
   return hipGetLastError();
 }
 

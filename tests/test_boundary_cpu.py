@@ -117,10 +117,15 @@ def test_setup_and_apply_argument_errors_without_gpu():
     assert L.fa_apply(h, 0, dummy, dummy, 10, 1e-8, 0, None, 0, 0, None, None) == _lib.FA_ERR_ARG
     assert L.fa_apply(h, 0, dummy, C.c_void_p(512), 0, 1e-8, 0, None, 0, 0, None, None) == \
         _lib.FA_ERR_ARG
-    # Chebyshev without an interval (CSR has none until it is set)
+    # a CSR op reads its row pointers to the host at creation: without a
+    # GPU that copy fails and creation reports it
     h2 = C.c_void_p()
     assert L.fa_create_csr(C.byref(h2), 4, 4, C.c_void_p(256), C.c_void_p(512),
-                           C.c_void_p(768), 0, 0, None) == 0
+                           C.c_void_p(768), 0, 0, None) == _lib.FA_ERR_HIP
+    # Chebyshev without an interval: a stencil whose x pair has a negative
+    # product (complex spectrum) gets none until it is set
+    st, h2 = _stencil((4, 4, 4), [6.0, -1.0, 1.0, -1.0, -1.0, -1.0, -1.0])
+    assert st == 0
     assert L.fa_poly_setup(h2, 3, _lib.FA_POLY_CHEB, None, None, 0, None) == _lib.FA_ERR_NO_INTERVAL
     assert L.fa_set_spectral_interval(h2, 2.0, 1.0) == _lib.FA_ERR_ARG
     assert L.fa_set_spectral_interval(h2, 0.5, 4.0) == 0
