@@ -8,7 +8,7 @@ stopping tolerance 1e-8 on the difference-of-iterates estimate.
 
 A step is one fa_apply solve (setup of the operator and polynomial excluded,
 inputs resident in HBM).  Printed as one JSON line with a roofline object for
-the dominant kernel (the stencil chain launch that evaluates two Clenshaw
+the dominant kernel (the stencil chain launch that evaluates three Clenshaw
 terms: HIP events around each run of such launches in every timed solve) and
 the CPU oracle timed on a bounded sample.  Extra fields report plain Arnoldi
 (degree 0), degrees 4 and 32 and the square root on the same GPU, and the
@@ -30,10 +30,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "f(A)b solves/s at rel err 1e-8, poly-precond vs plain Arnoldi; SpMV HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of st7_pair<true,true,true> at 128^3 (FETCH_SIZE x 2.00 +
-# WRITE_SIZE x 1.00, the factors of a 2 GiB copy), from the rocprofv3 counter
-# runs in profiles/st7_chain_convdiff128_deg16_hbm_counters.md
-PAIR_TRAFFIC_BYTES = (64540 + 32768) * 1024
+# HBM bytes per launch of the dominant kernel (the three-term middle launch
+# st7_multi<..., 3, 8, true, true> at 128^3: FETCH_SIZE x 2.00 + WRITE_SIZE x
+# 1.00, the factors of a 2 GiB copy), from the rocprofv3 counter runs in
+# profiles/st7_multi_convdiff128_deg16_hbm_counters.md
+MULTI_TRAFFIC_BYTES = (74532 + 32768) * 1024
 
 
 def log(msg):
@@ -158,16 +159,17 @@ def main():
     ms_chain = sum(s["ms_chain"] for s in stats)
     bytes_avg = sum(s["chain_bytes"] * s["n_chain"] for s in stats) / max(n_chain, 1)
     avg_ms = ms_chain / max(n_chain, 1)
-    # algorithmic bytes of one timed launch: two Clenshaw middle terms, each
+    terms = sum(s["n_chain_terms"] for s in stats) / max(n_chain, 1)  # per timed launch
+    # algorithmic bytes of one timed launch: its Clenshaw middle terms, each
     # the per-term figure of the method (read x, v, b_(k+2), write b_k: 4
     # vectors); the fused launch itself needs only 5 vectors (bytes_avg)
     per_term = 4 * (N ** 3) * 8
-    algo_bytes = 2 * per_term
+    algo_bytes = terms * per_term
     achieved = algo_bytes / (avg_ms * 1e-3) / 1e9
     achieved_min = bytes_avg / (avg_ms * 1e-3) / 1e9
     log(f"degree {K}: {value:.2f} solves/s, m = {st0['iters']}, err = {err:.2e}, "
-        f"chain launch {avg_ms * 1e3:.1f} us, {achieved:.0f} GB/s per-term accounting, "
-        f"{achieved_min:.0f} GB/s of the launch's own 5 vectors")
+        f"chain launch {avg_ms * 1e3:.1f} us ({terms:.0f} terms), {achieved:.0f} GB/s "
+        f"per-term accounting, {achieved_min:.0f} GB/s of the launch's own 5 vectors")
     op.release_workspace()
     del op
 
@@ -271,15 +273,17 @@ def main():
                    "n": N ** 3, "degree": K, "tol": tol, "kind": "invsqrt",
                    "orthogonalization": "CGS2", "preconditioning": "left"},
         "roofline": {"bound": "hbm",
-                     "kernel": "st7_pair<true,true,true> (two Clenshaw terms per launch)",
+                     "kernel": f"st7_multi<double, 3 terms> ({terms:.0f} Clenshaw terms per "
+                               "launch)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": PAIR_TRAFFIC_BYTES,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": MULTI_TRAFFIC_BYTES,
                      "algorithmic_bytes_per_launch": algo_bytes,
                      "algorithmic_unit": "one Clenshaw term = 4 vectors (x, v, b_k+2 read; "
-                                         "b_k written); 2 terms per launch",
+                                         f"b_k written); {terms:.0f} terms per launch",
                      "fused_launch_bytes": bytes_avg,
                      "frac_of_fused_launch_bytes": achieved_min / HBM_PEAK_GBS,
-                     "traffic_frac": PAIR_TRAFFIC_BYTES / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic_frac": (MULTI_TRAFFIC_BYTES / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                      if MULTI_TRAFFIC_BYTES else None),
                      "avg_launch_us": avg_ms * 1e3, "launches_timed": n_chain},
         "cpu_baseline": cpu,
         **extra,

@@ -99,7 +99,10 @@ enum {
   FA_HERMITIAN = 1u,     /* create: A is Hermitian; apply uses Lanczos (3-term)        */
   FA_FORCE_ARNOLDI = 4u, /* apply: Gram-Schmidt (CGS2) even for a Hermitian op          */
   FA_PROFILE = 8u,       /* apply: time the middle terms of every q(A) application      */
-  FA_NO_FUSION = 16u,    /* apply: one launch per recurrence term (no two-term launches) */
+  FA_NO_FUSION = 16u,    /* apply: one launch per recurrence term (no multi-term launches) */
+  FA_FUSE2 = 1024u,      /* apply: at most two recurrence terms per launch (default on a
+                            7-point stencil: three per launch in FP64, then a pair or
+                            a single term; two with FA_MIXED)                       */
   FA_TWO_PASS = 64u,     /* apply: two-pass Lanczos (Hermitian op, not with
                             FA_FORCE_ARNOLDI or FA_RIGHT_PREC, else
                             FA_ERR_UNSUPPORTED): pass 1 keeps three basis vectors
@@ -148,13 +151,14 @@ typedef struct {
   double ms_chain;        /* FA_PROFILE: device time of the timed chain launches: HIP
                              events bracket each run of consecutive launches of the
                              middle of a q(A) recurrence (the Clenshaw terms that read
-                             x, v, b_{k+2}, two per launch on a stencil; the Newton
-                             terms that read r, v), so the figure includes the short
-                             gaps between back-to-back launches                        */
+                             x, v, b_{k+2}, up to three per launch on a stencil; the
+                             Newton terms that read r, v), so the figure includes the
+                             short gaps between back-to-back launches                  */
   int64_t n_chain;        /* FA_PROFILE: number of chain launches timed                 */
   double chain_bytes;     /* FA_PROFILE: algorithmic bytes of one timed launch: x, each
                              combined vector and each output once, plus the operator's
                              own arrays (Wilson links, CSR arrays)                      */
+  int64_t n_chain_terms;  /* FA_PROFILE: recurrence terms in the timed launches        */
 } fa_stats;
 
 /*

@@ -30,6 +30,17 @@ _METHOD = {"auto": FA_POLY_AUTO, "cheb": FA_POLY_CHEB, "ritz": FA_POLY_RITZ,
            "harmonic": FA_POLY_HARMONIC, "ls": FA_POLY_LS}
 
 
+def _fuse_flags(fuse):
+    """Flags for the most recurrence terms per launch: True or 3, 2, False or 1."""
+    if fuse is True or fuse == 3:
+        return 0
+    if fuse is False or fuse == 1:
+        return FA_NO_FUSION
+    if fuse == 2:
+        return _lib.FA_FUSE2
+    raise ValueError("fuse must be True, False, 1, 2 or 3")
+
+
 def _stream(device):
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -169,7 +180,8 @@ class Operator:
               right=False, orth="dcgs2", raise_not_converged=False):
         """x ~ A^{-1/2} b or A^{1/2} b.  Returns (x, stats dict).
 
-        fuse=False runs one launch per recurrence term (no two-term launches);
+        fuse: most recurrence terms per launch on a 7-point stencil (True = 3,
+        2, or False / 1 for one launch per term);
         mixed=True runs the polynomial chain in FP32 (stencil, Chebyshev q);
         two_pass=True runs two-pass Lanczos (O(n) basis storage);
         right=True runs the right-preconditioned variant (Algorithm 2);
@@ -182,7 +194,7 @@ class Operator:
         x = out if out is not None else torch.empty_like(b)
         self._vec(x, "out")
         flags = ((FA_FORCE_ARNOLDI if force_arnoldi else 0) | (FA_PROFILE if profile else 0)
-                 | (0 if fuse else FA_NO_FUSION) | (FA_MIXED if mixed else 0)
+                 | _fuse_flags(fuse) | (FA_MIXED if mixed else 0)
                  | (FA_TWO_PASS if two_pass else 0) | (FA_RIGHT_PREC if right else 0)
                  | (_lib.FA_CGS2 if orth == "cgs2" else 0))
         _, wsp, nbytes = self._workspace(m_max, flags)
@@ -334,7 +346,7 @@ class Server:
         b = op._vec(b, "b")
         x = out if out is not None else torch.empty_like(b)
         op._vec(x, "out")
-        flags = ((FA_FORCE_ARNOLDI if force_arnoldi else 0) | (0 if fuse else FA_NO_FUSION)
+        flags = ((FA_FORCE_ARNOLDI if force_arnoldi else 0) | _fuse_flags(fuse)
                  | (FA_MIXED if mixed else 0) | (FA_TWO_PASS if two_pass else 0)
                  | (FA_RIGHT_PREC if right else 0))
         # b is produced on torch's stream; the server's streams do not wait for it

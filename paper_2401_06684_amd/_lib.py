@@ -24,7 +24,7 @@ FA_INVSQRT, FA_SQRT = 0, 1
 FA_STENCIL7, FA_WILSON4D = 0, 1
 FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_RITZ, FA_POLY_HARMONIC, FA_POLY_LS = 0, 1, 2, 3, 4
 FA_HERMITIAN, FA_FORCE_ARNOLDI, FA_PROFILE, FA_NO_FUSION, FA_MIXED = 1, 4, 8, 16, 32
-FA_TWO_PASS, FA_RIGHT_PREC, FA_GRAPH, FA_CGS2 = 64, 128, 256, 512
+FA_TWO_PASS, FA_RIGHT_PREC, FA_GRAPH, FA_CGS2, FA_FUSE2 = 64, 128, 256, 512, 1024
 
 EXPORTS = [
     "fa_create_csr", "fa_create_stencil", "fa_set_spectral_interval",
@@ -44,7 +44,7 @@ class fa_stats(C.Structure):
         ("checks", C.c_int32), ("mvms", C.c_int64), ("mvms_setup", C.c_int64),
         ("inner_products", C.c_int64), ("est_rel_change", C.c_double), ("h_last", C.c_double),
         ("ms_total", C.c_double), ("ms_host_fH", C.c_double), ("ms_chain", C.c_double),
-        ("n_chain", C.c_int64), ("chain_bytes", C.c_double),
+        ("n_chain", C.c_int64), ("chain_bytes", C.c_double), ("n_chain_terms", C.c_int64),
     ]
 
     def as_dict(self):

@@ -98,9 +98,11 @@ struct Prof {
     used += 2;
     return err;
   }
-  void count(int nlaunch, double bytes_each) {
+  int64_t terms = 0;  // recurrence terms of the timed launches
+  void count(int nlaunch, double bytes_each, int terms_each = 1) {
     launches += nlaunch;
     bytes += nlaunch * bytes_each;
+    terms += (int64_t)nlaunch * terms_each;
   }
   // after a stream sync: summed milliseconds
   double total_ms() const {
@@ -268,12 +270,14 @@ static int poly_apply_ls(const Op& op, const Poly& q, const void* x, void* out, 
 // q(A) x.  tmp holds 4 scratch vectors distinct from x and out.  The result
 // goes to `out` when that is safe and to a scratch vector otherwise (a
 // single-term launch may write over x pointwise, a two-term launch may not);
-// *res names the buffer that holds q(A) x.  With `fuse`, consecutive terms
-// of the 7-point stencil run two per launch.
+// *res names the buffer that holds q(A) x.  `fuse` is the most consecutive
+// terms of the 7-point stencil one launch may take (1, 2 or 3): groups of
+// three while three or more terms remain, then a pair or a single term
+// (FP32 chains: pairs).
 // pm = P32 (mixed precision): x and every intermediate vector are FP32 and
 // the last launch writes `out` in precision pout; pm = P64: everything FP64.
 static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, void* const tmp[4],
-                      const void** res, hipStream_t s, Prof* prof, int64_t* mvms, bool fuse,
+                      const void** res, hipStream_t s, Prof* prof, int64_t* mvms, int fuse,
                       Prec pm = P64, Prec pout = P64, void* wls = nullptr) {
   const int K = q.degree;
   if (q.method < 0 || K == 0) {
@@ -291,7 +295,7 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
   *mvms += K;
   const std::vector<Term> T = poly_terms(q);
   const int nT = (int)T.size();
-  const bool pairs = fuse && has_pair_kernel(op) && nT >= 2;
+  const bool pairs = fuse >= 2 && has_pair_kernel(op) && nT >= 2;
   if (!pairs) {
     // one launch per term; out_i may overwrite out_{i-2} in place (read pointwise)
     const void* xm1 = x;       // out_{i-1}
@@ -325,20 +329,27 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
     *res = xm1;
     return FA_OK;
   }
-  // two terms per launch: pair p = (T[2p], T[2p+1]) reads out_{2p-1}, out_{2p-2},
-  // x and writes out_{2p}, out_{2p+1} into the buffer set not holding its inputs
+  // groups of g = 3 or 2 terms per launch: the group (T[i], .., T[i+g-1])
+  // reads out_{i-1}, out_{i-2} and x and writes out_{i+g-2}, out_{i+g-1} into
+  // the buffer set not holding its inputs (the terms between stay on chip);
+  // term i + 1 takes out_{i-1} and term i + 2 out_i as its y1
   const void* xm1 = x;
   const void* xm2 = nullptr;
   int set = 0;
   bool timing = false;
   int i = 0;
-  for (; i + 1 < nT; i += 2) {
-    const bool has_next = i + 2 < nT;  // someone reads out_{2p} later
-    const bool last_pair = i + 2 >= nT;
+  // FP32 chains stay with pairs: the three-term kernel is bound by its
+  // per-plane latency, not by the bytes, so halving them gains nothing there
+  const int most = pm == P32 ? 2 : fuse;
+  for (;;) {
+    const int g = (most >= 3 && i + 3 <= nT) ? 3 : (i + 2 <= nT) ? 2 : 0;
+    if (g == 0) break;
+    const bool has_next = i + g < nT;  // someone reads out_{i+g-2} later
     void* o1 = has_next ? tmp[2 * set] : nullptr;
     void* o2 = tmp[2 * set + 1];
-    if (last_pair && out != x && out != xm1 && out != xm2) o2 = out;
-    const bool middle = T[i].y0 && T[i].y1 && T[i + 1].y1 && has_next;
+    if (!has_next && out != x && out != xm1 && out != xm2) o2 = out;
+    bool middle = T[i].y0 && T[i].y1 && has_next;
+    for (int t = 1; t < g; ++t) middle = middle && T[i + t].y1;
     if (prof && middle && !timing) {
       FA_HIP(prof->begin(s));
       timing = true;
@@ -347,15 +358,26 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
       FA_HIP(prof->end(s));
       timing = false;
     }
-    ChainCoef k2 = T[i + 1].k;
-    if (!T[i + 1].y1) k2.g1 = 0.0;
-    FA_HIP(launch_chain_pair(op, xm1, (T[i].y0 || T[i + 1].y0) ? x : nullptr,
-                             T[i].y1 ? xm2 : nullptr, o1, o2, T[i].k, k2, s, pm,
-                             last_pair && i + 2 >= nT ? pout : pm));
-    if (prof && timing) prof->count(1, chain_pair_bytes(op, true, true, o1 != nullptr, pm));
+    ChainCoef k[3];
+    for (int t = 0; t < g; ++t) {
+      k[t] = T[i + t].k;
+      if (t > 0 && !T[i + t].y1) k[t].g1 = 0.0;
+    }
+    const Prec po = has_next ? pm : pout;
+    if (g == 3) {
+      for (int t = 0; t < 3; ++t)
+        if (!T[i + t].y0) k[t].g0 = 0.0;
+      FA_HIP(launch_chain_triple(op, xm1, x, T[i].y1 ? xm2 : nullptr, o1, o2, k, s, pm, po));
+    } else {
+      FA_HIP(launch_chain_pair(op, xm1, (T[i].y0 || T[i + 1].y0) ? x : nullptr,
+                               T[i].y1 ? xm2 : nullptr, o1, o2, k[0], k[1], s, pm, po));
+    }
+    if (prof && timing)
+      prof->count(1, chain_pair_bytes(op, true, true, o1 != nullptr, pm), g);
     xm2 = o1;
     xm1 = o2;
     set ^= 1;
+    i += g;
   }
   if (prof && timing) FA_HIP(prof->end(s));
   if (i < nT) {  // odd number of terms: the last one alone (pointwise in out)
@@ -373,7 +395,7 @@ int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_
   void* const tmp[4] = {at(ws, L.off_P), at(ws, L.off_Q), at(ws, L.off_R), at(ws, L.off_S)};
   const void* res = nullptr;
   int64_t mv = 0;
-  int st = poly_apply(op, op.poly, x, y, tmp, &res, s, nullptr, &mv, true, P64, P64,
+  int st = poly_apply(op, op.poly, x, y, tmp, &res, s, nullptr, &mv, 3, P64, P64,
                       L.off_W ? at(ws, L.off_W) : nullptr);
   if (st) return st;
   if (res != y) FA_HIP(hipMemcpyAsync(y, res, op.n * elem_size(op.dtype), hipMemcpyDeviceToDevice, s));
@@ -468,7 +490,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   char* Y = right ? at(ws, L.off_Y) : nullptr;
   void* U = at(ws, L.off_U);
   void* const tmp[4] = {at(ws, L.off_P), at(ws, L.off_Q), at(ws, L.off_R), at(ws, L.off_S)};
-  const bool fuse = !(flags & FA_NO_FUSION);
+  const int fuse = (flags & FA_NO_FUSION) ? 1 : (flags & FA_FUSE2) ? 2 : 3;
   void* const wls = L.off_W ? at(ws, L.off_W) : nullptr;  // least-squares q
   // mixed precision: the polynomial chain in FP32 (stencil, Chebyshev q, K >= 1)
   const bool mixed = (flags & FA_MIXED) && K > 0;
@@ -822,6 +844,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     S.ms_chain = prof.total_ms();
     S.n_chain = prof.launches;
     S.chain_bytes = S.n_chain ? prof.bytes / (double)S.n_chain : 0.0;
+    S.n_chain_terms = prof.terms;
   }
   if (stats) *stats = S;
   return converged ? FA_OK : FA_WARN_NOT_CONVERGED;

@@ -281,11 +281,19 @@ def test_bitwise_deterministic_and_profile():
     x1, s1 = op.apply(b, m_max=60, tol=1e-10)
     x2, s2 = op.apply(b, m_max=60, tol=1e-10, profile=True)
     assert torch.equal(x1, x2)
-    # Clenshaw degree 8 = 8 terms = 4 two-term launches per q(A), of which the
-    # 2nd and 3rd read x, v, b_{k+2} and write both terms (5 vectors); 2 q(A)
-    # per step plus c = q(A) b
-    assert s2["n_chain"] == 2 * (2 * s2["iters"] + 1) and s2["ms_chain"] > 0
+    # Clenshaw degree 8 = 8 terms = launches of 3, 3 and 2 terms per q(A), of
+    # which the middle one reads x, v, b_{k+2} and writes its last two terms
+    # (5 vectors); 2 q(A) per step plus c = q(A) b
+    assert s2["n_chain"] == 2 * s2["iters"] + 1 and s2["ms_chain"] > 0
+    assert s2["n_chain_terms"] == 3 * s2["n_chain"]
     assert s2["chain_bytes"] == 5 * 8 * op.n
+    # at most two terms per launch: 4 pairs, the 2nd and 3rd timed
+    x4, s4 = op.apply(b, m_max=60, tol=1e-10, fuse=2, profile=True)
+    assert s4["n_chain"] == 2 * (2 * s4["iters"] + 1)
+    assert s4["n_chain_terms"] == 2 * s4["n_chain"]
+    assert s4["chain_bytes"] == 5 * 8 * op.n
+    # the grouping only drops zero terms and keeps every rounding: same bits
+    assert torch.equal(x4, x1)
     x3, s3 = op.apply(b, m_max=60, tol=1e-10, fuse=False, profile=True)
     assert s3["n_chain"] == 5 * (2 * s3["iters"] + 1)
     assert s3["chain_bytes"] == 4 * 8 * op.n
@@ -294,9 +302,10 @@ def test_bitwise_deterministic_and_profile():
 
 @pytest.mark.parametrize("degree", [1, 2, 3, 4, 5, 16, 17])
 @pytest.mark.parametrize("dims", [(70, 9, 11), (128, 16, 24), (33, 65, 5), (20, 20, 1)])
-def test_two_term_launches_match_single_terms(degree, dims):
-    """q(A) x and whole solves with two recurrence terms per launch equal the
-    single-term path and the oracle (ragged tiles in x, y and z)."""
+def test_multi_term_launches_match_single_terms(degree, dims):
+    """q(A) x and whole solves with three or two recurrence terms per launch
+    equal the single-term path and the oracle (ragged tiles in x, y and z;
+    degrees that leave a single term or a pair after the groups of three)."""
     coeffs = wl.convdiff_stencil(max(dims), 50.0)
     op = fa().Stencil7(dims, coeffs)
     op.poly_setup(degree, "cheb")
@@ -309,7 +318,10 @@ def test_two_term_launches_match_single_terms(degree, dims):
     m = min(6, op.n)
     x1, _ = op.apply(bd, m_max=m, tol=0.0)
     x2, _ = op.apply(bd, m_max=m, tol=0.0, fuse=False)
+    x3, _ = op.apply(bd, m_max=m, tol=0.0, fuse=2)
     assert_close(host(x1), host(x2), 1e-12)
+    # three-term groups reproduce the pairs bit for bit (same roundings)
+    assert torch.equal(x1, x3)
 
 
 # --------------------------------------------------------------------------
