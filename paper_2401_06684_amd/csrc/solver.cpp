@@ -8,6 +8,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "dense.hpp"
@@ -406,11 +408,62 @@ int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_
 // the preconditioned Arnoldi / Lanczos loop
 // --------------------------------------------------------------------------
 namespace {
+// Page-locked host memory for the iteration's small copies (columns of H,
+// projections, norms, coefficients).  A copy into pageable memory is staged
+// by the runtime through its own buffer and blocks the calling thread; one
+// into page-locked memory queues on the stream like a kernel.  Buffers are
+// pooled across calls and threads and kept for the life of the process.
+class PinnedPool {
+ public:
+  void* take(size_t bytes) {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      size_t best = free_.size();
+      for (size_t i = 0; i < free_.size(); ++i)
+        if (free_[i].second >= bytes && (best == free_.size() || free_[i].second < free_[best].second))
+          best = i;
+      if (best < free_.size()) {
+        void* p = free_[best].first;
+        free_.erase(free_.begin() + best);
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> g(mu_);
+    size_of_[p] = bytes;
+    return p;
+  }
+  void give(void* p) {
+    std::lock_guard<std::mutex> g(mu_);
+    free_.push_back({p, size_of_[p]});
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<std::pair<void*, size_t>> free_;
+  std::unordered_map<void*, size_t> size_of_;
+};
+PinnedPool& pinned_pool() {
+  static PinnedPool* pool = new PinnedPool;  // never destroyed (outlives the runtime's users)
+  return *pool;
+}
+struct PinnedLease {
+  void* p = nullptr;
+  explicit PinnedLease(size_t bytes) : p(pinned_pool().take(bytes)) {}
+  ~PinnedLease() {
+    if (p) pinned_pool().give(p);
+  }
+  PinnedLease(const PinnedLease&) = delete;
+  PinnedLease& operator=(const PinnedLease&) = delete;
+};
+
 struct HostH {
   int ldh = 0;
   bool band = false;        // Lanczos: column j holds rows j and j + 1 only
   int dtype = FA_F64;
-  std::vector<double> buf;  // column-major, ldh rows, (complex interleaved)
+  double* buf = nullptr;    // column-major, ldh rows, (complex interleaved)
+  std::vector<double> own;  // storage when buf is not given
   size_t off(int i, int j) const { return (size_t)j * ldh + (band ? i - j : i); }
   cd get(int i, int j) const {
     const size_t o = off(i, j);
@@ -442,7 +495,7 @@ int host_coeffs(const HostH& H, int m, bool lanczos, double beta, std::vector<cd
   }
   int st;
   if (H.dtype == FA_F64) {  // real Francis double-shift QR on the host copy
-    st = real_hess_invsqrt_e1(m, H.buf.data(), H.ldh, beta, z.data());
+    st = real_hess_invsqrt_e1(m, H.buf, H.ldh, beta, z.data());
   } else {
     std::vector<cd> Hc((size_t)m * m);
     for (int j = 0; j < m; ++j)
@@ -618,9 +671,25 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     FA_HIP(launch_normalize(op.dtype, n, w, nrm, w, Hent(j + 1, j), s));
     return FA_OK;
   };
-  // coefficient vector z to the device (negated with `neg`)
-  auto z_to_device = [&](const std::vector<cd>& zz, int len, bool neg, void* dst) -> int {
-    std::vector<double> zh((size_t)len * (es / 8));
+  // host side of the small copies: page-locked when available (see
+  // PinnedPool), else ordinary memory (the copies then block, same results)
+  const size_t ed = es / 8;  // doubles per element
+  const size_t n_h = (size_t)L.ldh * m_max * ed, n_sh = (size_t)(m_max + 2) * ed,
+               n_z = (size_t)m_max * ed, n_sc = 4;
+  const size_t n_pin = n_h + n_sh + 2 * n_z + n_sc;
+  PinnedLease lease(n_pin * sizeof(double));
+  std::vector<double> pageable(lease.p ? 0 : n_pin);
+  double* const pin = lease.p ? (double*)lease.p : pageable.data();
+  double* const h_host = pin;              // H, column-major with ldh rows
+  double* const sh_host = pin + n_h;       // a projection of u_{j+1}
+  double* const z_host = sh_host + n_sh;   // two coefficient vectors
+  double* const sc_host = z_host + 2 * n_z;  // scalars
+  // coefficient vector z to the device (negated with `neg`) from host slot
+  // `slot` (0 or 1); the slot must not be rewritten before the stream has
+  // passed this copy (every caller synchronizes before the next use)
+  auto z_to_device = [&](const std::vector<cd>& zz, int len, bool neg, void* dst,
+                         int slot = 0) -> int {
+    double* zh = z_host + (size_t)slot * n_z;
     const double sg = neg ? -1.0 : 1.0;
     for (int i = 0; i < len; ++i) {
       if (op.dtype == FA_C128) {
@@ -630,16 +699,16 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
         zh[i] = sg * zz[i].real();
       }
     }
-    FA_HIP(hipMemcpyAsync(dst, zh.data(), zh.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    FA_HIP(hipStreamSynchronize(s));  // zh is a local buffer
+    FA_HIP(hipMemcpyAsync(dst, zh, (size_t)len * ed * sizeof(double), hipMemcpyHostToDevice, s));
+    if (!lease.p) FA_HIP(hipStreamSynchronize(s));
     return FA_OK;
   };
 
   st = start_vector();
   if (st) return st;
-  double beta2 = 0.0;
-  FA_HIP(hipMemcpyAsync(&beta2, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+  FA_HIP(hipMemcpyAsync(sc_host, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
   FA_HIP(hipStreamSynchronize(s));
+  const double beta2 = sc_host[0];
   if (!std::isfinite(beta2)) return FA_ERR_NONFINITE;
   const double beta = std::sqrt(beta2);
   if (beta == 0.0) {
@@ -656,7 +725,8 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   H.ldh = L.ldh;
   H.band = L.band;
   H.dtype = op.dtype;
-  H.buf.assign((size_t)L.ldh * m_max * (op.dtype == FA_C128 ? 2 : 1), 0.0);
+  H.buf = h_host;
+  std::memset(h_host, 0, n_h * sizeof(double));
   int copied = 0;          // columns of H final on the host
   int refresh = 0;         // first column to copy again at the next check
   double colmax = 0.0;     // largest column norm of H seen (breakdown scale)
@@ -687,16 +757,16 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     if (!check) continue;
     // copy the new columns of H to the host
     const int from = std::min(copied, refresh);
-    FA_HIP(hipMemcpyAsync(H.buf.data() + (size_t)from * L.ldh * (es / 8), Hcol(from),
+    FA_HIP(hipMemcpyAsync(H.buf + (size_t)from * L.ldh * (es / 8), Hcol(from),
                           (size_t)(jj - from) * L.ldh * es, hipMemcpyDeviceToHost, s));
     if (dcgs2) {
       // column j still lacks its second pass (done on the device in the next
       // step): project u_{j+1} on [q_0 .. q_j, u_{j+1}] and finish the host
       // copy: H(0:j, j) += s', H(j+1, j) = (||u_{j+1}||^2 - ||s'||^2)^{1/2}
       FA_HIP(launch_project(op.dtype, n, jj + 1, V, L.ldv, Vc(jj), part, hcur, nullptr, 0, s));
-      std::vector<double> sh((size_t)(jj + 1) * (es / 8));
-      FA_HIP(hipMemcpyAsync(sh.data(), hcur, sh.size() * sizeof(double), hipMemcpyDeviceToHost,
-                            s));
+      const double* sh = sh_host;
+      FA_HIP(hipMemcpyAsync(sh_host, hcur, (size_t)(jj + 1) * ed * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
       FA_HIP(hipStreamSynchronize(s));
       auto sv = [&](int i) {
         return op.dtype == FA_C128 ? cd(sh[2 * i], sh[2 * i + 1]) : cd(sh[i], 0.0);
@@ -767,15 +837,14 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       if (st) return st;
       FA_HIP(launch_combine(op.dtype, n, jj, Y, L.ldv, zd, tmp[0], s));
       FA_HIP(launch_update(op.dtype, n, 0, V, L.ldv, hcur, tmp[0], part, nrm, s));
-      double dn2 = 0.0, zn2 = 0.0;
-      FA_HIP(hipMemcpyAsync(&dn2, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
-      st = z_to_device(z, jj, false, zd);
+      FA_HIP(hipMemcpyAsync(sc_host + 1, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+      st = z_to_device(z, jj, false, zd, 1);
       if (st) return st;
       FA_HIP(launch_combine(op.dtype, n, jj, Y, L.ldv, zd, tmp[0], s));
       FA_HIP(launch_update(op.dtype, n, 0, V, L.ldv, hcur, tmp[0], part, nrm, s));
-      FA_HIP(hipMemcpyAsync(&zn2, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+      FA_HIP(hipMemcpyAsync(sc_host + 2, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
       FA_HIP(hipStreamSynchronize(s));
-      est = std::sqrt(dn2 / zn2);
+      est = std::sqrt(sc_host[1] / sc_host[2]);
     } else {  // V orthonormal: the iterates' difference from the coefficients
       double dn = 0.0, zn = 0.0;
       for (int i = 0; i < jj; ++i) {
@@ -800,7 +869,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   // final coefficients (if the loop did not end on a fresh check of size m)
   if ((int)z.size() != m || breakdown) {
     if (copied < m) {
-      FA_HIP(hipMemcpyAsync(H.buf.data() + (size_t)copied * L.ldh * (es / 8), Hcol(copied),
+      FA_HIP(hipMemcpyAsync(H.buf + (size_t)copied * L.ldh * (es / 8), Hcol(copied),
                             (size_t)(m - copied) * L.ldh * es, hipMemcpyDeviceToHost, s));
       FA_HIP(hipStreamSynchronize(s));
     }
@@ -927,8 +996,9 @@ int setup_ritz_values(const Op& op, int steps, bool harmonic, const void* d_star
   HostH H;
   H.ldh = L.ldh;
   H.dtype = op.dtype;
-  H.buf.assign((size_t)L.ldh * d * (es / 8), 0.0);
-  FA_HIP(hipMemcpyAsync(H.buf.data(), Hd, (size_t)L.ldh * d * es, hipMemcpyDeviceToHost, s));
+  H.own.assign((size_t)L.ldh * d * (es / 8), 0.0);
+  H.buf = H.own.data();
+  FA_HIP(hipMemcpyAsync(H.buf, Hd, (size_t)L.ldh * d * es, hipMemcpyDeviceToHost, s));
   FA_HIP(hipStreamSynchronize(s));
   // steps completed before a lucky breakdown (same rule as in fa_apply)
   int m = d;
