@@ -60,28 +60,44 @@ struct Geo {
   static constexpr int W(int t) { return TX + 2 * (NT - t); }
   static constexpr int H(int t) { return TY + 2 * (NT - t); }
   static constexpr int N(int t) { return W(t) * H(t); }
-  static constexpr int U = (N(1) + P - 1) / P;  // owned points per thread
-  static constexpr int HALO = N(0) - N(1);      // x only: the ring around region 1
-  // LDS (elements): two plane buffers per term 0 .. NT-1
-  static constexpr int off(int t) {
-    int o = 0;
-    for (int u = 0; u < t; ++u) o += 2 * N(u);
-    return o;
-  }
-  static constexpr int total() { return off(NT); }
+  static constexpr int RING = N(1) - P;   // region 1 minus the tile
+  static constexpr int HALO = N(0) - N(1);  // region 0 minus region 1 (x only)
+  // LDS (elements): two plane buffers of region-0 size for x and for each of
+  // the terms 1 .. NT-1, then one slot per thread for lanes with nothing to
+  // store
+  static constexpr int BUF = N(0);
+  static constexpr int DUMMY = 2 * NT * BUF;
+  static constexpr int total() { return DUMMY + P; }
 };
+
+// (a, b) coordinates in region 1 of ring point h (region 1 minus the tile):
+// NT - 1 rows above and below the tile, NT - 1 columns left and right
+template <int NT, int TY>
+__device__ __forceinline__ void ring_point(int h, int& a, int& b) {
+  using G = Geo<NT, TY>;
+  constexpr int w = NT - 1, W1 = G::W(1);
+  if (h < w * W1) {  // rows above
+    a = h % W1;
+    b = h / W1;
+  } else if (h < 2 * w * W1) {  // rows below
+    const int k = h - w * W1;
+    a = k % W1;
+    b = w + TY + k / W1;
+  } else {  // columns left and right of the tile rows
+    const int k = h - 2 * w * W1;
+    const int side = k / (w * TY), r = k % (w * TY);
+    a = (side == 0 ? 0 : w + G::TX) + r % w;
+    b = w + r / w;
+  }
+}
 
 template <typename T, typename TX, typename TO, int NT, int TY, bool Y1G, bool W1>
 // at least 4 waves per SIMD: two 512-thread workgroups per CU
-__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(4))) void st7_multi(St7M g, int kz, int gx, int gy, int nwg,
-                                                     const TX* __restrict__ x,
-                                                     const TX* __restrict__ v,
-                                                     const TX* __restrict__ y1,
-                                                     TO* __restrict__ out1,
-                                                     TO* __restrict__ out2,
-                                                     MultiCoef<NT> cd) {
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(4))) void st7_multi(
+    St7M g, int kz, int gx, int gy, int nwg, const TX* __restrict__ x, const TX* __restrict__ v,
+    const TX* __restrict__ y1, TO* __restrict__ out1, TO* __restrict__ out2, MultiCoef<NT> cd) {
   using G = Geo<NT, TY>;
-  constexpr int U = G::U;
+  constexpr int W0 = G::W(0);
   __shared__ T lds[G::total()];
   const T c0 = (T)g.c0, cxm = (T)g.cxm, cxp = (T)g.cxp, cym = (T)g.cym, cyp = (T)g.cyp,
           czm = (T)g.czm, czp = (T)g.czp;
@@ -92,182 +108,217 @@ __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(4))) vo
   const int tid = threadIdx.x;
   const int64_t plane = (int64_t)g.nx * g.ny;
 
-  // owned points: region-1 coordinates (a, b), grid offset, in-grid flag
-  int pa[U], pb[U];
-  bool own[U], ing[U];
-  int64_t poff[U];
+  // Two points per thread: u = 0 its tile point, u = 1 a point of the ring
+  // of region 1 around the tile (threads past the ring size repeat ring
+  // point 0 and store into their LDS dummy slot).  Every term is computed on
+  // every owned point, so no lane takes a branch of its own: a term t value
+  // outside region t is not valid (its neighbours lie outside what term t - 1
+  // has), but only region t of it is ever read.  Points outside the grid
+  // are set to zero; their loads read a clamped in-grid address.
+  int ci[2];        // LDS index (region-0 layout) of the point, or the dummy slot
+  bool ing[2];      // inside the grid
+  int64_t soff[2];  // in-plane offset of the point (clamped into the grid)
+  {
+    int a[2], b[2];
+    a[0] = tid % G::TX + (NT - 1);
+    b[0] = tid / G::TX + (NT - 1);
+    ring_point<NT, TY>(tid < G::RING ? tid : 0, a[1], b[1]);
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int r = tid + u * G::P;
-    own[u] = r < G::N(1);
-    pa[u] = r % G::W(1);
-    pb[u] = r / G::W(1);
-    const int i = i0 - (NT - 1) + pa[u], j = j0 - (NT - 1) + pb[u];
-    ing[u] = own[u] && i >= 0 && i < g.nx && j >= 0 && j < g.ny;
-    poff[u] = (int64_t)j * g.nx + i;
+    for (int u = 0; u < 2; ++u) {
+      const int i = i0 - (NT - 1) + a[u], j = j0 - (NT - 1) + b[u];
+      ing[u] = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+      soff[u] = (int64_t)min(max(j, 0), g.ny - 1) * g.nx + min(max(i, 0), g.nx - 1);
+      ci[u] = (b[u] + 1) * W0 + (a[u] + 1);
+    }
+    if (tid >= G::RING) ci[1] = G::DUMMY + tid;
   }
-  // one point of the x ring around region 1 (threads tid < HALO)
-  int hidx = 0;
+  // one point of region 0 outside region 1 per thread tid < HALO (x only)
+  int hci = G::DUMMY + tid;
   bool hing = false;
   int64_t hoff = 0;
   {
-    const int h = tid;
-    int xa = 0, ya = 0;
-    if (h < G::W(0)) {
+    const int h = tid < G::HALO ? tid : 0;
+    int xa, ya;
+    if (h < W0) {
       xa = h;
       ya = 0;
-    } else if (h < 2 * G::W(0)) {
-      xa = h - G::W(0);
+    } else if (h < 2 * W0) {
+      xa = h - W0;
       ya = G::H(0) - 1;
-    } else if (h < 2 * G::W(0) + G::H(1)) {
+    } else if (h < 2 * W0 + G::H(1)) {
       xa = 0;
-      ya = 1 + (h - 2 * G::W(0));
+      ya = 1 + (h - 2 * W0);
     } else {
-      xa = G::W(0) - 1;
-      ya = 1 + (h - 2 * G::W(0) - G::H(1));
+      xa = W0 - 1;
+      ya = 1 + (h - 2 * W0 - G::H(1));
     }
-    hidx = ya * G::W(0) + xa;
+    if (tid < G::HALO) hci = ya * W0 + xa;
     const int i = i0 - NT + xa, j = j0 - NT + ya;
-    hing = tid < G::HALO && i >= 0 && i < g.nx && j >= 0 && j < g.ny;
-    hoff = (int64_t)j * g.nx + i;
+    hing = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+    hoff = (int64_t)min(max(j, 0), g.ny - 1) * g.nx + min(max(i, 0), g.nx - 1);
   }
   auto zin = [&](int p) { return p >= 0 && p < g.nz; };
-  auto zoff = [&](int p) { return (int64_t)p * plane; };
+  // steps q0 .. qlast; the loop runs an even number of steps (unrolled by
+  // two), the extra one computing nothing (its planes are past the slab's)
+  const int q0 = k0 - NT + 1, qlast = k1 + NT - 2;
+  const int qend = q0 + ((qlast - q0 + 2) & ~1) - 1;
 
-  // rings: ring[s][k][u] = term s at the owned point u, produced two steps
-  // ago (k = 0), one step ago (k = 1), this step (k = 2); s = 0 is x
-  T ring[NT][3][U];
-  T vr[NT][U];  // v at planes q, q - 1, .., q - NT + 1
+  // rings: ring[s][k][u] = term s at owned point u, produced two steps ago
+  // (k = 0), one step ago (k = 1), this step (k = 2); s = 0 is x
+  T ring[NT][3][2];
+  T vr[NT][2];  // v at planes q, q - 1, .., q - NT + 1
 #pragma unroll
   for (int s = 0; s < NT; ++s)
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < 2; ++u) {
       ring[s][0][u] = ring[s][1][u] = ring[s][2][u] = T(0);
       vr[s][u] = T(0);
     }
 
-  // loads in flight, two steps ahead: slot 0 is consumed at step q (x at
-  // plane q + 1, v and y1 at plane q), slot 1 at step q + 1
-  T xn[2][U], xh[2] = {T(0), T(0)};
-  T vn[2][U], yn[2][U];
-  auto load_x = [&](int p, T* r, T& h) {
-    const bool z = zin(p);
+  // Loads in flight, two steps ahead, in two slots: step q consumes slot
+  // q - q0 mod 2 (x at plane q + 1, v and y1 at plane q) and refills it for
+  // step q + 2.  The loop is unrolled by two so that the slot is fixed at
+  // compile time: a register that a load is still filling is never copied
+  // (a copy would make the wave wait for the load then and there), and the
+  // loads read a clamped plane and point, the zero of points and planes
+  // outside the grid being applied only when the value is used.
+  T xq[2][2], xhq[2], vq[2][2], yq[2][2];
+  auto plane_off = [&](int p) { return (int64_t)min(max(p, 0), g.nz - 1) * plane; };
+  // (past the last plane the slab needs, the loads repeat that plane: they
+  // stay unconditional, so no slot register is ever merged with an older
+  // value, which would cost a copy and the wait it implies)
+  auto issue = [&](int qs, auto slot) {
+    constexpr int S = decltype(slot)::value;
+    const TX* xp = x + plane_off(min(qs + 1, k1 + NT - 1));
+    const TX* vp = v + plane_off(min(qs, qlast));
+    const TX* yp = y1 + plane_off(min(qs, qlast));
 #pragma unroll
-    for (int u = 0; u < U; ++u) r[u] = (z && ing[u]) ? (T)x[zoff(p) + poff[u]] : T(0);
-    h = (z && hing) ? (T)x[zoff(p) + hoff] : T(0);
-  };
-  auto load_vy = [&](int p, T* rv, T* ry) {
-    const bool z = zin(p);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      rv[u] = (z && ing[u]) ? (T)v[zoff(p) + poff[u]] : T(0);
-      ry[u] = (Y1G && z && ing[u]) ? (T)y1[zoff(p) + poff[u]] : T(0);
+    for (int u = 0; u < 2; ++u) {
+      xq[S][u] = (T)xp[soff[u]];
+      vq[S][u] = (T)vp[soff[u]];
+      yq[S][u] = Y1G ? (T)yp[soff[u]] : T(0);
     }
+    xhq[S] = (T)xp[hoff];
   };
-  // x plane p into its LDS buffer (owned points and the halo point)
-  auto put_x = [&](int p, const T* r, T h) {
-    T* X = lds + G::off(0) + (p & 1) * G::N(0);
+  // x plane p at the owned points and the halo point, zero outside the grid
+  // (used right away: the prologue)
+  auto load_x = [&](int p, T* r, T& h) {
+    const TX* xp = x + plane_off(p);
+    const bool z = zin(p);
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (own[u]) X[(pb[u] + 1) * G::W(0) + pa[u] + 1] = r[u];
-    if (tid < G::HALO) X[hidx] = h;
+    for (int u = 0; u < 2; ++u) {
+      const T w = (T)xp[soff[u]];
+      r[u] = (z && ing[u]) ? w : T(0);
+    }
+    const T w = (T)xp[hoff];
+    h = (z && hing) ? w : T(0);
+  };
+  // x plane p into its LDS buffer
+  auto put_x = [&](int p, const T* r, T h) {
+    T* X = lds + (p & 1) * G::BUF;
+    const int dummy_shift = (p & 1) * G::BUF;  // keep dummy slots where they are
+    X[ci[0]] = r[0];
+    X[ci[1] - (ci[1] >= G::DUMMY ? dummy_shift : 0)] = r[1];
+    X[hci - (hci >= G::DUMMY ? dummy_shift : 0)] = h;
   };
 
-  const int q0 = k0 - NT + 1, qend = k1 + NT - 2;
-  // prologue: x(q0 - 1) and x(q0) in the ring, x(q0) in LDS, x(q0 + 1) and
-  // v, y1 at planes q0 and q0 + 1 in registers
+  // prologue: x(q0 - 1) and x(q0) in the ring, x(q0) in LDS, the loads of
+  // the first two steps in flight
   {
-    T t0[U], t1[U], h1;
+    T t0[2], t1[2], h1;
     load_x(q0 - 1, t0, h1);
     load_x(q0, t1, h1);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < 2; ++u) {
       ring[0][0][u] = t0[u];
       ring[0][1][u] = t1[u];
     }
     put_x(q0, t1, h1);
   }
-  load_x(q0 + 1, xn[0], xh[0]);
-  load_vy(q0, vn[0], yn[0]);
-  load_x(q0 + 2, xn[1], xh[1]);
-  load_vy(q0 + 1, vn[1], yn[1]);
+  issue(q0, std::integral_constant<int, 0>());
+  issue(q0 + 1, std::integral_constant<int, 1>());
   __syncthreads();
 
-  for (int q = q0; q <= qend; ++q) {
+  auto step = [&](int q, auto slot) {
+    constexpr int S = decltype(slot)::value;
     // term 0: x(q + 1) into the ring and LDS; v, y1 at plane q into use
+    const bool zx = zin(q + 1), zv = zin(q);
+    T xc[2];
 #pragma unroll
-    for (int u = 0; u < U; ++u) ring[0][2][u] = xn[0][u];
-    put_x(q + 1, xn[0], xh[0]);
-    T ycur[U];
+    for (int u = 0; u < 2; ++u) {
+      xc[u] = (zx && ing[u]) ? xq[S][u] : T(0);
+      ring[0][2][u] = xc[u];
+    }
+    put_x(q + 1, xc, (zx && hing) ? xhq[S] : T(0));
+    T ycur[2];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < 2; ++u) {
 #pragma unroll
       for (int s = NT - 1; s > 0; --s) vr[s][u] = vr[s - 1][u];
-      vr[0][u] = vn[0][u];
-      ycur[u] = yn[0][u];
-      xn[0][u] = xn[1][u];
-      vn[0][u] = vn[1][u];
-      yn[0][u] = yn[1][u];
+      vr[0][u] = (zv && ing[u]) ? vq[S][u] : T(0);
+      ycur[u] = (zv && ing[u]) ? yq[S][u] : T(0);
     }
-    xh[0] = xh[1];
-    // loads for step q + 2 (none past the last plane the slab needs)
-    if (q + 3 <= k1 + NT - 1) load_x(q + 3, xn[1], xh[1]);
-    if (q + 2 <= qend) load_vy(q + 2, vn[1], yn[1]);
+    // the slot's loads for step q + 2, kept after the reads of the slot (a
+    // load scheduled above them would need another register and a copy)
+    __builtin_amdgcn_sched_barrier(0);
+    issue(q + 2, slot);
 
-    // terms 1 .. NT
+    // terms 1 .. NT (the last one on the tile points only)
 #pragma unroll
     for (int t = 1; t <= NT; ++t) {
       const int p = q - t + 1;
-      const bool need = p >= k0 - (NT - t) && p < k1 + (NT - t);
-      const bool zp = zin(p);
-      // in-plane neighbours of s_{t-1} at plane p (written at step q - 1)
-      const int wl = G::W(t - 1);
-      const T* L = lds + G::off(t - 1) + (p & 1) * G::N(t - 1);
-      T* D = (t < NT) ? lds + G::off(t) + (p & 1) * G::N(t) : nullptr;
-      const T a = (T)cd.a[t - 1], b = (T)cd.b[t - 1], e0 = (T)cd.g0[t - 1],
-              e1 = (T)cd.g1[t - 1];
+      if (p >= max(k0 - (NT - t), 0) && p < min(k1 + (NT - t), g.nz)) {
+        const T a = (T)cd.a[t - 1], b = (T)cd.b[t - 1], e0 = (T)cd.g0[t - 1],
+                e1 = (T)cd.g1[t - 1];
+        // in-plane neighbours of s_{t-1} at plane p (written at step q - 1)
+        const T* L = lds + (t - 1) * 2 * G::BUF + (p & 1) * G::BUF;
+        const bool outp = p >= k0 && p < k1;
+        const int64_t po = (int64_t)p * plane;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        // region-t coordinates of the owned point
-        const int ra = pa[u] - (t - 1), rb = pb[u] - (t - 1);
-        const bool inr = own[u] && ra >= 0 && ra < G::W(t) && rb >= 0 && rb < G::H(t);
-        T val = T(0);
-        if (inr && ing[u] && zp && need) {
-          const int c = (rb + 1) * wl + (ra + 1);  // the point in region t - 1
+        for (int u = 0; u < (t == NT ? 1 : 2); ++u) {
+          const int c = u == 0 ? ci[0] : (ci[1] >= G::DUMMY ? W0 + 1 : ci[1]);
           const T sv = ring[t - 1][1][u];
           T as = c0 * sv;
           as = fma(czm, ring[t - 1][0][u], as);
           as = fma(czp, ring[t - 1][2][u], as);
           as = fma(cxm, L[c - 1], as);
           as = fma(cxp, L[c + 1], as);
-          as = fma(cym, L[c - wl], as);
-          as = fma(cyp, L[c + wl], as);
-          val = fma(a, as, b * sv);
+          as = fma(cym, L[c - W0], as);
+          as = fma(cyp, L[c + W0], as);
+          T val = fma(a, as, b * sv);
           val = fma(e0, vr[t - 1][u], val);
           if (t == 1) {
             if (Y1G) val = fma(e1, ycur[u], val);
           } else {
             val = fma(e1, ring[t - 2][0][u], val);
           }
-          const bool tile = ra >= NT - t && ra < NT - t + G::TX && rb >= NT - t &&
-                            rb < NT - t + TY && p >= k0 && p < k1;
-          if (t == NT && tile) out2[zoff(p) + poff[u]] = (TO)val;
-          if (W1 && t == NT - 1 && tile) out1[zoff(p) + poff[u]] = (TO)val;
+          val = ing[u] ? val : T(0);
+          if (t < NT) {
+            ring[t][2][u] = val;
+            T* D = lds + t * 2 * G::BUF + (p & 1) * G::BUF;
+            D[ci[u] - (ci[u] >= G::DUMMY ? t * 2 * G::BUF + (p & 1) * G::BUF : 0)] = val;
+          }
+          if (u == 0 && outp && ing[0]) {
+            if (t == NT) out2[po + soff[0]] = (TO)val;
+            if (W1 && t == NT - 1) out1[po + soff[0]] = (TO)val;
+          }
         }
-        if (t < NT) {
-          ring[t][2][u] = val;
-          if (inr) D[rb * G::W(t) + ra] = val;
-        }
+      } else if (t < NT) {
+        ring[t][2][0] = ring[t][2][1] = T(0);
       }
     }
     __syncthreads();  // this step's planes visible; last step's buffers free
 #pragma unroll
     for (int s = 0; s < NT; ++s)
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < 2; ++u) {
         ring[s][0][u] = ring[s][1][u];
         ring[s][1][u] = ring[s][2][u];
       }
+  };
+  for (int q = q0; q <= qend; q += 2) {
+    step(q, std::integral_constant<int, 0>());
+    step(q + 1, std::integral_constant<int, 1>());
   }
 }
 
