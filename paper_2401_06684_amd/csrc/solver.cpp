@@ -274,8 +274,7 @@ static int poly_apply_ls(const Op& op, const Poly& q, const void* x, void* out, 
 // single-term launch may write over x pointwise, a two-term launch may not);
 // *res names the buffer that holds q(A) x.  `fuse` is the most consecutive
 // terms of the 7-point stencil one launch may take (1, 2 or 3): groups of
-// three while three or more terms remain, then a pair or a single term
-// (FP32 chains: pairs).
+// three while three or more terms remain, then a pair or a single term.
 // pm = P32 (mixed precision): x and every intermediate vector are FP32 and
 // the last launch writes `out` in precision pout; pm = P64: everything FP64.
 static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, void* const tmp[4],
@@ -340,11 +339,8 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
   int set = 0;
   bool timing = false;
   int i = 0;
-  // FP32 chains stay with pairs: the three-term kernel is bound by its
-  // per-plane latency, not by the bytes, so halving them gains nothing there
-  const int most = pm == P32 ? 2 : fuse;
   for (;;) {
-    const int g = (most >= 3 && i + 3 <= nT) ? 3 : (i + 2 <= nT) ? 2 : 0;
+    const int g = (fuse >= 3 && i + 3 <= nT) ? 3 : (i + 2 <= nT) ? 2 : 0;
     if (g == 0) break;
     const bool has_next = i + g < nT;  // someone reads out_{i+g-2} later
     void* o1 = has_next ? tmp[2 * set] : nullptr;
