@@ -267,20 +267,44 @@ __global__ __launch_bounds__(256) void blk_proj_k(int64_t n, const double* __res
 #pragma unroll
     for (int b = 0; b < T; ++b) acc[a][b] = dx4{0.0, 0.0, 0.0, 0.0};
   const int rl = lane >> 4, cl = lane & 15;
-  for (int64_t r0 = r_beg + 4 * wv; r0 < r_end; r0 += 16) {
-    const int64_t r = r0 + rl;
-    DVec<T> av, bv;
-    if (r < r_end) {
-      av = DVec<T>::load(Vi + r * S + T * cl);
-      bv = DVec<T>::load(W + r * S + T * cl);
-    } else {
+  // Rows are loaded NS iterations ahead into NS register slots (one wave
+  // per SIMD: the accumulators take the AGPRs, so the latency of HBM must be
+  // hidden inside the wave); the loop is unrolled by NS so that each slot is
+  // fixed at compile time, and a slot is refilled only after its MFMAs (a
+  // load scheduled above them would need another register and a copy of an
+  // unfinished load, i.e. a wait).  Rows past the chunk load a clamped row
+  // and count as zero.
+  constexpr int NS = 4;
+  if (r_beg < r_end) {
+    DVec<T> av[NS], bv[NS];
+    auto fetch = [&](int64_t r0, auto slot) {
+      constexpr int S2 = decltype(slot)::value;
+      const int64_t r = min(r0 + rl, r_end - 1);
+      av[S2] = DVec<T>::load(Vi + r * S + T * cl);
+      bv[S2] = DVec<T>::load(W + r * S + T * cl);
+    };
+    auto use = [&](int64_t r0, auto slot) {
+      constexpr int S2 = decltype(slot)::value;
+      const bool ok = r0 + rl < r_end;
 #pragma unroll
-      for (int t = 0; t < T; ++t) av.v[t] = bv.v[t] = 0.0;
+      for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int b = 0; b < T; ++b)
+          acc[a][b] = mfma16(ok ? av[S2].v[a] : 0.0, bv[S2].v[b], acc[a][b]);
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(r0 + 16 * NS, slot);
+    };
+    const int64_t first = r_beg + 4 * wv;
+    fetch(first, std::integral_constant<int, 0>());
+    fetch(first + 16, std::integral_constant<int, 1>());
+    fetch(first + 32, std::integral_constant<int, 2>());
+    fetch(first + 48, std::integral_constant<int, 3>());
+    for (int64_t r0 = first; r0 < r_end; r0 += 16 * NS) {
+      use(r0, std::integral_constant<int, 0>());
+      use(r0 + 16, std::integral_constant<int, 1>());
+      use(r0 + 32, std::integral_constant<int, 2>());
+      use(r0 + 48, std::integral_constant<int, 3>());
     }
-#pragma unroll
-    for (int a = 0; a < T; ++a)
-#pragma unroll
-      for (int b = 0; b < T; ++b) acc[a][b] = mfma16(av.v[a], bv.v[b], acc[a][b]);
   }
   // wave w adds its tiles into red in turn (w = 0 stores)
   for (int w = 0; w < 4; ++w) {
@@ -368,17 +392,38 @@ __global__ __launch_bounds__(256) void gemm_k(int64_t M, int K, double alpha,
   const double* Bb = B + (int64_t)(4 * rl) * ldb + c0 + T * cl;
   const int per = kb / 16;  // groups of 16 k per column block of A
   const int ng = K / 16;
-  for (int g = 0; g < ng; ++g) {
-    const int blk = g / per, kk = (g - blk * per) * 16;
-    const dx4 a4 = arow ? *reinterpret_cast<const dx4*>(Ab + (int64_t)blk * a_blk + kk)
-                        : dx4{0.0, 0.0, 0.0, 0.0};
-    const double* Bk = Bb + (int64_t)g * 16 * ldb;
+  // Groups are loaded two ahead into two register slots, the loop unrolled
+  // by two so that the slots are fixed at compile time; a slot is refilled
+  // only after its MFMAs (no copy of a register a load is still filling).
+  // Groups past the end load the last group again and count as zero; rows
+  // past M load row 0 and count as zero.
+  const double* Abase = arow ? Ab : A + 4 * rl;
+  dx4 a4[2];
+  DVec<T> bq[2][4];
+  auto fetch = [&](int g, auto slot) {
+    constexpr int S = decltype(slot)::value;
+    const int gc = min(g, ng - 1);
+    const int blk = gc / per, kk = (gc - blk * per) * 16;
+    a4[S] = *reinterpret_cast<const dx4*>(Abase + (int64_t)blk * a_blk + kk);
+    const double* Bk = Bb + (int64_t)gc * 16 * ldb;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const DVec<T> bq = DVec<T>::load(Bk + (int64_t)q * ldb);
+    for (int q = 0; q < 4; ++q) bq[S][q] = DVec<T>::load(Bk + (int64_t)q * ldb);
+  };
+  auto use = [&](int g, auto slot) {
+    constexpr int S = decltype(slot)::value;
+    const bool ok = arow && g < ng;
 #pragma unroll
-      for (int t = 0; t < T; ++t) acc[t] = mfma16(a4[q], bq.v[t], acc[t]);
-    }
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < T; ++t) acc[t] = mfma16(ok ? a4[S][q] : 0.0, bq[S][q].v[t], acc[t]);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(g + 2, slot);
+  };
+  fetch(0, std::integral_constant<int, 0>());
+  fetch(1, std::integral_constant<int, 1>());
+  for (int g = 0; g < ng; g += 2) {
+    use(g, std::integral_constant<int, 0>());
+    use(g + 1, std::integral_constant<int, 1>());
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
