@@ -97,6 +97,7 @@ __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(4))) vo
     St7M g, int kz, int gx, int gy, int nwg, const TX* __restrict__ x, const TX* __restrict__ v,
     const TX* __restrict__ y1, TO* __restrict__ out1, TO* __restrict__ out2, MultiCoef<NT> cd) {
   using G = Geo<NT, TY>;
+  static_assert(G::RING <= G::P && G::HALO <= G::P, "one ring and one halo point per thread");
   constexpr int W0 = G::W(0);
   __shared__ T lds[G::total()];
   const T c0 = (T)g.c0, cxm = (T)g.cxm, cxp = (T)g.cxp, cym = (T)g.cym, cyp = (T)g.cyp,
