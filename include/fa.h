@@ -175,7 +175,8 @@ typedef struct {
  * copy) to check them and to pick the work split: rows up to 16 times the
  * mean length (rounded to a power of two) are summed by lane groups, longer
  * ones (at most 900; the threshold doubles until so) by one 1024-thread
- * workgroup each.  Column indices are not validated.  A CSR op has no
+ * workgroup each, in the same launch; their list is copied to a small device
+ * array the op owns.  Column indices are not validated.  A CSR op has no
  * spectral interval until fa_set_spectral_interval is called.
  * Errors: FA_ERR_ARG (including row pointers that do not start at 0, end at
  * nnz and never decrease), FA_ERR_HIP.

@@ -73,6 +73,7 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
     op.vals = d_vals;
     op.nnz = nnz;
     // lanes per row: the power of two nearest above the mean row length
+    // (half or a quarter of it measured slower on the power-law graph)
     const double avg = (double)nnz / (double)n;
     int g = 1;
     while (g < 64 && g < avg) g <<= 1;
@@ -107,6 +108,20 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
         break;
       }
       thr *= 2;
+    }
+    if (!op.csr_long_rows.empty()) {  // the list on the device (op-owned)
+      const size_t bytes = op.csr_long_rows.size() * sizeof(int32_t);
+      void* d = nullptr;
+      if (hipMalloc(&d, bytes) != hipSuccess) {
+        delete h;
+        return FA_ERR_HIP;
+      }
+      op.csr_long_owned = std::shared_ptr<void>(d, [](void* p) { (void)hipFree(p); });
+      op.csr_long_dev = (const int32_t*)d;
+      if (hipMemcpy(d, op.csr_long_rows.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        delete h;
+        return FA_ERR_HIP;
+      }
     }
     *out = h;
     return FA_OK;

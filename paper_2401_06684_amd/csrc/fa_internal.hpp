@@ -61,6 +61,8 @@ struct Op {
   // left to a kernel with one 1024-thread workgroup per row
   int csr_long_thr = 0x7fffffff;
   std::vector<int32_t> csr_long_rows;
+  const int32_t* csr_long_dev = nullptr;  // the same list in device memory
+  std::shared_ptr<void> csr_long_owned;
   // stencil
   int dims[4] = {1, 1, 1, 1};
   double coef[7] = {0, 0, 0, 0, 0, 0, 0};

@@ -394,24 +394,66 @@ hipError_t launch_chain_pair(const Op& op, const void* x, const void* y0, const 
 // --------------------------------------------------------------------------
 // CSR, real or complex values: G lanes per row (G = power of two <= 64 close
 // to the mean row length), row sums reduced with shuffles inside the group.
-// Rows longer than `thr` (the long tail of a power-law degree distribution)
-// are skipped here and summed by csr_long, one 1024-thread workgroup each, so
-// that no lane group walks tens of thousands of entries alone.
+// Rows longer than `thr` (the long tail of a power-law degree distribution,
+// listed at creation) get a 1024-thread workgroup each, so that no lane group
+// walks tens of thousands of entries alone.  One launch does both: the first
+// nl workgroups take the long rows (the longest tasks, so they start first),
+// the others the remaining rows, and the long rows run concurrently with the
+// rest instead of after it.
 // --------------------------------------------------------------------------
 template <typename T, int G, bool Y0, bool Y1>
-__global__ __launch_bounds__(256) void csr_chain(int n, const int32_t* __restrict__ rowptr,
-                                                 const int32_t* __restrict__ colind,
-                                                 const T* __restrict__ vals,
-                                                 const T* __restrict__ x,
-                                                 const T* __restrict__ y0, const T* y1, T* out,
-                                                 T al, T be, T g0, T g1, int thr) {
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(1024) void csr_chain(int n, const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ colind,
+                                                  const T* __restrict__ vals,
+                                                  const T* __restrict__ x,
+                                                  const T* __restrict__ y0, const T* y1, T* out,
+                                                  T al, T be, T g0, T g1, int thr, int nl,
+                                                  const int32_t* __restrict__ long_rows) {
+  if ((int)blockIdx.x < nl) {
+    // a long row: the 1024 threads stride through it, loading 8 entries
+    // (index and value) before the 8 gathers of x so that the loads overlap;
+    // partial sums are added in a fixed order (wavefront shuffles, then the
+    // 16 wavefront sums in LDS)
+    __shared__ T ws[16];
+    const int row = long_rows[blockIdx.x];
+    const int e0 = rowptr[row], e1 = rowptr[row + 1];
+    T acc = zero(T{});
+    for (int base = e0 + (int)threadIdx.x; base < e1; base += 8 * 1024) {
+      int c[8];
+      T v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int e = min(base + k * 1024, e1 - 1);
+        c[k] = colind[e];
+        v[k] = vals[e];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const T t = mad(v[k], x[c[k]], acc);
+        acc = (base + k * 1024 < e1) ? t : acc;
+      }
+    }
+    acc = wave_sum(acc);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) ws[wv] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      T t = ws[0];
+      for (int w = 1; w < 16; ++w) t += ws[w];
+      T r = mad(al, t, be * x[row]);
+      if (Y0) r = mad(g0, y0[row], r);
+      if (Y1) r = mad(g1, y1[row], r);
+      out[row] = r;
+    }
+    return;
+  }
+  const int64_t gt = (int64_t)(blockIdx.x - nl) * blockDim.x + threadIdx.x;
   const int64_t row = gt / G;
   const int lane = (int)(gt % G);
   if (row >= n) return;  // whole groups leave together (G divides 64)
   T acc = zero(T{});
   const int e0 = rowptr[row], e1 = rowptr[row + 1];
-  if (e1 - e0 > thr) return;  // a long row: csr_long writes it
+  if (e1 - e0 > thr) return;  // a long row: its own workgroup writes it
   for (int e = e0 + lane; e < e1; e += G) acc = mad(vals[e], x[colind[e]], acc);
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) acc += shfl_down(acc, off, G);
@@ -423,71 +465,29 @@ __global__ __launch_bounds__(256) void csr_chain(int n, const int32_t* __restric
   }
 }
 
-struct LongRows {
-  int count;
-  int idx[kCsrLongMax];
-};
-
-// one long row per workgroup of 1024 threads; the partial sums are added in a
-// fixed order (wavefront shuffles, then the 16 wavefront sums in LDS)
-template <typename T, bool Y0, bool Y1>
-__global__ __launch_bounds__(1024) void csr_long(const int32_t* __restrict__ rowptr,
-                                                 const int32_t* __restrict__ colind,
-                                                 const T* __restrict__ vals,
-                                                 const T* __restrict__ x,
-                                                 const T* __restrict__ y0, const T* y1, T* out,
-                                                 T al, T be, T g0, T g1, LongRows lr) {
-  __shared__ T ws[16];
-  const int row = lr.idx[blockIdx.x];
-  const int e0 = rowptr[row], e1 = rowptr[row + 1];
-  T acc = zero(T{});
-#pragma unroll 4
-  for (int e = e0 + (int)threadIdx.x; e < e1; e += 1024) acc = mad(vals[e], x[colind[e]], acc);
-  acc = wave_sum(acc);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) ws[wv] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    T t = ws[0];
-    for (int w = 1; w < 16; ++w) t += ws[w];
-    T r = mad(al, t, be * x[row]);
-    if (Y0) r = mad(g0, y0[row], r);
-    if (Y1) r = mad(g1, y1[row], r);
-    out[row] = r;
-  }
-}
-
 template <typename T, int G>
 static void launch_csr_g(const Op& op, const T* x, const T* y0, const T* y1, T* out, T al,
                          T be, T g0, T g1, hipStream_t st) {
   const int n = (int)op.n;
   const int64_t threads = (int64_t)n * G;
-  const int grid = (int)((threads + 255) / 256);
+  const int nl = (int)op.csr_long_rows.size();
+  // 1024 threads per workgroup when there are long rows (their workgroups
+  // need them), else 256 (more workgroups for a small matrix)
+  const int bs = nl > 0 ? 1024 : 256;
+  const int grid = nl + (int)((threads + bs - 1) / bs);
   auto rp = op.rowptr;
   auto ci = op.colind;
   auto va = (const T*)op.vals;
   const int thr = op.csr_long_thr;
+  const int32_t* lr = op.csr_long_dev;
   if (y0 && y1)
-    csr_chain<T, G, true, true><<<grid, 256, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr);
+    csr_chain<T, G, true, true><<<grid, bs, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr, nl, lr);
   else if (y0)
-    csr_chain<T, G, true, false><<<grid, 256, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr);
+    csr_chain<T, G, true, false><<<grid, bs, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr, nl, lr);
   else if (y1)
-    csr_chain<T, G, false, true><<<grid, 256, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr);
+    csr_chain<T, G, false, true><<<grid, bs, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr, nl, lr);
   else
-    csr_chain<T, G, false, false><<<grid, 256, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr);
-  const int nl = (int)op.csr_long_rows.size();
-  if (nl == 0) return;
-  LongRows lr;
-  lr.count = nl;
-  for (int i = 0; i < nl; ++i) lr.idx[i] = op.csr_long_rows[i];
-  if (y0 && y1)
-    csr_long<T, true, true><<<nl, 1024, 0, st>>>(rp, ci, va, x, y0, y1, out, al, be, g0, g1, lr);
-  else if (y0)
-    csr_long<T, true, false><<<nl, 1024, 0, st>>>(rp, ci, va, x, y0, y1, out, al, be, g0, g1, lr);
-  else if (y1)
-    csr_long<T, false, true><<<nl, 1024, 0, st>>>(rp, ci, va, x, y0, y1, out, al, be, g0, g1, lr);
-  else
-    csr_long<T, false, false><<<nl, 1024, 0, st>>>(rp, ci, va, x, y0, y1, out, al, be, g0, g1, lr);
+    csr_chain<T, G, false, false><<<grid, bs, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr, nl, lr);
 }
 
 template <typename T>
