@@ -401,6 +401,10 @@ hipError_t launch_chain_pair(const Op& op, const void* x, const void* y0, const 
 // the others the remaining rows, and the long rows run concurrently with the
 // rest instead of after it.
 // --------------------------------------------------------------------------
+// entries of a long row loaded per thread before their gathers (16 and 32
+// measured slower: the extra registers cost the other rows occupancy)
+constexpr int kLongBatch = 8;
+
 template <typename T, int G, bool Y0, bool Y1>
 __global__ __launch_bounds__(1024) void csr_chain(int n, const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ colind,
@@ -410,25 +414,26 @@ __global__ __launch_bounds__(1024) void csr_chain(int n, const int32_t* __restri
                                                   T al, T be, T g0, T g1, int thr, int nl,
                                                   const int32_t* __restrict__ long_rows) {
   if ((int)blockIdx.x < nl) {
-    // a long row: the 1024 threads stride through it, loading 8 entries
-    // (index and value) before the 8 gathers of x so that the loads overlap;
+    // a long row: the 1024 threads stride through it, loading kLongBatch
+    // entries (index and value) before their gathers of x so that the loads
+    // overlap;
     // partial sums are added in a fixed order (wavefront shuffles, then the
     // 16 wavefront sums in LDS)
     __shared__ T ws[16];
     const int row = long_rows[blockIdx.x];
     const int e0 = rowptr[row], e1 = rowptr[row + 1];
     T acc = zero(T{});
-    for (int base = e0 + (int)threadIdx.x; base < e1; base += 8 * 1024) {
-      int c[8];
-      T v[8];
+    for (int base = e0 + (int)threadIdx.x; base < e1; base += kLongBatch * 1024) {
+      int c[kLongBatch];
+      T v[kLongBatch];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < kLongBatch; ++k) {
         const int e = min(base + k * 1024, e1 - 1);
         c[k] = colind[e];
         v[k] = vals[e];
       }
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < kLongBatch; ++k) {
         const T t = mad(v[k], x[c[k]], acc);
         acc = (base + k * 1024 < e1) ? t : acc;
       }
