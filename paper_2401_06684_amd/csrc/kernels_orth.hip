@@ -373,6 +373,86 @@ __global__ __launch_bounds__(kThreads) void dcgs2_col_k(int j, const T* __restri
   }
 }
 
+// The three small steps between the two sweeps of a delayed-CGS2 step in
+// one 1024-thread workgroup (one launch instead of three):
+//   1. S[c] = sum_b part[c * nblk + b] for the 2 (j + 1) projections (wave w
+//      takes columns w, w + 16, ..; lanes stride the partials, then a
+//      fixed-order wave reduction), kept in LDS;
+//   2. the coefficients: nu, gamma, cs = s, cp = p and the finished column
+//      j - 1 of H (as dcgs2_coef_k);
+//   3. the first-pass column j of H (as dcgs2_col_k): rows in blocks of 64
+//      lanes, the 16 waves take every 16th column, partial sums added in
+//      LDS in a fixed order.
+// Every sum is in a fixed order: the result does not depend on timing.
+constexpr int kFinThreads = 1024;
+template <typename T>
+__global__ __launch_bounds__(kFinThreads) void dcgs2_finish_k(int j, int nblk,
+                                                              const T* __restrict__ part, T* H,
+                                                              int64_t ldh, T* __restrict__ cs,
+                                                              T* __restrict__ cp,
+                                                              T* __restrict__ sc) {
+  extern __shared__ unsigned char fin_lds[];
+  T* S = reinterpret_cast<T*>(fin_lds);  // 2 (j + 1) entries
+  __shared__ T colpart[kFinThreads / 64][64];
+  __shared__ double s_nu;
+  __shared__ T s_gam;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int NW = kFinThreads / 64;
+  // 1. the projections
+  for (int c = wv; c < 2 * (j + 1); c += NW) {
+    T a = zero(T{});
+    for (int b = lane; b < nblk; b += 64) a += part[(int64_t)c * nblk + b];
+    a = wave_sum(a);
+    if (lane == 0) S[c] = a;
+  }
+  __syncthreads();
+  // 2. the coefficients (one wave)
+  if (wv == 0) {
+    double ss = 0.0;
+    T sp = zero(T{});
+    for (int i = lane; i < j; i += 64) {
+      ss += abs2(S[2 * i]);
+      sp = cmad(S[2 * i], S[2 * i + 1], sp);
+    }
+    ss = wave_sum(ss);
+    sp = wave_sum(sp);
+    if (lane == 0) {
+      const double alpha = re_of(S[2 * j]);
+      const double nu2 = alpha - ss;
+      const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+      s_nu = nu;
+      s_gam = div_real(S[2 * j + 1] - sp, nu);
+      sc[0] = mk_real(nu > 0.0 ? 1.0 / nu : 0.0, T{});
+      sc[1] = s_gam;
+      H[(int64_t)(j - 1) * ldh + j] = mk_real(nu, T{});
+    }
+  }
+  for (int i = tid; i < j; i += kFinThreads) {
+    H[(int64_t)(j - 1) * ldh + i] += S[2 * i];
+    cs[i] = S[2 * i];
+    cp[i] = S[2 * i + 1];
+  }
+  __syncthreads();  // column j - 1 of H and s_nu, s_gam visible to the block
+  // 3. the first-pass column j: (Q_{j+1}^H z - Hbar s) / nu
+  const double inv = s_nu > 0.0 ? 1.0 / s_nu : 0.0;
+  for (int i0 = 0; i0 <= j; i0 += 64) {
+    const int i = i0 + lane;
+    T t = zero(T{});
+    if (i <= j)
+      for (int c = max(0, i - 1) + wv; c < j; c += NW) t = mad(H[(int64_t)c * ldh + i], S[2 * c], t);
+    colpart[wv][lane] = t;
+    __syncthreads();
+    if (wv == 0 && i <= j) {
+      T tt = colpart[0][lane];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) tt += colpart[w][lane];
+      const T top = (i < j) ? S[2 * i + 1] : s_gam;
+      H[(int64_t)j * ldh + i] = mk_real(inv, T{}) * (top - tt);
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void update2_k(int64_t n, int ncols, const T* __restrict__ V,
                                                       int64_t ldv, const T* __restrict__ cs,
@@ -432,15 +512,24 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
   char* cs = (char*)coef;
   char* cp = cs + (size_t)j * es;
   char* sc = cp + (size_t)j * es;
+  // one launch while the 2 (j + 1) projections fit 32 KB of LDS, else the
+  // three kernels
+  const size_t lds = 2 * (size_t)(j + 1) * es;
+  const bool fused = lds <= 32768;
   if (dtype == FA_C128) {
     project2_k<cplx><<<p.nblk, kThreads, 0, s>>>(n, j + 1, (const cplx*)V, ldv, (const cplx*)u,
                                                  (const cplx*)z, (cplx*)part, p.nblk);
-    reduce_cols_k<cplx><<<2 * (j + 1), kThreads, 0, s>>>(p.nblk, (const cplx*)part, (cplx*)S,
-                                                         nullptr, 0);
-    dcgs2_coef_k<cplx><<<1, kThreads, 0, s>>>(j, (const cplx*)S, (cplx*)H, ldh, (cplx*)cs,
-                                              (cplx*)cp, (cplx*)sc);
-    dcgs2_col_k<cplx><<<(j + 64) / 64, kThreads, 0, s>>>(j, (const cplx*)S, (cplx*)H, ldh,
-                                                         (const cplx*)sc);
+    if (fused) {
+      dcgs2_finish_k<cplx><<<1, kFinThreads, lds, s>>>(j, p.nblk, (const cplx*)part, (cplx*)H,
+                                                      ldh, (cplx*)cs, (cplx*)cp, (cplx*)sc);
+    } else {
+      reduce_cols_k<cplx><<<2 * (j + 1), kThreads, 0, s>>>(p.nblk, (const cplx*)part, (cplx*)S,
+                                                           nullptr, 0);
+      dcgs2_coef_k<cplx><<<1, kThreads, 0, s>>>(j, (const cplx*)S, (cplx*)H, ldh, (cplx*)cs,
+                                                (cplx*)cp, (cplx*)sc);
+      dcgs2_col_k<cplx><<<(j + 64) / 64, kThreads, 0, s>>>(j, (const cplx*)S, (cplx*)H, ldh,
+                                                           (const cplx*)sc);
+    }
     update2_k<cplx><<<p.nblk, kThreads, 0, s>>>(n, j, (const cplx*)V, ldv, (const cplx*)cs,
                                                 (const cplx*)cp, (const cplx*)sc, (cplx*)u,
                                                 (cplx*)z);
@@ -448,12 +537,18 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
     project2_k<double><<<p.nblk, kThreads, 0, s>>>(n, j + 1, (const double*)V, ldv,
                                                    (const double*)u, (const double*)z,
                                                    (double*)part, p.nblk);
-    reduce_cols_k<double><<<2 * (j + 1), kThreads, 0, s>>>(p.nblk, (const double*)part,
-                                                           (double*)S, nullptr, 0);
-    dcgs2_coef_k<double><<<1, kThreads, 0, s>>>(j, (const double*)S, (double*)H, ldh,
-                                                (double*)cs, (double*)cp, (double*)sc);
-    dcgs2_col_k<double><<<(j + 64) / 64, kThreads, 0, s>>>(j, (const double*)S, (double*)H, ldh,
-                                                           (const double*)sc);
+    if (fused) {
+      dcgs2_finish_k<double><<<1, kFinThreads, lds, s>>>(j, p.nblk, (const double*)part,
+                                                        (double*)H, ldh, (double*)cs,
+                                                        (double*)cp, (double*)sc);
+    } else {
+      reduce_cols_k<double><<<2 * (j + 1), kThreads, 0, s>>>(p.nblk, (const double*)part,
+                                                             (double*)S, nullptr, 0);
+      dcgs2_coef_k<double><<<1, kThreads, 0, s>>>(j, (const double*)S, (double*)H, ldh,
+                                                  (double*)cs, (double*)cp, (double*)sc);
+      dcgs2_col_k<double><<<(j + 64) / 64, kThreads, 0, s>>>(j, (const double*)S, (double*)H,
+                                                             ldh, (const double*)sc);
+    }
     update2_k<double><<<p.nblk, kThreads, 0, s>>>(n, j, (const double*)V, ldv,
                                                   (const double*)cs, (const double*)cp,
                                                   (const double*)sc, (double*)u, (double*)z);
