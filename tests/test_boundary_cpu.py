@@ -59,6 +59,26 @@ def test_create_stencil_validation():
     assert _lib.lib().fa_destroy(h) == _lib.FA_OK
 
 
+def test_create_wilson_validation_and_link_copy_without_gpu():
+    """The Wilson op copies its links into device memory it owns at
+    creation: argument errors come first, then, without a GPU, the copy's
+    failure is reported (nothing is created)."""
+    L = _lib.lib()
+    h = C.c_void_p()
+    p = (C.c_double * 1)(0.05)
+    d4 = (C.c_int32 * 4)(4, 4, 4, 4)
+    # missing links, lattice extent below 2, Hermitian flag: argument errors
+    assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1, None, 0,
+                               None) == _lib.FA_ERR_ARG
+    d_bad = (C.c_int32 * 4)(4, 1, 4, 4)
+    assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d_bad, p, 1, C.c_void_p(256), 0,
+                               None) == _lib.FA_ERR_ARG
+    assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1, C.c_void_p(256),
+                               _lib.FA_HERMITIAN, None) == _lib.FA_ERR_ARG
+    assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1, C.c_void_p(256), 0,
+                               None) == _lib.FA_ERR_HIP
+
+
 @pytest.mark.parametrize("coeffs,dims", [
     (wl.laplace_stencil(2), (32, 32, 1)),
     (wl.laplace_stencil(3), (100, 100, 100)),

@@ -90,6 +90,34 @@ def test_wilson_apply(shape):
     assert_close(y, ops.wilson_apply(U, m0, x), 1e-14)
 
 
+def test_wilson_links_copied_at_creation():
+    """The op keeps its own (reordered) copy of the links: the caller's
+    device array can be overwritten and freed after creation."""
+    import ctypes as C
+    from paper_2401_06684_amd import _lib
+    Lt = Lz = Ly = Lx = 4
+    U = wl.random_su3(4 * Lt * Lz * Ly * Lx, 0.8, np.random.default_rng(7))
+    U = U.reshape(4, Lt, Lz, Ly, Lx, 3, 3)
+    dU = torch.from_numpy(np.ascontiguousarray(U)).to(DEV)
+    h = C.c_void_p()
+    d4 = (C.c_int32 * 4)(Lx, Ly, Lz, Lt)
+    p = (C.c_double * 1)(0.05)
+    st = _lib.lib().fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1,
+                                      C.c_void_p(dU.data_ptr()), 0, None)
+    assert st == 0
+    dU.fill_(float("nan"))  # the caller's array changes ...
+    torch.cuda.synchronize()
+    del dU                  # ... and goes away
+    torch.cuda.empty_cache()
+    x = wl.rhs(12 * Lt * Lz * Ly * Lx, seed=4, complex_=True)
+    dx, dy = dev(x), torch.empty(x.shape, dtype=torch.complex128, device=DEV)
+    torch.cuda.synchronize()
+    assert _lib.lib().fa_op_apply(h, C.c_void_p(dx.data_ptr()), C.c_void_p(dy.data_ptr()),
+                                  None) == 0
+    assert_close(host(dy), ops.wilson_apply(U, 0.05, x), 1e-14)
+    assert _lib.lib().fa_destroy(h) == 0
+
+
 # --------------------------------------------------------------------------
 # polynomial chain q(A) x
 # --------------------------------------------------------------------------
