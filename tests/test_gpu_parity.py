@@ -78,8 +78,9 @@ def test_csr_apply(which):
     assert_close(y, ops.csr_apply(rp, ci, va, x), 1e-14)
 
 
-@pytest.mark.parametrize("shape", [(4, 4, 4, 4), (6, 2, 4, 5)])
+@pytest.mark.parametrize("shape", [(4, 4, 4, 4), (6, 2, 4, 5), (4, 8, 4, 32)])
 def test_wilson_apply(shape):
+    """(Lt, Lz, Ly, Lx); the last shape has whole 16-site rows."""
     Lt, Lz, Ly, Lx = shape
     rng_links = wl.random_su3(4 * Lt * Lz * Ly * Lx, 0.8, np.random.default_rng(5))
     U = rng_links.reshape(4, Lt, Lz, Ly, Lx, 3, 3)
