@@ -30,11 +30,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "f(A)b solves/s at rel err 1e-8, poly-precond vs plain Arnoldi; SpMV HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the dominant kernel (the three-term middle launch
-# st7_multi<..., 3, 8, true, true> at 128^3: FETCH_SIZE x 2.00 + WRITE_SIZE x
-# 1.00, the factors of a 2 GiB copy), from the rocprofv3 counter runs in
-# profiles/st7_multi_convdiff128_deg16_hbm_counters.md
-MULTI_TRAFFIC_BYTES = (73777 + 32768) * 1024
+# HBM bytes per launch of the dominant kernel (the multi-term middle launch
+# st7_multi<..., NT, 8, true, true> at 128^3, keyed by NT: FETCH_SIZE x 2.00 +
+# WRITE_SIZE x 1.00, the factors of a 2 GiB copy), from the rocprofv3 counter
+# runs in profiles/st7_multi_convdiff128_deg16_hbm_counters.md
+MULTI_TRAFFIC_BYTES = {3: (73777 + 32768) * 1024}
 
 
 def log(msg):
@@ -160,6 +160,7 @@ def main():
     bytes_avg = sum(s["chain_bytes"] * s["n_chain"] for s in stats) / max(n_chain, 1)
     avg_ms = ms_chain / max(n_chain, 1)
     terms = sum(s["n_chain_terms"] for s in stats) / max(n_chain, 1)  # per timed launch
+    traffic = MULTI_TRAFFIC_BYTES.get(int(round(terms)))  # None: not measured for this kernel
     # algorithmic bytes of one timed launch as designed: x, v, b_(k+2) read
     # once and the two terms the next launch needs written once (5 vectors,
     # bytes_avg from the solve's statistics); per-term accounting (each term
@@ -196,9 +197,10 @@ def main():
     xm, dtm, stm = timed(o, 5, 1, profile=True, mixed=True, tol_=1e-7)
     nm = sum(s_["n_chain"] for s_ in stm)
     avg_m = sum(s_["ms_chain"] for s_ in stm) / max(nm, 1)
+    terms_m = sum(s_["n_chain_terms"] for s_ in stm) / max(nm, 1)
     extra["mixed_fp32_chain"] = {
         "solves_per_s": 5 / dtm, "iters": stm[-1]["iters"], "rel_err": rel_err(xm),
-        "tol": 1e-7, "kernel": "st7_multi<float, 3 terms>",
+        "tol": 1e-7, "kernel": f"st7_multi<float, {terms_m:.0f} terms>",
         "avg_launch_us": avg_m * 1e3, "bytes_per_launch": stm[-1]["chain_bytes"],
         "achieved_GBs": stm[-1]["chain_bytes"] / (avg_m * 1e-3) / 1e9}
     log(f"mixed precision: {5 / dtm:.2f} solves/s, m = {stm[-1]['iters']}, "
@@ -274,10 +276,10 @@ def main():
                    "n": N ** 3, "degree": K, "tol": tol, "kind": "invsqrt",
                    "orthogonalization": "CGS2", "preconditioning": "left"},
         "roofline": {"bound": "hbm",
-                     "kernel": f"st7_multi<double, 3 terms> ({terms:.0f} Clenshaw terms per "
-                               "launch)",
+                     "kernel": f"st7_multi<double, {terms:.0f} terms> ({terms:.0f} Clenshaw "
+                               "terms per launch)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": MULTI_TRAFFIC_BYTES,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_avg,
                      "algorithmic_unit": f"one launch = {terms:.0f} Clenshaw middle terms: x, v, "
                                          "b_k+2 read and the last two terms written (5 vectors)",
@@ -285,8 +287,8 @@ def main():
                          "bytes_per_launch": algo_bytes, "achieved": achieved_per_term,
                          "frac": achieved_per_term / HBM_PEAK_GBS,
                          "unit": "each term at 4 vectors, as one term per launch moves"},
-                     "traffic_frac": (MULTI_TRAFFIC_BYTES / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
-                                      if MULTI_TRAFFIC_BYTES else None),
+                     "traffic_frac": (traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                      if traffic else None),
                      "avg_launch_us": avg_ms * 1e3, "launches_timed": n_chain},
         "cpu_baseline": cpu,
         **extra,

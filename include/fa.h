@@ -101,8 +101,9 @@ enum {
   FA_PROFILE = 8u,       /* apply: time the middle terms of every q(A) application      */
   FA_NO_FUSION = 16u,    /* apply: one launch per recurrence term (no multi-term launches) */
   FA_FUSE2 = 1024u,      /* apply: at most two recurrence terms per launch (default on a
-                            7-point stencil: three per launch, then a pair or a
-                            single term)                                            */
+                            7-point stencil: four per launch, then the largest
+                            group that fits: three, a pair or a single term)    */
+  FA_FUSE3 = 2048u,      /* apply: at most three recurrence terms per launch        */
   FA_TWO_PASS = 64u,     /* apply: two-pass Lanczos (Hermitian op, not with
                             FA_FORCE_ARNOLDI or FA_RIGHT_PREC, else
                             FA_ERR_UNSUPPORTED): pass 1 keeps three basis vectors

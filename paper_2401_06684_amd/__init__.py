@@ -31,14 +31,16 @@ _METHOD = {"auto": FA_POLY_AUTO, "cheb": FA_POLY_CHEB, "ritz": FA_POLY_RITZ,
 
 
 def _fuse_flags(fuse):
-    """Flags for the most recurrence terms per launch: True or 3, 2, False or 1."""
-    if fuse is True or fuse == 3:
+    """Flags for the most recurrence terms per launch: True or 4, 3, 2, False or 1."""
+    if fuse is True or fuse == 4:
         return 0
     if fuse is False or fuse == 1:
         return FA_NO_FUSION
     if fuse == 2:
         return _lib.FA_FUSE2
-    raise ValueError("fuse must be True, False, 1, 2 or 3")
+    if fuse == 3:
+        return _lib.FA_FUSE3
+    raise ValueError("fuse must be True, False, 1, 2, 3 or 4")
 
 
 def _stream(device):
@@ -180,8 +182,8 @@ class Operator:
               right=False, orth="dcgs2", raise_not_converged=False):
         """x ~ A^{-1/2} b or A^{1/2} b.  Returns (x, stats dict).
 
-        fuse: most recurrence terms per launch on a 7-point stencil (True = 3,
-        2, or False / 1 for one launch per term);
+        fuse: most recurrence terms per launch on a 7-point stencil (True = 4,
+        3, 2, or False / 1 for one launch per term);
         mixed=True runs the polynomial chain in FP32 (stencil, Chebyshev q);
         two_pass=True runs two-pass Lanczos (O(n) basis storage);
         right=True runs the right-preconditioned variant (Algorithm 2);

@@ -295,7 +295,7 @@ int fa_apply(fa_op op, int kind, const void* d_b, void* d_x, int m_max, double t
              void* hip_stream, fa_stats* stats) {
   if (!op || !d_b || !d_x || d_b == d_x || m_max < 1 || check_every < 0 ||
       (kind != FA_INVSQRT && kind != FA_SQRT) || !std::isfinite(tol) ||
-      (flags & ~uint32_t(FA_FORCE_ARNOLDI | FA_PROFILE | FA_NO_FUSION | FA_FUSE2 | FA_MIXED |
+      (flags & ~uint32_t(FA_FORCE_ARNOLDI | FA_PROFILE | FA_NO_FUSION | FA_FUSE2 | FA_FUSE3 | FA_MIXED |
                          FA_TWO_PASS | FA_RIGHT_PREC | FA_CGS2)))
     return FA_ERR_ARG;
   if (!op->op.poly_ready) return FA_ERR_NO_POLY;

@@ -4,8 +4,9 @@
 // with s_0 = x and s_{-1} = y1, in one launch (the Clenshaw recurrence of a
 // Chebyshev polynomial, Sec. 5.1: s_{t-2} is b_{k+2}, v the vector q(A) acts
 // on).  Memory sees x, y1 and v read and s_{NT-1}, s_NT written: 5 vector
-// passes for NT terms (NT = 3: 5/3 per term, against 5/2 for two terms and 4
-// for one).  The intermediate terms never leave the chip.
+// passes for NT terms (NT = 4: 5/4 per term, NT = 3: 5/3, against 5/2 for two
+// terms and 4 for one).  The intermediate terms never leave the chip.  NT = 4
+// in FP64 takes 77.8 KB of LDS and 124 VGPRs: two workgroups per CU.
 //
 // A workgroup owns a 64 x TY tile of the (x, y) plane and marches through its
 // slab of kz planes in z.  Term t is needed on the tile grown by NT - t
@@ -356,25 +357,34 @@ hipError_t launch_multi_t(const Op& op, const void* x, const void* v, const void
 
 }  // namespace
 
-hipError_t launch_chain_triple(const Op& op, const void* x, const void* v, const void* y1,
-                               void* out1, void* out2, const ChainCoef k[3], hipStream_t s,
-                               Prec pin, Prec pout, int blocks) {
-  if (op.kind != OP_STENCIL7 || !x || !v || !out2) return hipErrorInvalidValue;
-  MultiCoef<3> c;
-  for (int t = 0; t < 3; ++t) {
+template <int NT>
+static hipError_t launch_multi_nt(const Op& op, const void* x, const void* v, const void* y1,
+                                  void* out1, void* out2, const ChainCoef* k, hipStream_t s,
+                                  Prec pin, Prec pout, int blocks) {
+  MultiCoef<NT> c;
+  for (int t = 0; t < NT; ++t) {
     c.a[t] = k[t].alpha.real();
     c.b[t] = k[t].beta.real();
     c.g0[t] = k[t].g0.real();
     c.g1[t] = k[t].g1.real();
   }
-  if (blocks <= 0) blocks = FA_MULTI_BLOCKS;
   constexpr int TY = FA_MULTI_TY;
   if (pin == P64 && pout == P64)
-    return launch_multi_t<double, double, double, 3, TY>(op, x, v, y1, out1, out2, c, blocks, s);
+    return launch_multi_t<double, double, double, NT, TY>(op, x, v, y1, out1, out2, c, blocks, s);
   if (pin == P32 && pout == P32)
-    return launch_multi_t<float, float, float, 3, TY>(op, x, v, y1, out1, out2, c, blocks, s);
+    return launch_multi_t<float, float, float, NT, TY>(op, x, v, y1, out1, out2, c, blocks, s);
   if (pin == P32 && pout == P64 && out1 == nullptr)
-    return launch_multi_t<float, float, double, 3, TY>(op, x, v, y1, out1, out2, c, blocks, s);
+    return launch_multi_t<float, float, double, NT, TY>(op, x, v, y1, out1, out2, c, blocks, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_chain_multi(const Op& op, int nt, const void* x, const void* v, const void* y1,
+                              void* out1, void* out2, const ChainCoef* k, hipStream_t s,
+                              Prec pin, Prec pout, int blocks) {
+  if (op.kind != OP_STENCIL7 || !x || !v || !out2) return hipErrorInvalidValue;
+  if (blocks <= 0) blocks = FA_MULTI_BLOCKS;
+  if (nt == 3) return launch_multi_nt<3>(op, x, v, y1, out1, out2, k, s, pin, pout, blocks);
+  if (nt == 4) return launch_multi_nt<4>(op, x, v, y1, out1, out2, k, s, pin, pout, blocks);
   return hipErrorInvalidValue;
 }
 

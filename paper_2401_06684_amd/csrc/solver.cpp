@@ -273,8 +273,9 @@ static int poly_apply_ls(const Op& op, const Poly& q, const void* x, void* out, 
 // goes to `out` when that is safe and to a scratch vector otherwise (a
 // single-term launch may write over x pointwise, a two-term launch may not);
 // *res names the buffer that holds q(A) x.  `fuse` is the most consecutive
-// terms of the 7-point stencil one launch may take (1, 2 or 3): groups of
-// three while three or more terms remain, then a pair or a single term.
+// terms of the 7-point stencil one launch may take (1 to 4): groups of `fuse`
+// terms while that many remain, then the largest group that fits, a pair or
+// a single term.
 // pm = P32 (mixed precision): x and every intermediate vector are FP32 and
 // the last launch writes `out` in precision pout; pm = P64: everything FP64.
 static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, void* const tmp[4],
@@ -330,7 +331,7 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
     *res = xm1;
     return FA_OK;
   }
-  // groups of g = 3 or 2 terms per launch: the group (T[i], .., T[i+g-1])
+  // groups of g = 4, 3 or 2 terms per launch: the group (T[i], .., T[i+g-1])
   // reads out_{i-1}, out_{i-2} and x and writes out_{i+g-2}, out_{i+g-1} into
   // the buffer set not holding its inputs (the terms between stay on chip);
   // term i + 1 takes out_{i-1} and term i + 2 out_i as its y1
@@ -340,7 +341,10 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
   bool timing = false;
   int i = 0;
   for (;;) {
-    const int g = (fuse >= 3 && i + 3 <= nT) ? 3 : (i + 2 <= nT) ? 2 : 0;
+    const int g = (fuse >= 4 && i + 4 <= nT)   ? 4
+                  : (fuse >= 3 && i + 3 <= nT) ? 3
+                  : (i + 2 <= nT)              ? 2
+                                               : 0;
     if (g == 0) break;
     const bool has_next = i + g < nT;  // someone reads out_{i+g-2} later
     void* o1 = has_next ? tmp[2 * set] : nullptr;
@@ -356,16 +360,16 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
       FA_HIP(prof->end(s));
       timing = false;
     }
-    ChainCoef k[3];
+    ChainCoef k[4];
     for (int t = 0; t < g; ++t) {
       k[t] = T[i + t].k;
       if (t > 0 && !T[i + t].y1) k[t].g1 = 0.0;
     }
     const Prec po = has_next ? pm : pout;
-    if (g == 3) {
-      for (int t = 0; t < 3; ++t)
+    if (g >= 3) {
+      for (int t = 0; t < g; ++t)
         if (!T[i + t].y0) k[t].g0 = 0.0;
-      FA_HIP(launch_chain_triple(op, xm1, x, T[i].y1 ? xm2 : nullptr, o1, o2, k, s, pm, po));
+      FA_HIP(launch_chain_multi(op, g, xm1, x, T[i].y1 ? xm2 : nullptr, o1, o2, k, s, pm, po));
     } else {
       FA_HIP(launch_chain_pair(op, xm1, (T[i].y0 || T[i + 1].y0) ? x : nullptr,
                                T[i].y1 ? xm2 : nullptr, o1, o2, k[0], k[1], s, pm, po));
@@ -393,7 +397,7 @@ int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_
   void* const tmp[4] = {at(ws, L.off_P), at(ws, L.off_Q), at(ws, L.off_R), at(ws, L.off_S)};
   const void* res = nullptr;
   int64_t mv = 0;
-  int st = poly_apply(op, op.poly, x, y, tmp, &res, s, nullptr, &mv, 3, P64, P64,
+  int st = poly_apply(op, op.poly, x, y, tmp, &res, s, nullptr, &mv, 4, P64, P64,
                       L.off_W ? at(ws, L.off_W) : nullptr);
   if (st) return st;
   if (res != y) FA_HIP(hipMemcpyAsync(y, res, op.n * elem_size(op.dtype), hipMemcpyDeviceToDevice, s));
@@ -539,7 +543,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   char* Y = right ? at(ws, L.off_Y) : nullptr;
   void* U = at(ws, L.off_U);
   void* const tmp[4] = {at(ws, L.off_P), at(ws, L.off_Q), at(ws, L.off_R), at(ws, L.off_S)};
-  const int fuse = (flags & FA_NO_FUSION) ? 1 : (flags & FA_FUSE2) ? 2 : 3;
+  const int fuse = (flags & FA_NO_FUSION) ? 1 : (flags & FA_FUSE2) ? 2 : (flags & FA_FUSE3) ? 3 : 4;
   void* const wls = L.off_W ? at(ws, L.off_W) : nullptr;  // least-squares q
   // mixed precision: the polynomial chain in FP32 (stencil, Chebyshev q, K >= 1)
   const bool mixed = (flags & FA_MIXED) && K > 0;

@@ -305,36 +305,45 @@ def test_not_converged_warning():
 
 def test_bitwise_deterministic_and_profile():
     op = fa().Stencil7((40, 33, 29), wl.convdiff_stencil(40, 50.0))
-    op.poly_setup(8, "cheb")
+    op.poly_setup(12, "cheb")
     b = dev(wl.rhs(op.n, seed=0))
     x1, s1 = op.apply(b, m_max=60, tol=1e-10)
     x2, s2 = op.apply(b, m_max=60, tol=1e-10, profile=True)
     assert torch.equal(x1, x2)
-    # Clenshaw degree 8 = 8 terms = launches of 3, 3 and 2 terms per q(A), of
+    # Clenshaw degree 12 = 12 terms = three launches of 4 terms per q(A), of
     # which the middle one reads x, v, b_{k+2} and writes its last two terms
     # (5 vectors); 2 q(A) per step plus c = q(A) b
     assert s2["n_chain"] == 2 * s2["iters"] + 1 and s2["ms_chain"] > 0
-    assert s2["n_chain_terms"] == 3 * s2["n_chain"]
+    assert s2["n_chain_terms"] == 4 * s2["n_chain"]
     assert s2["chain_bytes"] == 5 * 8 * op.n
-    # at most two terms per launch: 4 pairs, the 2nd and 3rd timed
+    # at most three terms per launch: 4 triples, the 2nd and 3rd timed
+    x5, s5 = op.apply(b, m_max=60, tol=1e-10, fuse=3, profile=True)
+    assert s5["n_chain"] == 2 * (2 * s5["iters"] + 1)
+    assert s5["n_chain_terms"] == 3 * s5["n_chain"]
+    assert s5["chain_bytes"] == 5 * 8 * op.n
+    # at most two terms per launch: 6 pairs, the 2nd to 5th timed
     x4, s4 = op.apply(b, m_max=60, tol=1e-10, fuse=2, profile=True)
-    assert s4["n_chain"] == 2 * (2 * s4["iters"] + 1)
+    assert s4["n_chain"] == 4 * (2 * s4["iters"] + 1)
     assert s4["n_chain_terms"] == 2 * s4["n_chain"]
     assert s4["chain_bytes"] == 5 * 8 * op.n
     # the grouping only drops zero terms and keeps every rounding: same bits
+    assert torch.equal(x5, x1)
     assert torch.equal(x4, x1)
     x3, s3 = op.apply(b, m_max=60, tol=1e-10, fuse=False, profile=True)
-    assert s3["n_chain"] == 5 * (2 * s3["iters"] + 1)
+    # one term per launch: terms 2 .. 10 timed (the first two have no b_{k+2},
+    # the last is not a middle term)
+    assert s3["n_chain"] == 9 * (2 * s3["iters"] + 1)
     assert s3["chain_bytes"] == 4 * 8 * op.n
     assert_close(host(x3), host(x1), 1e-13)
 
 
-@pytest.mark.parametrize("degree", [1, 2, 3, 4, 5, 16, 17])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4, 5, 6, 7, 16, 17])
 @pytest.mark.parametrize("dims", [(70, 9, 11), (128, 16, 24), (33, 65, 5), (20, 20, 1)])
 def test_multi_term_launches_match_single_terms(degree, dims):
-    """q(A) x and whole solves with three or two recurrence terms per launch
-    equal the single-term path and the oracle (ragged tiles in x, y and z;
-    degrees that leave a single term or a pair after the groups of three)."""
+    """q(A) x and whole solves with four, three or two recurrence terms per
+    launch equal the single-term path and the oracle (ragged tiles in x, y
+    and z; degrees that leave a single term, a pair or a triple after the
+    groups of four)."""
     coeffs = wl.convdiff_stencil(max(dims), 50.0)
     op = fa().Stencil7(dims, coeffs)
     op.poly_setup(degree, "cheb")
@@ -348,9 +357,11 @@ def test_multi_term_launches_match_single_terms(degree, dims):
     x1, _ = op.apply(bd, m_max=m, tol=0.0)
     x2, _ = op.apply(bd, m_max=m, tol=0.0, fuse=False)
     x3, _ = op.apply(bd, m_max=m, tol=0.0, fuse=2)
+    x4, _ = op.apply(bd, m_max=m, tol=0.0, fuse=3)
     assert_close(host(x1), host(x2), 1e-12)
-    # three-term groups reproduce the pairs bit for bit (same roundings)
+    # four- and three-term groups reproduce the pairs bit for bit (same roundings)
     assert torch.equal(x1, x3)
+    assert torch.equal(x1, x4)
 
 
 # --------------------------------------------------------------------------
@@ -480,7 +491,7 @@ def test_real_operator_complex_ritz_values(degree):
 # mixed precision: the polynomial chain in FP32, the rest FP64
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("degree", [1, 2, 3, 8, 16])
-@pytest.mark.parametrize("fuse", [True, False])
+@pytest.mark.parametrize("fuse", [True, 3, False])
 @pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
 def test_mixed_precision_against_fp64_oracle(degree, fuse, kind):
     """Per-result error of the mixed mode against the FP64 oracle: <= 1e-6."""
