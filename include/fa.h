@@ -149,12 +149,15 @@ typedef struct {
   double h_last;          /* h_{m+1,m}                                                  */
   double ms_total;        /* wall time of fa_apply                                      */
   double ms_host_fH;      /* host time spent in H_j^{-1/2} e_1                          */
-  double ms_chain;        /* FA_PROFILE: device time of the timed chain launches: HIP
-                             events bracket each run of consecutive launches of the
-                             middle of a q(A) recurrence (the Clenshaw terms that read
-                             x, v, b_{k+2}, up to three per launch on a stencil; the
-                             Newton terms that read r, v), so the figure includes the
-                             short gaps between back-to-back launches                  */
+  double ms_chain;        /* FA_PROFILE: device time of the timed chain launches, the
+                             launches of the middle of a q(A) recurrence (the Clenshaw
+                             terms that read x, v, b_{k+2}; the Newton terms that read
+                             r, v).  A stencil launch of three or four terms carries
+                             its own start and end event (the dispatch's own time);
+                             other launches are timed by HIP events bracketing each
+                             run of consecutive ones, which includes the short gaps
+                             between them.  Each event pair adds a few microseconds
+                             to the solve.                                             */
   int64_t n_chain;        /* FA_PROFILE: number of chain launches timed                 */
   double chain_bytes;     /* FA_PROFILE: algorithmic bytes of one timed launch: x, each
                              combined vector and each output once, plus the operator's

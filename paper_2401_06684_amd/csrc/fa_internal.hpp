@@ -107,10 +107,12 @@ inline bool has_pair_kernel(const Op& op) { return op.kind == OP_STENCIL7; }
 // nt = 3 or 4 consecutive terms s_t = a_t A s_{t-1} + b_t s_{t-1} + g0_t v +
 // g1_t s_{t-2} (s_0 = x, s_{-1} = y1 or zero when y1 is null) on a 7-point
 // stencil; writes s_{nt-1} to out1 (if not null) and s_nt to out2; k holds nt
-// terms; blocks = target workgroup count
+// terms; blocks = target workgroup count (0: default); ev0 / ev1, if not
+// null, receive the start and end time of the launch's own dispatch
 hipError_t launch_chain_multi(const Op& op, int nt, const void* x, const void* v, const void* y1,
                               void* out1, void* out2, const ChainCoef* k, hipStream_t s,
-                              Prec pin, Prec pout, int blocks = 0);
+                              Prec pin, Prec pout, int blocks = 0, hipEvent_t ev0 = nullptr,
+                              hipEvent_t ev1 = nullptr);
 
 // algorithmic bytes moved by one chain launch (x read once, y0, y1 read,
 // out written, plus the operator's own data); p = storage of the vectors

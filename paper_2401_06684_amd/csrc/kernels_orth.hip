@@ -401,6 +401,9 @@ __global__ __launch_bounds__(kFinThreads) void dcgs2_finish_k(int j, int nblk,
   // 1. the projections
   for (int c = wv; c < 2 * (j + 1); c += NW) {
     T a = zero(T{});
+    // unrolled so that several loads are in flight before their adds (the
+    // adds keep their order)
+#pragma unroll 8
     for (int b = lane; b < nblk; b += 64) a += part[(int64_t)c * nblk + b];
     a = wave_sum(a);
     if (lane == 0) S[c] = a;
@@ -438,8 +441,10 @@ __global__ __launch_bounds__(kFinThreads) void dcgs2_finish_k(int j, int nblk,
   for (int i0 = 0; i0 <= j; i0 += 64) {
     const int i = i0 + lane;
     T t = zero(T{});
-    if (i <= j)
+    if (i <= j) {
+#pragma unroll 4
       for (int c = max(0, i - 1) + wv; c < j; c += NW) t = mad(H[(int64_t)c * ldh + i], S[2 * c], t);
+    }
     colpart[wv][lane] = t;
     __syncthreads();
     if (wv == 0 && i <= j) {
@@ -512,10 +517,11 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
   char* cs = (char*)coef;
   char* cp = cs + (size_t)j * es;
   char* sc = cp + (size_t)j * es;
-  // one launch while the 2 (j + 1) projections fit 32 KB of LDS, else the
-  // three kernels
+  // one launch up to j = 32, else the three kernels: the one workgroup's
+  // work grows linearly in j (8.8 us at j = 20, 14.4 at 32, 75 at 158 on the
+  // 128^3 grid), the three kernels' stays near 15 us
   const size_t lds = 2 * (size_t)(j + 1) * es;
-  const bool fused = lds <= 32768;
+  const bool fused = lds <= 32768 && j <= 32;
   if (dtype == FA_C128) {
     project2_k<cplx><<<p.nblk, kThreads, 0, s>>>(n, j + 1, (const cplx*)V, ldv, (const cplx*)u,
                                                  (const cplx*)z, (cplx*)part, p.nblk);

@@ -26,6 +26,7 @@
 // The workgroup id is remapped so that each XCD gets a contiguous range of
 // slabs (the halo planes of neighbouring slabs then meet in one L2).
 // --------------------------------------------------------------------------
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -326,7 +327,8 @@ __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(4))) vo
 
 template <typename T, typename TX, typename TO, int NT, int TY>
 hipError_t launch_multi_t(const Op& op, const void* x, const void* v, const void* y1, void* out1,
-                          void* out2, const MultiCoef<NT>& c, int blocks, hipStream_t st) {
+                          void* out2, const MultiCoef<NT>& c, int blocks, hipStream_t st,
+                          hipEvent_t ev0, hipEvent_t ev1) {
   St7M g{op.dims[0], op.dims[1], op.dims[2], op.coef[0], op.coef[1], op.coef[2],
          op.coef[3], op.coef[4], op.coef[5], op.coef[6]};
   const int gx = (g.nx + 63) / 64, gy = (g.ny + TY - 1) / TY;
@@ -340,9 +342,10 @@ hipError_t launch_multi_t(const Op& op, const void* x, const void* v, const void
   const TX* yp = (const TX*)y1;
   TO* o1 = (TO*)out1;
   TO* o2 = (TO*)out2;
-#define FA_MULTI(A, B)                                                                   \
-  st7_multi<T, TX, TO, NT, TY, A, B><<<grid, block, 0, st>>>(g, kz, gx, gy, nwg, xp, vp, yp, \
-                                                              o1, o2, c)
+  // the events (if any) take the start and end time of this dispatch itself
+#define FA_MULTI(A, B)                                                                          \
+  hipExtLaunchKernelGGL(st7_multi<T, TX, TO, NT, TY, A, B>, grid, block, 0, st, ev0, ev1, 0, g, kz, \
+                        gx, gy, nwg, xp, vp, yp, o1, o2, c)
   if (y1 && out1)
     FA_MULTI(true, true);
   else if (y1)
@@ -360,7 +363,7 @@ hipError_t launch_multi_t(const Op& op, const void* x, const void* v, const void
 template <int NT>
 static hipError_t launch_multi_nt(const Op& op, const void* x, const void* v, const void* y1,
                                   void* out1, void* out2, const ChainCoef* k, hipStream_t s,
-                                  Prec pin, Prec pout, int blocks) {
+                                  Prec pin, Prec pout, int blocks, hipEvent_t e0, hipEvent_t e1) {
   MultiCoef<NT> c;
   for (int t = 0; t < NT; ++t) {
     c.a[t] = k[t].alpha.real();
@@ -370,21 +373,26 @@ static hipError_t launch_multi_nt(const Op& op, const void* x, const void* v, co
   }
   constexpr int TY = FA_MULTI_TY;
   if (pin == P64 && pout == P64)
-    return launch_multi_t<double, double, double, NT, TY>(op, x, v, y1, out1, out2, c, blocks, s);
+    return launch_multi_t<double, double, double, NT, TY>(op, x, v, y1, out1, out2, c, blocks, s,
+                                                          e0, e1);
   if (pin == P32 && pout == P32)
-    return launch_multi_t<float, float, float, NT, TY>(op, x, v, y1, out1, out2, c, blocks, s);
+    return launch_multi_t<float, float, float, NT, TY>(op, x, v, y1, out1, out2, c, blocks, s, e0,
+                                                       e1);
   if (pin == P32 && pout == P64 && out1 == nullptr)
-    return launch_multi_t<float, float, double, NT, TY>(op, x, v, y1, out1, out2, c, blocks, s);
+    return launch_multi_t<float, float, double, NT, TY>(op, x, v, y1, out1, out2, c, blocks, s,
+                                                        e0, e1);
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_chain_multi(const Op& op, int nt, const void* x, const void* v, const void* y1,
                               void* out1, void* out2, const ChainCoef* k, hipStream_t s,
-                              Prec pin, Prec pout, int blocks) {
+                              Prec pin, Prec pout, int blocks, hipEvent_t ev0, hipEvent_t ev1) {
   if (op.kind != OP_STENCIL7 || !x || !v || !out2) return hipErrorInvalidValue;
   if (blocks <= 0) blocks = FA_MULTI_BLOCKS;
-  if (nt == 3) return launch_multi_nt<3>(op, x, v, y1, out1, out2, k, s, pin, pout, blocks);
-  if (nt == 4) return launch_multi_nt<4>(op, x, v, y1, out1, out2, k, s, pin, pout, blocks);
+  if (nt == 3)
+    return launch_multi_nt<3>(op, x, v, y1, out1, out2, k, s, pin, pout, blocks, ev0, ev1);
+  if (nt == 4)
+    return launch_multi_nt<4>(op, x, v, y1, out1, out2, k, s, pin, pout, blocks, ev0, ev1);
   return hipErrorInvalidValue;
 }
 

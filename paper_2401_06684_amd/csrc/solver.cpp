@@ -82,8 +82,7 @@ struct Prof {
   size_t used = 0;
   int64_t launches = 0;
   double bytes = 0;  // algorithmic bytes of the timed launches
-  hipError_t begin(hipStream_t s) {
-    if (!on) return hipSuccess;
+  hipError_t reserve() {
     if (used + 2 > t_events.size()) {
       for (int i = 0; i < 64; ++i) {
         hipEvent_t e;
@@ -92,6 +91,13 @@ struct Prof {
         t_events.push_back(e);
       }
     }
+    return hipSuccess;
+  }
+  // a bracket of events around a run of launches (each event its own packet)
+  hipError_t begin(hipStream_t s) {
+    if (!on) return hipSuccess;
+    hipError_t err = reserve();
+    if (err != hipSuccess) return err;
     return hipEventRecord(t_events[used], s);
   }
   hipError_t end(hipStream_t s) {
@@ -99,6 +105,15 @@ struct Prof {
     hipError_t err = hipEventRecord(t_events[used + 1], s);
     used += 2;
     return err;
+  }
+  // the event pair one launch stamps with its own dispatch's start and end
+  hipError_t pair(hipEvent_t* e0, hipEvent_t* e1) {
+    hipError_t err = reserve();
+    if (err != hipSuccess) return err;
+    *e0 = t_events[used];
+    *e1 = t_events[used + 1];
+    used += 2;
+    return hipSuccess;
   }
   int64_t terms = 0;  // recurrence terms of the timed launches
   void count(int nlaunch, double bytes_each, int terms_each = 1) {
@@ -352,14 +367,19 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
     if (!has_next && out != x && out != xm1 && out != xm2) o2 = out;
     bool middle = T[i].y0 && T[i].y1 && has_next;
     for (int t = 1; t < g; ++t) middle = middle && T[i + t].y1;
-    if (prof && middle && !timing) {
-      FA_HIP(prof->begin(s));
-      timing = true;
-    }
-    if (prof && timing && !middle) {
+    // multi-term launches are timed by their own dispatch, pairs by a
+    // bracket of events around each run of them
+    const bool own = g >= 3;
+    if (prof && timing && (!middle || own)) {
       FA_HIP(prof->end(s));
       timing = false;
     }
+    if (prof && middle && !own && !timing) {
+      FA_HIP(prof->begin(s));
+      timing = true;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof && middle && own) FA_HIP(prof->pair(&e0, &e1));
     ChainCoef k[4];
     for (int t = 0; t < g; ++t) {
       k[t] = T[i + t].k;
@@ -369,12 +389,13 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
     if (g >= 3) {
       for (int t = 0; t < g; ++t)
         if (!T[i + t].y0) k[t].g0 = 0.0;
-      FA_HIP(launch_chain_multi(op, g, xm1, x, T[i].y1 ? xm2 : nullptr, o1, o2, k, s, pm, po));
+      FA_HIP(launch_chain_multi(op, g, xm1, x, T[i].y1 ? xm2 : nullptr, o1, o2, k, s, pm, po, 0,
+                                e0, e1));
     } else {
       FA_HIP(launch_chain_pair(op, xm1, (T[i].y0 || T[i + 1].y0) ? x : nullptr,
                                T[i].y1 ? xm2 : nullptr, o1, o2, k[0], k[1], s, pm, po));
     }
-    if (prof && timing)
+    if (prof && middle)
       prof->count(1, chain_pair_bytes(op, true, true, o1 != nullptr, pm), g);
     xm2 = o1;
     xm1 = o2;
