@@ -71,6 +71,20 @@ Layout make_layout(const Op& op, int m_max, uint32_t flags, bool with_poly) {
 // --------------------------------------------------------------------------
 namespace {
 thread_local std::vector<hipEvent_t> t_events;
+// per device: an event (no timing) marking the end of a check's copies
+thread_local std::vector<hipEvent_t> t_check_events;
+hipError_t check_event(hipEvent_t* e) {
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return err;
+  if ((int)t_check_events.size() <= dev) t_check_events.resize(dev + 1, nullptr);
+  if (!t_check_events[dev]) {
+    err = hipEventCreateWithFlags(&t_check_events[dev], hipEventDisableTiming);
+    if (err != hipSuccess) return err;
+  }
+  *e = t_check_events[dev];
+  return hipSuccess;
+}
 
 // Profiling: one pair of timing events around each run of consecutive middle
 // terms of a polynomial recurrence (the Clenshaw terms that read x, v and
@@ -623,9 +637,13 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     return FA_OK;
   };
   // one Krylov step: w = A q(A)^2 v_j in three stages, orthogonalized against
-  // the basis (CGS2) or the two latest vectors (Lanczos), normalized into v_{j+1}
+  // the basis (CGS2) or the two latest vectors (Lanczos), normalized into v_{j+1}.
+  // phase 0: the whole step; phase 1: only u = A v_j and y = q(A) u
+  // (Algorithm 1, K >= 1), y kept in half_y; phase 2: the rest of a step
+  // begun by phase 1
   int64_t ips = 0;
-  auto step = [&](int j) -> int {
+  const void* half_y = nullptr;
+  auto step = [&](int j, int phase) -> int {
     char* vj = Vc(j);
     char* w = Vc(j + 1);
     if (K == 0) {
@@ -644,11 +662,19 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       if (r) return r;
       ++mvms;
     } else {  // Algorithm 1: u = A v_j, y = q(A) u, w = q(A) y
-      FA_HIP(launch_chain(op, vj, nullptr, nullptr, U, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, P64, pm));
-      ++mvms;
-      const void* y = nullptr;
-      int r = poly_apply(op, q, U, U, tmp, &y, s, pp, &mvms, fuse, pm, pm, wls);
-      if (r) return r;
+      const void* y = half_y;
+      if (phase != 2) {
+        FA_HIP(launch_chain(op, vj, nullptr, nullptr, U, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, P64,
+                            pm));
+        ++mvms;
+        const int r = poly_apply(op, q, U, U, tmp, &y, s, pp, &mvms, fuse, pm, pm, wls);
+        if (r) return r;
+        if (phase == 1) {
+          half_y = y;
+          return FA_OK;
+        }
+      }
+      int r = FA_OK;
       void* tmp2[4];  // the scratch vectors other than the one holding y
       {
         void* all[5] = {U, tmp[0], tmp[1], tmp[2], tmp[3]};
@@ -768,9 +794,25 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   int last_host_m = 0;
   double t_resume = now_ms();
   int j_resume = 0;
+  // At a check the first half of the next step (u = A v_j, y = q(A) u) is
+  // enqueued behind the copies before the host waits for them, so the GPU
+  // works through the check's round trip (copies, host f(H), the next
+  // launches); it is left out when the last two estimates, extrapolated
+  // geometrically, predict convergence at this check.  If the iteration
+  // stops there, its output is never read and its counts are undone.
+  const bool can_half = K > 0 && !right && !two_pass && tol > 0.0;
+  int half_j = -1;  // the step whose first half is enqueued
+  std::vector<double> est_hist;
+  auto run_step = [&](int j) -> int {
+    if (half_j == j) {
+      half_j = -1;
+      return step(j, 2);
+    }
+    return step(j, 0);
+  };
   for (int j = 0; j < m_max; ++j) {
     if (j >= ahead_until) {
-      st = step(j);
+      st = run_step(j);
       if (st) return st;
     }
     const int jj = j + 1;
@@ -785,10 +827,38 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       // step): project u_{j+1} on [q_0 .. q_j, u_{j+1}] and finish the host
       // copy: H(0:j, j) += s', H(j+1, j) = (||u_{j+1}||^2 - ||s'||^2)^{1/2}
       FA_HIP(launch_project(op.dtype, n, jj + 1, V, L.ldv, Vc(jj), part, hcur, nullptr, 0, s));
-      const double* sh = sh_host;
       FA_HIP(hipMemcpyAsync(sh_host, hcur, (size_t)(jj + 1) * ed * sizeof(double),
                             hipMemcpyDeviceToHost, s));
+    }
+    int64_t half_mvms = 0;  // counts of a half step enqueued at this check
+    Prof prof_before_half = prof;
+    bool predict_more = true;
+    if (est_hist.size() >= 2 && est_hist[est_hist.size() - 2] > 0.0) {
+      const double a = est_hist[est_hist.size() - 2], b = est_hist.back();
+      predict_more = b * (b / a) > 10.0 * tol;
+    }
+    if (can_half && jj < m_max && predict_more) {
+      hipEvent_t ev;
+      FA_HIP(check_event(&ev));
+      FA_HIP(hipEventRecord(ev, s));
+      const int64_t m0 = mvms;
+      st = step(jj, 1);
+      if (st) return st;
+      half_mvms = mvms - m0;
+      half_j = jj;
+      FA_HIP(hipEventSynchronize(ev));
+    } else {
       FA_HIP(hipStreamSynchronize(s));
+    }
+    // takes the half step's counts and timings back out (the iteration stops here)
+    auto undo_half = [&]() {
+      if (half_j != jj) return;
+      mvms -= half_mvms;
+      prof = prof_before_half;
+      half_j = -1;
+    };
+    if (dcgs2) {
+      const double* sh = sh_host;
       auto sv = [&](int i) {
         return op.dtype == FA_C128 ? cd(sh[2 * i], sh[2 * i + 1]) : cd(sh[i], 0.0);
       };
@@ -800,8 +870,6 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       const double nu2 = sv(jj).real() - ss;
       H.set(jj, j, cd(nu2 > 0.0 ? std::sqrt(nu2) : 0.0, 0.0));
       ips += jj + 1;
-    } else {
-      FA_HIP(hipStreamSynchronize(s));
     }
     // scan new columns for a lucky breakdown / nonfinite entries
     int mb = -1;
@@ -824,13 +892,14 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     copied = jj;
     refresh = dcgs2 ? j : jj;
     if (mb > 0) {
+      undo_half();
       m = mb;
       breakdown = converged = true;
       break;
     }
     if (tol <= 0.0) break;
-    const int64_t mvms_here = mvms, ips_here = ips;
-    const Prof prof_here = prof;
+    const int64_t mvms_here = mvms - (half_j == jj ? half_mvms : 0), ips_here = ips;
+    const Prof prof_here = half_j == jj ? prof_before_half : prof;
     {
       const double step_ms = (now_ms() - t_resume) / std::max(1, jj - j_resume);
       const double ratio = last_host_m > 0 ? (double)jj / last_host_m : 0.0;
@@ -838,7 +907,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       int r = step_ms > 0.0 ? (int)(host_est / step_ms) : 0;
       r = std::min(r, std::min(k_chk - 1, m_max - jj));
       for (int a = 0; a < r; ++a) {
-        st = step(jj + a);
+        st = run_step(jj + a);
         if (st) return st;
       }
       ahead_until = jj + std::max(r, 0);
@@ -876,12 +945,14 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       est = std::sqrt(dn / zn);
     }
     zprev = z;
+    est_hist.push_back(est);
     if (est <= tol) {
       m = jj;
       converged = true;
       mvms = mvms_here;  // steps enqueued ahead are not part of the result
       ips = ips_here;
       prof = prof_here;
+      half_j = -1;
       break;
     }
     t_resume = now_ms();
@@ -908,7 +979,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     if (st) return st;
     FA_HIP(launch_scale(op.dtype, n, z[0], Vc(0), d_x, s));
     for (int j = 0; j + 1 < m; ++j) {
-      st = step(j);
+      st = step(j, 0);
       if (st) return st;
       FA_HIP(launch_update(op.dtype, n, 1, Vc(j + 1), L.ldv, (char*)zd + (size_t)(j + 1) * es,
                            d_x, part, nullptr, s));

@@ -197,6 +197,37 @@ def test_convdiff_converged_against_closed_form(degree, kind):
     assert_close(host(x), orc.x, 1e-10)
 
 
+@pytest.mark.parametrize("hermitian", [False, True])
+@pytest.mark.parametrize("check_every", [1, 3])
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+def test_check_overlap_leaves_no_trace(hermitian, check_every, kind):
+    """At a check the first half of the next step is enqueued before the host
+    waits for the check's copies; when the iteration stops at that check the
+    half step must change nothing: iterations and products with A equal the
+    oracle's (and Lanczos' inner products), x agrees with the oracle."""
+    N = 20
+    dims = (N, N, N)
+    coeffs = wl.laplace_stencil(3) if hermitian else wl.convdiff_stencil(N, 10.0)
+    op = fa().Stencil7(dims, coeffs, hermitian=hermitian)
+    op.poly_setup(4, "cheb")
+    b = wl.rhs(op.n, seed=3)
+    x, st = op.apply(dev(b), kind=kind, m_max=300, tol=1e-11, check_every=check_every)
+    assert st["converged"] == 1
+    a, bb = ops.stencil_interval(coeffs, dims)
+    orc = kr.fAb(lambda v: ops.stencil_apply(coeffs, dims, v), b, pl.chebyshev(a, bb, 4), kind,
+                 m_max=300, tol=1e-11, check_every=check_every,
+                 orth="lanczos" if hermitian else "cgs2")
+    assert st["iters"] == orc.iters
+    assert st["mvms"] == orc.mvms
+    if hermitian:
+        assert st["inner_products"] == orc.inner_products
+    assert_close(host(x), orc.x, 1e-10)
+    # the same solve again gives the same bits (the half steps are enqueued
+    # at the same checks)
+    x2, st2 = op.apply(dev(b), kind=kind, m_max=300, tol=1e-11, check_every=check_every)
+    assert torch.equal(x, x2) and st2["mvms"] == st["mvms"]
+
+
 @pytest.mark.parametrize("degree", [0, 8])
 def test_poisson2d_32_lanczos(degree):
     """2D Poisson 32x32, CSR, Hermitian: Lanczos, tol 1e-10, m_max 200."""
