@@ -223,3 +223,29 @@ def test_dense_tridiag_matches_oracle():
         assert np.allclose(fa.dense_tridiag_invsqrt_e1(a, b, 1.5), ref, rtol=1e-11)
     with pytest.raises(fa.FAError):
         fa.dense_tridiag_invsqrt_e1(np.array([1.0, -2.0]), np.array([0.1]), 1.0)
+
+
+def test_fusion_flags():
+    """The Python fuse argument maps onto the apply flags (True or 4: the
+    default of four terms per launch; 3, 2; False or 1: one term per launch),
+    and the library accepts each of those flags while rejecting an unknown
+    bit (argument checks that run before any GPU work)."""
+    import paper_2401_06684_amd as fa
+    assert fa._fuse_flags(True) == 0 and fa._fuse_flags(4) == 0
+    assert fa._fuse_flags(3) == _lib.FA_FUSE3
+    assert fa._fuse_flags(2) == _lib.FA_FUSE2
+    assert fa._fuse_flags(False) == _lib.FA_NO_FUSION and fa._fuse_flags(1) == _lib.FA_NO_FUSION
+    with pytest.raises(ValueError):
+        fa._fuse_flags(5)
+    L = _lib.lib()
+    st, h = _stencil((8, 8, 8), wl.laplace_stencil(3))
+    assert st == 0
+    assert L.fa_poly_setup(h, 4, _lib.FA_POLY_CHEB, None, None, 0, None) == 0
+    dummy = C.c_void_p(256)
+    for flags in (0, _lib.FA_FUSE3, _lib.FA_FUSE2, _lib.FA_NO_FUSION):
+        # past the flag check: the missing workspace is what is reported
+        assert L.fa_apply(h, 0, dummy, C.c_void_p(512), 10, 1e-8, 0, None, 0, flags, None,
+                          None) == _lib.FA_ERR_WORKSPACE
+    assert L.fa_apply(h, 0, dummy, C.c_void_p(512), 10, 1e-8, 0, None, 0, 1 << 20, None,
+                      None) == _lib.FA_ERR_ARG
+    L.fa_destroy(h)
