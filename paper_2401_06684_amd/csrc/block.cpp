@@ -241,11 +241,16 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
   BLK_HIP(hipMemsetAsync(flag, 0, (size_t)(m_max + 2) * sizeof(int), st));
 
   // q(A) applied to a block: x (precision px) -> out (precision pout) using
-  // the chain scratch blocks `tmp` (two of them); returns the buffer that
-  // holds the result.  Single term per launch; out_i may overwrite out_{i-2}.
+  // the chain scratch blocks `tmp` (four, none of them x or out).  Two terms
+  // per launch (the intermediate term stays on chip; launch outputs never
+  // alias their inputs, so the pairs alternate between two scratch sets), an
+  // odd last term alone; one term per launch if x is not in the chain
+  // precision.
   const std::vector<Term> T = K > 0 ? poly_terms(q) : std::vector<Term>();
   // z-planes per workgroup of the block stencil (tuned at the first A V_j)
   const std::vector<int64_t> zc_key{1, op.dims[0], op.dims[1], op.dims[2], s, (int)pc};
+  // ... and of the two-term launches (tuned at the first one)
+  const std::vector<int64_t> pair_key{2, op.dims[0], op.dims[1], op.dims[2], s, (int)pc};
   int zc = 8;
   {
     std::lock_guard<std::mutex> g(tuner().mu);
@@ -253,13 +258,49 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
     if (it != tuner().best.end()) zc = it->second;
   }
   hipStream_t cur = st;  // the stream the step launches go to (capture: a private one)
-  auto qblock = [&](const void* x, Prec px, void* out, Prec pout, void* tA, void* tB) -> int {
+  auto qblock = [&](const void* x, Prec px, void* out, Prec pout, void* const tmp[4]) -> int {
     const int nT = (int)T.size();
     const void* xm1 = x;
     const void* xm2 = nullptr;
     Prec pm1 = px;
-    void* slot[2] = {tA, tB};
-    for (int i = 0; i < nT; ++i) {
+    int i = 0;
+    if (px == pc) {
+      int set = 0;
+      for (; i + 2 <= nT; i += 2) {
+        const bool has_next = i + 2 < nT;  // a later launch reads out_{i}
+        void* o1 = has_next ? tmp[2 * set] : nullptr;
+        void* o2 = has_next ? tmp[2 * set + 1] : out;
+        ChainCoef k1 = T[i].k, k2 = T[i + 1].k;
+        if (!T[i].y0) k1.g0 = 0.0;
+        if (!T[i + 1].y0) k2.g0 = 0.0;
+        if (!T[i + 1].y1) k2.g1 = 0.0;
+        // z-march length of the pair launches: tuned at the first one (a
+        // pair recomputes s on two planes and reads x on four beyond its
+        // slab, so it wants longer slabs than a single term)
+        const void* y1 = T[i].y1 ? xm2 : nullptr;
+        const Prec po = has_next ? pc : pout;
+        int chosen = 0;
+        const int r = tune_pick(
+            pair_key, {8, 16, 32}, cur,
+            [&](int c) {
+              return launch_blk_chain_pair(op, s, xm1, x, y1, o1, o2, k1, k2, pc, po, cur, c);
+            },
+            &chosen, &S.ms_tune);
+        if (r) return r;
+        xm2 = o1;
+        xm1 = o2;
+        set ^= 1;
+      }
+      if (i < nT) {  // an odd last term alone, straight into out (which is
+        // none of its inputs)
+        BLK_HIP(launch_blk_chain(op, s, xm1, T[i].y0 ? x : nullptr, T[i].y1 ? xm2 : nullptr, out,
+                                 T[i].k, pc, px, pout, cur, zc));
+      }
+      mvms += (int64_t)K * s;
+      return FA_OK;
+    }
+    void* slot[2] = {tmp[0], tmp[1]};
+    for (; i < nT; ++i) {
       const bool last = i == nT - 1;
       void* dst = last ? out : ((i >= 2 && T[i].y1) ? (void*)xm2 : slot[i & 1]);
       if (dst == xm1) dst = slot[(i + 1) & 1];
@@ -360,10 +401,12 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
     BLK_HIP(hipMemcpyAsync(Vb(0), Bp, (size_t)n * s * 8, hipMemcpyDeviceToDevice, st));
   } else if (mixed) {
     BLK_HIP(launch_blk_to_f32(n * s, Bp, (float*)C[4], st));
-    int r = qblock(C[4], P32, Vb(0), P64, C[0], C[1]);
+    void* const tq[4] = {C[0], C[1], C[2], C[3]};
+    int r = qblock(C[4], P32, Vb(0), P64, tq);
     if (r) return r;
   } else {
-    int r = qblock(Bp, P64, Vb(0), P64, C[0], C[1]);
+    void* const tq[4] = {C[0], C[1], C[2], C[3]};
+    int r = qblock(Bp, P64, Vb(0), P64, tq);
     if (r) return r;
   }
   {
@@ -399,11 +442,12 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
         if (r) return r;
       }
       mvms += s;
-      int r = qblock(C[0], pc, C[1], pc, C[2], C[3]);
+      // (W, free until the second q(A) writes it, is scratch for the first)
+      void* const t1[4] = {C[2], C[3], C[4], W};
+      int r = qblock(C[0], pc, C[1], pc, t1);
       if (r) return r;
-      // q's result sits in C[1] unless the rotation moved it (single-term
-      // launches write `out` directly, so it is C[1])
-      r = qblock(C[1], pc, W, P64, C[2], C[3]);
+      void* const t2[4] = {C[0], C[2], C[3], C[4]};
+      r = qblock(C[1], pc, W, P64, t2);
       if (r) return r;
     }
     // block CGS2: H(0:(j+1)s, js:(j+1)s) = P1 + P2
@@ -430,11 +474,17 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
   // run step j: replayed from a captured graph when FA_GRAPH is set and its
   // launch parameters are tuned already, else launched one by one
   auto run_step = [&](int j) -> int {
-    const bool tuned = (K == 0 || is_tuned(zc_key)) && is_tuned({0, n, s, j + 1}) &&
-                       is_tuned({0, n, s, 1});
+    const bool tuned = (K == 0 || is_tuned(zc_key)) && (K < 2 || is_tuned(pair_key)) &&
+                       is_tuned({0, n, s, j + 1}) && is_tuned({0, n, s, 1});
     if (!use_graph || !tuned) return do_step(j);
+    int zc2 = 0;  // the pair launches' z-march
+    {
+      std::lock_guard<std::mutex> g(tuner().mu);
+      auto it = tuner().best.find(pair_key);
+      if (it != tuner().best.end()) zc2 = it->second;
+    }
     const std::vector<int64_t> key{(int64_t)op.uid, (int64_t)op.poly_version, (int64_t)(uintptr_t)ws,
-                                   s, m_max, mixed ? 1 : 0, j, zc, n};
+                                   s, m_max, mixed ? 1 : 0, j, zc, n, zc2};
     hipGraphExec_t exec = nullptr;
     {
       std::lock_guard<std::mutex> g(graphs().mu);

@@ -178,6 +178,15 @@ hipError_t launch_ls_step(int dtype, int64_t n, int k, void* W, int64_t ldv, con
 hipError_t launch_blk_chain(const Op& op, int s, const void* x, const void* y0, const void* y1,
                             void* out, const ChainCoef& k, Prec px, Prec py, Prec po,
                             hipStream_t st, int zc = 8);
+// two consecutive terms on a block (7-point stencil):
+//   s = k1.alpha A x + k1.beta x + k1.g0 v + k1.g1 y1 (y1 null: no term),
+//   out1 = s (if out1), out2 = k2.alpha A s + k2.beta s + k2.g0 v + k2.g1 x;
+// x, v, y1 in precision pin, out1 in pin, out2 in pout; outputs must not
+// alias inputs; zc = planes per workgroup
+hipError_t launch_blk_chain_pair(const Op& op, int s, const void* x, const void* v,
+                                 const void* y1, void* out1, void* out2, const ChainCoef& k1,
+                                 const ChainCoef& k2, Prec pin, Prec pout, hipStream_t st,
+                                 int zc = 8);
 hipError_t launch_blk_to_f32(int64_t count, const double* x, float* y, hipStream_t st);
 // P (row i*s + a, column b; leading dimension ldp) = (or +=) V_i^T W, i < nb,
 // V_i = V + i * v_blk; split-K over nsplit chunks of rows (part holds

@@ -6,6 +6,8 @@
 //
 //   st7_blk_k    : one recurrence term of q(A) on a block, 7-point stencil:
 //                  out = alpha A X + beta X + g0 Y0 + g1 Y1
+//   st7_blk_pair_k : two consecutive terms in one launch (the intermediate
+//                  term kept on chip)
 //   blk_proj_k   : split-K partial products V_i^T W (block Gram-Schmidt, Gram
 //                  matrices), FP64 MFMA 16x16x4
 //   gemm_k       : C = alpha A B + beta C, FP64 MFMA 16x16x4 (block updates
@@ -202,6 +204,283 @@ hipError_t launch_blk_chain(const Op& op, int s, const void* x, const void* y0, 
     return st7_blk_t<double, float, float>(g, lg_s, x, y0, y1, out, a, b, c0, c1, st);
   if (px == P32 && py == P32 && po == P64)
     return st7_blk_t<float, float, double>(g, lg_s, x, y0, y1, out, a, b, c0, c1, st);
+  return hipErrorInvalidValue;
+}
+
+// --------------------------------------------------------------------------
+// two consecutive recurrence terms on a block (7-point stencil):
+//   s = a1 A x + b1 x + e01 v + e11 y1,   out1 = s (if out1),
+//   out2 = a2 A s + b2 s + e02 v + e12 x
+// s never leaves the chip: 5 block passes for 2 terms instead of 8.
+// --------------------------------------------------------------------------
+// Workgroup tile: PX points along x, 4 lines along y, all S columns, marching
+// along z; 1024 threads, each owning CW columns (16 bytes: 4 FP32 or 2 FP64
+// values) of one tile point and of one point of the ring around the tile
+// (the tile grown by one point, where s is needed for the second term's
+// in-plane neighbours).  Step p computes s(p) on the tile and the ring (x's
+// in-plane neighbours read from memory and cache, its z-neighbours kept in
+// registers), then the second term at plane p - 1 on the tile (s's in-plane
+// neighbours from an LDS plane buffer, its z-neighbours from registers), then
+// stores s(p) into the other buffer: one barrier per plane.  Outputs must
+// not alias inputs (neighbouring tiles read x around their own).
+struct BlkPairCoef {
+  double a1, b1, e01, e11, a2, b2, e02, e12;
+};
+template <int S, int CW>
+struct BlkPairGeo {
+  static constexpr int CG = S / CW;          // column groups, one per thread
+  static constexpr int PY = 4;               // tile lines along y
+  static constexpr int PX = 1024 / (PY * CG);  // tile points along x
+  static constexpr int RW = PX + 2, RH = PY + 2;  // the grown tile
+  static constexpr int RING = 2 * RW + 2 * PY;    // its points outside the tile
+  static_assert(PX * PY * CG == 1024 && RING <= PX * PY, "one tile and one ring point per thread");
+};
+
+// CW consecutive values (16 bytes of U = T) or their conversion
+template <int CW, typename U, typename T>
+__device__ __forceinline__ void ldw(const U* p, T (&v)[CW]) {
+  if constexpr (CW == 4) {
+    U u[4];
+    ld4(p, u);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = (T)u[q];
+  } else {
+    static_assert(std::is_same<U, double>::value && CW == 2, "two doubles");
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    v[0] = (T)a.x;
+    v[1] = (T)a.y;
+  }
+}
+template <int CW, typename U, typename T>
+__device__ __forceinline__ void stw(U* p, const T (&v)[CW]) {
+  if constexpr (CW == 4) {
+    U u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = (U)v[q];
+    st4(p, u);
+  } else {
+    static_assert(std::is_same<U, double>::value && CW == 2, "two doubles");
+    *reinterpret_cast<double2*>(p) = double2{(double)v[0], (double)v[1]};
+  }
+}
+
+template <typename TX, typename TO, int S, bool Y1G, bool W1>
+__global__ __launch_bounds__(1024) void st7_blk_pair_k(BlkSt7 g, int gx, int gy,
+                                                       const TX* __restrict__ x,
+                                                       const TX* __restrict__ v,
+                                                       const TX* __restrict__ y1,
+                                                       TO* __restrict__ out1,
+                                                       TO* __restrict__ out2, BlkPairCoef cf) {
+  using T = blk_calc_t<TX, TX, TO>;
+  constexpr int CW = 16 / (int)sizeof(T);
+  using G = BlkPairGeo<S, CW>;
+  __shared__ T sb[2][G::RW * G::RH * S];
+  const int tid = threadIdx.x;
+  const int cg = tid % G::CG, pt = tid / G::CG;
+  const int c = CW * cg;
+  const int lid = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int bx = lid % gx, by = (lid / gx) % gy, bz = lid / (gx * gy);
+  const int i0 = bx * G::PX, j0 = by * G::PY;
+  const int k0 = bz * g.zc, k1 = min(k0 + g.zc, g.nz);
+  const int64_t ls = (int64_t)g.nx * S;  // one line of the block
+  const int64_t ps = ls * g.ny;          // one plane of the block
+  const T c0 = (T)g.c0, cxm = (T)g.cxm, cxp = (T)g.cxp, cym = (T)g.cym, cyp = (T)g.cyp,
+          czm = (T)g.czm, czp = (T)g.czp;
+  const T a1 = (T)cf.a1, b1 = (T)cf.b1, e01 = (T)cf.e01, e11 = (T)cf.e11;
+  const T a2 = (T)cf.a2, b2 = (T)cf.b2, e02 = (T)cf.e02, e12 = (T)cf.e12;
+  const bool has_ring = pt < G::RING;
+
+  // u = 0: the tile point, u = 1: ring point pt (threads past the ring size
+  // neither compute nor store one)
+  int ra[2], rb[2];  // coordinates in the grown tile
+  ra[0] = pt % G::PX + 1;
+  rb[0] = pt / G::PX + 1;
+  {
+    const int h = has_ring ? pt : 0;
+    if (h < G::RW) {
+      ra[1] = h;
+      rb[1] = 0;
+    } else if (h < 2 * G::RW) {
+      ra[1] = h - G::RW;
+      rb[1] = G::RH - 1;
+    } else {
+      const int r = h - 2 * G::RW;
+      ra[1] = (r / G::PY) ? G::RW - 1 : 0;
+      rb[1] = 1 + r % G::PY;
+    }
+  }
+  bool ing[2];     // the point lies in the grid
+  int64_t off[2];  // its in-plane offset (clamped into the grid)
+  int nbm[2];      // bits 0..3: neighbour W, E, S, N inside the grid
+  int li[2];       // LDS index of the point (grown-tile layout, column c)
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = i0 - 1 + ra[u], j = j0 - 1 + rb[u];
+    ing[u] = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+    off[u] = (int64_t)min(max(j, 0), g.ny - 1) * ls + (int64_t)min(max(i, 0), g.nx - 1) * S + c;
+    // a neighbour of a point outside the grid is never used (that point's
+    // value is zero); the bits then stay clear and the loads read `off`
+    nbm[u] = ing[u] ? ((i > 0) | ((i + 1 < g.nx) << 1) | ((j > 0) << 2) | ((j + 1 < g.ny) << 3))
+                    : 0;
+    li[u] = (rb[u] * G::RW + ra[u]) * S + c;
+  }
+  auto pin = [&](int p) { return p >= 0 && p < g.nz; };
+  auto poff = [&](int p) { return (int64_t)min(max(p, 0), g.nz - 1) * ps; };
+
+  T xr[2][3][CW];  // x at planes p - 1, p, p + 1 of each point
+  T sr[3][CW];     // s at planes p - 2, p - 1, p of the tile point
+  T vk[CW];        // v at plane p - 1 of the tile point
+#pragma unroll
+  for (int q = 0; q < CW; ++q) sr[0][q] = sr[1][q] = sr[2][q] = vk[q] = T(0);
+  auto load_pt = [&](const TX* base, int p, int u, T (&r)[CW]) {
+    ldw<CW>(base + poff(p) + off[u], r);
+    const bool z = pin(p) && ing[u];
+#pragma unroll
+    for (int q = 0; q < CW; ++q) r[q] = z ? r[q] : T(0);
+  };
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    load_pt(x, k0 - 2, u, xr[u][1]);
+    load_pt(x, k0 - 1, u, xr[u][2]);
+  }
+  for (int p = k0 - 1; p <= k1; ++p) {
+    // x(p - 1), x(p) into place, x(p + 1) loaded
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        xr[u][0][q] = xr[u][1][q];
+        xr[u][1][q] = xr[u][2][q];
+      }
+      load_pt(x, p + 1, u, xr[u][2]);
+    }
+    // s(p) on the tile point and the ring point
+    T sp[2][CW], vp[CW];
+    const bool zp = pin(p);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !has_ring) break;
+      const bool live = zp && ing[u];
+      T as[CW], w[CW];
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        as[q] = c0 * xr[u][1][q];
+        as[q] = fma(czm, xr[u][0][q], as[q]);
+        as[q] = fma(czp, xr[u][2][q], as[q]);
+      }
+      const TX* xb = x + poff(p) + off[u];
+      const int64_t dn[4] = {-S, S, -ls, ls};
+      const T cn[4] = {cxm, cxp, cym, cyp};
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const bool in = (nbm[u] >> d) & 1;
+        ldw<CW>(xb + (in ? dn[d] : 0), w);
+#pragma unroll
+        for (int q = 0; q < CW; ++q) as[q] = fma(cn[d], in ? w[q] : T(0), as[q]);
+      }
+      T vv[CW], yy[CW];
+      ldw<CW>(v + poff(p) + off[u], vv);
+      if (Y1G) ldw<CW>(y1 + poff(p) + off[u], yy);
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        T val = fma(a1, as[q], b1 * xr[u][1][q]);
+        val = fma(e01, live ? vv[q] : T(0), val);
+        if (Y1G) val = fma(e11, live ? yy[q] : T(0), val);
+        sp[u][q] = live ? val : T(0);
+        if (u == 0) vp[q] = live ? vv[q] : T(0);
+      }
+    }
+    // the second term at plane p - 1 on the tile point
+    const int pm = p - 1;
+    if (pm >= k0 && pm < k1) {
+      const T* L = sb[pm & 1] + li[0];
+      T nw[CW], ne[CW], ns[CW], nn[CW];
+      ldw<CW>(L - S, nw);
+      ldw<CW>(L + S, ne);
+      ldw<CW>(L - G::RW * S, ns);
+      ldw<CW>(L + G::RW * S, nn);
+      T o2[CW], o1[CW];
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+        const T sc = sr[2][q];  // s(p - 1)
+        T as = c0 * sc;
+        as = fma(czm, sr[1][q], as);
+        as = fma(czp, sp[0][q], as);
+        as = fma(cxm, nw[q], as);
+        as = fma(cxp, ne[q], as);
+        as = fma(cym, ns[q], as);
+        as = fma(cyp, nn[q], as);
+        T val = fma(a2, as, b2 * sc);
+        val = fma(e02, vk[q], val);
+        val = fma(e12, xr[0][0][q], val);
+        o2[q] = val;
+        o1[q] = sc;
+      }
+      if (ing[0]) {
+        stw<CW>(out2 + (int64_t)pm * ps + off[0], o2);
+        if (W1) stw<CW>(out1 + (int64_t)pm * ps + off[0], o1);
+      }
+    }
+    // s(p) into its plane buffer
+    stw<CW>(&sb[p & 1][li[0]], sp[0]);
+    if (has_ring) stw<CW>(&sb[p & 1][li[1]], sp[1]);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      sr[1][q] = sr[2][q];
+      sr[2][q] = sp[0][q];
+      vk[q] = vp[q];
+    }
+  }
+}
+
+template <typename TX, typename TO, int S>
+static hipError_t st7_blk_pair_s(const BlkSt7& g, const void* x, const void* v, const void* y1,
+                                 void* out1, void* out2, const BlkPairCoef& cf, hipStream_t st) {
+  using G = BlkPairGeo<S, 16 / (int)sizeof(blk_calc_t<TX, TX, TO>)>;
+  const int gx = (g.nx + G::PX - 1) / G::PX, gy = (g.ny + G::PY - 1) / G::PY;
+  const int grid = gx * gy * ((g.nz + g.zc - 1) / g.zc);
+  const TX *X = (const TX*)x, *Vp = (const TX*)v, *Y = (const TX*)y1;
+  TO *O1 = (TO*)out1, *O2 = (TO*)out2;
+#define FA_BLK_PAIR(A, B) \
+  st7_blk_pair_k<TX, TO, S, A, B><<<grid, 1024, 0, st>>>(g, gx, gy, X, Vp, Y, O1, O2, cf)
+  if (y1 && out1)
+    FA_BLK_PAIR(true, true);
+  else if (y1)
+    FA_BLK_PAIR(true, false);
+  else if (out1)
+    FA_BLK_PAIR(false, true);
+  else
+    FA_BLK_PAIR(false, false);
+#undef FA_BLK_PAIR
+  return hipGetLastError();
+}
+
+template <typename TX, typename TO>
+static hipError_t st7_blk_pair_t(const BlkSt7& g, int s, const void* x, const void* v,
+                                 const void* y1, void* out1, void* out2, const BlkPairCoef& cf,
+                                 hipStream_t st) {
+  if (s == 64) return st7_blk_pair_s<TX, TO, 64>(g, x, v, y1, out1, out2, cf, st);
+  if (s == 32) return st7_blk_pair_s<TX, TO, 32>(g, x, v, y1, out1, out2, cf, st);
+  return st7_blk_pair_s<TX, TO, 16>(g, x, v, y1, out1, out2, cf, st);
+}
+
+hipError_t launch_blk_chain_pair(const Op& op, int s, const void* x, const void* v,
+                                 const void* y1, void* out1, void* out2, const ChainCoef& k1,
+                                 const ChainCoef& k2, Prec pin, Prec pout, hipStream_t st,
+                                 int zc) {
+  if (zc < 1 || !x || !v || !out2 || (s != 16 && s != 32 && s != 64))
+    return hipErrorInvalidValue;
+  BlkSt7 g{op.dims[0], op.dims[1], op.dims[2], zc, op.coef[0], op.coef[1], op.coef[2],
+           op.coef[3], op.coef[4], op.coef[5], op.coef[6]};
+  const BlkPairCoef cf{k1.alpha.real(), k1.beta.real(), k1.g0.real(), k1.g1.real(),
+                       k2.alpha.real(), k2.beta.real(), k2.g0.real(), k2.g1.real()};
+  if (pin == P64 && pout == P64)
+    return st7_blk_pair_t<double, double>(g, s, x, v, y1, out1, out2, cf, st);
+  if (pin == P32 && pout == P32)
+    return st7_blk_pair_t<float, float>(g, s, x, v, y1, out1, out2, cf, st);
+  if (pin == P32 && pout == P64 && !out1)
+    return st7_blk_pair_t<float, double>(g, s, x, v, y1, out1, out2, cf, st);
   return hipErrorInvalidValue;
 }
 
