@@ -849,6 +849,48 @@ def test_csr_long_rows(complex_):
     assert_close(host(op.poly_apply(dev(x))), ref, 1e-9)
 
 
+@pytest.mark.parametrize("complex_", [False, True])
+def test_csr_very_long_rows_repeats_and_streams(complex_):
+    """Rows of 9,000 and 20,000 entries among rows of 3 (each long row summed
+    by its own workgroup): A x against the oracle, and the same bits on every
+    repeat and on two streams at once."""
+    rng = np.random.default_rng(11)
+    n = 30000
+    rows, cols = [], []
+    for i in range(n):
+        k = 20000 if i % 1999 == 0 else (9000 if i % 2503 == 0 else 3)
+        c = rng.choice(n, size=k, replace=False)
+        rows += [i] * len(c)
+        cols += list(c)
+    rows, cols = np.array(rows), np.array(cols)
+    vals = rng.standard_normal(len(rows)) * 0.01
+    if complex_:
+        vals = vals + 0.01j * rng.standard_normal(len(rows))
+    import scipy.sparse as sp
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    A = A + sp.diags(np.asarray(abs(A).sum(axis=1)).ravel() + 1.0)
+    A = A.tocsr()
+    A.sort_indices()
+    rp, ci, va = A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data
+    op = fa().CSR(rp, ci, va)
+    x = dev(wl.rhs(n, seed=3, complex_=complex_))
+    ref = ops.csr_apply(rp, ci, va, host(x))
+    y0 = op.op_apply(x).clone()
+    assert_close(host(y0), ref, 1e-14)
+    for _ in range(3):
+        assert torch.equal(op.op_apply(x), y0)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    outs = []
+    for _ in range(4):
+        for st in (s1, s2):
+            with torch.cuda.stream(st):
+                outs.append(op.op_apply(x))
+    torch.cuda.synchronize()
+    for y in outs:
+        assert torch.equal(y, y0)
+
+
 def test_csr_rejects_bad_row_pointers():
     rp = np.array([0, 2, 1, 3], dtype=np.int32)
     ci = np.array([0, 1, 2], dtype=np.int32)
