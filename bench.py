@@ -152,10 +152,10 @@ def main():
     log(f"headline: degree {K}, {args.warmup} warmup + {args.steps} timed solves")
     op = make(K)
     # the dominant kernel's launches are timed by their own dispatch (a start
-    # and an end event per launch) in every fifth timed solve: each timed
-    # launch costs the solve about 5 us, and a fifth of the solves already
-    # gives hundreds of launches
-    x, dt, stats = timed(op, args.steps, args.warmup, profile=True, profile_every=5)
+    # and an end event per launch) in every tenth timed solve: each timed
+    # launch costs the solve about 5 us, and two solves in twenty already give
+    # 172 launches
+    x, dt, stats = timed(op, args.steps, args.warmup, profile=True, profile_every=10)
     err = rel_err(x)
     value = args.steps / dt
     st0 = stats[-1]
