@@ -249,3 +249,18 @@ def test_fusion_flags():
     assert L.fa_apply(h, 0, dummy, C.c_void_p(512), 10, 1e-8, 0, None, 0, 1 << 20, None,
                       None) == _lib.FA_ERR_ARG
     L.fa_destroy(h)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more (flag or a multi-rank launch)
+    it exits with status 2 and says why, before touching a GPU."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    bench = os.path.join(root, "bench.py")
+    for extra, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "2"})):
+        r = subprocess.run([sys.executable, bench, *extra], capture_output=True, text=True,
+                           env={**os.environ, **env}, timeout=120)
+        assert r.returncode == 2
+        assert "one GPU" in r.stderr
+        assert r.stdout == ""
