@@ -79,15 +79,18 @@ def test_block_converged_against_closed_form(s, kind):
         assert np.max(col_err(Xh, orc.X)) < 1e-10
 
 
-@pytest.mark.parametrize("degree", [4, 16])
-def test_block_mixed_precision_per_column(degree):
-    dims = (18, 17, 16)
-    coeffs, B, A, a, b = _problem(dims, 50.0, 32, seed0=7)
+@pytest.mark.parametrize("degree,s,dims", [(4, 32, (18, 17, 16)), (16, 32, (18, 17, 16)),
+                                           (7, 16, (70, 9, 13)), (16, 64, (21, 10, 7))])
+def test_block_mixed_precision_per_column(degree, s, dims):
+    """Mixed block solves against the DST closed form per column: two terms
+    per block launch (an odd degree ends with one single term), tiles ragged
+    in x and y (16 columns: 64-point tiles along x) and short z-slabs."""
+    coeffs, B, A, a, b = _problem(dims, 50.0, s, seed0=7)
     op = fa().Stencil7(dims, coeffs)
     op.poly_setup(degree, "cheb")
     X, st = op.block_apply(dev(B), m_max=60, tol=1e-7, mixed=True)
     assert st["converged"] == 1
-    ref = np.stack([exact.stencil_fAb_dst(coeffs, dims, B[:, c]) for c in range(32)], 1)
+    ref = np.stack([exact.stencil_fAb_dst(coeffs, dims, B[:, c]) for c in range(s)], 1)
     err = col_err(host(X), ref)
     assert np.max(err) <= 1e-6, np.max(err)
 
