@@ -188,6 +188,11 @@ hipError_t launch_blk_chain_pair(const Op& op, int s, const void* x, const void*
                                  const ChainCoef& k2, Prec pin, Prec pout, hipStream_t st,
                                  int zc = 8);
 hipError_t launch_blk_to_f32(int64_t count, const double* x, float* y, hipStream_t st);
+// one workgroup: ha[0:na) = a, hb[0:nb) = b (ha, hb, flag in page-locked
+// coherent host memory, device-accessible), then *flag = seq once the copies
+// are visible to the host
+hipError_t launch_check_export(const double* a, int64_t na, double* ha, const double* b,
+                               int64_t nb, double* hb, int* flag, int seq, hipStream_t s);
 // P (row i*s + a, column b; leading dimension ldp) = (or +=) V_i^T W, i < nb,
 // V_i = V + i * v_blk; split-K over nsplit chunks of rows (part holds
 // nsplit * nb * s * s doubles)

@@ -458,6 +458,28 @@ __global__ __launch_bounds__(kFinThreads) void dcgs2_finish_k(int j, int nblk,
   }
 }
 
+// The device side of a convergence check: copies na doubles a -> ha and nb
+// doubles b -> hb, where ha and hb are page-locked, coherent host memory,
+// then stores `seq` into the host flag once every copied value is visible
+// to the host (each thread fences at system scope before the barrier that
+// precedes the flag's release store).  One workgroup.
+__global__ __launch_bounds__(1024) void check_export_k(const double* __restrict__ a, int64_t na,
+                                                       double* ha, const double* __restrict__ b,
+                                                       int64_t nb, double* hb, int* flag,
+                                                       int seq) {
+  for (int64_t i = threadIdx.x; i < na; i += 1024) ha[i] = a[i];
+  for (int64_t i = threadIdx.x; i < nb; i += 1024) hb[i] = b[i];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_check_export(const double* a, int64_t na, double* ha, const double* b,
+                               int64_t nb, double* hb, int* flag, int seq, hipStream_t s) {
+  check_export_k<<<1, 1024, 0, s>>>(a, na, ha, b, nb, hb, flag, seq);
+  return hipGetLastError();
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void update2_k(int64_t n, int ncols, const T* __restrict__ V,
                                                       int64_t ldv, const T* __restrict__ cs,

@@ -446,8 +446,10 @@ namespace {
 // Page-locked host memory for the iteration's small copies (columns of H,
 // projections, norms, coefficients).  A copy into pageable memory is staged
 // by the runtime through its own buffer and blocks the calling thread; one
-// into page-locked memory queues on the stream like a kernel.  Buffers are
-// pooled across calls and threads and kept for the life of the process.
+// into page-locked memory queues on the stream like a kernel.  The memory is
+// coherent (fine-grained), so a kernel can write the checks' data into it and
+// the host can watch a flag there.  Buffers are pooled across calls and
+// threads and kept for the life of the process.
 class PinnedPool {
  public:
   void* take(size_t bytes) {
@@ -464,7 +466,7 @@ class PinnedPool {
       }
     }
     void* p = nullptr;
-    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocCoherent) != hipSuccess) return nullptr;
     std::lock_guard<std::mutex> g(mu_);
     size_of_[p] = bytes;
     return p;
@@ -731,6 +733,37 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   double* const sh_host = pin + n_h;       // a projection of u_{j+1}
   double* const z_host = sh_host + n_sh;   // two coefficient vectors
   double* const sc_host = z_host + 2 * n_z;  // scalars
+  // With page-locked memory, a check's data reaches the host through one
+  // kernel that writes it there and then raises a flag (sc_host[3]) which the
+  // host watches: no copy commands, no event, no wait for the stream.
+  double* pin_dev = nullptr;  // the lease as the device addresses it
+  if (lease.p) {
+    void* dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, lease.p, 0) == hipSuccess) pin_dev = (double*)dp;
+  }
+  auto dev_of = [&](double* hp) { return pin_dev + (hp - pin); };
+  int* const flag_host = reinterpret_cast<int*>(sc_host + 3);
+  int chk_seq = 0;  // the value the next check raises the flag to (unique in the process,
+                    // so a late write by an earlier user of this area never matches)
+  auto next_seq = [] {
+    static std::atomic<int> counter{0};
+    return (counter.fetch_add(1) & 0x3fffffff) + 1;
+  };
+  // wait until the device has raised the flag to `seq` (the stream is
+  // synchronized instead if that takes implausibly long)
+  auto wait_flag = [&](int seq) -> int {
+    const double t0 = now_ms();
+    while (__atomic_load_n(flag_host, __ATOMIC_ACQUIRE) != seq) {
+#if defined(__x86_64__)
+      __builtin_ia32_pause();
+#endif
+      if (now_ms() - t0 > 2000.0) {
+        FA_HIP(hipStreamSynchronize(s));
+        return __atomic_load_n(flag_host, __ATOMIC_ACQUIRE) == seq ? FA_OK : FA_ERR_HIP;
+      }
+    }
+    return FA_OK;
+  };
   // coefficient vector z to the device (negated with `neg`) from host slot
   // `slot` (0 or 1); the slot must not be rewritten before the stream has
   // passed this copy (every caller synchronizes before the next use)
@@ -818,17 +851,26 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     const int jj = j + 1;
     const bool check = (tol > 0.0) ? (jj % k_chk == 0 || jj == m_max) : (jj == m_max);
     if (!check) continue;
-    // copy the new columns of H to the host
+    // the new columns of H to the host
     const int from = std::min(copied, refresh);
-    FA_HIP(hipMemcpyAsync(H.buf + (size_t)from * L.ldh * (es / 8), Hcol(from),
-                          (size_t)(jj - from) * L.ldh * es, hipMemcpyDeviceToHost, s));
-    if (dcgs2) {
-      // column j still lacks its second pass (done on the device in the next
-      // step): project u_{j+1} on [q_0 .. q_j, u_{j+1}] and finish the host
-      // copy: H(0:j, j) += s', H(j+1, j) = (||u_{j+1}||^2 - ||s'||^2)^{1/2}
+    double* const h_dst = H.buf + (size_t)from * L.ldh * ed;
+    const int64_t h_len = (int64_t)(jj - from) * L.ldh * ed;  // doubles
+    // column j still lacks its second pass (done on the device in the next
+    // step): project u_{j+1} on [q_0 .. q_j, u_{j+1}] and finish the host
+    // copy: H(0:j, j) += s', H(j+1, j) = (||u_{j+1}||^2 - ||s'||^2)^{1/2}
+    if (dcgs2)
       FA_HIP(launch_project(op.dtype, n, jj + 1, V, L.ldv, Vc(jj), part, hcur, nullptr, 0, s));
-      FA_HIP(hipMemcpyAsync(sh_host, hcur, (size_t)(jj + 1) * ed * sizeof(double),
+    const int64_t p_len = dcgs2 ? (int64_t)(jj + 1) * ed : 0;
+    if (pin_dev) {
+      FA_HIP(launch_check_export((const double*)Hcol(from), h_len, dev_of(h_dst),
+                                 (const double*)hcur, p_len, dev_of(sh_host),
+                                 (int*)dev_of(sc_host + 3), chk_seq = next_seq(), s));
+    } else {
+      FA_HIP(hipMemcpyAsync(h_dst, Hcol(from), (size_t)h_len * sizeof(double),
                             hipMemcpyDeviceToHost, s));
+      if (p_len)
+        FA_HIP(hipMemcpyAsync(sh_host, hcur, (size_t)p_len * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
     }
     int64_t half_mvms = 0;  // counts of a half step enqueued at this check
     Prof prof_before_half = prof;
@@ -838,15 +880,25 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       predict_more = b * (b / a) > 10.0 * tol;
     }
     if (can_half && jj < m_max && predict_more) {
-      hipEvent_t ev;
-      FA_HIP(check_event(&ev));
-      FA_HIP(hipEventRecord(ev, s));
+      hipEvent_t ev = nullptr;
+      if (!pin_dev) {
+        FA_HIP(check_event(&ev));
+        FA_HIP(hipEventRecord(ev, s));
+      }
       const int64_t m0 = mvms;
       st = step(jj, 1);
       if (st) return st;
       half_mvms = mvms - m0;
       half_j = jj;
-      FA_HIP(hipEventSynchronize(ev));
+      if (pin_dev) {
+        st = wait_flag(chk_seq);
+        if (st) return st;
+      } else {
+        FA_HIP(hipEventSynchronize(ev));
+      }
+    } else if (pin_dev) {
+      st = wait_flag(chk_seq);
+      if (st) return st;
     } else {
       FA_HIP(hipStreamSynchronize(s));
     }
