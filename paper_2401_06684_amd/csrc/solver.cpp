@@ -786,8 +786,15 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
 
   st = start_vector();
   if (st) return st;
-  FA_HIP(hipMemcpyAsync(sc_host, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
-  FA_HIP(hipStreamSynchronize(s));
+  if (pin_dev) {  // ||c||^2 to the host through the flag (see the checks)
+    FA_HIP(launch_check_export(nrm, 1, dev_of(sc_host), nullptr, 0, nullptr,
+                               (int*)dev_of(sc_host + 3), chk_seq = next_seq(), s));
+    st = wait_flag(chk_seq);
+    if (st) return st;
+  } else {
+    FA_HIP(hipMemcpyAsync(sc_host, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
+    FA_HIP(hipStreamSynchronize(s));
+  }
   const double beta2 = sc_host[0];
   if (!std::isfinite(beta2)) return FA_ERR_NONFINITE;
   const double beta = std::sqrt(beta2);
