@@ -304,8 +304,9 @@ def wilson_leg(fa, torch, wl, dev):
     """The 4D Wilson-Dirac-like operator on 16^4 (links exp(0.3 i H), m0 =
     0.05), A^{-1/2} b with a Ritz polynomial of degree 16, tol 1e-8, and
     the same with q == 1.  The Newton middle terms (read r with its 8
-    neighbours, the links, v; write r') are timed with HIP events: 4 spinor
-    fields + the links = 75.5 MB per launch."""
+    neighbours, the links, v; write r') are timed with HIP events: 3 spinor
+    fields + the links, which are special unitary and kept as two rows per
+    3 x 3 matrix (the third rebuilt in the kernel) = 62.9 MB per launch."""
     L = 16
     op = fa.Wilson(wl.su3_links(L, eps=0.3, seed=1), 0.05, device=dev)
     start = torch.from_numpy(wl.rhs(op.n, seed=11, complex_=True)).to(dev)

@@ -206,8 +206,11 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
  *     double complex[4][Lt][Lz][Ly][Lx][3][3] (direction mu = x, y, z, t, row
  *     major 3x3), read once on hip_stream (which is synchronized) into device
  *     memory the op owns, reordered so that one link element of consecutive
- *     sites is contiguous; the caller's array may be freed after the call
- *     (36 V complex doubles stay allocated until fa_destroy).  The
+ *     sites is contiguous; the caller's array may be freed after the call.
+ *     When every link is special unitary (row 2 equals conj(row 0 x row 1) to
+ *     within 1e-13, checked on the host at creation) only rows 0 and 1 are
+ *     kept (24 V complex doubles) and the kernels rebuild row 2; otherwise
+ *     all of it (36 V).  The copy stays allocated until fa_destroy.  The
  *     Wilson-Dirac operator is the matrix of Sec. 6, Example 2 (without
  *     clover term and chemical potential).
  *   flags: FA_HERMITIAN allowed only for symmetric stencils.

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <complex>
 #include <vector>
 
 #include "dense.hpp"
@@ -169,13 +170,30 @@ int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double*
       for (int d = 0; d < 4; ++d) op.dims[d] = dims[d];
       op.m0 = params[0];
       if (!std::isfinite(op.m0)) return FA_ERR_ARG;
+      // Special unitary links (det 1: row 2 = conj(row 0 x row 1) to within
+      // 1e-13) are stored as their first two rows and the kernel rebuilds the
+      // third (a third less link traffic); other links are stored whole.
+      hipStream_t st = stream_of(hip_stream);
+      std::vector<std::complex<double>> hu((size_t)V * 36);
+      if (hipStreamSynchronize(st) != hipSuccess ||
+          hipMemcpy(hu.data(), d_links, hu.size() * 16, hipMemcpyDeviceToHost) != hipSuccess)
+        return FA_ERR_HIP;
+      bool su3 = true;
+      for (size_t l = 0; l < (size_t)V * 4 && su3; ++l) {
+        const std::complex<double>* u = &hu[l * 9];
+        const std::complex<double> c[3] = {u[1] * u[5] - u[2] * u[4], u[2] * u[3] - u[0] * u[5],
+                                           u[0] * u[4] - u[1] * u[3]};
+        for (int j = 0; j < 3; ++j)
+          if (!(std::abs(u[6 + j] - std::conj(c[j])) <= 1e-13)) su3 = false;
+      }
+      op.links_rows = su3 ? 2 : 3;
+      const int ne = 3 * op.links_rows;
       // own structure-of-arrays copy of the links (coalesced link loads)
       void* us = nullptr;
-      if (hipMalloc(&us, (size_t)V * 36 * 16) != hipSuccess) return FA_ERR_HIP;
+      if (hipMalloc(&us, (size_t)V * 4 * ne * 16) != hipSuccess) return FA_ERR_HIP;
       op.links_owned = std::shared_ptr<void>(us, [](void* p) { (void)hipFree(p); });
       op.links = us;
-      hipStream_t st = stream_of(hip_stream);
-      if (launch_wilson_links_soa(V, d_links, us, st) != hipSuccess ||
+      if (launch_wilson_links_soa(V, ne, d_links, us, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess)
         return FA_ERR_HIP;
     } else {

@@ -70,6 +70,7 @@ struct Op {
   // row-major 3x3 element), in device memory this op owns (shared by copies)
   const void* links = nullptr;
   std::shared_ptr<void> links_owned;
+  int links_rows = 3;  // rows of each link stored (2: special unitary, row 2 rebuilt)
   double m0 = 0.0;
   // spectral interval
   bool has_interval = false;
@@ -125,8 +126,9 @@ hipError_t launch_to_f32(int64_t n, const double* x, float* y, hipStream_t s);
 // ---- kernel launchers (kernels_*.hip) ----
 // pin: storage of x, y0, y1; pout: storage of out.  FP32 storage (with FP32
 // arithmetic) is available for the 7-point stencil only.
-// Us[mu][e][s] = U[mu][s][e] (complex FP64, 4 directions, 9 elements, V sites)
-hipError_t launch_wilson_links_soa(int64_t V, const void* U, void* Us, hipStream_t s);
+// Us[mu][e][s] = U[mu][s][e] (complex FP64, 4 directions, the first ne = 9 or
+// 6 elements of each row-major 3x3 link, V sites)
+hipError_t launch_wilson_links_soa(int64_t V, int ne, const void* U, void* Us, hipStream_t s);
 hipError_t launch_chain(const Op& op, const void* x, const void* y0, const void* y1, void* out,
                         const ChainCoef& k, hipStream_t s, Prec pin = P64, Prec pout = P64);
 

@@ -579,13 +579,19 @@ struct HopCoef {
 
 // one hop: acc += (1 + sg g_mu) W x(nb), W = U (forward) or U^H (backward).
 // xs: this lane's neighbour spinor in LDS; Ue: link element 0 of the site in
-// the structure-of-arrays copy, element e at Ue[e V].
-template <bool Adj>
+// the structure-of-arrays copy, element e at Ue[e V].  R12: only rows 0 and 1
+// are stored (the links are special unitary) and row 2 = conj(row 0 x row 1).
+template <bool Adj, bool R12>
 __device__ __forceinline__ void wilson_hop(const cplx* xs, const cplx* __restrict__ Ue,
                                            int64_t V, const HopCoef& k, cplx acc[4][3]) {
   cplx u[9];
 #pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = Ue[e * V];
+  for (int e = 0; e < (R12 ? 6 : 9); ++e) u[e] = Ue[e * V];
+  if (R12) {
+    u[6] = conjg(u[1] * u[5] - u[2] * u[4]);
+    u[7] = conjg(u[2] * u[3] - u[0] * u[5]);
+    u[8] = conjg(u[0] * u[4] - u[1] * u[3]);
+  }
   cplx h[2][3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -631,7 +637,7 @@ __device__ __forceinline__ void wilson_stage(const cplx* __restrict__ x, int nb,
   for (int k = 0; k < 12; ++k) slice[k * kWilSites + sl] = v[k];
 }
 
-template <bool Y0, bool Y1>
+template <bool Y0, bool Y1, bool R12>
 __global__ __launch_bounds__(64) void wilson_chain(Wil w, const cplx* __restrict__ Us,
                                                    const cplx* __restrict__ x,
                                                    const cplx* __restrict__ y0,
@@ -685,13 +691,14 @@ __global__ __launch_bounds__(64) void wilson_chain(Wil w, const cplx* __restrict
   wilson_stage(x, sf, sl, mu, slice);
   __builtin_amdgcn_wave_barrier();
   k.sg = -1.0;
-  wilson_hop<false>(mine, Us + (int64_t)mu * 9 * V + s, V, k, acc);
+  constexpr int NE = R12 ? 6 : 9;  // link elements stored per site and direction
+  wilson_hop<false, R12>(mine, Us + (int64_t)mu * NE * V + s, V, k, acc);
   __builtin_amdgcn_wave_barrier();
   // backward hop: (1 + g_mu) U_mu(s - mu)^H x(s - mu)
   wilson_stage(x, sb, sl, mu, slice);
   __builtin_amdgcn_wave_barrier();
   k.sg = 1.0;
-  wilson_hop<true>(mine, Us + (int64_t)mu * 9 * V + sb, V, k, acc);
+  wilson_hop<true, R12>(mine, Us + (int64_t)mu * NE * V + sb, V, k, acc);
   __builtin_amdgcn_wave_barrier();
 
   // quad reduce-scatter: after the xor-2 step a lane holds rows {0,1} or
@@ -738,28 +745,41 @@ static hipError_t launch_wilson(const Op& op, const cplx* x, const cplx* y0, con
   const cplx al = host_to_dev<cplx>::conv(k.alpha), be = host_to_dev<cplx>::conv(k.beta),
              g0 = host_to_dev<cplx>::conv(k.g0), g1 = host_to_dev<cplx>::conv(k.g1);
   const cplx* U = (const cplx*)op.links;
-  if (y0 && y1)
-    wilson_chain<true, true><<<grid, 64, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1);
-  else if (y0)
-    wilson_chain<true, false><<<grid, 64, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1);
-  else if (y1)
-    wilson_chain<false, true><<<grid, 64, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1);
-  else
-    wilson_chain<false, false><<<grid, 64, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1);
+#define FA_WIL(A, B, R) wilson_chain<A, B, R><<<grid, 64, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1)
+#define FA_WIL_R(A, B)  \
+  if (op.links_rows == 2) \
+    FA_WIL(A, B, true);   \
+  else                    \
+    FA_WIL(A, B, false)
+  if (y0 && y1) {
+    FA_WIL_R(true, true);
+  } else if (y0) {
+    FA_WIL_R(true, false);
+  } else if (y1) {
+    FA_WIL_R(false, true);
+  } else {
+    FA_WIL_R(false, false);
+  }
+#undef FA_WIL_R
+#undef FA_WIL
   return hipGetLastError();
 }
 
-// Us[mu][e][s] = U[mu][s][e] for the 4 directions, 9 link elements, V sites
-__global__ void wilson_links_soa_k(int64_t V, const cplx* __restrict__ U, cplx* __restrict__ Us) {
+// Us[mu][e][s] = U[mu][s][e] for the 4 directions, the first ne of the 9
+// link elements (row-major: 9 = all, 6 = rows 0 and 1), V sites
+__global__ void wilson_links_soa_k(int64_t V, int ne, const cplx* __restrict__ U,
+                                   cplx* __restrict__ Us) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // over Us
-  if (i >= 36 * V) return;
-  const int64_t s = i % V, me = i / V, mu = me / 9, e = me - 9 * mu;
+  if (i >= 4 * ne * V) return;
+  const int64_t s = i % V, me = i / V, mu = me / ne, e = me - ne * mu;
   Us[i] = U[(mu * V + s) * 9 + e];
 }
 
-hipError_t launch_wilson_links_soa(int64_t V, const void* U, void* Us, hipStream_t st) {
-  const int64_t n = 36 * V;
-  wilson_links_soa_k<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(V, (const cplx*)U, (cplx*)Us);
+hipError_t launch_wilson_links_soa(int64_t V, int ne, const void* U, void* Us, hipStream_t st) {
+  if (ne != 6 && ne != 9) return hipErrorInvalidValue;
+  const int64_t n = 4 * ne * V;
+  wilson_links_soa_k<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(V, ne, (const cplx*)U,
+                                                                 (cplx*)Us);
   return hipGetLastError();
 }
 
@@ -794,7 +814,7 @@ double chain_bytes(const Op& op, bool has_y0, bool has_y1, Prec p) {
   double extra = 0.0;
   if (op.kind == OP_CSR)
     extra = (double)(op.n + 1) * 4 + (double)op.nnz * (4 + elem_size(op.dtype));
-  if (op.kind == OP_WILSON) extra = 4.0 * (double)(op.n / 12) * 9 * 16;
+  if (op.kind == OP_WILSON) extra = 4.0 * (double)(op.n / 12) * (3 * op.links_rows) * 16;
   return nvec * vec + extra;
 }
 

@@ -78,11 +78,19 @@ def test_csr_apply(which):
     assert_close(y, ops.csr_apply(rp, ci, va, x), 1e-14)
 
 
+@pytest.mark.parametrize("links", ["su3", "scaled", "phase"])
 @pytest.mark.parametrize("shape", [(4, 4, 4, 4), (6, 2, 4, 5), (4, 8, 4, 32)])
-def test_wilson_apply(shape):
-    """(Lt, Lz, Ly, Lx); the last shape has whole 16-site rows."""
+def test_wilson_apply(shape, links):
+    """(Lt, Lz, Ly, Lx); the last shape has whole 16-site rows.  Special
+    unitary links are kept as two rows (the third rebuilt in the kernel);
+    links scaled by 1.01 or multiplied by a phase (unitary, det != 1) are not
+    special unitary and are kept whole."""
     Lt, Lz, Ly, Lx = shape
     rng_links = wl.random_su3(4 * Lt * Lz * Ly * Lx, 0.8, np.random.default_rng(5))
+    if links == "scaled":
+        rng_links = 1.01 * rng_links
+    elif links == "phase":
+        rng_links = np.exp(0.3j) * rng_links
     U = rng_links.reshape(4, Lt, Lz, Ly, Lx, 3, 3)
     m0 = 0.05
     op = fa().Wilson(U, m0)
