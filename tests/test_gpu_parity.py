@@ -79,9 +79,9 @@ def test_csr_apply(which):
 
 
 @pytest.mark.parametrize("links", ["su3", "scaled", "phase"])
-@pytest.mark.parametrize("shape", [(4, 4, 4, 4), (6, 2, 4, 5), (4, 8, 4, 32)])
+@pytest.mark.parametrize("shape", [(4, 4, 4, 4), (6, 2, 4, 5), (4, 8, 4, 32), (4, 2, 6, 16)])
 def test_wilson_apply(shape, links):
-    """(Lt, Lz, Ly, Lx); the last shape has whole 16-site rows.  Special
+    """(Lt, Lz, Ly, Lx); the last two shapes have whole 16-site rows.  Special
     unitary links are kept as two rows (the third rebuilt in the kernel);
     links scaled by 1.01 or multiplied by a phase (unitary, det != 1) are not
     special unitary and are kept whole."""
