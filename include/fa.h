@@ -30,8 +30,15 @@
  *     (outputs undefined).  fa_status_string() names each code.
  *   - "d_" arguments are device pointers (memory of the current HIP device),
  *     "h_" arguments host pointers.  All device memory is owned by the caller;
- *     the library never allocates device memory.  It borrows operator arrays
- *     given to fa_create_* until fa_destroy.
+ *     the library never allocates device memory (it calls no hipMalloc): the
+ *     Krylov basis and scratch come in a caller workspace (fa_workspace_bytes),
+ *     an operator's own device data (the reordered Wilson links, the CSR list
+ *     of long rows) in caller "operator memory" (fa_op_device_bytes).  It
+ *     borrows operator arrays and operator memory given to fa_create_* until
+ *     fa_destroy.  The only memory it allocates is page-locked host memory
+ *     for the small copies at the stopping checks (pooled for the process).
+ *   - The library creates no streams: all device work goes to the caller's
+ *     streams (hip_stream arguments; fa_server_create takes one per worker).
  *   - hip_stream is a hipStream_t (NULL = the default stream).  All device
  *     work of a call is enqueued on it; calls that return host results
  *     synchronize that stream before returning.
@@ -77,10 +84,12 @@ enum { FA_F64 = 0, FA_C128 = 1 };
 /* functions */
 enum { FA_INVSQRT = 0, FA_SQRT = 1 };
 
-/* matrix-free operators for fa_create_stencil */
+/* matrix-free operators for fa_create_stencil; FA_CSR names fa_create_csr's
+ * operators in fa_op_device_bytes */
 enum {
   FA_STENCIL7 = 0, /* real 7-point (3D) or 5-point (nz = 1) stencil, zero Dirichlet  */
-  FA_WILSON4D = 1  /* Wilson-Dirac-like operator, periodic 4D lattice, complex       */
+  FA_WILSON4D = 1, /* Wilson-Dirac-like operator, periodic 4D lattice, complex       */
+  FA_CSR = 2       /* sparse matrix in CSR form (fa_create_csr)                       */
 };
 
 /* polynomial constructions for fa_poly_setup */
@@ -166,6 +175,18 @@ typedef struct {
 } fa_stats;
 
 /*
+ * fa_op_device_bytes -- bytes of caller "operator memory" (d_opmem) that
+ * fa_create_csr / fa_create_stencil may need for an operator of this kind and
+ * size (an upper bound: the op uses what it needs of it).
+ *   FA_STENCIL7: 0 (the op is its 7 coefficients).
+ *   FA_CSR     : 3840 (the list of long rows, at most 900 int32); n, nnz unused.
+ *   FA_WILSON4D: 576 V bytes (V = Lx Ly Lz Lt from dims): the links in the
+ *                kernels' order, whole; special unitary links use 384 V of it.
+ * Returns 0 for an unknown kind or invalid dims.  Needs no GPU.
+ */
+size_t fa_op_device_bytes(int kind, const int32_t dims[4], int64_t n, int64_t nnz);
+
+/*
  * fa_create_csr -- borrow a CSR matrix (the sparse matrix-vector product of
  * Sec. 6, Examples 1 and 3).
  *   n, nnz       : order and stored entries (n >= 1, nnz >= 0, < 2^31)
@@ -174,20 +195,24 @@ typedef struct {
  *   d_vals       : double[nnz] (FA_F64) or double complex[nnz] (FA_C128)
  *   dtype        : FA_F64 or FA_C128 (vectors passed to fa_apply use the same type)
  *   flags        : FA_HERMITIAN to select Lanczos in fa_apply
+ *   d_opmem      : operator memory, >= opmem_bytes bytes, 256-byte aligned,
+ *                  fa_op_device_bytes(FA_CSR, ...) suffices; borrowed until
+ *                  fa_destroy.  May be NULL when no row is long (see below).
  * The arrays are not copied; they must stay alive and unchanged until
- * fa_destroy.  The row pointers are read once to the host (a synchronous
- * copy) to check them and to pick the work split: rows up to 16 times the
- * mean length (rounded to a power of two) are summed by lane groups, longer
- * ones (at most 900; the threshold doubles until so) by one 1024-thread
- * workgroup each, in the same launch; their list is copied to a small device
- * array the op owns.  Column indices are not validated.  A CSR op has no
- * spectral interval until fa_set_spectral_interval is called.
- * Errors: FA_ERR_ARG (including row pointers that do not start at 0, end at
- * nnz and never decrease), FA_ERR_HIP.
+ * fa_destroy.  hip_stream is synchronized first (the arrays may be written
+ * on it); then the row pointers and column indices are read once to the host
+ * to check them and to pick the work split: rows up to 16 times the mean
+ * length (rounded to a power of two) are summed by lane groups, longer ones
+ * (at most 900; the threshold doubles until so) by one 1024-thread workgroup
+ * each, in the same launch; their list is written to d_opmem.  A CSR op has
+ * no spectral interval until fa_set_spectral_interval is called.
+ * Errors: FA_ERR_ARG (row pointers that do not start at 0, end at nnz and
+ * never decrease, or a column index outside [0, n)), FA_ERR_WORKSPACE (long
+ * rows and d_opmem NULL, misaligned or too small), FA_ERR_HIP.
  */
 int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
                   const int32_t* d_colind, const void* d_vals, int dtype, uint32_t flags,
-                  void* hip_stream);
+                  void* d_opmem, size_t opmem_bytes, void* hip_stream);
 
 /*
  * fa_create_stencil -- a matrix-free operator.
@@ -204,20 +229,24 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
  *     periodic, chiral-basis Euclidean gamma matrices; 12 complex per site,
  *     vectors [t][z][y][x][spin 4][colour 3] (FA_C128).  d_links: device
  *     double complex[4][Lt][Lz][Ly][Lx][3][3] (direction mu = x, y, z, t, row
- *     major 3x3), read once on hip_stream (which is synchronized) into device
- *     memory the op owns, reordered so that one link element of consecutive
- *     sites is contiguous; the caller's array may be freed after the call.
- *     When every link is special unitary (row 2 equals conj(row 0 x row 1) to
- *     within 1e-13, checked on the host at creation) only rows 0 and 1 are
- *     kept (24 V complex doubles) and the kernels rebuild row 2; otherwise
- *     all of it (36 V).  The copy stays allocated until fa_destroy.  The
- *     Wilson-Dirac operator is the matrix of Sec. 6, Example 2 (without
- *     clover term and chemical potential).
+ *     major 3x3), read once on hip_stream (which is synchronized) into the
+ *     operator memory d_opmem, reordered so that one link element of
+ *     consecutive sites is contiguous; the caller's link array may be freed
+ *     after the call, d_opmem must live until fa_destroy.  When every link is
+ *     special unitary (row 2 equals conj(row 0 x row 1) to within 1e-13,
+ *     checked on the host at creation) only rows 0 and 1 are kept (24 V
+ *     complex doubles) and the kernels rebuild row 2; otherwise all of it
+ *     (36 V).  The Wilson-Dirac operator is the matrix of Sec. 6, Example 2
+ *     (without clover term and chemical potential).
  *   flags: FA_HERMITIAN allowed only for symmetric stencils.
- * Errors: FA_ERR_ARG, FA_ERR_HIP (Wilson: the link copy failed).
+ *   d_opmem, opmem_bytes: operator memory (256-byte aligned), at least
+ *     fa_op_device_bytes(kind, dims, 0, 0) bytes; NULL for FA_STENCIL7.
+ * Errors: FA_ERR_ARG, FA_ERR_WORKSPACE (Wilson: d_opmem NULL, misaligned or
+ * smaller than the links kept), FA_ERR_HIP (Wilson: the link copy failed).
  */
 int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double* params,
-                      int nparams, const void* d_links, uint32_t flags, void* hip_stream);
+                      int nparams, const void* d_links, uint32_t flags, void* d_opmem,
+                      size_t opmem_bytes, void* hip_stream);
 
 /* Set (or replace) the real interval [lo, hi], 0 < lo < hi, assumed to hold
  * spec(A); used by FA_POLY_CHEB (Sec. 5.1).  Errors: FA_ERR_ARG. */
@@ -404,8 +433,9 @@ size_t fa_block_workspace_bytes(fa_op op, int s, int m_max, uint32_t flags);
  *   m_max    : maximal number of block steps; tol, check_every as fa_apply
  *   flags    : FA_MIXED (the stencil chain in FP32 storage and arithmetic;
  *              Gram-Schmidt, Cholesky QR, H^{-1/2} and X = V Z in FP64),
- *              FA_GRAPH (block steps from captured HIP graphs; the same
- *              launches, so the same results)
+ *              FA_GRAPH (block steps from HIP graphs captured on hip_stream,
+ *              which must not be the null stream; the same launches, so the
+ *              same results)
  * d_B and d_X must be 32-byte aligned.  Launch parameters (the split-K chunk
  * count of the projections per basis size, the z-march length of the
  * stencil) are autotuned at the first use of a problem shape in the process
@@ -427,8 +457,8 @@ int fa_block_apply(fa_op op, int kind, int s, const void* d_B, void* d_X, int m_
  * request is admitted as soon as a worker is idle and the device pool has
  * room for its workspace (fa_workspace_bytes(op, m_max, flags): the Krylov
  * basis of m_max + 1 vectors of n entries plus scratch), so basis memory
- * bounds the solves in flight.  Each worker owns a HIP stream (default
- * priority); admitted solves run concurrently on the device and a finished
+ * bounds the solves in flight.  Each worker runs on a stream of the caller
+ * (fa_server_create); admitted solves run concurrently on the device and a finished
  * solve frees its memory and worker at once, whatever step the others are
  * at.  Operators and polynomials stay on the device between requests (the
  * caller creates and sets them up once).  Results do not depend on what else
@@ -456,9 +486,12 @@ typedef struct {
 /* Create a server on the current device.  d_pool: device memory of
  * pool_bytes (256-byte aligned), borrowed for the server's lifetime, from
  * which request workspaces are carved.  n_workers (1..64): concurrent solves
- * at most (HIP maps the streams onto the device's hardware queues).
- * Errors: FA_ERR_ARG, FA_ERR_HIP. */
-int fa_server_create(fa_server* out, void* d_pool, size_t pool_bytes, int n_workers);
+ * at most.  hip_streams: n_workers hipStream_t of the caller (worker w runs
+ * its solves on hip_streams[w]; distinct streams let the solves overlap, HIP
+ * maps them onto the device's hardware queues), borrowed until
+ * fa_server_destroy returns.  Errors: FA_ERR_ARG, FA_ERR_HIP. */
+int fa_server_create(fa_server* out, void* d_pool, size_t pool_bytes, int n_workers,
+                     void* const* hip_streams);
 
 /* Queue one solve (arguments as fa_apply; FA_PROFILE not allowed).  d_b and
  * d_x must stay valid and untouched until the request is done; op must
@@ -478,8 +511,8 @@ int fa_server_wait(fa_server srv, uint64_t ticket, fa_request_info* info);
 /* Queue depth, solves in flight, completed count and pool occupancy. */
 int fa_server_status(fa_server srv, fa_server_info* info);
 
-/* Finish every queued request, stop the workers, destroy their streams.
- * No fa_server_wait may be pending.  The pool stays the caller's. */
+/* Finish every queued request and stop the workers.  No fa_server_wait may
+ * be pending.  The pool and the streams stay the caller's. */
 int fa_server_destroy(fa_server srv);
 
 #ifdef __cplusplus

@@ -284,6 +284,7 @@ def _two_pass_lanczos(apply_A, b, poly, kind, m_max, tol, check_every):
     m, est, checks, converged, breakdown = m_max, 1.0, 0, False, False
     colmax = 0.0
     ips = 0
+    history = []
     for j in range(m_max):
         w = Q(Q(A(v)))
         if j > 0:
@@ -304,6 +305,7 @@ def _two_pass_lanczos(apply_A, b, poly, kind, m_max, tol, check_every):
             zp = np.zeros_like(z)
             zp[:z_prev.size] = z_prev
             est = float(np.linalg.norm(z - zp) / np.linalg.norm(z))
+            history.append((jj, est))
             z_prev = z
             if est <= tol:
                 m, converged = jj, True
@@ -322,4 +324,4 @@ def _two_pass_lanczos(apply_A, b, poly, kind, m_max, tol, check_every):
         v_prev, v = v, w / off[j]
         x = x + z[j + 1] * v
     return Result(x=x, iters=m, converged=converged, breakdown=breakdown, mvms=mvms,
-                  inner_products=ips, est=est, checks=checks)
+                  inner_products=ips, est=est, checks=checks, history=history)

@@ -234,9 +234,19 @@ class Operator:
             ws = workspace(nbytes, self.device)
             self._ws["block"] = ws
         stats = _lib.fa_block_stats()
+        cur = torch.cuda.current_stream(self.device)
+        run = cur
+        if graph and cur.cuda_stream == 0:
+            # graphs are captured on the stream given; the null stream cannot be
+            run = self._ws.get("graph_stream")
+            if run is None:
+                run = self._ws["graph_stream"] = torch.cuda.Stream(self.device)
+            run.wait_stream(cur)
         st = lib().fa_block_apply(self._h, _KIND[kind], s, _ptr(B), _ptr(X), int(m_max),
                                   float(tol), int(check_every), ws[1], ws[2], flags,
-                                  _stream(self.device), C.byref(stats))
+                                  C.c_void_p(run.cuda_stream), C.byref(stats))
+        if run is not cur:
+            cur.wait_stream(run)
         check(st, "fa_block_apply")
         if st == _lib.FA_WARN_NOT_CONVERGED and raise_not_converged:
             raise FAError(st, "fa_block_apply")
@@ -276,7 +286,7 @@ class Stencil7(Operator):
         d4 = (C.c_int32 * 4)(nx, ny, nz, 1)
         c7 = (C.c_double * 7)(*[float(c) for c in coeffs])
         st = lib().fa_create_stencil(C.byref(h), _lib.FA_STENCIL7, d4, c7, 7, None,
-                                     FA_HERMITIAN if hermitian else 0, None)
+                                     FA_HERMITIAN if hermitian else 0, None, 0, None)
         check(st, "fa_create_stencil")
         super().__init__(h, torch.device(device), None)
         self.dims = (nx, ny, nz)
@@ -294,11 +304,13 @@ class CSR(Operator):
             va = va.to(torch.float64)
         dt = FA_C128 if va.dtype == torch.complex128 else FA_F64
         n = rp.numel() - 1
+        # operator memory (the library's list of long rows), owned by torch
+        mem, mp, mb = workspace(lib().fa_op_device_bytes(_lib.FA_CSR, None, n, ci.numel()), dev)
         h = C.c_void_p()
         st = lib().fa_create_csr(C.byref(h), n, ci.numel(), _ptr(rp), _ptr(ci), _ptr(va), dt,
-                                 FA_HERMITIAN if hermitian else 0, None)
+                                 FA_HERMITIAN if hermitian else 0, mp, mb, _stream(dev))
         check(st, "fa_create_csr")
-        super().__init__(h, dev, (rp, ci, va))
+        super().__init__(h, dev, (rp, ci, va, mem))
 
 
 class Wilson(Operator):
@@ -316,11 +328,13 @@ class Wilson(Operator):
         h = C.c_void_p()
         d4 = (C.c_int32 * 4)(Lx, Ly, Lz, Lt)
         p = (C.c_double * 1)(float(m0))
+        # operator memory for the library's reordered copy of the links
+        mem, mp, mb = workspace(lib().fa_op_device_bytes(_lib.FA_WILSON4D, d4, 0, 0), dev)
         # the library copies the links (reordered) on this stream and waits
         st = lib().fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1, _ptr(U), 0,
-                                     _stream(dev))
+                                     mp, mb, _stream(dev))
         check(st, "fa_create_stencil")
-        super().__init__(h, dev, ())
+        super().__init__(h, dev, (mem,))
         self.lattice = (Lt, Lz, Ly, Lx)
 
 
@@ -336,9 +350,13 @@ class Server:
     def __init__(self, pool_bytes, n_workers=4, device="cuda"):
         self.device = torch.device(device)
         self._pool, pp, nbytes = workspace(pool_bytes, self.device)
+        # one torch stream (default priority) per worker
+        self._streams = [torch.cuda.Stream(self.device) for _ in range(int(n_workers))]
+        sp = (C.c_void_p * len(self._streams))(*[s.cuda_stream for s in self._streams])
         torch.cuda.synchronize(self.device)
         h = C.c_void_p()
-        check(lib().fa_server_create(C.byref(h), pp, nbytes, int(n_workers)), "fa_server_create")
+        check(lib().fa_server_create(C.byref(h), pp, nbytes, int(n_workers), sp),
+              "fa_server_create")
         self._h = h
         self._live = {}
 

@@ -21,14 +21,14 @@ FA_ERR_UNSUPPORTED = -9
 
 FA_F64, FA_C128 = 0, 1
 FA_INVSQRT, FA_SQRT = 0, 1
-FA_STENCIL7, FA_WILSON4D = 0, 1
+FA_STENCIL7, FA_WILSON4D, FA_CSR = 0, 1, 2
 FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_RITZ, FA_POLY_HARMONIC, FA_POLY_LS = 0, 1, 2, 3, 4
 FA_HERMITIAN, FA_FORCE_ARNOLDI, FA_PROFILE, FA_NO_FUSION, FA_MIXED = 1, 4, 8, 16, 32
 FA_TWO_PASS, FA_RIGHT_PREC, FA_GRAPH, FA_CGS2, FA_FUSE2 = 64, 128, 256, 512, 1024
 FA_FUSE3 = 2048
 
 EXPORTS = [
-    "fa_create_csr", "fa_create_stencil", "fa_set_spectral_interval",
+    "fa_op_device_bytes", "fa_create_csr", "fa_create_stencil", "fa_set_spectral_interval",
     "fa_get_spectral_interval", "fa_poly_workspace_bytes", "fa_poly_setup", "fa_poly_setup_ls",
     "fa_poly_get", "fa_poly_get_ls",
     "fa_workspace_bytes", "fa_apply", "fa_op_apply", "fa_poly_apply", "fa_op_info",
@@ -105,8 +105,10 @@ def lib():
     dp = C.POINTER(C.c_double)
     ip = C.POINTER(C.c_int)
     sig = {
-        "fa_create_csr": (i32, [C.POINTER(vp), i64, i64, vp, vp, vp, i32, u32, vp]),
-        "fa_create_stencil": (i32, [C.POINTER(vp), i32, C.POINTER(C.c_int32), dp, i32, vp, u32, vp]),
+        "fa_op_device_bytes": (sz, [i32, C.POINTER(C.c_int32), i64, i64]),
+        "fa_create_csr": (i32, [C.POINTER(vp), i64, i64, vp, vp, vp, i32, u32, vp, sz, vp]),
+        "fa_create_stencil": (i32, [C.POINTER(vp), i32, C.POINTER(C.c_int32), dp, i32, vp, u32,
+                                    vp, sz, vp]),
         "fa_set_spectral_interval": (i32, [vp, dbl, dbl]),
         "fa_get_spectral_interval": (i32, [vp, dp, dp]),
         "fa_poly_workspace_bytes": (sz, [vp, i32, i32]),
@@ -126,7 +128,7 @@ def lib():
         "fa_block_workspace_bytes": (sz, [vp, i32, i32, u32]),
         "fa_block_apply": (i32, [vp, i32, i32, vp, vp, i32, dbl, i32, vp, sz, u32, vp,
                                  C.POINTER(fa_block_stats)]),
-        "fa_server_create": (i32, [C.POINTER(vp), vp, sz, i32]),
+        "fa_server_create": (i32, [C.POINTER(vp), vp, sz, i32, C.POINTER(vp)]),
         "fa_server_submit": (i32, [vp, vp, i32, vp, vp, i32, dbl, i32, u32,
                                    C.POINTER(C.c_uint64)]),
         "fa_server_poll": (i32, [vp, C.c_uint64, ip]),

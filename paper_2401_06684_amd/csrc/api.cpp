@@ -53,17 +53,37 @@ int guarded(F&& f) {
 
 extern "C" {
 
+size_t fa_op_device_bytes(int kind, const int32_t dims[4], int64_t n, int64_t nnz) {
+  (void)n;
+  (void)nnz;
+  switch (kind) {
+    case FA_STENCIL7:
+      return 0;
+    case FA_CSR:  // the list of long rows, at most kCsrLongMax int32
+      return (size_t)round_up((int64_t)kCsrLongMax * 4, 256);
+    case FA_WILSON4D: {
+      if (!dims) return 0;
+      int64_t V = 1;
+      for (int d = 0; d < 4; ++d) {
+        if (dims[d] < 2) return 0;
+        V *= dims[d];
+      }
+      return (size_t)round_up(V * 4 * 9 * 16, 256);  // whole links (the most kept)
+    }
+    default:
+      return 0;
+  }
+}
+
 int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
                   const int32_t* d_colind, const void* d_vals, int dtype, uint32_t flags,
-                  void* hip_stream) {
-  (void)hip_stream;
+                  void* d_opmem, size_t opmem_bytes, void* hip_stream) {
   if (!out || n < 1 || n >= (int64_t(1) << 31) || nnz < 0 || nnz >= (int64_t(1) << 31) ||
       !d_rowptr || (nnz > 0 && (!d_colind || !d_vals)) || (dtype != FA_F64 && dtype != FA_C128) ||
       (flags & ~uint32_t(FA_HERMITIAN)))
     return FA_ERR_ARG;
   return guarded([&] {
-    fa_op h = new fa_op_s;
-    Op& op = h->op;
+    Op op;
     op.uid = next_op_uid();
     op.kind = OP_CSR;
     op.dtype = dtype;
@@ -79,25 +99,25 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
     int g = 1;
     while (g < 64 && g < avg) g <<= 1;
     op.csr_group = g;
+    // the index arrays may still be in flight on the caller's stream
+    hipStream_t st = stream_of(hip_stream);
+    std::vector<int32_t> rp((size_t)n + 1), ci((size_t)nnz);
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(rp.data(), d_rowptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+            hipSuccess ||
+        (nnz > 0 &&
+         hipMemcpy(ci.data(), d_colind, ci.size() * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+             hipSuccess))
+      return FA_ERR_HIP;
+    // the kernels index with both arrays unchecked: the row pointers must
+    // describe nnz entries in order and every column index must lie in [0, n)
+    if (rp[0] != 0 || rp[(size_t)n] != nnz) return FA_ERR_ARG;
+    for (int64_t r = 0; r < n; ++r)
+      if (rp[r + 1] < rp[r]) return FA_ERR_ARG;
+    for (int64_t e = 0; e < nnz; ++e)
+      if (ci[e] < 0 || ci[e] >= n) return FA_ERR_ARG;
     // rows longer than 16 groups' worth (the tail of a skewed distribution),
     // at most kCsrLongMax of them, go to the one-workgroup-per-row kernel
-    std::vector<int32_t> rp((size_t)n + 1);
-    if (hipMemcpy(rp.data(), d_rowptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost) !=
-        hipSuccess) {
-      delete h;
-      return FA_ERR_HIP;
-    }
-    // the row pointers must describe nnz entries in order (the kernels index
-    // with them unchecked)
-    if (rp[0] != 0 || rp[(size_t)n] != nnz) {
-      delete h;
-      return FA_ERR_ARG;
-    }
-    for (int64_t r = 0; r < n; ++r)
-      if (rp[r + 1] < rp[r]) {
-        delete h;
-        return FA_ERR_ARG;
-      }
     int64_t thr = 16 * (int64_t)g;
     for (;;) {
       std::vector<int32_t> lr;
@@ -110,27 +130,25 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
       }
       thr *= 2;
     }
-    if (!op.csr_long_rows.empty()) {  // the list on the device (op-owned)
+    if (!op.csr_long_rows.empty()) {  // the list in the caller's operator memory
       const size_t bytes = op.csr_long_rows.size() * sizeof(int32_t);
-      void* d = nullptr;
-      if (hipMalloc(&d, bytes) != hipSuccess) {
-        delete h;
+      if (!d_opmem || opmem_bytes < bytes || ((uintptr_t)d_opmem & 255)) return FA_ERR_WORKSPACE;
+      op.csr_long_dev = (const int32_t*)d_opmem;
+      if (hipMemcpyAsync(d_opmem, op.csr_long_rows.data(), bytes, hipMemcpyHostToDevice, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
         return FA_ERR_HIP;
-      }
-      op.csr_long_owned = std::shared_ptr<void>(d, [](void* p) { (void)hipFree(p); });
-      op.csr_long_dev = (const int32_t*)d;
-      if (hipMemcpy(d, op.csr_long_rows.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
-        delete h;
-        return FA_ERR_HIP;
-      }
     }
+    fa_op h = new fa_op_s;
+    h->op = op;
     *out = h;
     return FA_OK;
   });
 }
 
 int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double* params,
-                      int nparams, const void* d_links, uint32_t flags, void* hip_stream) {
+                      int nparams, const void* d_links, uint32_t flags, void* d_opmem,
+                      size_t opmem_bytes, void* hip_stream) {
   if (!out || !dims || !params) return FA_ERR_ARG;
   if (flags & ~uint32_t(FA_HERMITIAN)) return FA_ERR_ARG;
   for (int d = 0; d < 4; ++d)
@@ -173,6 +191,10 @@ int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double*
       // Special unitary links (det 1: row 2 = conj(row 0 x row 1) to within
       // 1e-13) are stored as their first two rows and the kernel rebuilds the
       // third (a third less link traffic); other links are stored whole.
+      // operator memory: at least the two-row copy, checked again below
+      // once the link format is known
+      if (!d_opmem || opmem_bytes < (size_t)V * 4 * 6 * 16 || ((uintptr_t)d_opmem & 255))
+        return FA_ERR_WORKSPACE;
       hipStream_t st = stream_of(hip_stream);
       std::vector<std::complex<double>> hu((size_t)V * 36);
       if (hipStreamSynchronize(st) != hipSuccess ||
@@ -188,12 +210,12 @@ int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double*
       }
       op.links_rows = su3 ? 2 : 3;
       const int ne = 3 * op.links_rows;
-      // own structure-of-arrays copy of the links (coalesced link loads)
-      void* us = nullptr;
-      if (hipMalloc(&us, (size_t)V * 4 * ne * 16) != hipSuccess) return FA_ERR_HIP;
-      op.links_owned = std::shared_ptr<void>(us, [](void* p) { (void)hipFree(p); });
-      op.links = us;
-      if (launch_wilson_links_soa(V, ne, d_links, us, st) != hipSuccess ||
+      // structure-of-arrays copy of the links (coalesced link loads) in the
+      // caller's operator memory
+      const size_t need = (size_t)V * 4 * ne * 16;
+      if (!d_opmem || opmem_bytes < need || ((uintptr_t)d_opmem & 255)) return FA_ERR_WORKSPACE;
+      op.links = d_opmem;
+      if (launch_wilson_links_soa(V, ne, d_links, d_opmem, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess)
         return FA_ERR_HIP;
     } else {

@@ -167,20 +167,6 @@ GraphCache& graphs() {
   return c;
 }
 
-// A private stream per thread for stream capture (the caller's stream may be
-// the null stream, which cannot be captured).
-struct CaptureStream {
-  hipStream_t s = nullptr;
-  ~CaptureStream() {
-    if (s) (void)hipStreamDestroy(s);
-  }
-};
-hipStream_t capture_stream() {
-  thread_local CaptureStream cs;
-  if (!cs.s && hipStreamCreateWithFlags(&cs.s, hipStreamNonBlocking) != hipSuccess) cs.s = nullptr;
-  return cs.s;
-}
-
 }  // namespace
 
 void release_op_graphs(uint64_t uid) {
@@ -212,6 +198,7 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
   const bool mixed = (flags & FA_MIXED) && K > 0;
   const BlkLayout L = blk_layout(op, s, m_max, (flags & FA_MIXED) != 0);
   if (!ws || ws_bytes < L.bytes || ((uintptr_t)ws & 255)) return FA_ERR_WORKSPACE;
+  if ((flags & FA_GRAPH) && !st) return FA_ERR_ARG;  // the null stream cannot be captured
   const int k_chk = check_every > 0 ? check_every : std::max(1, 64 / (K + 1));
   const Prec pc = mixed ? P32 : P64;
   const int64_t n = op.n;
@@ -257,7 +244,7 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
     auto it = tuner().best.find(zc_key);
     if (it != tuner().best.end()) zc = it->second;
   }
-  hipStream_t cur = st;  // the stream the step launches go to (capture: a private one)
+  hipStream_t cur = st;  // the stream the step launches go to (captured with FA_GRAPH)
   auto qblock = [&](const void* x, Prec px, void* out, Prec pout, void* const tmp[4]) -> int {
     const int nT = (int)T.size();
     const void* xm1 = x;
@@ -497,14 +484,11 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
       BLK_HIP(hipGraphLaunch(exec, st));
       return FA_OK;
     }
-    hipStream_t cs = capture_stream();
-    if (!cs) return FA_ERR_HIP;
-    BLK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    cur = cs;
+    // captured on the caller's stream (not the null stream: checked at entry)
+    BLK_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     const int r = do_step(j);
-    cur = st;
     hipGraph_t graph = nullptr;
-    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    const hipError_t e = hipStreamEndCapture(st, &graph);
     if (r) {
       if (graph) (void)hipGraphDestroy(graph);
       return r;

@@ -367,65 +367,68 @@ int real_hess_invsqrt_e1(int m, const double* H, int ldh, double beta, cd* z) {
 
 int tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double beta,
                        double* z) {
-  // eigendecomposition T = Z diag(d) Z^T by implicit QL iterations with
-  // Wilkinson shifts, accumulating the rotations into Z
-  std::vector<double> d(alpha, alpha + m), e(m, 0.0), Z((size_t)m * m, 0.0);
+  // Symmetric QR algorithm: T = Q diag(d) Q^T by implicit single-shift QR
+  // sweeps with the Wilkinson shift on the bottom unreduced block (Golub and
+  // Van Loan, Matrix Computations, Sec. 8.3).  A sweep on rows lo..hi is a
+  // chain of plane rotations P_k (rows k, k+1): the first is chosen from the
+  // shifted first column (d_lo - mu, e_lo), each later one annihilates the
+  // bulge T(k-1, k+1) the previous one created; T <- P_k T P_k^T, Q <- Q P_k^T.
+  std::vector<double> d(alpha, alpha + m), e(std::max(m - 1, 1), 0.0), Q((size_t)m * m, 0.0);
   for (int i = 0; i + 1 < m; ++i) e[i] = offd[i];
-  for (int i = 0; i < m; ++i) Z[(size_t)i * m + i] = 1.0;
-  auto zz = [&](int i, int j) -> double& { return Z[(size_t)j * m + i]; };
-  for (int l = 0; l < m; ++l) {
-    int its = 0;
-    while (true) {
-      int mm = l;
-      for (; mm < m - 1; ++mm) {
-        const double dd = std::fabs(d[mm]) + std::fabs(d[mm + 1]);
-        if (std::fabs(e[mm]) <= kEps * dd) break;
+  for (int i = 0; i < m; ++i) Q[(size_t)i * m + i] = 1.0;
+  auto rotate_cols = [&](int k, double c, double s) {  // Q <- Q P_k^T
+    double* qk = &Q[(size_t)k * m];
+    double* qk1 = &Q[(size_t)(k + 1) * m];
+    for (int i = 0; i < m; ++i) {
+      const double u = qk[i], v = qk1[i];
+      qk[i] = c * u + s * v;
+      qk1[i] = c * v - s * u;
+    }
+  };
+  int hi = m - 1;
+  long sweeps = 0;
+  while (hi > 0) {
+    // negligible couplings split T into independent blocks
+    for (int i = 0; i < hi; ++i)
+      if (std::fabs(e[i]) <= kEps * (std::fabs(d[i]) + std::fabs(d[i + 1]))) e[i] = 0.0;
+    if (e[hi - 1] == 0.0) {  // d[hi] is an eigenvalue
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && e[lo - 1] != 0.0) --lo;
+    if (++sweeps > 40L * m) return DENSE_NOCONV;
+    // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block nearer d[hi]
+    const double t = 0.5 * (d[hi - 1] - d[hi]), eh = e[hi - 1];
+    const double mu = d[hi] - eh * eh / (t + (t >= 0.0 ? 1.0 : -1.0) * std::hypot(t, eh));
+    double x = d[lo] - mu, y = e[lo];  // the vector the next rotation acts on
+    for (int k = lo; k < hi; ++k) {
+      const double r = std::hypot(x, y);
+      const double c = r == 0.0 ? 1.0 : x / r, s = r == 0.0 ? 0.0 : y / r;
+      if (k > lo) e[k - 1] = r;  // the bulge T(k-1, k+1) is now zero
+      // the 2 x 2 block on rows and columns k, k+1
+      const double a = d[k], bb = d[k + 1], f = e[k];
+      const double cs = c * s, cc = c * c, ss = s * s;
+      d[k] = cc * a + 2.0 * cs * f + ss * bb;
+      d[k + 1] = ss * a - 2.0 * cs * f + cc * bb;
+      e[k] = cs * (bb - a) + (cc - ss) * f;
+      rotate_cols(k, c, s);
+      if (k + 1 < hi) {  // the coupling to row k + 2 moves the bulge down
+        x = e[k];
+        y = s * e[k + 1];
+        e[k + 1] *= c;
       }
-      if (mm == l) break;
-      if (++its > 100) return DENSE_NOCONV;
-      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = std::hypot(g, 1.0);
-      g = d[mm] - d[l] + e[l] / (g + std::copysign(r, g));
-      double s = 1.0, c = 1.0, p = 0.0;
-      int i = mm - 1;
-      bool early = false;
-      for (; i >= l; --i) {
-        const double f = s * e[i], b = c * e[i];
-        r = std::hypot(f, g);
-        e[i + 1] = r;
-        if (r == 0.0) {
-          d[i + 1] -= p;
-          e[mm] = 0.0;
-          early = true;
-          break;
-        }
-        s = f / r;
-        c = g / r;
-        g = d[i + 1] - p;
-        r = (d[i] - g) * s + 2.0 * c * b;
-        p = s * r;
-        d[i + 1] = g + p;
-        g = c * r - b;
-        for (int k = 0; k < m; ++k) {
-          const double t = zz(k, i + 1);
-          zz(k, i + 1) = s * zz(k, i) + c * t;
-          zz(k, i) = c * zz(k, i) - s * t;
-        }
-      }
-      if (early) continue;
-      d[l] -= p;
-      e[l] = g;
-      e[mm] = 0.0;
     }
   }
   for (int k = 0; k < m; ++k)
     if (!(d[k] > 0.0)) return DENSE_BRANCH;
+  // z = Q diag(d)^{-1/2} Q^T (beta e_1); row 0 of Q is Q^T e_1
   std::vector<double> w(m);
-  for (int k = 0; k < m; ++k) w[k] = zz(0, k) * beta / std::sqrt(d[k]);
+  for (int k = 0; k < m; ++k) w[k] = Q[(size_t)k * m] * beta / std::sqrt(d[k]);
   for (int i = 0; i < m; ++i) {
-    double s = 0.0;
-    for (int k = 0; k < m; ++k) s += zz(i, k) * w[k];
-    z[i] = s;
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) acc += Q[(size_t)k * m + i] * w[k];
+    z[i] = acc;
   }
   return DENSE_OK;
 }

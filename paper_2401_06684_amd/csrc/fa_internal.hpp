@@ -61,15 +61,13 @@ struct Op {
   // left to a kernel with one 1024-thread workgroup per row
   int csr_long_thr = 0x7fffffff;
   std::vector<int32_t> csr_long_rows;
-  const int32_t* csr_long_dev = nullptr;  // the same list in device memory
-  std::shared_ptr<void> csr_long_owned;
+  const int32_t* csr_long_dev = nullptr;  // the same list in the caller's operator memory
   // stencil
   int dims[4] = {1, 1, 1, 1};
   double coef[7] = {0, 0, 0, 0, 0, 0, 0};
   // Wilson: the links in the structure-of-arrays order Us[mu][e][s] (e the
-  // row-major 3x3 element), in device memory this op owns (shared by copies)
+  // row-major 3x3 element), in the caller's operator memory
   const void* links = nullptr;
-  std::shared_ptr<void> links_owned;
   int links_rows = 3;  // rows of each link stored (2: special unitary, row 2 rebuilt)
   double m0 = 0.0;
   // spectral interval

@@ -172,9 +172,10 @@ struct fa_server_s {
 
 extern "C" {
 
-int fa_server_create(fa_server* out, void* d_pool, size_t pool_bytes, int n_workers) {
+int fa_server_create(fa_server* out, void* d_pool, size_t pool_bytes, int n_workers,
+                     void* const* hip_streams) {
   if (!out || !d_pool || ((uintptr_t)d_pool & 255) || pool_bytes < 256 || n_workers < 1 ||
-      n_workers > 64)
+      n_workers > 64 || !hip_streams)
     return FA_ERR_ARG;
   fa_server_s* srv = new (std::nothrow) fa_server_s;
   if (!srv) return FA_ERR_ARG;
@@ -184,15 +185,7 @@ int fa_server_create(fa_server* out, void* d_pool, size_t pool_bytes, int n_work
   }
   srv->pool_base = (char*)d_pool;
   srv->pool.init(pool_bytes & ~size_t(255));
-  for (int w = 0; w < n_workers; ++w) {
-    hipStream_t s;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-      for (hipStream_t t : srv->streams) (void)hipStreamDestroy(t);
-      delete srv;
-      return FA_ERR_HIP;
-    }
-    srv->streams.push_back(s);
-  }
+  for (int w = 0; w < n_workers; ++w) srv->streams.push_back((hipStream_t)hip_streams[w]);
   try {
     for (int w = 0; w < n_workers; ++w) srv->workers.emplace_back([srv, w] { srv->worker(w); });
   } catch (...) {
@@ -202,7 +195,6 @@ int fa_server_create(fa_server* out, void* d_pool, size_t pool_bytes, int n_work
     }
     srv->cv_work.notify_all();
     for (auto& t : srv->workers) t.join();
-    for (hipStream_t t : srv->streams) (void)hipStreamDestroy(t);
     delete srv;
     return FA_ERR_ARG;
   }
@@ -291,7 +283,6 @@ int fa_server_destroy(fa_server srv) {
   }
   srv->cv_work.notify_all();
   for (auto& t : srv->workers) t.join();  // the queue drains first
-  for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
   delete srv;
   return FA_OK;
 }

@@ -42,7 +42,8 @@ def _stencil(dims, coeffs, flags=0):
     h = C.c_void_p()
     d4 = (C.c_int32 * 4)(*dims, 1)
     c7 = (C.c_double * 7)(*coeffs)
-    st = L.fa_create_stencil(C.byref(h), _lib.FA_STENCIL7, d4, c7, 7, None, flags, None)
+    st = L.fa_create_stencil(C.byref(h), _lib.FA_STENCIL7, d4, c7, 7, None, flags, None, 0,
+                             None)
     return st, h
 
 
@@ -60,23 +61,49 @@ def test_create_stencil_validation():
 
 
 def test_create_wilson_validation_and_link_copy_without_gpu():
-    """The Wilson op copies its links into device memory it owns at
-    creation: argument errors come first, then, without a GPU, the copy's
-    failure is reported (nothing is created)."""
+    """The Wilson op copies its links into caller operator memory at
+    creation: argument and memory errors come first, then, without a GPU, the
+    copy's failure is reported (nothing is created)."""
     L = _lib.lib()
     h = C.c_void_p()
     p = (C.c_double * 1)(0.05)
     d4 = (C.c_int32 * 4)(4, 4, 4, 4)
+    mem = C.c_void_p(1 << 20)
+    nb = L.fa_op_device_bytes(_lib.FA_WILSON4D, d4, 0, 0)
     # missing links, lattice extent below 2, Hermitian flag: argument errors
     assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1, None, 0,
-                               None) == _lib.FA_ERR_ARG
+                               mem, nb, None) == _lib.FA_ERR_ARG
     d_bad = (C.c_int32 * 4)(4, 1, 4, 4)
     assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d_bad, p, 1, C.c_void_p(256), 0,
-                               None) == _lib.FA_ERR_ARG
+                               mem, nb, None) == _lib.FA_ERR_ARG
     assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1, C.c_void_p(256),
-                               _lib.FA_HERMITIAN, None) == _lib.FA_ERR_ARG
+                               _lib.FA_HERMITIAN, mem, nb, None) == _lib.FA_ERR_ARG
+    # operator memory missing, too small for the two-row links, misaligned
+    V = 4 ** 4
+    for m, b in ((None, nb), (mem, 4 * 6 * 16 * V - 256), (C.c_void_p((1 << 20) + 8), nb)):
+        assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1, C.c_void_p(256), 0,
+                                   m, b, None) == _lib.FA_ERR_WORKSPACE
     assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1, C.c_void_p(256), 0,
-                               None) == _lib.FA_ERR_HIP
+                               mem, nb, None) == _lib.FA_ERR_HIP
+
+
+def test_operator_memory_query():
+    """fa_op_device_bytes: the caller-provided device memory of each operator
+    kind (the library itself allocates none)."""
+    L = _lib.lib()
+    d4 = (C.c_int32 * 4)(16, 16, 16, 16)
+    V = 16 ** 4
+    # Wilson: whole links in the kernels' order, 4 directions x 9 complex per site
+    assert L.fa_op_device_bytes(_lib.FA_WILSON4D, d4, 0, 0) == 4 * 9 * 16 * V
+    d_odd = (C.c_int32 * 4)(3, 5, 7, 2)
+    assert L.fa_op_device_bytes(_lib.FA_WILSON4D, d_odd, 0, 0) == \
+        -(-4 * 9 * 16 * 210 // 256) * 256
+    assert L.fa_op_device_bytes(_lib.FA_WILSON4D, (C.c_int32 * 4)(4, 1, 4, 4), 0, 0) == 0
+    assert L.fa_op_device_bytes(_lib.FA_WILSON4D, None, 0, 0) == 0
+    # CSR: the list of at most 900 long rows (int32), 256-byte rounded
+    assert L.fa_op_device_bytes(_lib.FA_CSR, None, 281903, 2594228) == 3840
+    assert L.fa_op_device_bytes(_lib.FA_STENCIL7, (C.c_int32 * 4)(8, 8, 8, 1), 0, 0) == 0
+    assert L.fa_op_device_bytes(7, d4, 0, 0) == 0
 
 
 @pytest.mark.parametrize("coeffs,dims", [
@@ -141,7 +168,7 @@ def test_setup_and_apply_argument_errors_without_gpu():
     # GPU that copy fails and creation reports it
     h2 = C.c_void_p()
     assert L.fa_create_csr(C.byref(h2), 4, 4, C.c_void_p(256), C.c_void_p(512),
-                           C.c_void_p(768), 0, 0, None) == _lib.FA_ERR_HIP
+                           C.c_void_p(768), 0, 0, None, 0, None) == _lib.FA_ERR_HIP
     # Chebyshev without an interval: a stencil whose x pair has a negative
     # product (complex spectrum) gets none until it is set
     st, h2 = _stencil((4, 4, 4), [6.0, -1.0, 1.0, -1.0, -1.0, -1.0, -1.0])
@@ -221,6 +248,19 @@ def test_dense_tridiag_matches_oracle():
         b = 0.7 * rng.random(m - 1)
         ref = kr.tridiagonal_invsqrt_e1(a, b, 1.5)
         assert np.allclose(fa.dense_tridiag_invsqrt_e1(a, b, 1.5), ref, rtol=1e-11)
+    # Toeplitz (equal diagonals: the shift meets ties), glued blocks with
+    # negligible couplings (the deflation path), graded entries
+    m = 300
+    cases = [(np.full(m, 2.05), -np.ones(m - 1))]
+    b = 0.5 * rng.random(m - 1)
+    b[[40, 41, 150, 151, 152]] = [1e-18, 0.0, 1e-17, 3e-19, 0.0]
+    cases.append((1.0 + rng.random(m), b))
+    g = np.logspace(0, -6, 80)
+    cases.append((g + 1e-3, 0.3 * np.sqrt(g[:-1] * g[1:])))
+    for a, b in cases:
+        ref = kr.tridiagonal_invsqrt_e1(a, b, 1.5)
+        z = fa.dense_tridiag_invsqrt_e1(a, b, 1.5)
+        assert np.linalg.norm(z - ref) <= 1e-11 * np.linalg.norm(ref)
     with pytest.raises(fa.FAError):
         fa.dense_tridiag_invsqrt_e1(np.array([1.0, -2.0]), np.array([0.1]), 1.0)
 

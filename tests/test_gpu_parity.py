@@ -111,8 +111,12 @@ def test_wilson_links_copied_at_creation():
     h = C.c_void_p()
     d4 = (C.c_int32 * 4)(Lx, Ly, Lz, Lt)
     p = (C.c_double * 1)(0.05)
+    nb = _lib.lib().fa_op_device_bytes(_lib.FA_WILSON4D, d4, 0, 0)
+    mem = torch.empty(nb, dtype=torch.uint8, device=DEV)  # torch-owned operator memory
+    assert mem.data_ptr() % 256 == 0
     st = _lib.lib().fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1,
-                                      C.c_void_p(dU.data_ptr()), 0, None)
+                                      C.c_void_p(dU.data_ptr()), 0,
+                                      C.c_void_p(mem.data_ptr()), nb, None)
     assert st == 0
     dU.fill_(float("nan"))  # the caller's array changes ...
     torch.cuda.synchronize()

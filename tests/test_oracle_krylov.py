@@ -328,3 +328,66 @@ def test_two_pass_lanczos_equals_one_pass(degree):
     # pass 2 repeats c = q(A) b and m - 1 steps of the three-stage product
     assert two.mvms == 2 * one.mvms - (2 * degree + 1)
     assert rel(two.x, exact.stencil_fAb_dst(coeffs, dims, b)) < 1e-9
+
+
+# --------------------------------------------------------------------------
+# the stopping estimate against the iterates it stands for
+# --------------------------------------------------------------------------
+def _fixed_m_iterates(run, checkpoints):
+    """f_j for each checkpoint j from separate runs that stop at exactly j
+    steps (tol <= 0): the returned x, formed by the method's final combination
+    (V_j z_j, Y_j z_j, or the second Lanczos pass), not by the check's
+    coefficient-vector arithmetic."""
+    return {j: run(j) for j in checkpoints}
+
+
+@pytest.mark.parametrize("variant", ["left", "right", "two_pass", "left_complex"])
+def test_stopping_estimate_equals_relative_change_of_iterates(variant):
+    """Sec. 3.1 and Sec. 6: at checkpoint j (a multiple of k, and m_max) the
+    estimate is ||f_j - f_{j-k}|| / ||f_j||, the first checkpoint comparing with
+    f_0 = 0 (estimate 1).  Each recorded estimate is recomputed here from two
+    explicitly formed n-vectors, the iterates of runs fixed at j and j - k
+    steps.  Comparing with the wrong checkpoint, normalising by the older
+    iterate, dropping the zero padding of z_{j-k} or (right variant) using
+    ||z_j - z_{j-k}|| although Y is not orthonormal, all fail it."""
+    k, m_max = 3, 11
+    if variant in ("left", "right"):
+        N = 9
+        dims = (N, N, N)
+        coeffs = wl.convdiff_stencil(N, 50.0)  # non-normal: Y far from orthonormal
+        A = stencil_problem(coeffs, dims)
+        a, bb = ops.stencil_interval(coeffs, dims)
+        q = pl.chebyshev(a, bb, 2)
+        b = wl.rhs(N ** 3, seed=3)
+        kw = dict(orth="cgs2", side=variant)
+    elif variant == "two_pass":
+        N = 9
+        dims = (N, N, N)
+        coeffs = wl.laplace_stencil(3)
+        A = stencil_problem(coeffs, dims)
+        a, bb = ops.stencil_interval(coeffs, dims)
+        q = pl.chebyshev(a, bb, 1)
+        b = wl.rhs(N ** 3, seed=3)
+        kw = dict(orth="lanczos", two_pass=True)
+    else:
+        L = (2, 2, 2, 4)
+        U = wl.random_su3(4 * int(np.prod(L)), 0.3, np.random.default_rng(5))
+        U = U.reshape(4, L[3], L[2], L[1], L[0], 3, 3)
+        A = lambda v: ops.wilson_apply(U, 0.4, v)  # noqa: E731
+        b = wl.rhs(12 * int(np.prod(L)), seed=3, complex_=True)
+        q = None
+        kw = dict(orth="cgs2", side="left")
+    run = kr.fAb(A, b, q, "invsqrt", m_max=m_max, tol=1e-300, check_every=k, **kw)
+    assert not run.converged and run.iters == m_max
+    cps = [j for j, _ in run.history]
+    assert cps == [3, 6, 9, 11]          # multiples of k, then m_max
+    xs = _fixed_m_iterates(
+        lambda j: kr.fAb(A, b, q, "invsqrt", m_max=j, tol=0.0, **kw).x, cps)
+    prev = np.zeros_like(b, dtype=np.result_type(b, 1.0))
+    for j, est in run.history:
+        ref = float(np.linalg.norm(xs[j] - prev) / np.linalg.norm(xs[j]))
+        assert abs(est - ref) <= 1e-9 * ref + 1e-13, (j, est, ref)
+        prev = xs[j]
+    assert run.history[0][1] == 1.0
+    # the estimate falls as the iterates converge (so the pin is not vacuous)
+    assert run.history[-1][1] < 0.1 * run.history[1][1]
