@@ -304,3 +304,34 @@ def test_bench_refuses_more_than_one_gpu():
         assert r.returncode == 2
         assert "one GPU" in r.stderr
         assert r.stdout == ""
+
+
+def test_bench_oracle_leg_on_a_small_grid():
+    """bench.py's oracle leg (the only bench code that calls the oracle): the
+    references, the timed median of 3 whole solves with setup and host f(H)
+    apart, and the 2D Poisson leg, on a 10^3 grid (CPU only)."""
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    N = 10
+    dims = (N, N, N)
+    coeffs = wl.convdiff_stencil(N, 10.0)
+    out = bench.cpu_baseline(coeffs, dims, 4, 1e-8)
+    from oracle import exact
+    b = wl.rhs(N ** 3, seed=0)
+    xs = exact.stencil_fAb_dst(coeffs, dims, b, "invsqrt")
+    assert np.linalg.norm(out["x_ref_invsqrt"] - xs) <= 1e-10 * np.linalg.norm(xs)
+    xq = exact.stencil_fAb_dst(coeffs, dims, b, "sqrt")
+    assert np.linalg.norm(out["x_ref_sqrt"] - xq) <= 1e-9 * np.linalg.norm(xq)
+    assert out["kind"] == "oracle" and out["unit"] == "solves/s" and out["cores"] >= 1
+    assert len(out["runs_s"]) == 3 and out["value"] == 1.0 / out["s_per_solve_median"]
+    assert 0.0 <= out["s_setup"] < out["s_per_solve_median"]
+    assert 0.0 < out["s_host_fH"] < out["s_per_solve_median"]
+    assert out["rel_err_vs_ref"] < 1e-7
+    for deg in (0, 8):
+        assert out["poisson2d_32"][f"degree_{deg}"]["s_per_solve"] > 0
+        r = out["poisson2d_32_ref"][deg]
+        x2 = exact.stencil_fAb_dst(wl.laplace_stencil(2), (32, 32, 1), wl.rhs(1024, seed=0))
+        assert np.linalg.norm(r - x2) <= 1e-10 * np.linalg.norm(x2)

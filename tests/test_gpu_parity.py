@@ -5,7 +5,9 @@ relative; q(A) x 1e-12; whole solves 1e-10 (the bar for all-FP64 results),
 both at a fixed Krylov dimension and at convergence.  Comparisons are element
 by element (max-norm relative to the reference's max-norm) and in 2-norm.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -17,6 +19,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -30,6 +33,15 @@ def _need_gpu():
 def fa():
     import paper_2401_06684_amd as m
     return m
+
+
+def exported_newton_poly(op, real_operator):
+    """The oracle's Newton-form polynomial on the nodes, coefficients and
+    scaling the GPU exported (fa_poly_get), so that an oracle evaluation with
+    it isolates the chain and the solve from the setup's rounding."""
+    p = op.poly()
+    return pl.Poly(kind="newton", degree=p["degree"], theta=np.array(p["theta"]),
+                   eta=np.array(p["eta"]), rho=p["rho"], real_operator=real_operator)
 
 
 def dev(x):
@@ -165,8 +177,12 @@ def test_ritz_setup_and_chain_wilson():
     assert np.max(np.abs(gt - rt)) <= 1e-9 * np.max(np.abs(rt))
     x = wl.rhs(op.n, seed=12, complex_=True)
     y = host(op.poly_apply(dev(x)))
+    # against the oracle's own setup: the nodes differ by setup rounding
     ref, _ = q.apply(apply_A, x)
     assert_close(y, ref, 1e-8)
+    # against the oracle's Horner recurrence on the exported nodes
+    ref, _ = exported_newton_poly(op, False).apply(apply_A, x)
+    assert_close(y, ref, 1e-12)
 
 
 # --------------------------------------------------------------------------
@@ -187,6 +203,38 @@ def test_convdiff_fixed_m(degree, m, kind):
     assert st["iters"] == ref.iters == m
     assert st["mvms"] == ref.mvms
     assert_close(host(x), ref.x, 1e-10)
+
+
+@pytest.mark.parametrize("degree", [0, 4])
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+def test_cgs2_every_step_against_oracle(degree, kind):
+    """orth="cgs2" (FA_CGS2): both classical Gram-Schmidt passes in every
+    Arnoldi step, the oracle's own scheme, on the non-normal Pe = 50 stencil
+    (ragged tiles): fixed m (same iterate, products with A and inner products)
+    and at convergence with both sides at tol 1e-12; the delayed scheme (the
+    default) gives the same result."""
+    dims = (21, 18, 13)
+    coeffs = wl.convdiff_stencil(21, 50.0)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(degree, "cheb")
+    a, bb = ops.stencil_interval(coeffs, dims)
+    q = pl.chebyshev(a, bb, degree)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)  # noqa: E731
+    b = wl.rhs(op.n, seed=0)
+    m = 30 if degree == 0 else 12
+    x, st = op.apply(dev(b), kind=kind, m_max=m, tol=0.0, orth="cgs2")
+    ref = kr.fAb(A, b, q, kind, m_max=m, tol=0.0, orth="cgs2")
+    assert st["iters"] == ref.iters == m
+    assert st["mvms"] == ref.mvms and st["inner_products"] == ref.inner_products
+    assert_close(host(x), ref.x, 1e-10)
+    x, st = op.apply(dev(b), kind=kind, m_max=300, tol=1e-12, orth="cgs2")
+    ref = kr.fAb(A, b, q, kind, m_max=300, tol=1e-12, orth="cgs2")
+    assert st["converged"] == 1 and st["iters"] == ref.iters
+    assert st["mvms"] == ref.mvms and st["inner_products"] == ref.inner_products
+    assert_close(host(x), ref.x, 1e-10)
+    xd, sd = op.apply(dev(b), kind=kind, m_max=300, tol=1e-12)
+    assert sd["iters"] == st["iters"]
+    assert_close(host(xd), host(x), 1e-10)
 
 
 @pytest.mark.parametrize("degree", [0, 4, 16])
@@ -242,7 +290,10 @@ def test_check_overlap_leaves_no_trace(hermitian, check_every, kind):
 
 @pytest.mark.parametrize("degree", [0, 8])
 def test_poisson2d_32_lanczos(degree):
-    """2D Poisson 32x32, CSR, Hermitian: Lanczos, tol 1e-10, m_max 200."""
+    """2D Poisson 32x32, CSR, Hermitian: Lanczos, m_max 200.  Compared at
+    convergence (plain Lanczos loses orthogonality, so fixed-m iterates are
+    rounding-sensitive): both sides at tol 1e-12, agreement to 1e-10 with the
+    oracle and with the DST closed form."""
     N = 32
     coeffs = wl.laplace_stencil(2)
     rp, ci, va = wl.stencil_csr((N, N, 1), coeffs)
@@ -251,14 +302,17 @@ def test_poisson2d_32_lanczos(degree):
     op.set_spectral_interval(lo, hi)
     op.poly_setup(degree, "cheb")
     b = wl.rhs(N * N, seed=0)
-    x, st = op.apply(dev(b), kind="invsqrt", m_max=200, tol=1e-10)
-    assert st["converged"] == 1
+    x, st = op.apply(dev(b), kind="invsqrt", m_max=200, tol=1e-12)
     assert st["inner_products"] == 2 * st["iters"]
     orc = kr.fAb(lambda v: ops.csr_apply(rp, ci, va, v), b, pl.chebyshev(lo, hi, degree),
-                 "invsqrt", m_max=200, tol=1e-10, orth="lanczos")
-    assert st["iters"] == orc.iters
-    assert_close(host(x), orc.x, 1e-9)
-    assert_close(host(x), exact.stencil_fAb_dst(coeffs, (N, N, 1), b), 1e-9)
+                 "invsqrt", m_max=200, tol=1e-12, orth="lanczos")
+    assert st["iters"] == orc.iters and st["converged"] == orc.converged
+    assert_close(host(x), orc.x, 1e-10)
+    assert_close(host(x), exact.stencil_fAb_dst(coeffs, (N, N, 1), b), 1e-10)
+    # the configuration's own tolerance 1e-10: the error is below it
+    x10, st10 = op.apply(dev(b), kind="invsqrt", m_max=200, tol=1e-10)
+    assert st10["converged"] == 1
+    assert_close(host(x10), exact.stencil_fAb_dst(coeffs, (N, N, 1), b), 1e-10)
 
 
 @pytest.mark.parametrize("degree", [0, 8])
@@ -323,6 +377,42 @@ def test_lucky_breakdown_diagonal():
         x, st = op.apply(dev(b), kind=kind, m_max=50, tol=1e-12, check_every=5)
         assert st["breakdown"] == 1 and st["iters"] == 4
         assert_close(host(x), f * b, 1e-12)
+
+
+def test_csr_creation_rejects_bad_indices():
+    """fa_create_csr reads the index arrays to the host and refuses row
+    pointers out of order and column indices outside [0, n) (the kernels
+    index with them unchecked), before any kernel runs."""
+    import ctypes as C
+    from paper_2401_06684_amd import _lib
+    rp, ci, va = wl.stencil_csr((8, 8, 1), wl.laplace_stencil(2))
+    n, nnz = len(rp) - 1, len(ci)
+    L = _lib.lib()
+    mem = torch.empty(L.fa_op_device_bytes(_lib.FA_CSR, None, n, nnz), dtype=torch.uint8,
+                      device=DEV)
+    for bad in ("col_high", "col_neg", "rowptr"):
+        r, c = rp.copy(), ci.copy()
+        if bad == "col_high":
+            c[nnz // 2] = n
+        elif bad == "col_neg":
+            c[3] = -1
+        else:
+            r[5], r[6] = r[6], r[5]
+        dr = torch.from_numpy(r.astype(np.int32)).to(DEV)
+        dc = torch.from_numpy(c.astype(np.int32)).to(DEV)
+        dv = dev(va)
+        h = C.c_void_p()
+        st = L.fa_create_csr(C.byref(h), n, nnz, C.c_void_p(dr.data_ptr()),
+                             C.c_void_p(dc.data_ptr()), C.c_void_p(dv.data_ptr()), 0, 0,
+                             C.c_void_p(mem.data_ptr()), mem.numel(),
+                             C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert st == _lib.FA_ERR_ARG, bad
+    # the valid matrix is accepted
+    with pytest.raises(fa().FAError):
+        fa().CSR(rp, np.where(np.arange(nnz) == 7, n + 3, ci), va)
+    op = fa().CSR(rp, ci, va)
+    x = wl.rhs(n, seed=1)
+    assert_close(host(op.op_apply(dev(x))), ops.csr_apply(rp, ci, va, x), 1e-14)
 
 
 def test_branch_and_hessenberg_errors():
@@ -434,15 +524,117 @@ def test_convdiff_128_full_size():
     assert_close(host(x32), host(xi), 1e-8)
 
 
+@pytest.fixture(scope="module")
+def convdiff128():
+    N = 128
+    coeffs = wl.convdiff_stencil(N, 50.0)
+    with open(os.path.join(GOLDEN, "convdiff128_reference.json")) as f:
+        ref = json.load(f)
+    assert ref["N"] == N and ref["Pe"] == 50.0 and ref["rhs_seed"] == 0
+    op = fa().Stencil7((N, N, N), coeffs)
+    return op, dev(wl.rhs(N ** 3, seed=0)), ref
+
+
+def against_sampled_reference(x, ref):
+    """Relative errors of x against a sampled oracle reference: the largest
+    sampled entry error over the largest sampled entry, the root-mean-square
+    sampled error scaled to the 2-norm (an estimate of ||x - x*|| / ||x*||),
+    and the difference of the 2-norms."""
+    idx = torch.as_tensor(ref["indices"], device=x.device)
+    xs = x[idx].cpu().numpy()
+    rv = np.array(ref["values"])
+    d = xs - rv
+    n = x.numel()
+    e_inf = float(np.max(np.abs(d)) / np.max(np.abs(rv)))
+    e_rms = float(math.sqrt(n / len(rv) * float(d @ d)) / ref["norm2"])
+    e_norm = abs(float(torch.linalg.vector_norm(x).item()) - ref["norm2"]) / ref["norm2"]
+    return e_inf, e_rms, e_norm
+
+
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+@pytest.mark.parametrize("degree", [0, 4, 16, 32])
+def test_convdiff_128_every_degree_against_oracle_reference(convdiff128, degree, kind):
+    """The 128^3 configuration at its own settings (Chebyshev degrees 0, 4,
+    16, 32; A^{-1/2} b and A^{1/2} b; tol 1e-8): each result within 1e-8 of the
+    oracle's tol-1e-12 solve (stored at 2048 sampled entries with its 2-norm
+    by tests/golden/make_convdiff128_reference.py; Sec. 6 measures errors
+    against a reference solution)."""
+    op, bd, ref = convdiff128
+    op.poly_setup(degree, "cheb")
+    m_max = 600 if degree == 0 else 200
+    x, st = op.apply(bd, kind=kind, m_max=m_max, tol=1e-8)
+    assert st["converged"] == 1
+    e_inf, e_rms, e_norm = against_sampled_reference(x, ref[kind])
+    assert e_inf <= 1e-8 and e_rms <= 1e-8 and e_norm <= 1e-8, (e_inf, e_rms, e_norm)
+
+
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+def test_convdiff_128_tight_solve_against_oracle_reference(convdiff128, kind):
+    """Both sides at tol 1e-12 with the same degree (32): agreement to 1e-10."""
+    op, bd, ref = convdiff128
+    op.poly_setup(ref["degree"], "cheb")
+    x, st = op.apply(bd, kind=kind, m_max=60, tol=ref["tol"])
+    # checks every step (k = 64 / 33 = 1): an estimate within rounding of
+    # 1e-12 may stop one side a step apart
+    assert st["converged"] == 1 and abs(st["iters"] - ref[kind]["iters"]) <= 1
+    e_inf, e_rms, e_norm = against_sampled_reference(x, ref[kind])
+    assert e_inf <= 1e-10 and e_rms <= 1e-10 and e_norm <= 1e-10, (e_inf, e_rms, e_norm)
+
+
 # --------------------------------------------------------------------------
 # the 16^4 Wilson-like workload at full size
 # --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def wilson16():
+    """The 16^4 lattice of the configuration: links exp(0.3 i H), m0 = 0.05."""
+    L = 16
+    U = wl.su3_links(L, eps=0.3, seed=1)
+    m0 = 0.05
+    return U, m0, fa().Wilson(U, m0)
+
+
+def test_wilson_16_ritz_setup_and_chain_against_oracle(wilson16):
+    """Full 16^4 size, Ritz degree 16 (Sec. 5.2): the GPU's setup (17 Arnoldi
+    steps, Leja order, scaled Newton coefficients) against the oracle's, and
+    q(A) x against the oracle's Horner recurrence on the exported nodes."""
+    U, m0, op = wilson16
+    start = wl.rhs(op.n, seed=11, complex_=True)
+    op.poly_setup(16, "ritz", start=dev(start))
+    apply_A = lambda v: ops.wilson_apply(U, m0, v)  # noqa: E731
+    q = pl.ritz(apply_A, start, 16, real_operator=False)
+    p = op.poly()
+    key = lambda z: (round(z.real, 6), round(z.imag, 6))  # noqa: E731
+    gt = np.array(sorted(p["theta"], key=key))
+    rt = np.array(sorted(q.theta, key=key))
+    assert p["degree"] == q.degree == 16
+    assert np.max(np.abs(gt - rt)) <= 1e-9 * np.max(np.abs(rt))
+    x = wl.rhs(op.n, seed=12, complex_=True)
+    y = host(op.poly_apply(dev(x)))
+    ref, nmv = exported_newton_poly(op, False).apply(apply_A, x)
+    assert nmv == 16
+    assert_close(y, ref, 1e-12)
+
+
+def test_wilson_16_fixed_m_solve_against_oracle(wilson16):
+    """Full 16^4 size, Ritz degree 16, Algorithm 1 at a fixed Krylov
+    dimension m = 2 (c = q(A) b, then two steps of q(A) q(A) A: 82 products
+    with A on the host) against the oracle with the exported polynomial."""
+    U, m0, op = wilson16
+    op.poly_setup(16, "ritz", start=dev(wl.rhs(op.n, seed=11, complex_=True)))
+    b = wl.rhs(op.n, seed=0, complex_=True)
+    x, st = op.apply(dev(b), kind="invsqrt", m_max=2, tol=0.0)
+    apply_A = lambda v: ops.wilson_apply(U, m0, v)  # noqa: E731
+    ref = kr.fAb(apply_A, b, exported_newton_poly(op, False), "invsqrt", m_max=2, tol=0.0)
+    assert st["iters"] == ref.iters == 2 and st["mvms"] == ref.mvms == 16 + 2 * 33
+    assert_close(host(x), ref.x, 1e-10)
+
+
 def test_wilson_16_full_size():
     """16^4 lattice, links exp(0.3 i H), m0 = 0.05, Ritz degree 16, tol 1e-8.
 
-    At this size the oracle is too slow for a whole solve; the checks are
-    properties that hold at any size: agreement with the plain method and
-    with another degree, and A^{1/2} (A^{-1/2} b) = b."""
+    Converged solves on the full lattice (the oracle pins the setup, the
+    chain and a fixed-m solve at this size above): properties that hold at
+    any size, agreement with another degree and A^{1/2} (A^{-1/2} b) = b."""
     L = 16
     U = wl.su3_links(L, eps=0.3, seed=1)
     m0 = 0.05
