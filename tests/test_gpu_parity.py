@@ -535,13 +535,14 @@ def convdiff128():
     return op, dev(wl.rhs(N ** 3, seed=0)), ref
 
 
-def against_sampled_reference(x, ref):
+def against_sampled_reference(x, ref, kind):
     """Relative errors of x against a sampled oracle reference: the largest
     sampled entry error over the largest sampled entry, the root-mean-square
     sampled error scaled to the 2-norm (an estimate of ||x - x*|| / ||x*||),
     and the difference of the 2-norms."""
     idx = torch.as_tensor(ref["indices"], device=x.device)
     xs = x[idx].cpu().numpy()
+    ref = ref[kind]
     rv = np.array(ref["values"])
     d = xs - rv
     n = x.numel()
@@ -564,7 +565,7 @@ def test_convdiff_128_every_degree_against_oracle_reference(convdiff128, degree,
     m_max = 600 if degree == 0 else 200
     x, st = op.apply(bd, kind=kind, m_max=m_max, tol=1e-8)
     assert st["converged"] == 1
-    e_inf, e_rms, e_norm = against_sampled_reference(x, ref[kind])
+    e_inf, e_rms, e_norm = against_sampled_reference(x, ref, kind)
     assert e_inf <= 1e-8 and e_rms <= 1e-8 and e_norm <= 1e-8, (e_inf, e_rms, e_norm)
 
 
@@ -577,7 +578,7 @@ def test_convdiff_128_tight_solve_against_oracle_reference(convdiff128, kind):
     # checks every step (k = 64 / 33 = 1): an estimate within rounding of
     # 1e-12 may stop one side a step apart
     assert st["converged"] == 1 and abs(st["iters"] - ref[kind]["iters"]) <= 1
-    e_inf, e_rms, e_norm = against_sampled_reference(x, ref[kind])
+    e_inf, e_rms, e_norm = against_sampled_reference(x, ref, kind)
     assert e_inf <= 1e-10 and e_rms <= 1e-10 and e_norm <= 1e-10, (e_inf, e_rms, e_norm)
 
 
