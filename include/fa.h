@@ -357,6 +357,28 @@ int fa_apply(fa_op op, int kind, const void* d_b, void* d_x, int m_max, double t
              int check_every, void* d_workspace, size_t ws_bytes, uint32_t flags,
              void* hip_stream, fa_stats* stats);
 
+/*
+ * fa_apply_noalloc -- fa_apply for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Arguments, flags and results as fa_apply, without the
+ * workspace: the library keeps one static device array of
+ * FA_NOALLOC_MAX_BYTES (64 MiB) per device, held from the library's first
+ * use on that device until the process ends, and runs the solve in it.
+ *   - The call allocates nothing: no device or page-locked memory, no HIP
+ *     events (so no FA_PROFILE: FA_ERR_ARG; the stopping checks copy through
+ *     pageable memory and the next step is not overlapped with them).
+ *   - fa_workspace_bytes(op, m_max, flags) must not exceed
+ *     FA_NOALLOC_MAX_BYTES, else FA_ERR_WORKSPACE (nothing runs).
+ *   - All calls on one device share the array: the library serializes them
+ *     (a host lock, held until the call's device work has finished), so
+ *     concurrent calls from several threads wait for each other; the array
+ *     keeps the last call's contents, and no call relies on them.
+ * Errors: as fa_apply.
+ */
+#define FA_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int fa_apply_noalloc(fa_op op, int kind, const void* d_b, void* d_x, int m_max, double tol,
+                     int check_every, uint32_t flags, void* hip_stream, fa_stats* stats);
+
 /* y = A x on the device (one operator application, the "mvm" of the paper's
  * tables).  x, y: device vectors of length n, not aliased. */
 int fa_op_apply(fa_op op, const void* d_x, void* d_y, void* hip_stream);

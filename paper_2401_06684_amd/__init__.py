@@ -211,6 +211,26 @@ class Operator:
         d["status"] = st
         return x, d
 
+    def apply_noalloc(self, b, kind="invsqrt", m_max=100, tol=1e-10, check_every=0, out=None,
+                      fuse=True, mixed=False, orth="dcgs2"):
+        """apply() through fa_apply_noalloc: the solve runs in the library's
+        static device array (FA_NOALLOC_MAX_BYTES), no workspace is passed.
+        Returns (x, stats dict)."""
+        if orth not in ("dcgs2", "cgs2"):
+            raise ValueError("orth must be 'dcgs2' or 'cgs2'")
+        b = self._vec(b, "b")
+        x = out if out is not None else torch.empty_like(b)
+        self._vec(x, "out")
+        flags = _fuse_flags(fuse) | (FA_MIXED if mixed else 0) | (
+            _lib.FA_CGS2 if orth == "cgs2" else 0)
+        stats = _lib.fa_stats()
+        st = lib().fa_apply_noalloc(self._h, _KIND[kind], _ptr(b), _ptr(x), m_max, float(tol),
+                                    check_every, flags, _stream(self.device), C.byref(stats))
+        check(st, "fa_apply_noalloc")
+        d = stats.as_dict()
+        d["status"] = st
+        return x, d
+
     def block_apply(self, B, kind="invsqrt", m_max=30, tol=1e-10, check_every=0, out=None,
                     mixed=False, graph=False, raise_not_converged=False):
         """X ~ A^{-1/2} B or A^{1/2} B for the columns of B (n x s, s in

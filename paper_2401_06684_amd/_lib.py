@@ -31,7 +31,7 @@ EXPORTS = [
     "fa_op_device_bytes", "fa_create_csr", "fa_create_stencil", "fa_set_spectral_interval",
     "fa_get_spectral_interval", "fa_poly_workspace_bytes", "fa_poly_setup", "fa_poly_setup_ls",
     "fa_poly_get", "fa_poly_get_ls",
-    "fa_workspace_bytes", "fa_apply", "fa_op_apply", "fa_poly_apply", "fa_op_info",
+    "fa_workspace_bytes", "fa_apply", "fa_apply_noalloc", "fa_op_apply", "fa_poly_apply", "fa_op_info",
     "fa_destroy", "fa_status_string", "fa_dense_invsqrt_e1", "fa_dense_tridiag_invsqrt_e1",
     "fa_block_workspace_bytes", "fa_block_apply",
     "fa_server_create", "fa_server_submit", "fa_server_poll", "fa_server_wait",
@@ -118,6 +118,7 @@ def lib():
         "fa_poly_get_ls": (i32, [vp, C.POINTER(C.c_int64), dp, dp]),
         "fa_workspace_bytes": (sz, [vp, i32, u32]),
         "fa_apply": (i32, [vp, i32, vp, vp, i32, dbl, i32, vp, sz, u32, vp, C.POINTER(fa_stats)]),
+        "fa_apply_noalloc": (i32, [vp, i32, vp, vp, i32, dbl, i32, u32, vp, C.POINTER(fa_stats)]),
         "fa_op_apply": (i32, [vp, vp, vp, vp]),
         "fa_poly_apply": (i32, [vp, vp, vp, vp, sz, vp]),
         "fa_op_info": (i32, [vp, C.POINTER(C.c_int64), ip]),

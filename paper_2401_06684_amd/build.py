@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libfa.so")
 ARCH = os.environ.get("FA_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["kernels_chain.hip", "kernels_orth.hip", "solver.cpp", "api.cpp", "dense.cpp",
-           "lspoly.cpp", "server.cpp", "kernels_block.hip", "block.cpp", "kernels_st7multi.hip"]
+           "lspoly.cpp", "server.cpp", "kernels_block.hip", "block.cpp", "kernels_st7multi.hip",
+           "noalloc.cpp"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -15,10 +15,6 @@
 
 using namespace fa;
 
-struct fa_op_s {
-  Op op;
-};
-
 namespace {
 hipStream_t stream_of(void* s) { return (hipStream_t)s; }
 

@@ -220,3 +220,8 @@ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline size_t elem_size(int dtype) { return dtype == FA_C128 ? 16 : 8; }
 
 }  // namespace fa
+
+// the opaque handle of the C ABI
+struct fa_op_s {
+  fa::Op op;
+};

@@ -487,7 +487,8 @@ PinnedPool& pinned_pool() {
 }
 struct PinnedLease {
   void* p = nullptr;
-  explicit PinnedLease(size_t bytes) : p(pinned_pool().take(bytes)) {}
+  // bytes == 0: no area (the pool is not touched)
+  explicit PinnedLease(size_t bytes) : p(bytes ? pinned_pool().take(bytes) : nullptr) {}
   ~PinnedLease() {
     if (p) pinned_pool().give(p);
   }
@@ -726,7 +727,8 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   const size_t n_h = (size_t)L.ldh * m_max * ed, n_sh = (size_t)(m_max + 2) * ed,
                n_z = (size_t)m_max * ed, n_sc = 4;
   const size_t n_pin = n_h + n_sh + 2 * n_z + n_sc;
-  PinnedLease lease(n_pin * sizeof(double));
+  // kApplyNoAlloc: no page-locked area (it may have to be allocated)
+  PinnedLease lease((flags & kApplyNoAlloc) ? 0 : n_pin * sizeof(double));
   std::vector<double> pageable(lease.p ? 0 : n_pin);
   double* const pin = lease.p ? (double*)lease.p : pageable.data();
   double* const h_host = pin;              // H, column-major with ldh rows
@@ -840,7 +842,9 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   // launches); it is left out when the last two estimates, extrapolated
   // geometrically, predict convergence at this check.  If the iteration
   // stops there, its output is never read and its counts are undone.
-  const bool can_half = K > 0 && !right && !two_pass && tol > 0.0;
+  // (the half step's wait needs an event without page-locked memory, and
+  // kApplyNoAlloc creates none)
+  const bool can_half = K > 0 && !right && !two_pass && tol > 0.0 && !(flags & kApplyNoAlloc);
   int half_j = -1;  // the step whose first half is enqueued
   std::vector<double> est_hist;
   auto run_step = [&](int j) -> int {

@@ -30,6 +30,11 @@ struct Term {
 // the terms of q(A) v for a Chebyshev or (complex) Newton-form q (K terms)
 std::vector<Term> poly_terms(const Poly& q);
 
+// internal fa_apply flag (outside the public flag bits): allocate nothing,
+// i.e. no page-locked check area (pageable copies instead) and no events
+// (no half steps across the checks); profiling is refused by the caller
+constexpr uint32_t kApplyNoAlloc = 1u << 30;
+
 int op_apply(const Op& op, const void* x, void* y, hipStream_t s);
 int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_t s);
 int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double tol,
