@@ -179,7 +179,9 @@ typedef struct {
  * fa_create_csr / fa_create_stencil may need for an operator of this kind and
  * size (an upper bound: the op uses what it needs of it).
  *   FA_STENCIL7: 0 (the op is its 7 coefficients).
- *   FA_CSR     : 3840 (the list of long rows, at most 900 int32); n, nnz unused.
+ *   FA_CSR     : the work split of the n rows (a table of row blocks and a
+ *                list of long rows): 8 n and 4 n bytes, each rounded up to a
+ *                multiple of 256; nnz unused.
  *   FA_WILSON4D: 576 V bytes (V = Lx Ly Lz Lt from dims): the links in the
  *                kernels' order, whole; special unitary links use 384 V of it.
  * Returns 0 for an unknown kind or invalid dims.  Needs no GPU.
@@ -195,20 +197,21 @@ size_t fa_op_device_bytes(int kind, const int32_t dims[4], int64_t n, int64_t nn
  *   d_vals       : double[nnz] (FA_F64) or double complex[nnz] (FA_C128)
  *   dtype        : FA_F64 or FA_C128 (vectors passed to fa_apply use the same type)
  *   flags        : FA_HERMITIAN to select Lanczos in fa_apply
- *   d_opmem      : operator memory, >= opmem_bytes bytes, 256-byte aligned,
- *                  fa_op_device_bytes(FA_CSR, ...) suffices; borrowed until
- *                  fa_destroy.  May be NULL when no row is long (see below).
+ *   d_opmem      : operator memory, opmem_bytes bytes, 256-byte aligned,
+ *                  fa_op_device_bytes(FA_CSR, NULL, n, nnz) bytes suffice;
+ *                  borrowed until fa_destroy.
  * The arrays are not copied; they must stay alive and unchanged until
  * fa_destroy.  hip_stream is synchronized first (the arrays may be written
  * on it); then the row pointers and column indices are read once to the host
- * to check them and to pick the work split: rows up to 16 times the mean
- * length (rounded to a power of two) are summed by lane groups, longer ones
- * (at most 900; the threshold doubles until so) by one 1024-thread workgroup
- * each, in the same launch; their list is written to d_opmem.  A CSR op has
- * no spectral interval until fa_set_spectral_interval is called.
+ * to check them and to pick the work split, written to d_opmem: blocks of
+ * consecutive rows with at most 4096 entries and 512 rows each (one
+ * 512-thread workgroup streams a block's entries through LDS and sums each
+ * row with a lane group sized to the block), and rows of more than 4096
+ * entries, a workgroup each, in the same launch.  A CSR op has no spectral
+ * interval until fa_set_spectral_interval is called.
  * Errors: FA_ERR_ARG (row pointers that do not start at 0, end at nnz and
- * never decrease, or a column index outside [0, n)), FA_ERR_WORKSPACE (long
- * rows and d_opmem NULL, misaligned or too small), FA_ERR_HIP.
+ * never decrease, or a column index outside [0, n)), FA_ERR_WORKSPACE
+ * (d_opmem NULL, misaligned or too small for the split), FA_ERR_HIP.
  */
 int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
                   const int32_t* d_colind, const void* d_vals, int dtype, uint32_t flags,
@@ -380,8 +383,13 @@ int fa_apply_noalloc(fa_op op, int kind, const void* d_b, void* d_x, int m_max, 
                      int check_every, uint32_t flags, void* hip_stream, fa_stats* stats);
 
 /* y = A x on the device (one operator application, the "mvm" of the paper's
- * tables).  x, y: device vectors of length n, not aliased. */
-int fa_op_apply(fa_op op, const void* d_x, void* d_y, void* hip_stream);
+ * tables).  x, y: device vectors of length n, not aliased.  d_workspace
+ * (optional, >= fa_workspace_bytes(op, 1, 0) bytes, 256-byte aligned) lets a
+ * CSR op split rows of more than 4096 entries over several workgroups; with
+ * NULL each such row is summed by one workgroup (same result, bit for bit).
+ * Errors: FA_ERR_ARG, FA_ERR_WORKSPACE, FA_ERR_HIP. */
+int fa_op_apply(fa_op op, const void* d_x, void* d_y, void* d_workspace, size_t ws_bytes,
+                void* hip_stream);
 
 /* y = q(A) x by the polynomial's recurrence (Clenshaw for CHEB, Horner for
  * RITZ), K products with A.  d_workspace: >= fa_workspace_bytes(op, 1, 0). */

@@ -166,12 +166,15 @@ class Operator:
         return lib().fa_workspace_bytes(self._h, m_max, flags)
 
     def _workspace(self, m_max, flags=0):
+        # one cached workspace per stream: calls on different streams may
+        # overlap, and a workspace must not be shared by overlapping calls
         nbytes = self.workspace_bytes(m_max, flags)
-        ws = self._ws.get("apply")
+        key = ("apply", torch.cuda.current_stream(self.device).cuda_stream)
+        ws = self._ws.get(key)
         if ws is None or ws[2] < nbytes:
-            self._ws.pop("apply", None)
+            self._ws.pop(key, None)
             ws = workspace(nbytes, self.device)
-            self._ws["apply"] = ws
+            self._ws[key] = ws
         return ws
 
     def release_workspace(self):
@@ -274,11 +277,17 @@ class Operator:
         d["status"] = st
         return X, d
 
-    def op_apply(self, x, out=None):
-        """y = A x (one operator application)."""
+    def op_apply(self, x, out=None, split_long_rows=True):
+        """y = A x (one operator application).  A CSR op splits rows of more
+        than 4096 entries over several workgroups in a scratch workspace
+        (split_long_rows=False: one workgroup per such row, the same bits)."""
         x = self._vec(x, "x")
         y = out if out is not None else torch.empty_like(x)
-        check(lib().fa_op_apply(self._h, _ptr(x), _ptr(y), _stream(self.device)), "fa_op_apply")
+        wsp, nbytes = C.c_void_p(0), 0
+        if split_long_rows:
+            _, wsp, nbytes = self._workspace(1)
+        check(lib().fa_op_apply(self._h, _ptr(x), _ptr(y), wsp, nbytes, _stream(self.device)),
+              "fa_op_apply")
         return y
 
     def poly_apply(self, x, out=None):

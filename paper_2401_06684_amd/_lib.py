@@ -119,7 +119,7 @@ def lib():
         "fa_workspace_bytes": (sz, [vp, i32, u32]),
         "fa_apply": (i32, [vp, i32, vp, vp, i32, dbl, i32, vp, sz, u32, vp, C.POINTER(fa_stats)]),
         "fa_apply_noalloc": (i32, [vp, i32, vp, vp, i32, dbl, i32, u32, vp, C.POINTER(fa_stats)]),
-        "fa_op_apply": (i32, [vp, vp, vp, vp]),
+        "fa_op_apply": (i32, [vp, vp, vp, vp, sz, vp]),
         "fa_poly_apply": (i32, [vp, vp, vp, vp, sz, vp]),
         "fa_op_info": (i32, [vp, C.POINTER(C.c_int64), ip]),
         "fa_destroy": (i32, [vp]),

@@ -55,8 +55,11 @@ size_t fa_op_device_bytes(int kind, const int32_t dims[4], int64_t n, int64_t nn
   switch (kind) {
     case FA_STENCIL7:
       return 0;
-    case FA_CSR:  // the list of long rows, at most kCsrLongMax int32
-      return (size_t)round_up((int64_t)kCsrLongMax * 4, 256);
+    case FA_CSR: {  // the tables of row blocks, chunks of long rows and long rows
+      if (n < 1 || nnz < 0) return 0;
+      const int64_t nl = nnz / (kCsrBlockEntries + 1) + 1, nc = 2 * nl + nnz / kCsrBlockEntries;
+      return (size_t)(round_up(16 * n, 256) + round_up(16 * nc, 256) + round_up(12 * nl, 256));
+    }
     case FA_WILSON4D: {
       if (!dims) return 0;
       int64_t V = 1;
@@ -89,12 +92,6 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
     op.colind = d_colind;
     op.vals = d_vals;
     op.nnz = nnz;
-    // lanes per row: the power of two nearest above the mean row length
-    // (half or a quarter of it measured slower on the power-law graph)
-    const double avg = (double)nnz / (double)n;
-    int g = 1;
-    while (g < 64 && g < avg) g <<= 1;
-    op.csr_group = g;
     // the index arrays may still be in flight on the caller's stream
     hipStream_t st = stream_of(hip_stream);
     std::vector<int32_t> rp((size_t)n + 1), ci((size_t)nnz);
@@ -112,29 +109,56 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
       if (rp[r + 1] < rp[r]) return FA_ERR_ARG;
     for (int64_t e = 0; e < nnz; ++e)
       if (ci[e] < 0 || ci[e] >= n) return FA_ERR_ARG;
-    // rows longer than 16 groups' worth (the tail of a skewed distribution),
-    // at most kCsrLongMax of them, go to the one-workgroup-per-row kernel
-    int64_t thr = 16 * (int64_t)g;
-    for (;;) {
-      std::vector<int32_t> lr;
-      for (int64_t r = 0; r < n && (int)lr.size() <= kCsrLongMax; ++r)
-        if (rp[r + 1] - rp[r] > thr) lr.push_back((int32_t)r);
-      if ((int)lr.size() <= kCsrLongMax) {
-        op.csr_long_rows = lr;
-        op.csr_long_thr = (int)std::min<int64_t>(thr, 0x7fffffff);
-        break;
+    // the work split: blocks of consecutive rows with at most
+    // kCsrBlockEntries entries and kCsrBlockRows rows, cut greedily; a row
+    // with more entries than a block holds is cut into chunks of
+    // kCsrBlockEntries, a workgroup each
+    std::vector<int32_t> blk, chk, lng;
+    for (int64_t r = 0; r < n;) {
+      if (rp[r + 1] - rp[r] > kCsrBlockEntries) {
+        const int32_t li = (int32_t)(lng.size() / 3), c0 = (int32_t)(chk.size() / 4);
+        int32_t nc = 0;
+        for (int64_t e = rp[r]; e < rp[r + 1]; e += kCsrBlockEntries, ++nc) {
+          chk.push_back((int32_t)r);
+          chk.push_back((int32_t)e);
+          chk.push_back((int32_t)std::min<int64_t>(e + kCsrBlockEntries, rp[r + 1]));
+          chk.push_back(li);
+        }
+        lng.push_back((int32_t)r);
+        lng.push_back(c0);
+        lng.push_back(nc);
+        ++r;
+        continue;
       }
-      thr *= 2;
+      const int64_t r0 = r;
+      while (r < n && r - r0 < kCsrBlockRows && rp[r + 1] - rp[r] <= kCsrBlockEntries &&
+             rp[r + 1] - rp[r0] <= kCsrBlockEntries)
+        ++r;
+      blk.push_back((int32_t)r0);
+      blk.push_back((int32_t)r);
+      blk.push_back(rp[r0]);
+      blk.push_back(rp[r]);
     }
-    if (!op.csr_long_rows.empty()) {  // the list in the caller's operator memory
-      const size_t bytes = op.csr_long_rows.size() * sizeof(int32_t);
-      if (!d_opmem || opmem_bytes < bytes || ((uintptr_t)d_opmem & 255)) return FA_ERR_WORKSPACE;
-      op.csr_long_dev = (const int32_t*)d_opmem;
-      if (hipMemcpyAsync(d_opmem, op.csr_long_rows.data(), bytes, hipMemcpyHostToDevice, st) !=
-              hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess)
-        return FA_ERR_HIP;
-    }
+    op.csr_nblk = (int)(blk.size() / 4);
+    op.csr_nchunk = (int)(chk.size() / 4);
+    op.csr_nlong = (int)(lng.size() / 3);
+    // the three tables in the caller's operator memory, each 256-byte aligned
+    const size_t b_blk = blk.size() * 4, b_chk = chk.size() * 4, b_lng = lng.size() * 4;
+    const size_t off_chk = (size_t)round_up((int64_t)b_blk, 256);
+    const size_t off_lng = off_chk + (size_t)round_up((int64_t)b_chk, 256);
+    const size_t need = off_lng + b_lng;
+    if (!d_opmem || opmem_bytes < need || ((uintptr_t)d_opmem & 255)) return FA_ERR_WORKSPACE;
+    char* const m = (char*)d_opmem;
+    op.csr_blk_dev = (const int32_t*)m;
+    op.csr_chunk_dev = (const int32_t*)(m + off_chk);
+    op.csr_long_dev = (const int32_t*)(m + off_lng);
+    if ((b_blk && hipMemcpyAsync(m, blk.data(), b_blk, hipMemcpyHostToDevice, st) != hipSuccess) ||
+        (b_chk &&
+         hipMemcpyAsync(m + off_chk, chk.data(), b_chk, hipMemcpyHostToDevice, st) != hipSuccess) ||
+        (b_lng &&
+         hipMemcpyAsync(m + off_lng, lng.data(), b_lng, hipMemcpyHostToDevice, st) != hipSuccess) ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return FA_ERR_HIP;
     fa_op h = new fa_op_s;
     h->op = op;
     *out = h;
@@ -361,9 +385,12 @@ int fa_block_apply(fa_op op, int kind, int s, const void* d_B, void* d_X, int m_
   });
 }
 
-int fa_op_apply(fa_op op, const void* d_x, void* d_y, void* hip_stream) {
+int fa_op_apply(fa_op op, const void* d_x, void* d_y, void* d_workspace, size_t ws_bytes,
+                void* hip_stream) {
   if (!op || !d_x || !d_y || d_x == d_y) return FA_ERR_ARG;
-  return op_apply(op->op, d_x, d_y, stream_of(hip_stream));
+  if (d_workspace && (ws_bytes < make_layout(op->op, 1, 0).bytes || ((uintptr_t)d_workspace & 255)))
+    return FA_ERR_WORKSPACE;
+  return guarded([&] { return op_apply(op->op, d_x, d_y, d_workspace, stream_of(hip_stream)); });
 }
 
 int fa_poly_apply(fa_op op, const void* d_x, void* d_y, void* d_workspace, size_t ws_bytes,

@@ -28,6 +28,8 @@ __device__ __forceinline__ double cmad(double a, double b, double c) { return fm
 __device__ __forceinline__ cplx cmad(cplx a, cplx b, cplx c) {
   return {fma(a.x, b.x, fma(a.y, b.y, c.x)), fma(a.x, b.y, fma(-a.y, b.x, c.y))};
 }
+__device__ __forceinline__ bool is_zero(double a) { return a == 0.0; }
+__device__ __forceinline__ bool is_zero(cplx a) { return a.x == 0.0 && a.y == 0.0; }
 __device__ __forceinline__ double abs2(double a) { return a * a; }
 __device__ __forceinline__ double abs2(cplx a) { return fma(a.x, a.x, a.y * a.y); }
 __device__ __forceinline__ cplx times_i(cplx a) { return {-a.y, a.x}; }   //  i a

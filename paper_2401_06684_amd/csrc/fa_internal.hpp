@@ -56,12 +56,16 @@ struct Op {
   const int32_t* colind = nullptr;
   const void* vals = nullptr;
   int64_t nnz = 0;
-  int csr_group = 1;  // lanes per row
-  // rows longer than csr_long_thr (at most kCsrLongMax of them, sorted) are
-  // left to a kernel with one 1024-thread workgroup per row
-  int csr_long_thr = 0x7fffffff;
-  std::vector<int32_t> csr_long_rows;
-  const int32_t* csr_long_dev = nullptr;  // the same list in the caller's operator memory
+  // work split, in the caller's operator memory: csr_nblk blocks of
+  // consecutive rows with at most kCsrBlockEntries entries and kCsrBlockRows
+  // rows each ({r0, r1, rowptr[r0], rowptr[r1]}), and csr_nlong rows with
+  // more than kCsrBlockEntries entries ({row, first chunk, chunks}), cut into
+  // csr_nchunk chunks of at most kCsrBlockEntries ({row, begin, end, long
+  // index})
+  int csr_nblk = 0, csr_nlong = 0, csr_nchunk = 0;
+  const int32_t* csr_blk_dev = nullptr;
+  const int32_t* csr_chunk_dev = nullptr;
+  const int32_t* csr_long_dev = nullptr;
   // stencil
   int dims[4] = {1, 1, 1, 1};
   double coef[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -83,7 +87,19 @@ struct Op {
 // a fresh process-wide unique id (thread-safe)
 uint64_t next_op_uid();
 
-constexpr int kCsrLongMax = 900;  // long rows passed by value to their kernel
+// CSR work split: a row block is at most kCsrBlockRows rows with at most
+// kCsrBlockEntries entries, one workgroup of kCsrThreads threads with
+// kCsrPer entries each; longer rows are cut into chunks of that size
+#ifndef FA_CSR_THREADS
+#define FA_CSR_THREADS 512
+#endif
+#ifndef FA_CSR_PER
+#define FA_CSR_PER 8
+#endif
+constexpr int kCsrThreads = FA_CSR_THREADS;
+constexpr int kCsrPer = FA_CSR_PER;
+constexpr int kCsrBlockEntries = kCsrThreads * kCsrPer;
+constexpr int kCsrBlockRows = kCsrThreads;
 
 // storage precision of the vectors of one chain launch
 enum Prec { P64 = 0, P32 = 1 };
@@ -112,6 +128,16 @@ hipError_t launch_chain_multi(const Op& op, int nt, const void* x, const void* v
                               void* out1, void* out2, const ChainCoef* k, hipStream_t s,
                               Prec pin, Prec pout, int blocks = 0, hipEvent_t ev0 = nullptr,
                               hipEvent_t ev1 = nullptr);
+
+// Scratch of a CSR launch whose long rows are split over several workgroups
+// (their partial sums and one counter per long row): the bytes a call needs
+// (0: the op has no long rows), clearing its counters before the first launch
+// of a call, and the scratch the CSR launches of the calling thread use
+// (nullptr: each long row summed by one workgroup, the same bits); returns
+// the previous one.
+size_t csr_scratch_bytes(const Op& op);
+hipError_t csr_scratch_clear(const Op& op, void* scratch, hipStream_t s);
+void* set_csr_scratch(void* p);
 
 // algorithmic bytes moved by one chain launch (x read once, y0, y1 read,
 // out written, plus the operator's own data); p = storage of the vectors

@@ -392,107 +392,239 @@ hipError_t launch_chain_pair(const Op& op, const void* x, const void* y0, const 
 }
 
 // --------------------------------------------------------------------------
-// CSR, real or complex values: G lanes per row (G = power of two <= 64 close
-// to the mean row length), row sums reduced with shuffles inside the group.
-// Rows longer than `thr` (the long tail of a power-law degree distribution,
-// listed at creation) get a 1024-thread workgroup each, so that no lane group
-// walks tens of thousands of entries alone.  One launch does both: the first
-// nl workgroups take the long rows (the longest tasks, so they start first),
-// the others the remaining rows, and the long rows run concurrently with the
-// rest instead of after it.
+// CSR, real or complex values, as a stream of row blocks (the CSR-stream
+// scheme of Greathouse and Daga's CSR-Adaptive, written for 512-thread
+// workgroups): at creation the rows are cut into blocks of consecutive rows
+// holding at most kCsrBlockEntries entries and kCsrBlockRows rows.  A block's
+// workgroup
+//   1. loads the block's entries, kCsrPer per thread, coalesced (column
+//      index and value of entry e0 + tid + 512 k), gathers x at the columns
+//      with all of a thread's loads in flight, and stores the products in LDS;
+//   2. sums each row's products out of LDS with a lane group of tr lanes, tr
+//      the largest power of two <= 512 / rows (at most 64), in a fixed order,
+//      and writes the rows of the block in order (coalesced).
+// So every thread has several independent entries in flight instead of one.
+// Rows with more than kCsrBlockEntries entries (the tail of a skewed degree
+// distribution) are cut into chunks of kCsrBlockEntries: one CU gathers about
+// one cache line per clock, so a row of tens of thousands of entries must be
+// spread over many CUs.  With scratch for the chunks' partial sums (SPLIT),
+// every chunk is a workgroup of its own (the first ones of the launch); the
+// workgroup that finishes a row's last chunk adds the row's partial sums in
+// chunk order and writes the row, so the result does not depend on the
+// order the chunks finish.  Without scratch one workgroup walks all chunks of
+// the row and adds the same partial sums in the same order: the same bits.
 // --------------------------------------------------------------------------
-// entries of a long row loaded per thread before their gathers (16 and 32
-// measured slower: the extra registers cost the other rows occupancy)
-constexpr int kLongBatch = 8;
+static_assert(kCsrBlockEntries == kCsrThreads * kCsrPer, "one pass of loads per block or chunk");
+static_assert(kCsrBlockRows == kCsrThreads, "at most one row per lane group");
+static_assert(kCsrThreads % 64 == 0 && kCsrThreads <= 1024, "whole wavefronts");
 
-template <typename T, int G, bool Y0, bool Y1>
-__global__ __launch_bounds__(1024) void csr_chain(int n, const int32_t* __restrict__ rowptr,
-                                                  const int32_t* __restrict__ colind,
-                                                  const T* __restrict__ vals,
-                                                  const T* __restrict__ x,
-                                                  const T* __restrict__ y0, const T* y1, T* out,
-                                                  T al, T be, T g0, T g1, int thr, int nl,
-                                                  const int32_t* __restrict__ long_rows) {
-  if ((int)blockIdx.x < nl) {
-    // a long row: the 1024 threads stride through it, loading kLongBatch
-    // entries (index and value) before their gathers of x so that the loads
-    // overlap;
-    // partial sums are added in a fixed order (wavefront shuffles, then the
-    // 16 wavefront sums in LDS)
-    __shared__ T ws[16];
-    const int row = long_rows[blockIdx.x];
-    const int e0 = rowptr[row], e1 = rowptr[row + 1];
-    T acc = zero(T{});
-    for (int base = e0 + (int)threadIdx.x; base < e1; base += kLongBatch * 1024) {
-      int c[kLongBatch];
-      T v[kLongBatch];
+// the sum of the products of entries [eb, ee) (at most kCsrBlockEntries) by
+// the whole workgroup: per-thread sums in entry order, then the wavefront
+// sums, then the 8 wavefront sums in order; every thread returns it.  ws:
+// 8 LDS slots, free again when the call returns.
+template <typename T>
+__device__ __forceinline__ T csr_chunk_sum(const int32_t* __restrict__ colind,
+                                           const T* __restrict__ vals, const T* __restrict__ x,
+                                           int eb, int ee, T* ws) {
+  const int tid = threadIdx.x;
+  int c[kCsrPer];
+  T v[kCsrPer];
 #pragma unroll
-      for (int k = 0; k < kLongBatch; ++k) {
-        const int e = min(base + k * 1024, e1 - 1);
-        c[k] = colind[e];
-        v[k] = vals[e];
-      }
+  for (int k = 0; k < kCsrPer; ++k) {
+    const int e = min(eb + tid + k * kCsrThreads, ee - 1);
+    c[k] = colind[e];
+    v[k] = vals[e];
+  }
+  T acc = zero(T{});
 #pragma unroll
-      for (int k = 0; k < kLongBatch; ++k) {
-        const T t = mad(v[k], x[c[k]], acc);
-        acc = (base + k * 1024 < e1) ? t : acc;
+  for (int k = 0; k < kCsrPer; ++k) {
+    const T t = mad(v[k], x[c[k]], acc);
+    acc = (eb + tid + k * kCsrThreads < ee) ? t : acc;
+  }
+  acc = wave_sum(acc);
+  if ((tid & 63) == 0) ws[tid >> 6] = acc;
+  __syncthreads();
+  T t = ws[0];
+#pragma unroll
+  for (int w = 1; w < kCsrThreads / 64; ++w) t += ws[w];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ void agent_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void agent_store(cplx* p, cplx v) {
+  __hip_atomic_store(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double agent_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ cplx agent_load(const cplx* p) {
+  return {__hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+          __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+}
+
+template <typename T, bool Y0, bool Y1>
+__device__ __forceinline__ void csr_write_row(int row, T sum, const T* __restrict__ x,
+                                              const T* __restrict__ y0, const T* y1, T* out,
+                                              T al, T be, T g0, T g1, bool use_x) {
+  T r = al * sum;
+  if (use_x) r = mad(be, x[row], r);
+  if (Y0) r = mad(g0, y0[row], r);
+  if (Y1) r = mad(g1, y1[row], r);
+  out[row] = r;
+}
+
+// Work tables (operator memory):
+//   blk  : per block 4 int32 {r0, r1, e0 = rowptr[r0], e1 = rowptr[r1]}
+//   chunk: per chunk of a long row 4 int32 {row, eb, ee, long index}
+//   lng  : per long row 3 int32 {row, first chunk, chunks}
+// Scratch (SPLIT): the chunks' partial sums, then one counter per long row
+// (zero before the launch; the row's last chunk sets it back to zero).
+template <typename T, bool Y0, bool Y1, bool SPLIT>
+__global__ __launch_bounds__(kCsrThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 || kCsrThreads <= 256 ? 8 : 4))) void csr_chain(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+    const T* __restrict__ vals, const T* __restrict__ x, const T* __restrict__ y0, const T* y1,
+    T* out, T al, T be, T g0, T g1, int nfirst, const int4* __restrict__ blk,
+    const int4* __restrict__ chunk, const int32_t* __restrict__ lng, T* part, int* cnt) {
+  __shared__ T prod[kCsrBlockEntries];
+  __shared__ int lrp[kCsrBlockRows + 1];
+  __shared__ T ws[kCsrThreads / 64];
+  __shared__ int last;
+  const int tid = threadIdx.x;
+  const bool use_x = !is_zero(be);
+  if ((int)blockIdx.x < nfirst) {
+    if (SPLIT) {  // one chunk of a long row
+      const int4 ck = chunk[blockIdx.x];
+      const T sum = csr_chunk_sum(colind, vals, x, ck.y, ck.z, ws);
+      const int row = lng[3 * ck.w], c0 = lng[3 * ck.w + 1], nc = lng[3 * ck.w + 2];
+      if (tid == 0) {
+        agent_store(part + blockIdx.x, sum);
+        // release: the partial sum is visible before the count says so
+        const int prev = __hip_atomic_fetch_add(cnt + ck.w, 1, __ATOMIC_ACQ_REL,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        last = prev == nc - 1;
       }
-    }
-    acc = wave_sum(acc);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) ws[wv] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      T t = ws[0];
-      for (int w = 1; w < 16; ++w) t += ws[w];
-      T r = mad(al, t, be * x[row]);
-      if (Y0) r = mad(g0, y0[row], r);
-      if (Y1) r = mad(g1, y1[row], r);
-      out[row] = r;
+      __syncthreads();
+      if (last && tid == 0) {  // every chunk of the row is done: add them in order
+        T t = agent_load(part + c0);
+        for (int c = 1; c < nc; ++c) t += agent_load(part + c0 + c);
+        csr_write_row<T, Y0, Y1>(row, t, x, y0, y1, out, al, be, g0, g1, use_x);
+        __hip_atomic_store(cnt + ck.w, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    } else {  // a whole long row: its chunks one after the other
+      const int row = lng[3 * blockIdx.x], c0 = lng[3 * blockIdx.x + 1],
+                nc = lng[3 * blockIdx.x + 2];
+      T t = zero(T{});
+      for (int c = 0; c < nc; ++c) {
+        const int4 ck = chunk[c0 + c];
+        const T sum = csr_chunk_sum(colind, vals, x, ck.y, ck.z, ws);
+        t = (c == 0) ? sum : t + sum;
+      }
+      if (tid == 0) csr_write_row<T, Y0, Y1>(row, t, x, y0, y1, out, al, be, g0, g1, use_x);
     }
     return;
   }
-  const int64_t gt = (int64_t)(blockIdx.x - nl) * blockDim.x + threadIdx.x;
-  const int64_t row = gt / G;
-  const int lane = (int)(gt % G);
-  if (row >= n) return;  // whole groups leave together (G divides 64)
-  T acc = zero(T{});
-  const int e0 = rowptr[row], e1 = rowptr[row + 1];
-  if (e1 - e0 > thr) return;  // a long row: its own workgroup writes it
-  for (int e = e0 + lane; e < e1; e += G) acc = mad(vals[e], x[colind[e]], acc);
+  const int4 bk = blk[(int)blockIdx.x - nfirst];
+  const int r0 = bk.x, R = bk.y - bk.x, e0 = bk.z, ne = bk.w - bk.z;
+  // the lane group of this thread and its row (known before any load)
+  int tr = 64;
+  while (tr > 1 && tr * R > kCsrThreads) tr >>= 1;
+  const int gi = tid / tr, li = tid % tr;
+  // loads that do not depend on each other, all issued first: this thread's
+  // row pointer, the row's epilogue operands, the block's entries
+  const int rpv = rowptr[r0 + min(tid, R)] - e0;
+  T xr = zero(T{}), y0r = zero(T{}), y1r = zero(T{});
+  if (gi < R && li == 0) {
+    if (use_x) xr = x[r0 + gi];
+    if (Y0) y0r = y0[r0 + gi];
+    if (Y1) y1r = y1[r0 + gi];
+  }
+  if (ne > 0) {
+    int c[kCsrPer];
+    T v[kCsrPer];
 #pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) acc += shfl_down(acc, off, G);
-  if (lane == 0) {
-    T r = mad(al, acc, be * x[row]);
-    if (Y0) r = mad(g0, y0[row], r);
-    if (Y1) r = mad(g1, y1[row], r);
-    out[row] = r;
+    for (int k = 0; k < kCsrPer; ++k) {
+      const int e = e0 + min(tid + k * kCsrThreads, ne - 1);
+      c[k] = colind[e];
+      v[k] = vals[e];
+    }
+#pragma unroll
+    for (int k = 0; k < kCsrPer; ++k) {
+      const T t = v[k] * x[c[k]];
+      if (tid + k * kCsrThreads < ne) prod[tid + k * kCsrThreads] = t;
+    }
+  }
+  if (tid <= R) lrp[tid] = rpv;
+  if (tid == 0) lrp[R] = ne;  // (R may equal the thread count)
+  __syncthreads();
+  if (gi < R) {  // whole lane groups (tr divides 64) take this branch together
+    const int lo = lrp[gi], hi = lrp[gi + 1];
+    T acc = zero(T{});
+    for (int e = lo + li; e < hi; e += tr) acc += prod[e];
+    for (int off = tr / 2; off > 0; off >>= 1) acc += shfl_down(acc, off, tr);
+    if (li == 0) {
+      T r = al * acc;
+      if (use_x) r = mad(be, xr, r);
+      if (Y0) r = mad(g0, y0r, r);
+      if (Y1) r = mad(g1, y1r, r);
+      out[r0 + gi] = r;
+    }
   }
 }
 
-template <typename T, int G>
-static void launch_csr_g(const Op& op, const T* x, const T* y0, const T* y1, T* out, T al,
-                         T be, T g0, T g1, hipStream_t st) {
-  const int n = (int)op.n;
-  const int64_t threads = (int64_t)n * G;
-  const int nl = (int)op.csr_long_rows.size();
-  // 1024 threads per workgroup when there are long rows (their workgroups
-  // need them), else 256 (more workgroups for a small matrix)
-  const int bs = nl > 0 ? 1024 : 256;
-  const int grid = nl + (int)((threads + bs - 1) / bs);
+template <typename T>
+__global__ void csr_zero_counters(int* cnt, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) cnt[i] = 0;
+}
+
+namespace {
+thread_local void* t_csr_scratch = nullptr;
+}
+void* set_csr_scratch(void* p) {
+  void* old = t_csr_scratch;
+  t_csr_scratch = p;
+  return old;
+}
+
+size_t csr_scratch_bytes(const Op& op) {
+  if (op.kind != OP_CSR || op.csr_nlong == 0) return 0;
+  return (size_t)round_up((int64_t)op.csr_nchunk * (int64_t)elem_size(op.dtype), 256) +
+         (size_t)round_up((int64_t)op.csr_nlong * 4, 256);
+}
+
+hipError_t csr_scratch_clear(const Op& op, void* scratch, hipStream_t st) {
+  if (op.kind != OP_CSR || op.csr_nlong == 0 || !scratch) return hipSuccess;
+  int* cnt = (int*)((char*)scratch +
+                    round_up((int64_t)op.csr_nchunk * (int64_t)elem_size(op.dtype), 256));
+  csr_zero_counters<int><<<(op.csr_nlong + 255) / 256, 256, 0, st>>>(cnt, op.csr_nlong);
+  return hipGetLastError();
+}
+
+template <typename T, bool Y0, bool Y1>
+static void launch_csr_y(const Op& op, const T* x, const T* y0, const T* y1, T* out, T al, T be,
+                         T g0, T g1, hipStream_t st) {
   auto rp = op.rowptr;
   auto ci = op.colind;
   auto va = (const T*)op.vals;
-  const int thr = op.csr_long_thr;
-  const int32_t* lr = op.csr_long_dev;
-  if (y0 && y1)
-    csr_chain<T, G, true, true><<<grid, bs, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr, nl, lr);
-  else if (y0)
-    csr_chain<T, G, true, false><<<grid, bs, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr, nl, lr);
-  else if (y1)
-    csr_chain<T, G, false, true><<<grid, bs, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr, nl, lr);
-  else
-    csr_chain<T, G, false, false><<<grid, bs, 0, st>>>(n, rp, ci, va, x, y0, y1, out, al, be, g0, g1, thr, nl, lr);
+  const int4* bk = (const int4*)op.csr_blk_dev;
+  const int4* ck = (const int4*)op.csr_chunk_dev;
+  const int32_t* lg = op.csr_long_dev;
+  void* sc = op.csr_nlong ? t_csr_scratch : nullptr;
+  if (sc) {
+    T* part = (T*)sc;
+    int* cnt = (int*)((char*)sc + round_up((int64_t)op.csr_nchunk * (int64_t)sizeof(T), 256));
+    const int grid = op.csr_nchunk + op.csr_nblk;
+    csr_chain<T, Y0, Y1, true><<<grid, kCsrThreads, 0, st>>>(
+        rp, ci, va, x, y0, y1, out, al, be, g0, g1, op.csr_nchunk, bk, ck, lg, part, cnt);
+  } else {
+    const int grid = op.csr_nlong + op.csr_nblk;
+    csr_chain<T, Y0, Y1, false><<<grid, kCsrThreads, 0, st>>>(
+        rp, ci, va, x, y0, y1, out, al, be, g0, g1, op.csr_nlong, bk, ck, lg, nullptr, nullptr);
+  }
 }
 
 template <typename T>
@@ -500,15 +632,15 @@ static hipError_t launch_csr(const Op& op, const T* x, const T* y0, const T* y1,
                              const ChainCoef& k, hipStream_t st) {
   const T al = host_to_dev<T>::conv(k.alpha), be = host_to_dev<T>::conv(k.beta),
           g0 = host_to_dev<T>::conv(k.g0), g1 = host_to_dev<T>::conv(k.g1);
-  switch (op.csr_group) {
-    case 1: launch_csr_g<T, 1>(op, x, y0, y1, out, al, be, g0, g1, st); break;
-    case 2: launch_csr_g<T, 2>(op, x, y0, y1, out, al, be, g0, g1, st); break;
-    case 4: launch_csr_g<T, 4>(op, x, y0, y1, out, al, be, g0, g1, st); break;
-    case 8: launch_csr_g<T, 8>(op, x, y0, y1, out, al, be, g0, g1, st); break;
-    case 16: launch_csr_g<T, 16>(op, x, y0, y1, out, al, be, g0, g1, st); break;
-    case 32: launch_csr_g<T, 32>(op, x, y0, y1, out, al, be, g0, g1, st); break;
-    default: launch_csr_g<T, 64>(op, x, y0, y1, out, al, be, g0, g1, st); break;
-  }
+  if (op.csr_nlong + op.csr_nblk == 0) return hipSuccess;
+  if (y0 && y1)
+    launch_csr_y<T, true, true>(op, x, y0, y1, out, al, be, g0, g1, st);
+  else if (y0)
+    launch_csr_y<T, true, false>(op, x, y0, y1, out, al, be, g0, g1, st);
+  else if (y1)
+    launch_csr_y<T, false, true>(op, x, y0, y1, out, al, be, g0, g1, st);
+  else
+    launch_csr_y<T, false, false>(op, x, y0, y1, out, al, be, g0, g1, st);
   return hipGetLastError();
 }
 

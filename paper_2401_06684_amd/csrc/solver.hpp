@@ -16,6 +16,7 @@ struct Layout {
          off_nrm = 0, off_z = 0;
   size_t off_W = 0;  // least-squares polynomial: its d basis vectors (0: none)
   size_t off_dc = 0; // coefficients of the delayed-reorthogonalization step
+  size_t off_csr = 0, csr_bytes = 0;  // CSR long rows split over workgroups (0: none)
   size_t bytes = 0;
 };
 // with_poly: include the storage the op's polynomial needs (least squares)
@@ -35,7 +36,24 @@ std::vector<Term> poly_terms(const Poly& q);
 // (no half steps across the checks); profiling is refused by the caller
 constexpr uint32_t kApplyNoAlloc = 1u << 30;
 
-int op_apply(const Op& op, const void* x, void* y, hipStream_t s);
+// the calling thread's CSR launches use `scratch` (may be null) while this
+// lives; the counters in it are cleared on construction (check ok())
+class CsrScratchScope {
+ public:
+  CsrScratchScope(const Op& op, void* scratch, hipStream_t s)
+      : err_(csr_scratch_clear(op, scratch, s)), prev_(set_csr_scratch(scratch)) {}
+  ~CsrScratchScope() { set_csr_scratch(prev_); }
+  bool ok() const { return err_ == hipSuccess; }
+  CsrScratchScope(const CsrScratchScope&) = delete;
+  CsrScratchScope& operator=(const CsrScratchScope&) = delete;
+
+ private:
+  hipError_t err_;
+  void* prev_;
+};
+
+// y = A x; ws (may be null) of make_layout(op, 1, 0).bytes splits long CSR rows
+int op_apply(const Op& op, const void* x, void* y, void* ws, hipStream_t s);
 int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_t s);
 int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double tol,
           int check_every, void* ws, size_t ws_bytes, uint32_t flags, hipStream_t s,

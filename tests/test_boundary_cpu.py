@@ -100,8 +100,12 @@ def test_operator_memory_query():
         -(-4 * 9 * 16 * 210 // 256) * 256
     assert L.fa_op_device_bytes(_lib.FA_WILSON4D, (C.c_int32 * 4)(4, 1, 4, 4), 0, 0) == 0
     assert L.fa_op_device_bytes(_lib.FA_WILSON4D, None, 0, 0) == 0
-    # CSR: the list of at most 900 long rows (int32), 256-byte rounded
-    assert L.fa_op_device_bytes(_lib.FA_CSR, None, 281903, 2594228) == 3840
+    # CSR: the table of row blocks (at most n pairs of int32) and the list of
+    # long rows (at most n int32), each 256-byte rounded
+    n = 281903
+    assert L.fa_op_device_bytes(_lib.FA_CSR, None, n, 2594228) == \
+        -(-8 * n // 256) * 256 + -(-4 * n // 256) * 256
+    assert L.fa_op_device_bytes(_lib.FA_CSR, None, 0, 0) == 0
     assert L.fa_op_device_bytes(_lib.FA_STENCIL7, (C.c_int32 * 4)(8, 8, 8, 1), 0, 0) == 0
     assert L.fa_op_device_bytes(7, d4, 0, 0) == 0
 

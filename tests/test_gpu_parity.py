@@ -138,7 +138,7 @@ def test_wilson_links_copied_at_creation():
     dx, dy = dev(x), torch.empty(x.shape, dtype=torch.complex128, device=DEV)
     torch.cuda.synchronize()
     assert _lib.lib().fa_op_apply(h, C.c_void_p(dx.data_ptr()), C.c_void_p(dy.data_ptr()),
-                                  None) == 0
+                                  None, 0, None) == 0
     assert_close(host(dy), ops.wilson_apply(U, 0.05, x), 1e-14)
     assert _lib.lib().fa_destroy(h) == 0
 
@@ -669,6 +669,30 @@ def test_powerlaw_csr_apply_full_size():
     assert_close(host(op.op_apply(dev(xv))), ops.csr_apply(rp, ci, va, xv), 1e-14)
 
 
+def test_powerlaw_digraph_sqrt_against_oracle():
+    """Sec. 6, Example 3 in shape: L^{1/2} b as L^{-1/2} (L b) for the singular
+    in-degree Laplacian of a directed power-law graph (n = 20,000 here),
+    b a canonical unit vector, Ritz polynomial of degree 8 from a random start,
+    re-orthogonalized Arnoldi, checks every 32 / d = 3 steps.  The oracle runs
+    with the GPU's exported polynomial; both at tol 1e-12 (same iterations,
+    agreement 1e-10), and at the example's tol 1e-7 the same iterations."""
+    n = 20000
+    rp, ci, va = wl.powerlaw_digraph_laplacian_csr(n, 184000, seed=5)
+    op = fa().CSR(rp, ci, va)
+    start = wl.rhs(n, seed=8)
+    op.poly_setup(8, "ritz", start=dev(start))
+    q = exported_newton_poly(op, True)
+    assert np.all(q.theta.real > 0)
+    b = np.zeros(n)
+    b[int(np.random.default_rng(0).integers(n))] = 1.0
+    A = lambda v: ops.csr_apply(rp, ci, va, v)  # noqa: E731
+    for tol, bar in ((1e-12, 1e-10), (1e-7, 1e-10)):
+        x, st = op.apply(dev(b), kind="sqrt", m_max=300, tol=tol, check_every=3)
+        orc = kr.fAb(A, b, q, "sqrt", m_max=300, tol=tol, check_every=3)
+        assert st["converged"] == 1 and st["iters"] == orc.iters and st["mvms"] == orc.mvms
+        assert_close(host(x), orc.x, bar)
+
+
 @pytest.mark.parametrize("degree", [0, 4, 8])
 def test_singular_digraph_laplacian_sqrt(degree):
     """Sec. 4 (implicit desingularization): L^{1/2} b as L^{-1/2}(L b) for the
@@ -1056,9 +1080,11 @@ def test_csr_long_rows(complex_):
 
 @pytest.mark.parametrize("complex_", [False, True])
 def test_csr_very_long_rows_repeats_and_streams(complex_):
-    """Rows of 9,000 and 20,000 entries among rows of 3 (each long row summed
-    by its own workgroup): A x against the oracle, and the same bits on every
-    repeat and on two streams at once."""
+    """Rows of 9,000 and 20,000 entries among rows of 3 (each long row cut into
+    chunks of 4,096 entries on separate workgroups, the last one adding the
+    partial sums in order): A x against the oracle, and the same bits on every
+    repeat, on two streams at once (each with its own scratch), and with one
+    workgroup per long row (no scratch)."""
     rng = np.random.default_rng(11)
     n = 30000
     rows, cols = [], []
@@ -1094,6 +1120,38 @@ def test_csr_very_long_rows_repeats_and_streams(complex_):
     torch.cuda.synchronize()
     for y in outs:
         assert torch.equal(y, y0)
+    assert torch.equal(op.op_apply(x, split_long_rows=False), y0)
+
+
+@pytest.mark.parametrize("complex_", [False, True])
+def test_csr_rows_at_the_block_and_chunk_bounds(complex_):
+    """Rows of 0, 1, 4095, 4096, 4097, 8192, 8193 and 12,289 entries, runs of
+    512 short rows, and the Clenshaw-type epilogue with both extra vectors:
+    blocks end at 4,096 entries or 512 rows, longer rows are cut into chunks
+    (one entry past a multiple of 4,096 makes a chunk of one); split and
+    unsplit long rows give the same bits, and both match the oracle."""
+    rng = np.random.default_rng(13)
+    lens = [0, 1, 4095, 3, 4096, 0, 4097, 2] + [1] * 600 + [8192, 8193, 12289, 5, 0, 7]
+    n = len(lens) + 20000
+    lens = lens + list(rng.integers(0, 12, 20000))
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate([rng.choice(n, size=k, replace=False) for k in lens]).astype(np.int32)
+    va = rng.standard_normal(rp[-1])
+    if complex_:
+        va = va + 1j * rng.standard_normal(rp[-1])
+    op = fa().CSR(rp, ci, va)
+    x = wl.rhs(n, seed=3, complex_=complex_)
+    y = op.op_apply(dev(x)).clone()
+    assert_close(host(y), ops.csr_apply(rp, ci, va, x), 1e-14)
+    assert torch.equal(op.op_apply(dev(x), split_long_rows=False), y)
+    # out = alpha A x + beta x + g0 y0 + g1 y1 through a Chebyshev q(A) of
+    # degree 3 (its middle terms carry both extra vectors)
+    lam = np.abs(va).max() * 2e4
+    op.set_spectral_interval(1.0, lam)
+    op.poly_setup(3, "cheb")
+    q = pl.chebyshev(1.0, lam, 3)
+    ref, _ = q.apply(lambda v: ops.csr_apply(rp, ci, va, v), x)
+    assert_close(host(op.poly_apply(dev(x))), ref, 1e-12)
 
 
 def test_csr_rejects_bad_row_pointers():
