@@ -179,9 +179,10 @@ typedef struct {
  * fa_create_csr / fa_create_stencil may need for an operator of this kind and
  * size (an upper bound: the op uses what it needs of it).
  *   FA_STENCIL7: 0 (the op is its 7 coefficients).
- *   FA_CSR     : the work split of the n rows (a table of row blocks and a
- *                list of long rows): 8 n and 4 n bytes, each rounded up to a
- *                multiple of 256; nnz unused.
+ *   FA_CSR     : the work split of the n rows and nnz entries, bounded by
+ *                16 n bytes of row blocks, 16 c bytes of chunks of long rows
+ *                and 12 l bytes of long rows, each rounded up to a multiple
+ *                of 256, where l = nnz / 4097 + 1, c = 2 l + nnz / 4096.
  *   FA_WILSON4D: 576 V bytes (V = Lx Ly Lz Lt from dims): the links in the
  *                kernels' order, whole; special unitary links use 384 V of it.
  * Returns 0 for an unknown kind or invalid dims.  Needs no GPU.

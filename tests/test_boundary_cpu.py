@@ -100,11 +100,16 @@ def test_operator_memory_query():
         -(-4 * 9 * 16 * 210 // 256) * 256
     assert L.fa_op_device_bytes(_lib.FA_WILSON4D, (C.c_int32 * 4)(4, 1, 4, 4), 0, 0) == 0
     assert L.fa_op_device_bytes(_lib.FA_WILSON4D, None, 0, 0) == 0
-    # CSR: the table of row blocks (at most n pairs of int32) and the list of
-    # long rows (at most n int32), each 256-byte rounded
-    n = 281903
-    assert L.fa_op_device_bytes(_lib.FA_CSR, None, n, 2594228) == \
-        -(-8 * n // 256) * 256 + -(-4 * n // 256) * 256
+    # CSR: the tables of row blocks (at most n, 4 int32 each), of chunks of
+    # long rows (4 int32 each) and of long rows (3 int32 each), 256-byte rounded
+    def up(b):
+        return -(-b // 256) * 256
+
+    for n, nnz in ((281903, 2594228), (1024, 4992), (5, 40000)):
+        nl = nnz // 4097 + 1
+        nc = 2 * nl + nnz // 4096
+        assert L.fa_op_device_bytes(_lib.FA_CSR, None, n, nnz) == \
+            up(16 * n) + up(16 * nc) + up(12 * nl)
     assert L.fa_op_device_bytes(_lib.FA_CSR, None, 0, 0) == 0
     assert L.fa_op_device_bytes(_lib.FA_STENCIL7, (C.c_int32 * 4)(8, 8, 8, 1), 0, 0) == 0
     assert L.fa_op_device_bytes(7, d4, 0, 0) == 0
