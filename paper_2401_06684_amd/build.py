@@ -20,7 +20,7 @@ ARCH = os.environ.get("FA_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["kernels_chain.hip", "kernels_orth.hip", "solver.cpp", "api.cpp", "dense.cpp",
            "lspoly.cpp", "server.cpp", "kernels_block.hip", "block.cpp", "kernels_st7multi.hip",
-           "noalloc.cpp"]
+           "noalloc.cpp", "kernels_small.hip"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -105,8 +105,10 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
     // the kernels index with both arrays unchecked: the row pointers must
     // describe nnz entries in order and every column index must lie in [0, n)
     if (rp[0] != 0 || rp[(size_t)n] != nnz) return FA_ERR_ARG;
-    for (int64_t r = 0; r < n; ++r)
+    for (int64_t r = 0; r < n; ++r) {
       if (rp[r + 1] < rp[r]) return FA_ERR_ARG;
+      op.csr_maxrow = std::max<int>(op.csr_maxrow, rp[r + 1] - rp[r]);
+    }
     for (int64_t e = 0; e < nnz; ++e)
       if (ci[e] < 0 || ci[e] >= n) return FA_ERR_ARG;
     // the work split: blocks of consecutive rows with at most

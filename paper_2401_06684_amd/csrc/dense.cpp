@@ -372,19 +372,18 @@ int tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double be
   // Van Loan, Matrix Computations, Sec. 8.3).  A sweep on rows lo..hi is a
   // chain of plane rotations P_k (rows k, k+1): the first is chosen from the
   // shifted first column (d_lo - mu, e_lo), each later one annihilates the
-  // bulge T(k-1, k+1) the previous one created; T <- P_k T P_k^T, Q <- Q P_k^T.
-  std::vector<double> d(alpha, alpha + m), e(std::max(m - 1, 1), 0.0), Q((size_t)m * m, 0.0);
-  for (int i = 0; i + 1 < m; ++i) e[i] = offd[i];
-  for (int i = 0; i < m; ++i) Q[(size_t)i * m + i] = 1.0;
-  auto rotate_cols = [&](int k, double c, double s) {  // Q <- Q P_k^T
-    double* qk = &Q[(size_t)k * m];
-    double* qk1 = &Q[(size_t)(k + 1) * m];
-    for (int i = 0; i < m; ++i) {
-      const double u = qk[i], v = qk1[i];
-      qk[i] = c * u + s * v;
-      qk1[i] = c * v - s * u;
-    }
+  // bulge T(k-1, k+1) the previous one created; T <- P_k T P_k^T, and
+  // Q = P_1^T P_2^T ... P_N^T.  Only Q^T e_1 and one product Q w are needed,
+  // so the rotations are recorded and applied to those two vectors (O(m^2)
+  // work instead of O(m^3) for Q itself).
+  struct Rot {
+    int k;
+    double c, s;
   };
+  std::vector<double> d(alpha, alpha + m), e(std::max(m - 1, 1), 0.0);
+  for (int i = 0; i + 1 < m; ++i) e[i] = offd[i];
+  std::vector<Rot> rot;
+  rot.reserve((size_t)8 * m);
   int hi = m - 1;
   long sweeps = 0;
   while (hi > 0) {
@@ -400,10 +399,11 @@ int tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double be
     if (++sweeps > 40L * m) return DENSE_NOCONV;
     // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block nearer d[hi]
     const double t = 0.5 * (d[hi - 1] - d[hi]), eh = e[hi - 1];
-    const double mu = d[hi] - eh * eh / (t + (t >= 0.0 ? 1.0 : -1.0) * std::hypot(t, eh));
+    // (sqrt of sums of squares: the entries are far from overflow here)
+    const double mu = d[hi] - eh * eh / (t + (t >= 0.0 ? 1.0 : -1.0) * std::sqrt(t * t + eh * eh));
     double x = d[lo] - mu, y = e[lo];  // the vector the next rotation acts on
     for (int k = lo; k < hi; ++k) {
-      const double r = std::hypot(x, y);
+      const double r = std::sqrt(x * x + y * y);
       const double c = r == 0.0 ? 1.0 : x / r, s = r == 0.0 ? 0.0 : y / r;
       if (k > lo) e[k - 1] = r;  // the bulge T(k-1, k+1) is now zero
       // the 2 x 2 block on rows and columns k, k+1
@@ -412,7 +412,7 @@ int tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double be
       d[k] = cc * a + 2.0 * cs * f + ss * bb;
       d[k + 1] = ss * a - 2.0 * cs * f + cc * bb;
       e[k] = cs * (bb - a) + (cc - ss) * f;
-      rotate_cols(k, c, s);
+      rot.push_back({k, c, s});
       if (k + 1 < hi) {  // the coupling to row k + 2 moves the bulge down
         x = e[k];
         y = s * e[k + 1];
@@ -422,13 +422,20 @@ int tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double be
   }
   for (int k = 0; k < m; ++k)
     if (!(d[k] > 0.0)) return DENSE_BRANCH;
-  // z = Q diag(d)^{-1/2} Q^T (beta e_1); row 0 of Q is Q^T e_1
-  std::vector<double> w(m);
-  for (int k = 0; k < m; ++k) w[k] = Q[(size_t)k * m] * beta / std::sqrt(d[k]);
-  for (int i = 0; i < m; ++i) {
-    double acc = 0.0;
-    for (int k = 0; k < m; ++k) acc += Q[(size_t)k * m + i] * w[k];
-    z[i] = acc;
+  // u = Q^T e_1 = P_N ... P_1 e_1
+  std::vector<double> u(m, 0.0);
+  u[0] = 1.0;
+  for (const Rot& g : rot) {
+    const double p = u[g.k], q = u[g.k + 1];
+    u[g.k] = g.c * p + g.s * q;
+    u[g.k + 1] = g.c * q - g.s * p;
+  }
+  // z = Q diag(d)^{-1/2} (beta u) = P_1^T ... P_N^T w
+  for (int k = 0; k < m; ++k) z[k] = u[k] * beta / std::sqrt(d[k]);
+  for (auto it = rot.rbegin(); it != rot.rend(); ++it) {
+    const double p = z[it->k], q = z[it->k + 1];
+    z[it->k] = it->c * p - it->s * q;
+    z[it->k + 1] = it->s * p + it->c * q;
   }
   return DENSE_OK;
 }

@@ -63,6 +63,7 @@ struct Op {
   // csr_nchunk chunks of at most kCsrBlockEntries ({row, begin, end, long
   // index})
   int csr_nblk = 0, csr_nlong = 0, csr_nchunk = 0;
+  int csr_maxrow = 0;  // entries of the longest row
   const int32_t* csr_blk_dev = nullptr;
   const int32_t* csr_chunk_dev = nullptr;
   const int32_t* csr_long_dev = nullptr;
@@ -138,6 +139,31 @@ hipError_t launch_chain_multi(const Op& op, int nt, const void* x, const void* v
 size_t csr_scratch_bytes(const Op& op);
 hipError_t csr_scratch_clear(const Op& op, void* scratch, hipStream_t s);
 void* set_csr_scratch(void* p);
+
+// Small Hermitian problems: the Lanczos steps j0 .. j1 - 1 of Algorithm 1 in
+// one workgroup (kernels_small.hip).  Real FP64, n <= kSmallMaxN, a 7-point
+// stencil or a CSR matrix with rows of at most kSmallRow entries, q == 1 or
+// a Chebyshev q of at most kSmallMaxTerms terms.
+constexpr int kSmallMaxN = 2048, kSmallRow = 8, kSmallMaxTerms = 32;
+struct SmallTerm {  // out = a A x + b x + g0 v (if y0) + g1 out_{-2} (if y1)
+  double a, b, g0, g1;
+  int y0, y1;
+};
+struct SmallLanczosArgs {
+  int n, j0, j1, nterms;
+  int64_t ldv;
+  double* V;  // basis, column-major, ldv
+  double* H;  // banded H: column j = (H(j, j), H(j + 1, j))
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const double* vals;
+  int nx, ny, nz;
+  double c[7];
+  SmallTerm t[kSmallMaxTerms];
+};
+bool small_lanczos_ok(const Op& op, const Poly& q);
+hipError_t launch_small_lanczos(const Op& op, const std::vector<SmallTerm>& terms, int j0,
+                                int j1, void* V, int64_t ldv, void* H, hipStream_t s);
 
 // algorithmic bytes moved by one chain launch (x read once, y0, y1 read,
 // out written, plus the operator's own data); p = storage of the vectors

@@ -857,10 +857,32 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   // stops there, its output is never read and its counts are undone.
   // (the half step's wait needs an event without page-locked memory, and
   // kApplyNoAlloc creates none)
-  const bool can_half = K > 0 && !right && !two_pass && tol > 0.0 && !(flags & kApplyNoAlloc);
+  // Small Hermitian problems: the steps up to the next check in one launch
+  // of one workgroup (kernels_small.hip; FA_NO_FUSION keeps one launch per
+  // recurrence term)
+  const bool small = lanczos && !right && !two_pass && !mixed && !(flags & FA_NO_FUSION) &&
+                     small_lanczos_ok(op, q);
+  std::vector<SmallTerm> small_terms;
+  if (small && K > 0)
+    for (const Term& t : poly_terms(q))
+      small_terms.push_back(SmallTerm{t.k.alpha.real(), t.k.beta.real(), t.k.g0.real(),
+                                      t.k.g1.real(), t.y0 ? 1 : 0, t.y1 ? 1 : 0});
+  int small_until = 0;  // steps below this index are enqueued in a launch already
+  const bool can_half =
+      K > 0 && !right && !two_pass && tol > 0.0 && !(flags & kApplyNoAlloc) && !small;
   int half_j = -1;  // the step whose first half is enqueued
   std::vector<double> est_hist;
   auto run_step = [&](int j) -> int {
+    if (small) {
+      if (j < small_until) return FA_OK;
+      // to the next check (tol <= 0: to m_max)
+      const int end = tol > 0.0 ? std::min(m_max, (j / k_chk + 1) * k_chk) : m_max;
+      FA_HIP(launch_small_lanczos(op, small_terms, j, end, V, L.ldv, Hd, s));
+      mvms += (int64_t)(end - j) * (2 * K + 1);
+      ips += 2 * (int64_t)(end - j);
+      small_until = end;
+      return FA_OK;
+    }
     if (half_j == j) {
       half_j = -1;
       return step(j, 2);

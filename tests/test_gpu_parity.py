@@ -1160,3 +1160,71 @@ def test_csr_rejects_bad_row_pointers():
     va = np.ones(3)
     with pytest.raises(fa().FAError):
         fa().CSR(rp, ci, va)
+
+
+# --------------------------------------------------------------------------
+# small Hermitian problems: the Lanczos steps between checks in one launch
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(32, 32, 1), (12, 11, 10), (7, 5, 3)])
+@pytest.mark.parametrize("degree", [0, 3, 8])
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+@pytest.mark.parametrize("check_every", [0, 1, 5])
+def test_small_lanczos_against_oracle(shape, degree, kind, check_every):
+    """n <= 2048 (one or two entries per thread): the one-workgroup Lanczos
+    segments against the oracle's Lanczos (both at tol 1e-12: same
+    iterations and products with A, agreement 1e-10), against the DST closed
+    form, and against the step-by-step launches (fuse=False); CSR for the
+    5-point matrix, the stencil for the 3D grids; checks every k steps."""
+    coeffs = wl.laplace_stencil(3 if shape[2] > 1 else 2)
+    a, bb = ops.stencil_interval(coeffs, shape)
+    if shape[2] == 1:
+        rp, ci, va = wl.stencil_csr(shape, coeffs)
+        op = fa().CSR(rp, ci, va, hermitian=True)
+        op.set_spectral_interval(a, bb)
+        A = lambda v: ops.csr_apply(rp, ci, va, v)  # noqa: E731
+    else:
+        op = fa().Stencil7(shape, coeffs, hermitian=True)
+        A = lambda v: ops.stencil_apply(coeffs, shape, v)  # noqa: E731
+    op.poly_setup(degree, "cheb")
+    b = wl.rhs(op.n, seed=0)
+    m_max = min(300, op.n)
+    x, st = op.apply(dev(b), kind=kind, m_max=m_max, tol=1e-12, check_every=check_every)
+    orc = kr.fAb(A, b, pl.chebyshev(a, bb, degree), kind, m_max=m_max, tol=1e-12,
+                 check_every=check_every, orth="lanczos")
+    assert st["iters"] == orc.iters and st["mvms"] == orc.mvms
+    assert st["inner_products"] == orc.inner_products == 2 * orc.iters
+    assert st["converged"] == orc.converged
+    assert_close(host(x), orc.x, 1e-10)
+    assert_close(host(x), exact.stencil_fAb_dst(coeffs, shape, b, kind), 1e-10)
+    x1, s1 = op.apply(dev(b), kind=kind, m_max=m_max, tol=1e-12, check_every=check_every,
+                      fuse=False)
+    assert s1["iters"] == st["iters"]
+    assert_close(host(x), host(x1), 1e-12)
+
+
+def test_small_lanczos_fixed_m_and_breakdown():
+    """Fixed Krylov dimension (tol 0: one launch for all m steps) against the
+    oracle, and a lucky breakdown in the middle of a launch's steps (a
+    diagonal matrix with 4 distinct values: the host finds h_{5,4} ~ 0 and
+    keeps 4 steps; the steps computed past it are not used)."""
+    coeffs = wl.laplace_stencil(3)
+    shape = (9, 8, 7)
+    op = fa().Stencil7(shape, coeffs, hermitian=True)
+    op.poly_setup(4, "cheb")
+    a, bb = ops.stencil_interval(coeffs, shape)
+    b = wl.rhs(op.n, seed=2)
+    x, st = op.apply(dev(b), m_max=6, tol=0.0)
+    orc = kr.fAb(lambda v: ops.stencil_apply(coeffs, shape, v), b, pl.chebyshev(a, bb, 4),
+                 "invsqrt", m_max=6, tol=0.0, orth="lanczos")
+    assert st["iters"] == 6 and st["mvms"] == orc.mvms
+    assert_close(host(x), orc.x, 1e-10)
+    d = np.repeat([0.5, 1.5, 4.0, 9.0], 300)
+    n = d.size
+    op = fa().CSR(np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d,
+                  hermitian=True)
+    op.poly_setup(0)
+    bd = wl.rhs(n, seed=3)
+    for kind, f in (("invsqrt", d ** -0.5), ("sqrt", d ** 0.5)):
+        x, st = op.apply(dev(bd), kind=kind, m_max=50, tol=1e-12, check_every=10)
+        assert st["breakdown"] == 1 and st["iters"] == 4
+        assert_close(host(x), f * bd, 1e-12)
