@@ -39,9 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE x 1.00, the factors of a 2 GiB copy), from the rocprofv3 counter
 # runs in profiles/st7_multi_convdiff128_deg16_hbm_counters.md
 MULTI_TRAFFIC_BYTES = {3: (73777 + 32768) * 1024, 4: (83750 + 32768) * 1024}
-# the same at the larger grids of the chain leg beyond the Infinity Cache,
-# keyed by (N, NT); empty until measured for the current kernel
-BIG_TRAFFIC_BYTES = {}
+# the same at the larger grid of the chain leg beyond the 256 MB Infinity
+# Cache, keyed by (N, NT), from profiles/st7_multi_convdiff256_deg16_hbm_counters.md
+BIG_TRAFFIC_BYTES = {(256, 4): (263503 * 2 + 262144) * 1024}
 
 
 def log(msg):
@@ -69,6 +69,12 @@ def main():
     ap.add_argument("--csr-only", action="store_true", help="only run the CSR SpMV leg")
     ap.add_argument("--wilson-only", action="store_true", help="only run the Wilson leg")
     ap.add_argument("--serve-only", action="store_true", help="only run the serving leg")
+    ap.add_argument("--poisson-only", action="store_true",
+                    help="only run the 2D Poisson 32 x 32 leg (no oracle)")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="only run two plain Arnoldi solves each on the 128^3 "
+                         "convection-diffusion and the 16^4 Wilson operators (Gram-Schmidt "
+                         "sweeps over bases of up to 448 and 192 vectors)")
     ap.add_argument("--qps", type=float, default=2000.0, help="serving arrival rate")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-workers", type=int, default=8)
@@ -106,6 +112,12 @@ def main():
         return
     if args.serve_only:
         print(json.dumps({"serving": serving_leg(args, fa, torch, wl, dev)}), flush=True)
+        return
+    if args.poisson_only:
+        print(json.dumps({"poisson2d_32": poisson_leg(fa, torch, wl, dev, None)}), flush=True)
+        return
+    if args.plain_only:
+        print(json.dumps({"plain": plain_leg(fa, torch, wl, dev)}), flush=True)
         return
     N = args.N
     dims = (N, N, N)
@@ -347,6 +359,33 @@ def main():
         **extra,
     }
     print(json.dumps(line), flush=True)
+
+
+def plain_leg(fa, torch, wl, dev):
+    """Two plain Arnoldi solves (degree 0, tol 1e-8) each on the 128^3
+    convection-diffusion operator (m = 448, real) and the 16^4 Wilson
+    operator (m = 192, complex): the delayed-CGS2 sweeps at every basis size
+    up to those (the first solve of each warms up)."""
+    out = {}
+    N = 128
+    op = fa.Stencil7((N, N, N), wl.convdiff_stencil(N, 50.0), device=dev)
+    op.poly_setup(0)
+    b = torch.from_numpy(wl.rhs(N ** 3, seed=0)).to(dev)
+    for _ in range(2):
+        _, st = op.apply(b, m_max=1000, tol=1e-8)
+    out["convdiff3d_128"] = {"iters": st["iters"], "ms": st["ms_total"]}
+    op.release_workspace()
+    del op, b
+    op = fa.Wilson(wl.su3_links(16, eps=0.3, seed=1), 0.05, device=dev)
+    op.poly_setup(0)
+    b = torch.from_numpy(wl.rhs(op.n, seed=0, complex_=True)).to(dev)
+    for _ in range(2):
+        _, st = op.apply(b, m_max=1000, tol=1e-8)
+    out["wilson4d_16"] = {"iters": st["iters"], "ms": st["ms_total"]}
+    op.release_workspace()
+    for k, v in out.items():
+        log(f"plain {k}: m = {v['iters']}, {v['ms']:.1f} ms")
+    return out
 
 
 def poisson_leg(fa, torch, wl, dev, orc):

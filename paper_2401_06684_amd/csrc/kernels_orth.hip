@@ -25,6 +25,33 @@ constexpr int kThreads = 256;
 constexpr int kRpt = 8;  // rows per thread in the GEMV sweeps
 constexpr int kCb = 4;   // columns per reduction round in project
 
+// The projections on complex vectors reduce 2 columns per round instead of
+// 4: with 4 columns of two complex vectors the round's loads and sums held
+// 146 registers (three waves per SIMD) and the two-vector sweep ran at
+// 3.45 TB/s on the 16^4 lattice; measured over rows per thread {2, 4, 8}
+// x columns per round {1, 2, 3, 4} (2048 / rows threads per workgroup, the
+// same 2048 rows per workgroup and so the same partial sums layout), 8 rows
+// and 2 columns reach 4.7 TB/s at bases of 64 to 191 vectors.
+#ifndef FA_PROJ_CPLX_RPT
+#define FA_PROJ_CPLX_RPT 8
+#endif
+#ifndef FA_PROJ_CPLX_CB
+#define FA_PROJ_CPLX_CB 2
+#endif
+template <typename T>
+constexpr int proj_rpt() {
+  return sizeof(T) == 16 ? FA_PROJ_CPLX_RPT : kRpt;
+}
+// columns per reduction round of the projections
+template <typename T>
+constexpr int proj_cb() {
+  return sizeof(T) == 16 ? FA_PROJ_CPLX_CB : kCb;
+}
+template <typename T>
+constexpr int proj_threads() {
+  return kThreads * kRpt / proj_rpt<T>();
+}
+
 RedPlan red_plan(int64_t n) {
   RedPlan p;
   p.rows = kThreads * kRpt;
@@ -47,49 +74,48 @@ __device__ __forceinline__ T block_sum(T v, T* sh /* [4] */) {
 }
 
 // part[c * nblk + blk] = sum over the block's rows of conj(V[r, c]) w[r]
-template <typename T>
-__global__ __launch_bounds__(kThreads) void project_k(int64_t n, int ncols, const T* __restrict__ V,
+template <typename T, int RPT = proj_rpt<T>(), int NTH = proj_threads<T>(), int CB = proj_cb<T>()>
+__global__ __launch_bounds__(NTH) void project_k(int64_t n, int ncols, const T* __restrict__ V,
                                                       int64_t ldv, const T* __restrict__ w,
                                                       T* __restrict__ part, int nblk) {
-  __shared__ T red[kThreads / 64][kCb];
+  __shared__ T red[NTH / 64][CB];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t r0 = (int64_t)blockIdx.x * (kThreads * kRpt) + tid;
-  T wr[kRpt];
+  const int64_t r0 = (int64_t)blockIdx.x * (NTH * RPT) + tid;
+  T wr[RPT];
 #pragma unroll
-  for (int q = 0; q < kRpt; ++q) {
-    const int64_t r = r0 + (int64_t)q * kThreads;
+  for (int q = 0; q < RPT; ++q) {
+    const int64_t r = r0 + (int64_t)q * NTH;
     wr[q] = (r < n) ? w[r] : zero(T{});
   }
-  const bool full = r0 + (int64_t)(kRpt - 1) * kThreads < n;
-  for (int c0 = 0; c0 < ncols; c0 += kCb) {
-    T acc[kCb];
+  const bool full = r0 + (int64_t)(RPT - 1) * NTH < n;
+  for (int c0 = 0; c0 < ncols; c0 += CB) {
+    T acc[CB];
 #pragma unroll
-    for (int cc = 0; cc < kCb; ++cc) {
+    for (int cc = 0; cc < CB; ++cc) {
       acc[cc] = zero(T{});
       if (c0 + cc < ncols) {
         const T* col = V + (int64_t)(c0 + cc) * ldv + r0;
         if (full) {
 #pragma unroll
-          for (int q = 0; q < kRpt; ++q) acc[cc] = cmad(col[q * kThreads], wr[q], acc[cc]);
+          for (int q = 0; q < RPT; ++q) acc[cc] = cmad(col[q * NTH], wr[q], acc[cc]);
         } else {
 #pragma unroll
-          for (int q = 0; q < kRpt; ++q)
-            if (r0 + (int64_t)q * kThreads < n) acc[cc] = cmad(col[q * kThreads], wr[q], acc[cc]);
+          for (int q = 0; q < RPT; ++q)
+            if (r0 + (int64_t)q * NTH < n) acc[cc] = cmad(col[q * NTH], wr[q], acc[cc]);
         }
       }
     }
 #pragma unroll
-    for (int cc = 0; cc < kCb; ++cc) acc[cc] = wave_sum(acc[cc]);
+    for (int cc = 0; cc < CB; ++cc) acc[cc] = wave_sum(acc[cc]);
     if (lane == 0) {
 #pragma unroll
-      for (int cc = 0; cc < kCb; ++cc) red[wv][cc] = acc[cc];
+      for (int cc = 0; cc < CB; ++cc) red[wv][cc] = acc[cc];
     }
     __syncthreads();
-    if (tid < kCb && c0 + tid < ncols) {
+    if (tid < CB && c0 + tid < ncols) {
       T s = red[0][tid];
-      s += red[1][tid];
-      s += red[2][tid];
-      s += red[3][tid];
+#pragma unroll
+      for (int w = 1; w < NTH / 64; ++w) s += red[w][tid];
       part[(int64_t)(c0 + tid) * nblk + blockIdx.x] = s;
     }
     __syncthreads();
@@ -238,42 +264,42 @@ hipError_t launch_ls_step(int dtype, int64_t n, int k, void* W, int64_t ldv, con
 //   update2  : q_j = (u_j - Q_j s) / nu (in place of u_j) and
 //              u_{j+1} = (z - Q_j p - q_j gamma) / nu (in place of z)
 // --------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kThreads) void project2_k(int64_t n, int ncols,
+template <typename T, int RPT = proj_rpt<T>(), int NTH = proj_threads<T>(), int CB = proj_cb<T>()>
+__global__ __launch_bounds__(NTH) void project2_k(int64_t n, int ncols,
                                                        const T* __restrict__ V, int64_t ldv,
                                                        const T* __restrict__ w0,
                                                        const T* __restrict__ w1,
                                                        T* __restrict__ part, int nblk) {
-  __shared__ T red[kThreads / 64][2 * kCb];
+  __shared__ T red[NTH / 64][2 * CB];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t r0 = (int64_t)blockIdx.x * (kThreads * kRpt) + tid;
-  T a0[kRpt], a1[kRpt];
+  const int64_t r0 = (int64_t)blockIdx.x * (NTH * RPT) + tid;
+  T a0[RPT], a1[RPT];
 #pragma unroll
-  for (int q = 0; q < kRpt; ++q) {
-    const int64_t r = r0 + (int64_t)q * kThreads;
+  for (int q = 0; q < RPT; ++q) {
+    const int64_t r = r0 + (int64_t)q * NTH;
     a0[q] = (r < n) ? w0[r] : zero(T{});
     a1[q] = (r < n) ? w1[r] : zero(T{});
   }
-  const bool full = r0 + (int64_t)(kRpt - 1) * kThreads < n;
-  for (int c0 = 0; c0 < ncols; c0 += kCb) {
-    T acc[2 * kCb];
+  const bool full = r0 + (int64_t)(RPT - 1) * NTH < n;
+  for (int c0 = 0; c0 < ncols; c0 += CB) {
+    T acc[2 * CB];
 #pragma unroll
-    for (int cc = 0; cc < kCb; ++cc) {
+    for (int cc = 0; cc < CB; ++cc) {
       acc[2 * cc] = acc[2 * cc + 1] = zero(T{});
       if (c0 + cc < ncols) {
         const T* col = V + (int64_t)(c0 + cc) * ldv + r0;
         if (full) {  // no row checks: all loads of the round issue together
 #pragma unroll
-          for (int q = 0; q < kRpt; ++q) {
-            const T v = col[q * kThreads];
+          for (int q = 0; q < RPT; ++q) {
+            const T v = col[q * NTH];
             acc[2 * cc] = cmad(v, a0[q], acc[2 * cc]);
             acc[2 * cc + 1] = cmad(v, a1[q], acc[2 * cc + 1]);
           }
         } else {
 #pragma unroll
-          for (int q = 0; q < kRpt; ++q) {
-            if (r0 + (int64_t)q * kThreads < n) {
-              const T v = col[q * kThreads];
+          for (int q = 0; q < RPT; ++q) {
+            if (r0 + (int64_t)q * NTH < n) {
+              const T v = col[q * NTH];
               acc[2 * cc] = cmad(v, a0[q], acc[2 * cc]);
               acc[2 * cc + 1] = cmad(v, a1[q], acc[2 * cc + 1]);
             }
@@ -282,17 +308,16 @@ __global__ __launch_bounds__(kThreads) void project2_k(int64_t n, int ncols,
       }
     }
 #pragma unroll
-    for (int e = 0; e < 2 * kCb; ++e) acc[e] = wave_sum(acc[e]);
+    for (int e = 0; e < 2 * CB; ++e) acc[e] = wave_sum(acc[e]);
     if (lane == 0) {
 #pragma unroll
-      for (int e = 0; e < 2 * kCb; ++e) red[wv][e] = acc[e];
+      for (int e = 0; e < 2 * CB; ++e) red[wv][e] = acc[e];
     }
     __syncthreads();
-    if (tid < 2 * kCb && c0 + tid / 2 < ncols) {
+    if (tid < 2 * CB && c0 + tid / 2 < ncols) {
       T t = red[0][tid];
-      t += red[1][tid];
-      t += red[2][tid];
-      t += red[3][tid];
+#pragma unroll
+      for (int w = 1; w < NTH / 64; ++w) t += red[w][tid];
       part[(int64_t)(2 * c0 + tid) * nblk + blockIdx.x] = t;
     }
     __syncthreads();
@@ -545,7 +570,7 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
   const size_t lds = 2 * (size_t)(j + 1) * es;
   const bool fused = lds <= 32768 && j <= 32;
   if (dtype == FA_C128) {
-    project2_k<cplx><<<p.nblk, kThreads, 0, s>>>(n, j + 1, (const cplx*)V, ldv, (const cplx*)u,
+    project2_k<cplx><<<p.nblk, proj_threads<cplx>(), 0, s>>>(n, j + 1, (const cplx*)V, ldv, (const cplx*)u,
                                                  (const cplx*)z, (cplx*)part, p.nblk);
     if (fused) {
       dcgs2_finish_k<cplx><<<1, kFinThreads, lds, s>>>(j, p.nblk, (const cplx*)part, (cplx*)H,
@@ -562,7 +587,7 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
                                                 (const cplx*)cp, (const cplx*)sc, (cplx*)u,
                                                 (cplx*)z);
   } else {
-    project2_k<double><<<p.nblk, kThreads, 0, s>>>(n, j + 1, (const double*)V, ldv,
+    project2_k<double><<<p.nblk, proj_threads<double>(), 0, s>>>(n, j + 1, (const double*)V, ldv,
                                                    (const double*)u, (const double*)z,
                                                    (double*)part, p.nblk);
     if (fused) {
@@ -589,7 +614,7 @@ template <typename T>
 static hipError_t project_t(int64_t n, int ncols, const T* V, int64_t ldv, const T* w, T* part,
                             T* h, T* hsum, int mode, hipStream_t s) {
   const RedPlan p = red_plan(n);
-  project_k<T><<<p.nblk, kThreads, 0, s>>>(n, ncols, V, ldv, w, part, p.nblk);
+  project_k<T><<<p.nblk, proj_threads<T>(), 0, s>>>(n, ncols, V, ldv, w, part, p.nblk);
   reduce_cols_k<T><<<ncols, kThreads, 0, s>>>(p.nblk, part, h, hsum, mode);
   return hipGetLastError();
 }
