@@ -15,8 +15,10 @@ which every GPU result's true error is taken, and the median of 3 timed
 oracle solves of the headline configuration.  Extra fields: every degree of
 the configuration (0 = plain Arnoldi, 4, 16, 32) for A^{-1/2} b and A^{1/2} b,
 one launch per term, mixed precision, the chain at 256^3 (beyond the 256 MB
-Infinity Cache), the 2D Poisson 32 x 32 configuration, the Wilson 16^4 and CSR
-legs, the batched leg (64 right-hand sides) and the serving workload: Poisson
+Infinity Cache), the 2D Poisson 32 x 32 configuration, Table 1's workload
+(the 3D Laplacian on 100^3, right preconditioning, one and two passes at the
+printed iteration counts, true errors against the closed form), the Wilson
+16^4 and CSR legs, the batched leg (64 right-hand sides) and the serving workload: Poisson
 arrivals of a request mix (2D Laplacian 256^2, convection-diffusion 64^3 /
 96^3 / 128^3, Wilson 16^4; f in {sqrt, invsqrt}, tol in {1e-6, 1e-10}) through
 the library's request loop, with solves/s and p50/p99 latency.
@@ -71,6 +73,8 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="only run the serving leg")
     ap.add_argument("--poisson-only", action="store_true",
                     help="only run the 2D Poisson 32 x 32 leg (no oracle)")
+    ap.add_argument("--table1-only", action="store_true",
+                    help="only run Table 1's 100^3 Laplacian rows (no closed-form errors)")
     ap.add_argument("--plain-only", action="store_true",
                     help="only run two plain Arnoldi solves each on the 128^3 "
                          "convection-diffusion and the 16^4 Wilson operators (Gram-Schmidt "
@@ -115,6 +119,10 @@ def main():
         return
     if args.poisson_only:
         print(json.dumps({"poisson2d_32": poisson_leg(fa, torch, wl, dev, None)}), flush=True)
+        return
+    if args.table1_only:
+        print(json.dumps({"table1_laplace3d_100": table1_leg(fa, torch, wl, dev, None)}),
+              flush=True)
         return
     if args.plain_only:
         print(json.dumps({"plain": plain_leg(fa, torch, wl, dev)}), flush=True)
@@ -308,6 +316,9 @@ def main():
     # ---- 2D Poisson 32 x 32 (CSR, Lanczos), the small configuration ---------
     extra["poisson2d_32"] = poisson_leg(fa, torch, wl, dev, orc)
 
+    # ---- Table 1's workload: the 3D Laplacian on 100^3 ------------------------
+    extra["table1_laplace3d_100"] = table1_leg(fa, torch, wl, dev, orc)
+
     # ---- Wilson 16^4 (the lattice operator) --------------------------------
     extra["wilson4d_16"] = wilson_leg(fa, torch, wl, dev)
 
@@ -325,6 +336,7 @@ def main():
     cpu = None
     if orc is not None:
         orc.pop("poisson2d_32_ref", None)
+        orc.pop("table1_ref", None)
         cpu = orc
 
     line = {
@@ -430,6 +442,55 @@ def poisson_leg(fa, torch, wl, dev, orc):
                if orc is not None else ""))
     op.release_workspace()
     return out
+
+
+def table1_leg(fa, torch, wl, dev, orc):
+    """Sec. 6, Example 1, Table 1's workload: the 3D Laplacian on 100^3
+    interior points (n = 10^6, Hermitian: Lanczos), b ~ N(0, 1) seed 0 scaled
+    to unit norm, Chebyshev q with d coefficients on the exact interval, right
+    preconditioning (Algorithm 2).  Each row runs the printed iteration count
+    as a fixed m (the same mvms and inner products as the printed row), one
+    pass (1P, y_j stored) and two passes (2P, O(n) memory), median of 3;
+    the true error is against the DST closed form the oracle leg computed.
+    The printed times are context (MATLAB on an 8-core laptop CPU)."""
+    import numpy as np
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests",
+                                    "golden", "table1_laplace3d.json")))
+    N = g["N"]
+    op = fa.Stencil7((N, N, N), wl.laplace_stencil(3), hermitian=True, device=dev)
+    b = wl.rhs(N ** 3, seed=0)
+    b = torch.from_numpy(b / np.linalg.norm(b)).to(dev)
+    x = torch.empty_like(b)
+    ref = torch.from_numpy(orc["table1_ref"]).to(dev) if orc is not None else None
+    rows = []
+    for r in g["rows"]:
+        d, m = r["d"], r["iterations"]
+        op.poly_setup(d - 1, "cheb")
+        row = {"d": d, "iterations": m}
+        for name, tp in (("1P", False), ("2P", True)):
+            op.apply(b, m_max=m, tol=0.0, right=True, two_pass=tp, out=x)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                _, st = op.apply(b, m_max=m, tol=0.0, right=True, two_pass=tp, out=x)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            t = float(np.median(ts))
+            row[f"ms_{name}"] = t * 1e3
+            row[f"mvms_{name}"] = st["mvms"]
+            row[f"inner_products_{name}"] = st["inner_products"]
+            row[f"printed_s_{name}"] = r[f"time_{name}_s"]
+            if ref is not None:
+                row[f"rel_err_{name}_vs_closed_form"] = float(
+                    torch.linalg.vector_norm(x - ref) / torch.linalg.vector_norm(ref))
+        rows.append(row)
+        log(f"Table 1 d = {d:2d}, m = {m:3d}: 1P {row['ms_1P']:7.2f} ms, 2P {row['ms_2P']:7.2f} ms"
+            + (f", error {row['rel_err_1P_vs_closed_form']:.1e} / "
+               f"{row['rel_err_2P_vs_closed_form']:.1e}" if ref is not None else ""))
+        op.release_workspace()
+    return {"workload": "laplace3d_100^3 invsqrt, Chebyshev, right preconditioning, fixed m = "
+                        "the printed iterations", "rows": rows}
 
 
 def wilson_leg(fa, torch, wl, dev):
@@ -764,11 +825,12 @@ def cpu_baseline(coeffs, dims, degree, tol):
       configuration (degree `degree`, tol `tol`), timed; the polynomial setup
       and the host H_j^{-1/2} e_1 evaluations are reported apart;
     * the 2D Poisson 32 x 32 configuration: oracle seconds per solve at
-      degrees 0 and 8 (tol 1e-10, Lanczos) and tol-1e-12 references."""
+      degrees 0 and 8 (tol 1e-10, Lanczos) and tol-1e-12 references;
+    * Table 1's workload (100^3 Laplacian): the DST closed form of A^{-1/2} b."""
     import numpy as np
 
     import workloads as wl
-    from oracle import krylov, operators, polynomials
+    from oracle import exact, krylov, operators, polynomials
 
     try:
         from threadpoolctl import threadpool_info
@@ -828,6 +890,11 @@ def cpu_baseline(coeffs, dims, degree, tol):
             p2[f"degree_{deg}"] = {"s_per_solve": float(np.median(ts)), "iters": r2.iters}
             p2ref[deg] = krylov.fAb(A2, b2, q2, "invsqrt", m_max=200, tol=1e-12,
                                     orth="lanczos").x
+        # Table 1's workload (Sec. 6, Example 1): the closed form of A^{-1/2} b
+        N1 = 100
+        b1 = wl.rhs(N1 ** 3, seed=0)
+        b1 = b1 / np.linalg.norm(b1)
+        t1ref = exact.stencil_fAb_dst(wl.laplace_stencil(3), (N1, N1, N1), b1, "invsqrt")
     finally:
         krylov.hessenberg_invsqrt_e1 = inner
     med = sorted(runs, key=lambda r: r["s_total"])[1]
@@ -845,7 +912,8 @@ def cpu_baseline(coeffs, dims, degree, tol):
             "reference_solve": {"degree": 32, "tol": 1e-12, "iters": ref.iters,
                                 "s": t_ref},
             "poisson2d_32": p2,
-            "x_ref_invsqrt": ref.x, "x_ref_sqrt": x_sqrt, "poisson2d_32_ref": p2ref}
+            "x_ref_invsqrt": ref.x, "x_ref_sqrt": x_sqrt, "poisson2d_32_ref": p2ref,
+            "table1_ref": t1ref}
 
 
 if __name__ == "__main__":

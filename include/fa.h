@@ -114,12 +114,16 @@ enum {
                             group that fits: three, a pair or a single term)    */
   FA_FUSE3 = 2048u,      /* apply: at most three recurrence terms per launch        */
   FA_TWO_PASS = 64u,     /* apply: two-pass Lanczos (Hermitian op, not with
-                            FA_FORCE_ARNOLDI or FA_RIGHT_PREC, else
-                            FA_ERR_UNSUPPORTED): pass 1 keeps three basis vectors
-                            and computes H_m and z_m = H_m^{-1/2} e_1 ||c||; pass 2
-                            regenerates v_1..v_m with the same kernels and
-                            accumulates x = sum_i z_i v_i.  Workspace O(n), about
-                            twice the products with A.                            */
+                            FA_FORCE_ARNOLDI, else FA_ERR_UNSUPPORTED): pass 1
+                            keeps three basis vectors and computes H_m and
+                            z_m = H_m^{-1/2} e_1 ||c||; pass 2 regenerates
+                            v_1..v_m with the same kernels and accumulates
+                            x = sum_i z_i v_i.  Workspace O(n), about twice the
+                            products with A.  With FA_RIGHT_PREC (Algorithm 2)
+                            x = q(A) (V_m z_m), one more q(A) at the end, and
+                            only a fixed m (tol <= 0; else FA_ERR_UNSUPPORTED:
+                            the right variant's stopping estimate needs the
+                            stored y_j).                                         */
   FA_RIGHT_PREC = 128u,  /* apply: right preconditioning (Algorithm 2): the basis of
                             K_m(A q(A)^2, b), y_j = q(A) v_j stored, x = Y_m z_m with
                             z_m = H_m^{-1/2} e_1 ||b||.  The stopping estimate is

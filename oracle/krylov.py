@@ -114,14 +114,16 @@ def fAb(apply_A, b, poly: Poly | None = None, kind="invsqrt", m_max=100, tol=1e-
     difference-of-iterates estimate; with x_true given the true relative error
     ||f_j - x_true|| / ||x_true|| is tested instead (as in Example 1's tables).
     tol <= 0 runs exactly m_max steps.
-    two_pass (Lanczos, left): the first pass keeps only the three-term
+    two_pass (Lanczos): the first pass keeps only the three-term
     coefficients (and the two latest vectors); after it stops, a second pass
     regenerates the basis with the same coefficients and accumulates
     x = V_m z_m, so no basis is stored and the products with A double (the
-    two-pass Lanczos of Sec. 6, Example 1).
+    two-pass Lanczos of Sec. 6, Example 1).  With side "right" the iterate
+    Y_m z_m is q(A) (V_m z_m), one more q(A) after pass 2; there the
+    stopping estimate would need the y_j, so only a fixed m (tol <= 0) is run.
     """
     if two_pass:
-        return _two_pass_lanczos(apply_A, b, poly or one(), kind, m_max, tol, check_every)
+        return _two_pass_lanczos(apply_A, b, poly or one(), kind, m_max, tol, check_every, side)
     poly = poly or one()
     b = np.asarray(b)
     dt = np.result_type(b, 1.0)
@@ -249,8 +251,13 @@ def fAb(apply_A, b, poly: Poly | None = None, kind="invsqrt", m_max=100, tol=1e-
                   V=V[:, :m + 1].copy() if keep_basis else None, history=history)
 
 
-def _two_pass_lanczos(apply_A, b, poly, kind, m_max, tol, check_every):
-    """Two-pass Lanczos for Hermitian A q(A)^2 (Sec. 6, Example 1)."""
+def _two_pass_lanczos(apply_A, b, poly, kind, m_max, tol, check_every, side="left"):
+    """Two-pass Lanczos for Hermitian A q(A)^2 (Sec. 6, Example 1), with
+    the start vector and product of Algorithm 1 (left) or Algorithm 2 (right)."""
+    if side not in ("left", "right"):
+        raise ValueError("side must be 'left' or 'right'")
+    if side == "right" and tol > 0.0:
+        raise ValueError("two-pass with right preconditioning runs a fixed m (tol <= 0)")
     b = np.asarray(b)
     dt = np.result_type(b, 1.0)
     mvms = 0
@@ -266,9 +273,15 @@ def _two_pass_lanczos(apply_A, b, poly, kind, m_max, tol, check_every):
         mvms += k
         return y.astype(dt, copy=False)
 
+    def start():  # Algorithm 1: c = q(A) b; Algorithm 2: b itself
+        return Q(b) if side == "left" else np.array(b, dtype=dt)
+
+    def product(v):  # Algorithm 1: q(A) q(A) A v; Algorithm 2: A q(A) q(A) v
+        return Q(Q(A(v))) if side == "left" else A(Q(Q(v))).astype(dt, copy=False)
+
     if kind == "sqrt":
         b = A(b).astype(dt, copy=False)
-    c = Q(b)
+    c = start()
     beta = float(np.linalg.norm(c))
     n = b.size
     if beta == 0.0:
@@ -286,7 +299,7 @@ def _two_pass_lanczos(apply_A, b, poly, kind, m_max, tol, check_every):
     ips = 0
     history = []
     for j in range(m_max):
-        w = Q(Q(A(v)))
+        w = product(v)
         if j > 0:
             w = w - off[j - 1] * v_prev
         alpha[j] = np.real(np.vdot(v, w))
@@ -312,16 +325,18 @@ def _two_pass_lanczos(apply_A, b, poly, kind, m_max, tol, check_every):
                 break
     z = tridiagonal_invsqrt_e1(alpha[:m], off[:m - 1], beta)
     # pass 2: regenerate v_1..v_m with the stored coefficients and combine
-    c = Q(b)
+    c = start()
     v_prev = np.zeros(n, dtype=dt)
     v = c / beta
     x = z[0] * v
     for j in range(m - 1):
-        w = Q(Q(A(v)))
+        w = product(v)
         if j > 0:
             w = w - off[j - 1] * v_prev
         w = w - alpha[j] * v
         v_prev, v = v, w / off[j]
         x = x + z[j + 1] * v
+    if side == "right":
+        x = Q(x)  # Y_m z_m = q(A) V_m z_m
     return Result(x=x, iters=m, converged=converged, breakdown=breakdown, mvms=mvms,
                   inner_products=ips, est=est, checks=checks, history=history)

@@ -189,7 +189,8 @@ class Operator:
         3, 2, or False / 1 for one launch per term);
         mixed=True runs the polynomial chain in FP32 (stencil, Chebyshev q);
         two_pass=True runs two-pass Lanczos (O(n) basis storage);
-        right=True runs the right-preconditioned variant (Algorithm 2);
+        right=True runs the right-preconditioned variant (Algorithm 2; with
+        two_pass only at a fixed m, tol <= 0);
         orth="cgs2" runs both Gram-Schmidt passes in every Arnoldi step
         (default "dcgs2": the second pass delayed by one step).
         """

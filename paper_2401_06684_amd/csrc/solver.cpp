@@ -42,10 +42,11 @@ Layout make_layout(const Op& op, int m_max, uint32_t flags, bool with_poly) {
     return o;
   };
   // two-pass Lanczos keeps a ring of three basis vectors; right
-  // preconditioning also stores y_j = q(A) v_j
-  const int nbasis = (flags & FA_TWO_PASS) ? 3 : m_max + 1;
+  // preconditioning also stores y_j = q(A) v_j (two-pass: only the latest)
+  const bool two_pass = (flags & FA_TWO_PASS) != 0;
+  const int nbasis = two_pass ? 3 : m_max + 1;
   L.off_V = take((size_t)nbasis * L.ldv * es);
-  L.off_Y = (flags & FA_RIGHT_PREC) ? take((size_t)m_max * L.ldv * es) : 0;
+  L.off_Y = (flags & FA_RIGHT_PREC) ? take((size_t)(two_pass ? 1 : m_max) * L.ldv * es) : 0;
   L.off_U = take((size_t)L.ldv * es);
   L.off_P = take((size_t)L.ldv * es);
   L.off_Q = take((size_t)L.ldv * es);
@@ -582,7 +583,9 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   const bool two_pass = (flags & FA_TWO_PASS) != 0;
   // Algorithm 2 (right preconditioning); with q == 1 it is Algorithm 1
   const bool right = (flags & FA_RIGHT_PREC) && K > 0;
-  if (two_pass && (!lanczos || (flags & FA_RIGHT_PREC))) return FA_ERR_UNSUPPORTED;
+  // two-pass with Algorithm 2: fixed m only (its stopping estimate needs the
+  // stored y_j, which the two-pass form does not keep)
+  if (two_pass && (!lanczos || (right && tol > 0.0))) return FA_ERR_UNSUPPORTED;
   // Arnoldi: CGS2 with the reorthogonalization delayed by one step (one sweep
   // of projections and one of updates per step), unless FA_CGS2 asks for the
   // two classical passes in each step; the right-preconditioned variant keeps
@@ -607,7 +610,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   double* nrm = (double*)at(ws, L.off_nrm);
   void* zd = at(ws, L.off_z);
   auto Vc = [&](int j) -> char* { return V + (size_t)(two_pass ? j % 3 : j) * L.ldv * es; };
-  auto Yc = [&](int j) -> char* { return Y + (size_t)j * L.ldv * es; };
+  auto Yc = [&](int j) -> char* { return Y + (size_t)(two_pass ? 0 : j) * L.ldv * es; };
   auto Hcol = [&](int j) -> char* { return Hd + (size_t)j * L.ldh * es; };
   // entry H(i, j) (Lanczos: i in {j, j + 1})
   auto Hent = [&](int i, int j) -> char* {
@@ -1070,7 +1073,8 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   }
   if (two_pass) {
     // second pass: regenerate v_1..v_m with the same (deterministic) kernels
-    // and accumulate x = sum_i z_i v_i, the basis never stored
+    // and accumulate x = sum_i z_i v_i, the basis never stored; Algorithm 2's
+    // Y_m z_m = q(A) (V_m z_m) takes one more q(A) at the end
     st = z_to_device(z, m, true, zd);
     if (st) return st;
     st = start_vector();
@@ -1081,6 +1085,12 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       if (st) return st;
       FA_HIP(launch_update(op.dtype, n, 1, Vc(j + 1), L.ldv, (char*)zd + (size_t)(j + 1) * es,
                            d_x, part, nullptr, s));
+    }
+    if (right) {
+      const void* r = nullptr;
+      st = poly_apply(op, q, d_x, U, tmp, &r, s, pp, &mvms, fuse, P64, P64, wls);
+      if (st) return st;
+      if (r != d_x) FA_HIP(launch_scale(op.dtype, n, cd(1.0), r, d_x, s));
     }
   } else {
     // f_m = V_m z_m (Algorithm 1) or Y_m z_m (Algorithm 2)

@@ -953,6 +953,33 @@ def test_two_pass_lanczos(degree, kind):
     assert op.workspace_bytes(3000, tp) - op.workspace_bytes(300, tp) < 64 * (3000 - 300)
 
 
+@pytest.mark.parametrize("degree", [0, 4])
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+def test_two_pass_right_fixed_m(degree, kind):
+    """Two-pass with Algorithm 2 (Table 1's 2P column) at a fixed m: the
+    oracle's right two-pass iterate, the GPU's one-pass right iterate, and the
+    count of two passes plus the final q(A)."""
+    N = 20
+    dims = (N, N, N)
+    coeffs = wl.laplace_stencil(3)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    op = fa().Stencil7(dims, coeffs, hermitian=True)
+    op.poly_setup(degree, "cheb")
+    a, bb = ops.stencil_interval(coeffs, dims)
+    q = pl.chebyshev(a, bb, degree)
+    b = wl.rhs(op.n, seed=0)
+    m = 24
+    x1, s1 = op.apply(dev(b), kind=kind, m_max=m, tol=0.0, right=True)
+    x2, s2 = op.apply(dev(b), kind=kind, m_max=m, tol=0.0, right=True, two_pass=True)
+    assert s1["iters"] == s2["iters"] == m
+    assert_close(host(x2), host(x1), 1e-12)
+    orc = kr.fAb(A, b, q, kind, m_max=m, tol=0.0, orth="lanczos", side="right", two_pass=True)
+    assert s2["mvms"] == orc.mvms
+    assert_close(host(x2), orc.x, 1e-10)
+    tp = fa().FA_TWO_PASS | fa()._lib.FA_RIGHT_PREC
+    assert op.workspace_bytes(300, tp) < op.workspace_bytes(300, fa()._lib.FA_RIGHT_PREC) / 10
+
+
 def test_variant_flag_errors():
     dims = (8, 8, 8)
     coeffs = wl.convdiff_stencil(8, 10.0)
@@ -966,8 +993,9 @@ def test_variant_flag_errors():
         op.apply(b, right=True, mixed=True)
     oph = fa().Stencil7(dims, wl.laplace_stencil(3), hermitian=True)
     oph.poly_setup(4, "cheb")
-    with pytest.raises(fa().FAError):
-        oph.apply(b, two_pass=True, right=True)
+    with pytest.raises(fa().FAError) as e:  # right two-pass: a fixed m only
+        oph.apply(b, two_pass=True, right=True, tol=1e-8)
+    assert e.value.status == fa()._lib.FA_ERR_UNSUPPORTED
     with pytest.raises(fa().FAError):
         oph.apply(b, two_pass=True, force_arnoldi=True)
 

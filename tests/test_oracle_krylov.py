@@ -325,6 +325,33 @@ def test_two_pass_lanczos_equals_one_pass(degree):
     assert rel(two.x, exact.stencil_fAb_dst(coeffs, dims, b)) < 1e-9
 
 
+@pytest.mark.parametrize("degree", [0, 4])
+def test_two_pass_right_equals_one_pass_right(degree):
+    """Two-pass with Algorithm 2 at a fixed m: the iterate Y_m z_m of the
+    one-pass right variant (which stores the y_j), the DST closed form once
+    converged, and the operation count of two passes plus one q(A)."""
+    N = 20
+    dims = (N, N, N)
+    coeffs = wl.laplace_stencil(3)
+    A = lambda v: ops.stencil_apply(coeffs, dims, v)
+    a, bb = ops.stencil_interval(coeffs, dims)
+    q = pl.chebyshev(a, bb, degree)
+    b = wl.rhs(N ** 3, seed=0)
+    m = 120 if degree == 0 else 30
+    one = kr.fAb(A, b, q, "invsqrt", m_max=m, tol=0.0, orth="lanczos", side="right")
+    two = kr.fAb(A, b, q, "invsqrt", m_max=m, tol=0.0, orth="lanczos", side="right",
+                 two_pass=True)
+    assert two.iters == one.iters == m
+    assert rel(two.x, one.x) < 1e-12
+    assert rel(two.x, exact.stencil_fAb_dst(coeffs, dims, b)) < 1e-9
+    # pass 1: m steps; pass 2: m - 1 steps and the final q(A)
+    assert two.mvms == (2 * m - 1) * (2 * degree + 1) + degree
+    # the right variant's stopping estimate needs the stored y_j
+    with pytest.raises(ValueError):
+        kr.fAb(A, b, q, "invsqrt", m_max=m, tol=1e-8, orth="lanczos", side="right",
+               two_pass=True)
+
+
 # --------------------------------------------------------------------------
 # the stopping estimate against the iterates it stands for
 # --------------------------------------------------------------------------
