@@ -429,8 +429,9 @@ int fa_dense_tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, 
  *
  * The block form of Algorithm 1 (an extension: the paper treats one
  * right-hand side): C = q(A) B' = V_1 R_0 (B' = B, or A B for FA_SQRT);
- * each step W = q(A) (q(A) (A V_j)) on the whole block (one stencil launch per
- * recurrence term for all s columns), classical block Gram-Schmidt twice as
+ * each step W = q(A) (q(A) (A V_j)) on the s columns as one batch (the
+ * single-vector stencil launches, up to four recurrence terms each, over all
+ * columns at once), classical block Gram-Schmidt twice as
  * FP64 matrix-core products (H(:, j) = [V_1..V_j]^T W summed over both
  * passes), W = V_{j+1} H_{j+1,j} by Cholesky QR twice; every k steps
  * Z_j = H_j^{-1/2} E_1 R_0 (coupled Newton-Schulz iteration on the device, FP64)
@@ -443,7 +444,8 @@ typedef struct {
   int32_t breakdown;   /* the new block vanished (invariant block space)      */
   int32_t checks;
   int32_t ns_iters;    /* Newton-Schulz iterations of the last H^{-1/2}       */
-  int32_t zc;          /* z-planes per workgroup of the stencil (autotuned)   */
+  int32_t zc;          /* z-planes per workgroup of the row-major block
+                          stencil launches (A B for FA_SQRT, A V_j with q = 1) */
   int32_t graph_steps; /* block steps replayed from (or captured into) graphs */
   int32_t reserved;
   int64_t mvms;        /* products of A with single vectors (s per block)    */

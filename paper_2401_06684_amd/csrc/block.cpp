@@ -13,8 +13,13 @@
 //   X = [V_1..V_m] Z.
 //
 // Blocks are row-major n x s (the s values of a grid point contiguous), the
-// basis FP64; with FA_MIXED the stencil chain runs in FP32 storage with FP32
-// arithmetic and writes the FP64 block W, everything else stays FP64.
+// basis FP64, for the Gram-Schmidt products.  The stencil chain of a step
+// runs on the s columns as a batch of s vectors: V_j is moved to column-major
+// order, A and q(A) twice run as the single-vector chain launches (up to four
+// Clenshaw terms per launch, the intermediate terms on chip) over the whole
+// batch, and the result is moved back into the row-major W.  With FA_MIXED
+// the chain runs in FP32 storage with FP32 arithmetic; everything else stays
+// FP64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,6 +32,11 @@
 
 #include "fa_internal.hpp"
 #include "solver.hpp"
+
+// workgroups the multi-term chain launches aim at over the batch of columns
+#ifndef FA_BLK_MULTI_BLOCKS
+#define FA_BLK_MULTI_BLOCKS 1536
+#endif
 
 namespace fa {
 
@@ -227,83 +237,33 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
   BLK_HIP(hipMemsetAsync(H, 0, (size_t)(L.M + s) * L.ldh * 8, st));
   BLK_HIP(hipMemsetAsync(flag, 0, (size_t)(m_max + 2) * sizeof(int), st));
 
-  // q(A) applied to a block: x (precision px) -> out (precision pout) using
-  // the chain scratch blocks `tmp` (four, none of them x or out).  Two terms
-  // per launch (the intermediate term stays on chip; launch outputs never
-  // alias their inputs, so the pairs alternate between two scratch sets), an
-  // odd last term alone; one term per launch if x is not in the chain
-  // precision.
-  const std::vector<Term> T = K > 0 ? poly_terms(q) : std::vector<Term>();
-  // z-planes per workgroup of the block stencil (tuned at the first A V_j)
-  const std::vector<int64_t> zc_key{1, op.dims[0], op.dims[1], op.dims[2], s, (int)pc};
-  // ... and of the two-term launches (tuned at the first one)
-  const std::vector<int64_t> pair_key{2, op.dims[0], op.dims[1], op.dims[2], s, (int)pc};
-  int zc = 8;
-  {
-    std::lock_guard<std::mutex> g(tuner().mu);
-    auto it = tuner().best.find(zc_key);
-    if (it != tuner().best.end()) zc = it->second;
-  }
+  // z-planes per workgroup of the row-major block stencil launches (A B for
+  // the square root, A V_j without a polynomial)
+  const int zc = 8;
   hipStream_t cur = st;  // the stream the step launches go to (captured with FA_GRAPH)
-  auto qblock = [&](const void* x, Prec px, void* out, Prec pout, void* const tmp[4]) -> int {
-    const int nT = (int)T.size();
-    const void* xm1 = x;
-    const void* xm2 = nullptr;
-    Prec pm1 = px;
-    int i = 0;
-    if (px == pc) {
-      int set = 0;
-      for (; i + 2 <= nT; i += 2) {
-        const bool has_next = i + 2 < nT;  // a later launch reads out_{i}
-        void* o1 = has_next ? tmp[2 * set] : nullptr;
-        void* o2 = has_next ? tmp[2 * set + 1] : out;
-        ChainCoef k1 = T[i].k, k2 = T[i + 1].k;
-        if (!T[i].y0) k1.g0 = 0.0;
-        if (!T[i + 1].y0) k2.g0 = 0.0;
-        if (!T[i + 1].y1) k2.g1 = 0.0;
-        // z-march length of the pair launches: tuned at the first one (a
-        // pair recomputes s on two planes and reads x on four beyond its
-        // slab, so it wants longer slabs than a single term)
-        const void* y1 = T[i].y1 ? xm2 : nullptr;
-        const Prec po = has_next ? pc : pout;
-        int chosen = 0;
-        const int r = tune_pick(
-            pair_key, {8, 16, 32}, cur,
-            [&](int c) {
-              return launch_blk_chain_pair(op, s, xm1, x, y1, o1, o2, k1, k2, pc, po, cur, c);
-            },
-            &chosen, &S.ms_tune);
-        if (r) return r;
-        xm2 = o1;
-        xm1 = o2;
-        set ^= 1;
-      }
-      if (i < nT) {  // an odd last term alone, straight into out (which is
-        // none of its inputs)
-        BLK_HIP(launch_blk_chain(op, s, xm1, T[i].y0 ? x : nullptr, T[i].y1 ? xm2 : nullptr, out,
-                                 T[i].k, pc, px, pout, cur, zc));
-      }
-      mvms += (int64_t)K * s;
-      return FA_OK;
-    }
-    void* slot[2] = {tmp[0], tmp[1]};
-    for (; i < nT; ++i) {
-      const bool last = i == nT - 1;
-      void* dst = last ? out : ((i >= 2 && T[i].y1) ? (void*)xm2 : slot[i & 1]);
-      if (dst == xm1) dst = slot[(i + 1) & 1];
-      const Prec po = last ? pout : pc;
-      // the first term reads x (precision px); later terms read the chain
-      // precision, and y0 = x must then be in the chain precision too
-      BLK_HIP(launch_blk_chain(op, s, xm1, T[i].y0 ? x : nullptr, T[i].y1 ? xm2 : nullptr, dst,
-                               T[i].k, pm1, px, po, cur, zc));
-      xm2 = xm1;
-      xm1 = dst;
-      pm1 = po;
-    }
-    mvms += (int64_t)K * s;
+  // the op as a batch of s column vectors of n (the chain scratch blocks hold
+  // s * n values of the chain precision)
+  Op opb = op;
+  opb.nbatch = s;
+  opb.bstride = n;
+  opb.multi_blocks = FA_BLK_MULTI_BLOCKS;
+  // q(A) on the batch in column-major x (chain precision; x is overwritten):
+  // the result is x or one of tmp
+  auto qcols = [&](void* x, void* const tmp[4], void** res) -> int {
+    const void* r = nullptr;
+    int64_t mv = 0;
+    const int e = poly_apply_chain(opb, x, x, tmp, &r, cur, &mv, pc);
+    if (e) return e;
+    mvms += mv * s;
+    *res = const_cast<void*>(r);
     return FA_OK;
   };
-
+  // the four of C[0..4] that are not `y`
+  auto others = [&](const void* y, void* (&t)[4]) {
+    int c = 0;
+    for (int i = 0; i < 5; ++i)
+      if (C[i] != y && c < 4) t[c++] = C[i];
+  };
   // P (ldp) = [V_1..V_nb]^T W with the split-K chunk count tuned per shape
   auto proj = [&](int nb, const double* Vp, int64_t vb, const double* W, double* P,
                   int ldp) -> int {
@@ -386,15 +346,13 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
   }
   if (K == 0) {
     BLK_HIP(hipMemcpyAsync(Vb(0), Bp, (size_t)n * s * 8, hipMemcpyDeviceToDevice, st));
-  } else if (mixed) {
-    BLK_HIP(launch_blk_to_f32(n * s, Bp, (float*)C[4], st));
-    void* const tq[4] = {C[0], C[1], C[2], C[3]};
-    int r = qblock(C[4], P32, Vb(0), P64, tq);
+  } else {  // C = q(A) B' on the columns
+    BLK_HIP(launch_blk_rows_to_cols(n, s, Bp, C[0], pc, st));
+    void* const tq[4] = {C[1], C[2], C[3], C[4]};
+    void* res = nullptr;
+    int r = qcols(C[0], tq, &res);
     if (r) return r;
-  } else {
-    void* const tq[4] = {C[0], C[1], C[2], C[3]};
-    int r = qblock(Bp, P64, Vb(0), P64, tq);
-    if (r) return r;
+    BLK_HIP(launch_blk_cols_to_rows(n, s, res, pc, Vb(0), st));
   }
   {
     int r = cholqr2(Vb(0), R0, s, m_max + 1);
@@ -416,26 +374,27 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
                                P64, P64, P64, cur, zc));
       mvms += s;
     } else {
-      // U = A V_j (chain precision; the z-march length is tuned on this
-      // launch), then q twice, the last launch writes FP64 W
+      // V_j to columns (FP64, in W, free until the end of the step), U = A V_j
+      // in the chain precision, then q(A) twice on the batch, and the result
+      // back to rows in W
+      BLK_HIP(launch_blk_rows_to_cols(n, s, Vb(j), W, P64, cur));
+      BLK_HIP(launch_chain(opb, W, nullptr, nullptr, C[0], ChainCoef{1.0, 0.0, 0.0, 0.0}, cur,
+                           P64, pc));
+      mvms += s;
+      void* y = nullptr;
       {
-        const int r = tune_pick(
-            zc_key, {4, 8, 16}, cur,
-            [&](int c) {
-              return launch_blk_chain(op, s, Vb(j), nullptr, nullptr, C[0],
-                                      ChainCoef{1.0, 0.0, 0.0, 0.0}, P64, P64, pc, cur, c);
-            },
-            &zc, &S.ms_tune);
+        void* const t1[4] = {C[1], C[2], C[3], C[4]};
+        const int r = qcols(C[0], t1, &y);
         if (r) return r;
       }
-      mvms += s;
-      // (W, free until the second q(A) writes it, is scratch for the first)
-      void* const t1[4] = {C[2], C[3], C[4], W};
-      int r = qblock(C[0], pc, C[1], pc, t1);
-      if (r) return r;
-      void* const t2[4] = {C[0], C[2], C[3], C[4]};
-      r = qblock(C[1], pc, W, P64, t2);
-      if (r) return r;
+      void* w = nullptr;
+      {
+        void* t2[4];
+        others(y, t2);
+        const int r = qcols(y, t2, &w);
+        if (r) return r;
+      }
+      BLK_HIP(launch_blk_cols_to_rows(n, s, w, pc, W, cur));
     }
     // block CGS2: H(0:(j+1)s, js:(j+1)s) = P1 + P2
     const int nb = j + 1;
@@ -461,17 +420,10 @@ int block_apply(const Op& op, int kind, int s, const void* d_B, void* d_X, int m
   // run step j: replayed from a captured graph when FA_GRAPH is set and its
   // launch parameters are tuned already, else launched one by one
   auto run_step = [&](int j) -> int {
-    const bool tuned = (K == 0 || is_tuned(zc_key)) && (K < 2 || is_tuned(pair_key)) &&
-                       is_tuned({0, n, s, j + 1}) && is_tuned({0, n, s, 1});
+    const bool tuned = is_tuned({0, n, s, j + 1}) && is_tuned({0, n, s, 1});
     if (!use_graph || !tuned) return do_step(j);
-    int zc2 = 0;  // the pair launches' z-march
-    {
-      std::lock_guard<std::mutex> g(tuner().mu);
-      auto it = tuner().best.find(pair_key);
-      if (it != tuner().best.end()) zc2 = it->second;
-    }
     const std::vector<int64_t> key{(int64_t)op.uid, (int64_t)op.poly_version, (int64_t)(uintptr_t)ws,
-                                   s, m_max, mixed ? 1 : 0, j, zc, n, zc2};
+                                   s, m_max, mixed ? 1 : 0, j, zc, n};
     hipGraphExec_t exec = nullptr;
     {
       std::lock_guard<std::mutex> g(graphs().mu);

@@ -70,6 +70,12 @@ struct Op {
   // stencil
   int dims[4] = {1, 1, 1, 1};
   double coef[7] = {0, 0, 0, 0, 0, 0, 0};
+  // a batch of nbatch vectors, bstride elements apart, in each stencil chain
+  // launch (set on a copy of the op by the block solver); multi_blocks: the
+  // workgroup count the multi-term launches aim at (0: the default)
+  int nbatch = 1;
+  int64_t bstride = 0;
+  int multi_blocks = 0;
   // Wilson: the links in the structure-of-arrays order Us[mu][e][s] (e the
   // row-major 3x3 element), in the caller's operator memory
   const void* links = nullptr;
@@ -230,16 +236,12 @@ hipError_t launch_ls_step(int dtype, int64_t n, int k, void* W, int64_t ldv, con
 hipError_t launch_blk_chain(const Op& op, int s, const void* x, const void* y0, const void* y1,
                             void* out, const ChainCoef& k, Prec px, Prec py, Prec po,
                             hipStream_t st, int zc = 8);
-// two consecutive terms on a block (7-point stencil):
-//   s = k1.alpha A x + k1.beta x + k1.g0 v + k1.g1 y1 (y1 null: no term),
-//   out1 = s (if out1), out2 = k2.alpha A s + k2.beta s + k2.g0 v + k2.g1 x;
-// x, v, y1 in precision pin, out1 in pin, out2 in pout; outputs must not
-// alias inputs; zc = planes per workgroup
-hipError_t launch_blk_chain_pair(const Op& op, int s, const void* x, const void* v,
-                                 const void* y1, void* out1, void* out2, const ChainCoef& k1,
-                                 const ChainCoef& k2, Prec pin, Prec pout, hipStream_t st,
-                                 int zc = 8);
-hipError_t launch_blk_to_f32(int64_t count, const double* x, float* y, hipStream_t st);
+// a row-major n x s FP64 block to s vectors of n (column c at c * n; FP64 or
+// FP32: py) and back; s in {16, 32, 64}; no aliasing
+hipError_t launch_blk_rows_to_cols(int64_t n, int s, const double* X, void* Y, Prec py,
+                                   hipStream_t st);
+hipError_t launch_blk_cols_to_rows(int64_t n, int s, const void* Y, Prec py, double* X,
+                                   hipStream_t st);
 // one workgroup: ha[0:na) = a, hb[0:nb) = b (ha, hb, flag in page-locked
 // coherent host memory, device-accessible), then *flag = seq once the copies
 // are visible to the host

@@ -4,10 +4,11 @@
 // n x s block at p * s + c, so the s values of one grid point are contiguous
 // (one wavefront row of 64 lanes for s = 64).
 //
-//   st7_blk_k    : one recurrence term of q(A) on a block, 7-point stencil:
-//                  out = alpha A X + beta X + g0 Y0 + g1 Y1
-//   st7_blk_pair_k : two consecutive terms in one launch (the intermediate
-//                  term kept on chip)
+//   st7_blk_k    : one recurrence term on a block, 7-point stencil:
+//                  out = alpha A X + beta X + g0 Y0 + g1 Y1 (A B for the
+//                  square root, A V_j without a polynomial; with a polynomial
+//                  the chain runs on the columns as a batch of vectors)
+//   blk_rows_to_cols_k / blk_cols_to_rows_k : a block to s vectors and back
 //   blk_proj_k   : split-K partial products V_i^T W (block Gram-Schmidt, Gram
 //                  matrices), FP64 MFMA 16x16x4
 //   gemm_k       : C = alpha A B + beta C, FP64 MFMA 16x16x4 (block updates
@@ -208,291 +209,86 @@ hipError_t launch_blk_chain(const Op& op, int s, const void* x, const void* y0, 
 }
 
 // --------------------------------------------------------------------------
-// two consecutive recurrence terms on a block (7-point stencil):
-//   s = a1 A x + b1 x + e01 v + e11 y1,   out1 = s (if out1),
-//   out2 = a2 A s + b2 s + e02 v + e12 x
-// s never leaves the chip: 5 block passes for 2 terms instead of 8.
+// layout changes between a row-major n x s block (FP64) and s vectors of n
+// (column c at c * n, FP64 or FP32): a workgroup moves 64 points x s columns
+// through LDS, reading and writing 64 consecutive values per wavefront
 // --------------------------------------------------------------------------
-// Workgroup tile: PX points along x, 4 lines along y, all S columns, marching
-// along z; 1024 threads, each owning CW columns (16 bytes: 4 FP32 or 2 FP64
-// values) of one tile point and of one point of the ring around the tile
-// (the tile grown by one point, where s is needed for the second term's
-// in-plane neighbours).  Step p computes s(p) on the tile and the ring (x's
-// in-plane neighbours read from memory and cache, its z-neighbours kept in
-// registers), then the second term at plane p - 1 on the tile (s's in-plane
-// neighbours from an LDS plane buffer, its z-neighbours from registers), then
-// stores s(p) into the other buffer: one barrier per plane.  Outputs must
-// not alias inputs (neighbouring tiles read x around their own).
-struct BlkPairCoef {
-  double a1, b1, e01, e11, a2, b2, e02, e12;
-};
-template <int S, int CW>
-struct BlkPairGeo {
-  static constexpr int CG = S / CW;          // column groups, one per thread
-  static constexpr int PY = 4;               // tile lines along y
-  static constexpr int PX = 1024 / (PY * CG);  // tile points along x
-  static constexpr int RW = PX + 2, RH = PY + 2;  // the grown tile
-  static constexpr int RING = 2 * RW + 2 * PY;    // its points outside the tile
-  static_assert(PX * PY * CG == 1024 && RING <= PX * PY, "one tile and one ring point per thread");
-};
-
-// CW consecutive values (16 bytes of U = T) or their conversion
-template <int CW, typename U, typename T>
-__device__ __forceinline__ void ldw(const U* p, T (&v)[CW]) {
-  if constexpr (CW == 4) {
-    U u[4];
-    ld4(p, u);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = (T)u[q];
-  } else {
-    static_assert(std::is_same<U, double>::value && CW == 2, "two doubles");
-    const double2 a = *reinterpret_cast<const double2*>(p);
-    v[0] = (T)a.x;
-    v[1] = (T)a.y;
-  }
-}
-template <int CW, typename U, typename T>
-__device__ __forceinline__ void stw(U* p, const T (&v)[CW]) {
-  if constexpr (CW == 4) {
-    U u[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) u[q] = (U)v[q];
-    st4(p, u);
-  } else {
-    static_assert(std::is_same<U, double>::value && CW == 2, "two doubles");
-    *reinterpret_cast<double2*>(p) = double2{(double)v[0], (double)v[1]};
-  }
-}
-
-template <typename TX, typename TO, int S, bool Y1G, bool W1>
-__global__ __launch_bounds__(1024) void st7_blk_pair_k(BlkSt7 g, int gx, int gy,
-                                                       const TX* __restrict__ x,
-                                                       const TX* __restrict__ v,
-                                                       const TX* __restrict__ y1,
-                                                       TO* __restrict__ out1,
-                                                       TO* __restrict__ out2, BlkPairCoef cf) {
-  using T = blk_calc_t<TX, TX, TO>;
-  constexpr int CW = 16 / (int)sizeof(T);
-  using G = BlkPairGeo<S, CW>;
-  __shared__ T sb[2][G::RW * G::RH * S];
+template <typename TC, int S>
+__global__ __launch_bounds__(256) void blk_rows_to_cols_k(int64_t n, const double* __restrict__ X,
+                                                          TC* __restrict__ Y) {
+  __shared__ double t[S][65];
+  constexpr int E = 64 * S / 256;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
   const int tid = threadIdx.x;
-  const int cg = tid % G::CG, pt = tid / G::CG;
-  const int c = CW * cg;
-  const int lid = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int bx = lid % gx, by = (lid / gx) % gy, bz = lid / (gx * gy);
-  const int i0 = bx * G::PX, j0 = by * G::PY;
-  const int k0 = bz * g.zc, k1 = min(k0 + g.zc, g.nz);
-  const int64_t ls = (int64_t)g.nx * S;  // one line of the block
-  const int64_t ps = ls * g.ny;          // one plane of the block
-  const T c0 = (T)g.c0, cxm = (T)g.cxm, cxp = (T)g.cxp, cym = (T)g.cym, cyp = (T)g.cyp,
-          czm = (T)g.czm, czp = (T)g.czp;
-  const T a1 = (T)cf.a1, b1 = (T)cf.b1, e01 = (T)cf.e01, e11 = (T)cf.e11;
-  const T a2 = (T)cf.a2, b2 = (T)cf.b2, e02 = (T)cf.e02, e12 = (T)cf.e12;
-  const bool has_ring = pt < G::RING;
-
-  // u = 0: the tile point, u = 1: ring point pt (threads past the ring size
-  // compute ring point 0 but store nothing: with no branch around the ring
-  // work, the loads of both points issue together, 5 % faster in FP32)
-  int ra[2], rb[2];  // coordinates in the grown tile
-  ra[0] = pt % G::PX + 1;
-  rb[0] = pt / G::PX + 1;
-  {
-    const int h = has_ring ? pt : 0;
-    if (h < G::RW) {
-      ra[1] = h;
-      rb[1] = 0;
-    } else if (h < 2 * G::RW) {
-      ra[1] = h - G::RW;
-      rb[1] = G::RH - 1;
-    } else {
-      const int r = h - 2 * G::RW;
-      ra[1] = (r / G::PY) ? G::RW - 1 : 0;
-      rb[1] = 1 + r % G::PY;
-    }
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int e = tid + 256 * k, p = e / S, c = e % S;
+    t[c][p] = p0 + p < n ? X[(p0 + p) * S + c] : 0.0;
   }
-  bool ing[2];     // the point lies in the grid
-  int64_t off[2];  // its in-plane offset (clamped into the grid)
-  int nbm[2];      // bits 0..3: neighbour W, E, S, N inside the grid
-  int li[2];       // LDS index of the point (grown-tile layout, column c)
+  __syncthreads();
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int i = i0 - 1 + ra[u], j = j0 - 1 + rb[u];
-    ing[u] = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
-    off[u] = (int64_t)min(max(j, 0), g.ny - 1) * ls + (int64_t)min(max(i, 0), g.nx - 1) * S + c;
-    // a neighbour of a point outside the grid is never used (that point's
-    // value is zero); the bits then stay clear and the loads read `off`
-    nbm[u] = ing[u] ? ((i > 0) | ((i + 1 < g.nx) << 1) | ((j > 0) << 2) | ((j + 1 < g.ny) << 3))
-                    : 0;
-    li[u] = (rb[u] * G::RW + ra[u]) * S + c;
-  }
-  auto pin = [&](int p) { return p >= 0 && p < g.nz; };
-  auto poff = [&](int p) { return (int64_t)min(max(p, 0), g.nz - 1) * ps; };
-
-  T xr[2][3][CW];  // x at planes p - 1, p, p + 1 of each point
-  T sr[3][CW];     // s at planes p - 2, p - 1, p of the tile point
-  T vk[CW];        // v at plane p - 1 of the tile point
-#pragma unroll
-  for (int q = 0; q < CW; ++q) sr[0][q] = sr[1][q] = sr[2][q] = vk[q] = T(0);
-  auto load_pt = [&](const TX* base, int p, int u, T (&r)[CW]) {
-    ldw<CW>(base + poff(p) + off[u], r);
-    const bool z = pin(p) && ing[u];
-#pragma unroll
-    for (int q = 0; q < CW; ++q) r[q] = z ? r[q] : T(0);
-  };
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    load_pt(x, k0 - 2, u, xr[u][1]);
-    load_pt(x, k0 - 1, u, xr[u][2]);
-  }
-  for (int p = k0 - 1; p <= k1; ++p) {
-    // x(p - 1), x(p) into place, x(p + 1) loaded
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-#pragma unroll
-      for (int q = 0; q < CW; ++q) {
-        xr[u][0][q] = xr[u][1][q];
-        xr[u][1][q] = xr[u][2][q];
-      }
-      load_pt(x, p + 1, u, xr[u][2]);
-    }
-    // s(p) on the tile point and the ring point
-    T sp[2][CW], vp[CW];
-    const bool zp = pin(p);
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const bool live = zp && ing[u];
-      T as[CW], w[CW];
-#pragma unroll
-      for (int q = 0; q < CW; ++q) {
-        as[q] = c0 * xr[u][1][q];
-        as[q] = fma(czm, xr[u][0][q], as[q]);
-        as[q] = fma(czp, xr[u][2][q], as[q]);
-      }
-      const TX* xb = x + poff(p) + off[u];
-      const int64_t dn[4] = {-S, S, -ls, ls};
-      const T cn[4] = {cxm, cxp, cym, cyp};
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        const bool in = (nbm[u] >> d) & 1;
-        ldw<CW>(xb + (in ? dn[d] : 0), w);
-#pragma unroll
-        for (int q = 0; q < CW; ++q) as[q] = fma(cn[d], in ? w[q] : T(0), as[q]);
-      }
-      T vv[CW], yy[CW];
-      ldw<CW>(v + poff(p) + off[u], vv);
-      if (Y1G) ldw<CW>(y1 + poff(p) + off[u], yy);
-#pragma unroll
-      for (int q = 0; q < CW; ++q) {
-        T val = fma(a1, as[q], b1 * xr[u][1][q]);
-        val = fma(e01, live ? vv[q] : T(0), val);
-        if (Y1G) val = fma(e11, live ? yy[q] : T(0), val);
-        sp[u][q] = live ? val : T(0);
-        if (u == 0) vp[q] = live ? vv[q] : T(0);
-      }
-    }
-    // the second term at plane p - 1 on the tile point
-    const int pm = p - 1;
-    if (pm >= k0 && pm < k1) {
-      const T* L = sb[pm & 1] + li[0];
-      T nw[CW], ne[CW], ns[CW], nn[CW];
-      ldw<CW>(L - S, nw);
-      ldw<CW>(L + S, ne);
-      ldw<CW>(L - G::RW * S, ns);
-      ldw<CW>(L + G::RW * S, nn);
-      T o2[CW], o1[CW];
-#pragma unroll
-      for (int q = 0; q < CW; ++q) {
-        const T sc = sr[2][q];  // s(p - 1)
-        T as = c0 * sc;
-        as = fma(czm, sr[1][q], as);
-        as = fma(czp, sp[0][q], as);
-        as = fma(cxm, nw[q], as);
-        as = fma(cxp, ne[q], as);
-        as = fma(cym, ns[q], as);
-        as = fma(cyp, nn[q], as);
-        T val = fma(a2, as, b2 * sc);
-        val = fma(e02, vk[q], val);
-        val = fma(e12, xr[0][0][q], val);
-        o2[q] = val;
-        o1[q] = sc;
-      }
-      if (ing[0]) {
-        stw<CW>(out2 + (int64_t)pm * ps + off[0], o2);
-        if (W1) stw<CW>(out1 + (int64_t)pm * ps + off[0], o1);
-      }
-    }
-    // s(p) into its plane buffer
-    stw<CW>(&sb[p & 1][li[0]], sp[0]);
-    if (has_ring) stw<CW>(&sb[p & 1][li[1]], sp[1]);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < CW; ++q) {
-      sr[1][q] = sr[2][q];
-      sr[2][q] = sp[0][q];
-      vk[q] = vp[q];
-    }
+  for (int k = 0; k < E; ++k) {
+    const int f = tid + 256 * k, c = f / 64, p = f % 64;
+    if (p0 + p < n) Y[(int64_t)c * n + p0 + p] = (TC)t[c][p];
   }
 }
 
-template <typename TX, typename TO, int S>
-static hipError_t st7_blk_pair_s(const BlkSt7& g, const void* x, const void* v, const void* y1,
-                                 void* out1, void* out2, const BlkPairCoef& cf, hipStream_t st) {
-  using G = BlkPairGeo<S, 16 / (int)sizeof(blk_calc_t<TX, TX, TO>)>;
-  const int gx = (g.nx + G::PX - 1) / G::PX, gy = (g.ny + G::PY - 1) / G::PY;
-  const int grid = gx * gy * ((g.nz + g.zc - 1) / g.zc);
-  const TX *X = (const TX*)x, *Vp = (const TX*)v, *Y = (const TX*)y1;
-  TO *O1 = (TO*)out1, *O2 = (TO*)out2;
-#define FA_BLK_PAIR(A, B) \
-  st7_blk_pair_k<TX, TO, S, A, B><<<grid, 1024, 0, st>>>(g, gx, gy, X, Vp, Y, O1, O2, cf)
-  if (y1 && out1)
-    FA_BLK_PAIR(true, true);
-  else if (y1)
-    FA_BLK_PAIR(true, false);
-  else if (out1)
-    FA_BLK_PAIR(false, true);
+template <typename TC, int S>
+__global__ __launch_bounds__(256) void blk_cols_to_rows_k(int64_t n, const TC* __restrict__ Y,
+                                                          double* __restrict__ X) {
+  __shared__ double t[S][65];
+  constexpr int E = 64 * S / 256;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int f = tid + 256 * k, c = f / 64, p = f % 64;
+    t[c][p] = p0 + p < n ? (double)Y[(int64_t)c * n + p0 + p] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int e = tid + 256 * k, p = e / S, c = e % S;
+    if (p0 + p < n) X[(p0 + p) * S + c] = t[c][p];
+  }
+}
+
+template <typename TC>
+static hipError_t rows_to_cols_t(int64_t n, int s, const double* X, TC* Y, hipStream_t st) {
+  const int grid = (int)((n + 63) / 64);
+  if (s == 64)
+    blk_rows_to_cols_k<TC, 64><<<grid, 256, 0, st>>>(n, X, Y);
+  else if (s == 32)
+    blk_rows_to_cols_k<TC, 32><<<grid, 256, 0, st>>>(n, X, Y);
   else
-    FA_BLK_PAIR(false, false);
-#undef FA_BLK_PAIR
+    blk_rows_to_cols_k<TC, 16><<<grid, 256, 0, st>>>(n, X, Y);
   return hipGetLastError();
 }
 
-template <typename TX, typename TO>
-static hipError_t st7_blk_pair_t(const BlkSt7& g, int s, const void* x, const void* v,
-                                 const void* y1, void* out1, void* out2, const BlkPairCoef& cf,
-                                 hipStream_t st) {
-  if (s == 64) return st7_blk_pair_s<TX, TO, 64>(g, x, v, y1, out1, out2, cf, st);
-  if (s == 32) return st7_blk_pair_s<TX, TO, 32>(g, x, v, y1, out1, out2, cf, st);
-  return st7_blk_pair_s<TX, TO, 16>(g, x, v, y1, out1, out2, cf, st);
-}
-
-hipError_t launch_blk_chain_pair(const Op& op, int s, const void* x, const void* v,
-                                 const void* y1, void* out1, void* out2, const ChainCoef& k1,
-                                 const ChainCoef& k2, Prec pin, Prec pout, hipStream_t st,
-                                 int zc) {
-  if (zc < 1 || !x || !v || !out2 || (s != 16 && s != 32 && s != 64))
-    return hipErrorInvalidValue;
-  BlkSt7 g{op.dims[0], op.dims[1], op.dims[2], zc, op.coef[0], op.coef[1], op.coef[2],
-           op.coef[3], op.coef[4], op.coef[5], op.coef[6]};
-  const BlkPairCoef cf{k1.alpha.real(), k1.beta.real(), k1.g0.real(), k1.g1.real(),
-                       k2.alpha.real(), k2.beta.real(), k2.g0.real(), k2.g1.real()};
-  if (pin == P64 && pout == P64)
-    return st7_blk_pair_t<double, double>(g, s, x, v, y1, out1, out2, cf, st);
-  if (pin == P32 && pout == P32)
-    return st7_blk_pair_t<float, float>(g, s, x, v, y1, out1, out2, cf, st);
-  if (pin == P32 && pout == P64 && !out1)
-    return st7_blk_pair_t<float, double>(g, s, x, v, y1, out1, out2, cf, st);
-  return hipErrorInvalidValue;
-}
-
-__global__ __launch_bounds__(256) void blk_to_f32_k(int64_t n, const double* __restrict__ x,
-                                                    float* __restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) y[i] = (float)x[i];
-}
-
-hipError_t launch_blk_to_f32(int64_t count, const double* x, float* y, hipStream_t st) {
-  blk_to_f32_k<<<(int)((count + 255) / 256), 256, 0, st>>>(count, x, y);
+template <typename TC>
+static hipError_t cols_to_rows_t(int64_t n, int s, const TC* Y, double* X, hipStream_t st) {
+  const int grid = (int)((n + 63) / 64);
+  if (s == 64)
+    blk_cols_to_rows_k<TC, 64><<<grid, 256, 0, st>>>(n, Y, X);
+  else if (s == 32)
+    blk_cols_to_rows_k<TC, 32><<<grid, 256, 0, st>>>(n, Y, X);
+  else
+    blk_cols_to_rows_k<TC, 16><<<grid, 256, 0, st>>>(n, Y, X);
   return hipGetLastError();
+}
+
+hipError_t launch_blk_rows_to_cols(int64_t n, int s, const double* X, void* Y, Prec py,
+                                   hipStream_t st) {
+  if (s != 16 && s != 32 && s != 64) return hipErrorInvalidValue;
+  return py == P64 ? rows_to_cols_t<double>(n, s, X, (double*)Y, st)
+                   : rows_to_cols_t<float>(n, s, X, (float*)Y, st);
+}
+
+hipError_t launch_blk_cols_to_rows(int64_t n, int s, const void* Y, Prec py, double* X,
+                                   hipStream_t st) {
+  if (s != 16 && s != 32 && s != 64) return hipErrorInvalidValue;
+  return py == P64 ? cols_to_rows_t<double>(n, s, (const double*)Y, X, st)
+                   : cols_to_rows_t<float>(n, s, (const float*)Y, X, st);
 }
 
 // --------------------------------------------------------------------------
@@ -527,8 +323,12 @@ template <> struct DVec<4> {
   }
 };
 
+#ifndef FA_PROJ_NS
+#define FA_PROJ_NS 2
+#endif
 template <int T>
-__global__ __launch_bounds__(256) void blk_proj_k(int64_t n, const double* __restrict__ V,
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(FA_PROJ_NS <= 2 ? 2 : 1))) void blk_proj_k(int64_t n, const double* __restrict__ V,
                                                   int64_t v_blk, const double* __restrict__ W,
                                                   double* __restrict__ part, int64_t chunk,
                                                   int nb) {
@@ -553,7 +353,8 @@ __global__ __launch_bounds__(256) void blk_proj_k(int64_t n, const double* __res
   // load scheduled above them would need another register and a copy of an
   // unfinished load, i.e. a wait).  Rows past the chunk load a clamped row
   // and count as zero.
-  constexpr int NS = 4;
+  constexpr int NS = FA_PROJ_NS;
+  static_assert(NS == 2 || NS == 4, "two or four register slots");
   if (r_beg < r_end) {
     DVec<T> av[NS], bv[NS];
     auto fetch = [&](int64_t r0, auto slot) {
@@ -576,13 +377,17 @@ __global__ __launch_bounds__(256) void blk_proj_k(int64_t n, const double* __res
     const int64_t first = r_beg + 4 * wv;
     fetch(first, std::integral_constant<int, 0>());
     fetch(first + 16, std::integral_constant<int, 1>());
-    fetch(first + 32, std::integral_constant<int, 2>());
-    fetch(first + 48, std::integral_constant<int, 3>());
+    if constexpr (NS == 4) {
+      fetch(first + 32, std::integral_constant<int, 2 % NS>());
+      fetch(first + 48, std::integral_constant<int, 3 % NS>());
+    }
     for (int64_t r0 = first; r0 < r_end; r0 += 16 * NS) {
       use(r0, std::integral_constant<int, 0>());
       use(r0 + 16, std::integral_constant<int, 1>());
-      use(r0 + 32, std::integral_constant<int, 2>());
-      use(r0 + 48, std::integral_constant<int, 3>());
+      if constexpr (NS == 4) {
+        use(r0 + 32, std::integral_constant<int, 2 % NS>());
+        use(r0 + 48, std::integral_constant<int, 3 % NS>());
+      }
     }
   }
   // wave w adds its tiles into red in turn (w = 0 stores)
@@ -652,22 +457,30 @@ hipError_t launch_blk_proj(int64_t n, int s, int nb, const double* V, int64_t v_
 // 16 k, MFMA step q of lane group g takes k = 4 g + q (one 32-byte load of A
 // per lane), and in column tile t the MFMA column j stands for column
 // T j + t (one T-wide load of B per k, and T-wide stores of C).
-template <int T>
+template <int T, int R>
 __global__ __launch_bounds__(256) void gemm_k(int64_t M, int K, double alpha,
                                               const double* __restrict__ A, int64_t a_blk,
                                               int64_t lda, int kb, const double* __restrict__ B,
                                               int64_t ldb, double beta, double* C, int64_t ldc) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int rl = lane >> 4, cl = lane & 15;
-  const int64_t r0 = (int64_t)blockIdx.x * 64 + wv * 16;
+  const int64_t r0 = (int64_t)blockIdx.x * 64 * R + wv * 16 * R;
   const int c0 = blockIdx.y * 16 * T;
   if (r0 >= M) return;
-  dx4 acc[T];
+  dx4 acc[R][T];
 #pragma unroll
-  for (int t = 0; t < T; ++t) acc[t] = dx4{0.0, 0.0, 0.0, 0.0};
-  const int64_t ra = r0 + cl;  // the A row this lane supplies
-  const bool arow = ra < M;
-  const double* Ab = A + ra * lda + 4 * rl;
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[r][t] = dx4{0.0, 0.0, 0.0, 0.0};
+  // the A rows this lane supplies (row tile r: r0 + 16 r + cl)
+  bool arow[R];
+  const double* Abase[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t ra = r0 + 16 * r + cl;
+    arow[r] = ra < M;
+    Abase[r] = (arow[r] ? A + ra * lda : A) + 4 * rl;
+  }
   const double* Bb = B + (int64_t)(4 * rl) * ldb + c0 + T * cl;
   const int per = kb / 16;  // groups of 16 k per column block of A
   const int ng = K / 16;
@@ -676,25 +489,29 @@ __global__ __launch_bounds__(256) void gemm_k(int64_t M, int K, double alpha,
   // only after its MFMAs (no copy of a register a load is still filling).
   // Groups past the end load the last group again and count as zero; rows
   // past M load row 0 and count as zero.
-  const double* Abase = arow ? Ab : A + 4 * rl;
-  dx4 a4[2];
+  dx4 a4[2][R];
   DVec<T> bq[2][4];
   auto fetch = [&](int g, auto slot) {
     constexpr int S = decltype(slot)::value;
     const int gc = min(g, ng - 1);
     const int blk = gc / per, kk = (gc - blk * per) * 16;
-    a4[S] = *reinterpret_cast<const dx4*>(Abase + (int64_t)blk * a_blk + kk);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      a4[S][r] = *reinterpret_cast<const dx4*>(Abase[r] + (int64_t)blk * a_blk + kk);
     const double* Bk = Bb + (int64_t)gc * 16 * ldb;
 #pragma unroll
     for (int q = 0; q < 4; ++q) bq[S][q] = DVec<T>::load(Bk + (int64_t)q * ldb);
   };
   auto use = [&](int g, auto slot) {
     constexpr int S = decltype(slot)::value;
-    const bool ok = arow && g < ng;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int t = 0; t < T; ++t) acc[t] = mfma16(ok ? a4[S][q] : 0.0, bq[S][q].v[t], acc[t]);
+      for (int r = 0; r < R; ++r) {
+        const double a = (arow[r] && g < ng) ? a4[S][r][q] : 0.0;
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[r][t] = mfma16(a, bq[S][q].v[t], acc[r][t]);
+      }
     __builtin_amdgcn_sched_barrier(0);
     fetch(g + 2, slot);
   };
@@ -705,16 +522,122 @@ __global__ __launch_bounds__(256) void gemm_k(int64_t M, int K, double alpha,
     use(g + 1, std::integral_constant<int, 1>());
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t row = r0 + rl + 4 * q;
-    if (row < M) {
-      double* d = C + row * ldc + c0 + T * cl;
+  for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int t = 0; t < T; ++t)
-        d[t] = beta == 0.0 ? alpha * acc[t][q] : alpha * acc[t][q] + beta * d[t];
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = r0 + 16 * r + rl + 4 * q;
+      if (row < M) {
+        double* d = C + row * ldc + c0 + T * cl;
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+          d[t] = beta == 0.0 ? alpha * acc[r][t][q] : alpha * acc[r][t][q] + beta * d[t];
+      }
     }
-  }
 }
+
+// The same product for N a multiple of 64 with the B operand shared through
+// LDS: the workgroup stages each group of 16 k x 64 columns of B once (a
+// coalesced 32-byte load per thread, two groups ahead in registers) and every
+// wave reads its permuted B values from there, so the L1 carries only A.
+// Each wave computes R row tiles of 16 (R A rows per lane, one B read for all).
+template <int R>
+__global__ __launch_bounds__(256) void gemm_lds_k(int64_t M, int K, double alpha,
+                                                  const double* __restrict__ A, int64_t a_blk,
+                                                  int64_t lda, int kb,
+                                                  const double* __restrict__ B, int64_t ldb,
+                                                  double beta, double* C, int64_t ldc) {
+  constexpr int T = 4;
+  __shared__ __align__(16) double bs[2][16][64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int rl = lane >> 4, cl = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * 64 * R + wv * 16 * R;
+  const int c0 = blockIdx.y * 64;
+  // every wave takes part in the staging and the barriers, also one whose
+  // rows all lie past M (it computes zeros and stores nothing)
+  dx4 acc[R][T];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[r][t] = dx4{0.0, 0.0, 0.0, 0.0};
+  bool arow[R];
+  const double* Abase[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t ra = r0 + 16 * r + cl;
+    arow[r] = ra < M;
+    Abase[r] = (arow[r] ? A + ra * lda : A) + 4 * rl;
+  }
+  // this thread's part of a B group: row tid / 16, columns 4 (tid % 16) + 0..3
+  const int bk = tid >> 4, bc = 4 * (tid & 15);
+  const double* Bt = B + (int64_t)bk * ldb + c0 + bc;
+  const int per = kb / 16;
+  const int ng = K / 16;
+  dx4 a4[2][R];
+  dx4 b4[2];
+  auto fetch = [&](int g, auto slot) {
+    constexpr int S = decltype(slot)::value;
+    const int gc = min(g, ng - 1);
+    const int blk = gc / per, kk = (gc - blk * per) * 16;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      a4[S][r] = *reinterpret_cast<const dx4*>(Abase[r] + (int64_t)blk * a_blk + kk);
+    b4[S] = *reinterpret_cast<const dx4*>(Bt + (int64_t)gc * 16 * ldb);
+  };
+  auto stage = [&](int buf, auto slot) {
+    constexpr int S = decltype(slot)::value;
+    *reinterpret_cast<dx4*>(&bs[buf][bk][bc]) = b4[S];
+  };
+  // group g: B(g) is in buffer g & 1; the MFMAs, then the loads of group
+  // g + 2 into slot g & 1, then B(g + 1) (loaded a group ago) into the other
+  // buffer, whose last reads were before the previous barrier
+  auto use = [&](int g, auto slot) {
+    constexpr int S = decltype(slot)::value;
+    const double* Lb = &bs[S][4 * rl][T * cl];
+    dx4 bq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bq[q] = *reinterpret_cast<const dx4*>(Lb + q * 64);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double a = (arow[r] && g < ng) ? a4[S][r][q] : 0.0;
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[r][t] = mfma16(a, bq[q][t], acc[r][t]);
+      }
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(g + 2, slot);
+    stage(S ^ 1, std::integral_constant<int, S ^ 1>());
+    __syncthreads();
+  };
+  fetch(0, std::integral_constant<int, 0>());
+  fetch(1, std::integral_constant<int, 1>());
+  stage(0, std::integral_constant<int, 0>());
+  __syncthreads();
+  for (int g = 0; g < ng; g += 2) {
+    use(g, std::integral_constant<int, 0>());
+    use(g + 1, std::integral_constant<int, 1>());
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = r0 + 16 * r + rl + 4 * q;
+      if (row < M) {
+        double* d = C + row * ldc + c0 + T * cl;
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+          d[t] = beta == 0.0 ? alpha * acc[r][t][q] : alpha * acc[r][t][q] + beta * d[t];
+      }
+    }
+}
+
+// row tiles of 16 per wave in the large products
+#ifndef FA_GEMM_R
+#define FA_GEMM_R 1
+#endif
+#ifndef FA_GEMM_LDS
+#define FA_GEMM_LDS 1
+#endif
 
 hipError_t launch_gemm(int64_t M, int N, int K, double alpha, const double* A, int64_t a_blk,
                        int64_t lda, int kb, const double* B, int64_t ldb, double beta, double* C,
@@ -725,13 +648,18 @@ hipError_t launch_gemm(int64_t M, int N, int K, double alpha, const double* A, i
   const int T = N % 64 == 0 ? 4 : N % 32 == 0 ? 2 : 1;
   if (ldb % T || ldc % T || ((uintptr_t)B & (8 * T - 1)) || ((uintptr_t)C & (8 * T - 1)))
     return hipErrorInvalidValue;
-  const int gx = (int)((M + 63) / 64);
+  constexpr int R = FA_GEMM_R;
+  const int gx = (int)((M + 64 * R - 1) / (64 * R));
   if (N % 64 == 0) {
-    gemm_k<4><<<dim3(gx, N / 64), 256, 0, st>>>(M, K, alpha, A, a_blk, lda, kb, B, ldb, beta, C, ldc);
+#if FA_GEMM_LDS
+    gemm_lds_k<R><<<dim3(gx, N / 64), 256, 0, st>>>(M, K, alpha, A, a_blk, lda, kb, B, ldb, beta, C, ldc);
+#else
+    gemm_k<4, R><<<dim3(gx, N / 64), 256, 0, st>>>(M, K, alpha, A, a_blk, lda, kb, B, ldb, beta, C, ldc);
+#endif
   } else if (N % 32 == 0) {
-    gemm_k<2><<<dim3(gx, N / 32), 256, 0, st>>>(M, K, alpha, A, a_blk, lda, kb, B, ldb, beta, C, ldc);
+    gemm_k<2, R><<<dim3(gx, N / 32), 256, 0, st>>>(M, K, alpha, A, a_blk, lda, kb, B, ldb, beta, C, ldc);
   } else {
-    gemm_k<1><<<dim3(gx, N / 16), 256, 0, st>>>(M, K, alpha, A, a_blk, lda, kb, B, ldb, beta, C, ldc);
+    gemm_k<1, R><<<dim3(gx, N / 16), 256, 0, st>>>(M, K, alpha, A, a_blk, lda, kb, B, ldb, beta, C, ldc);
   }
   return hipGetLastError();
 }

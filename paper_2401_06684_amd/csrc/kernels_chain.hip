@@ -46,6 +46,7 @@ using calc_t = typename std::conditional<std::is_same<TX, double>::value &&
 
 template <typename TX, typename TO, bool Y0, bool Y1>
 __global__ __launch_bounds__(ST_TX* ST_TY) void st7_chain(St7 s, int kz, int gx, int gy, int nwg,
+                                                          int64_t bstride,
                                                           const TX* __restrict__ x,
                                                           const TX* __restrict__ y0,
                                                           const TX* y1, TO* out, double al_,
@@ -54,7 +55,16 @@ __global__ __launch_bounds__(ST_TX* ST_TY) void st7_chain(St7 s, int kz, int gx,
   const T al = (T)al_, be = (T)be_, g0 = (T)g0_, g1 = (T)g1_;
   const T c0 = (T)s.c0, cxm = (T)s.cxm, cxp = (T)s.cxp, cym = (T)s.cym, cyp = (T)s.cyp,
           czm = (T)s.czm, czp = (T)s.czp;
-  const int lid = xcd_contiguous(blockIdx.x, nwg);
+  // a batch of vectors (bstride elements apart): nwg workgroups per vector
+  const int lall = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int col = lall / nwg, lid = lall - col * nwg;
+  {
+    const int64_t o = (int64_t)col * bstride;
+    x += o;
+    if (Y0) y0 += o;
+    if (Y1) y1 += o;
+    out += o;
+  }
   const int bx = lid % gx, by = (lid / gx) % gy, bz = lid / (gx * gy);
   const int i = bx * ST_TX + (threadIdx.x & (ST_TX - 1));
   const int j = by * ST_TY + (threadIdx.x / ST_TX);
@@ -94,22 +104,28 @@ static hipError_t launch_st7_t(const Op& op, const void* xv, const void* y0v, co
   St7 s{op.dims[0], op.dims[1], op.dims[2], op.coef[0], op.coef[1], op.coef[2],
         op.coef[3], op.coef[4], op.coef[5], op.coef[6]};
   const int gx = (s.nx + ST_TX - 1) / ST_TX, gy = (s.ny + ST_TY - 1) / ST_TY;
-  // enough z-slabs for ~2048 workgroups, at least one plane per thread
+  // enough z-slabs for ~2048 workgroups over the batch, at least one plane
+  // per thread
+  const int nb = std::max(1, op.nbatch);
   const int64_t want = 2048;
-  int gz = (int)std::min<int64_t>(s.nz, std::max<int64_t>(1, want / ((int64_t)gx * gy)));
+  int gz = (int)std::min<int64_t>(s.nz, std::max<int64_t>(1, want / ((int64_t)gx * gy * nb)));
   const int kz = (s.nz + gz - 1) / gz;
   gz = (s.nz + kz - 1) / kz;
   const int nwg = gx * gy * gz;
+  const int64_t bs = nb > 1 ? op.bstride : 0;
   const double al = k.alpha.real(), be = k.beta.real(), g0 = k.g0.real(), g1 = k.g1.real();
-  const dim3 grid(nwg), block(ST_TX * ST_TY);
+  const dim3 grid(nwg * nb), block(ST_TX * ST_TY);
+#define FA_ST7(A, B) \
+  st7_chain<TX, TO, A, B><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, bs, x, y0, y1, out, al, be, g0, g1)
   if (y0 && y1)
-    st7_chain<TX, TO, true, true><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
+    FA_ST7(true, true);
   else if (y0)
-    st7_chain<TX, TO, true, false><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
+    FA_ST7(true, false);
   else if (y1)
-    st7_chain<TX, TO, false, true><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
+    FA_ST7(false, true);
   else
-    st7_chain<TX, TO, false, false><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out, al, be, g0, g1);
+    FA_ST7(false, false);
+#undef FA_ST7
   return hipGetLastError();
 }
 
@@ -166,6 +182,7 @@ __device__ __forceinline__ int sslot(int q) { return (q + 6) % 3; }
 
 template <typename TX, typename TO, bool Y0, bool Y1, bool W1>
 __global__ __launch_bounds__(P_THREADS) void st7_pair(St7 s, int kz, int gx, int gy, int nwg,
+                                                      int64_t bstride,
                                                       const TX* __restrict__ x,
                                                       const TX* __restrict__ y0,
                                                       const TX* __restrict__ y1,
@@ -179,7 +196,17 @@ __global__ __launch_bounds__(P_THREADS) void st7_pair(St7 s, int kz, int gx, int
           czm = (T)s.czm, czp = (T)s.czp;
   __shared__ T xs[4][P_XH][P_XW];
   __shared__ T ss[3][P_SH][P_SW];
-  const int lid = xcd_contiguous(blockIdx.x, nwg);
+  // a batch of vectors (bstride elements apart): nwg workgroups per vector
+  const int lall = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int col = lall / nwg, lid = lall - col * nwg;
+  {
+    const int64_t o = (int64_t)col * bstride;
+    x += o;
+    if (Y0) y0 += o;
+    if (Y1) y1 += o;
+    if (W1) out1 += o;
+    out2 += o;
+  }
 #if FA_PAIR_ZFIRST
   const int gz = nwg / (gx * gy);
   const int bz = lid % gz, bx = (lid / gz) % gx, by = lid / (gz * gx);
@@ -354,15 +381,17 @@ static hipError_t launch_st7_pair_t(const Op& op, const void* xv, const void* y0
   const int gx = (s.nx + P_TX - 1) / P_TX, gy = (s.ny + P_TY - 1) / P_TY;
   // about FA_PAIR_BLOCKS workgroups, at least 2 planes each (the x ring reads
   // 2 extra planes on each side of a workgroup's slab)
+  const int nb = std::max(1, op.nbatch);
   int gz = (int)std::max<int64_t>(
-      1, std::min<int64_t>(s.nz / 2, FA_PAIR_BLOCKS / ((int64_t)gx * gy)));
+      1, std::min<int64_t>(s.nz / 2, FA_PAIR_BLOCKS / ((int64_t)gx * gy * nb)));
   const int kz = (s.nz + gz - 1) / gz;
   gz = (s.nz + kz - 1) / kz;
   const int nwg = gx * gy * gz;
+  const int64_t bs = nb > 1 ? op.bstride : 0;
   const bool w1 = out1 != nullptr;
-  const dim3 grid(nwg), block(P_THREADS);
+  const dim3 grid(nwg * nb), block(P_THREADS);
 #define FA_PAIR(A, B, C) \
-  st7_pair<TX, TO, A, B, C><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, x, y0, y1, out1, out2, c)
+  st7_pair<TX, TO, A, B, C><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, bs, x, y0, y1, out1, out2, c)
   if (y0 && y1) {
     if (w1) FA_PAIR(true, true, true); else FA_PAIR(true, true, false);
   } else if (y0) {
@@ -918,7 +947,8 @@ hipError_t launch_wilson_links_soa(int64_t V, int ne, const void* U, void* Us, h
 // --------------------------------------------------------------------------
 hipError_t launch_chain(const Op& op, const void* x, const void* y0, const void* y1, void* out,
                         const ChainCoef& k, hipStream_t s, Prec pin, Prec pout) {
-  if ((pin != P64 || pout != P64) && op.kind != OP_STENCIL7) return hipErrorInvalidValue;
+  if ((pin != P64 || pout != P64 || op.nbatch > 1) && op.kind != OP_STENCIL7)
+    return hipErrorInvalidValue;
   switch (op.kind) {
     case OP_STENCIL7:
       return launch_st7(op, x, y0, y1, out, k, s, pin, pout);

@@ -96,15 +96,26 @@ __device__ __forceinline__ void ring_point(int h, int& a, int& b) {
 template <typename T, typename TX, typename TO, int NT, int TY, bool Y1G, bool W1>
 // at least 4 waves per SIMD: two 512-thread workgroups per CU
 __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(4))) void st7_multi(
-    St7M g, int kz, int gx, int gy, int nwg, const TX* __restrict__ x, const TX* __restrict__ v,
-    const TX* __restrict__ y1, TO* __restrict__ out1, TO* __restrict__ out2, MultiCoef<NT> cd) {
+    St7M g, int kz, int gx, int gy, int nwg, int64_t bstride, const TX* __restrict__ x,
+    const TX* __restrict__ v, const TX* __restrict__ y1, TO* __restrict__ out1,
+    TO* __restrict__ out2, MultiCoef<NT> cd) {
   using G = Geo<NT, TY>;
   static_assert(G::RING <= G::P && G::HALO <= G::P, "one ring and one halo point per thread");
   constexpr int W0 = G::W(0);
   __shared__ T lds[G::total()];
   const T c0 = (T)g.c0, cxm = (T)g.cxm, cxp = (T)g.cxp, cym = (T)g.cym, cyp = (T)g.cyp,
           czm = (T)g.czm, czp = (T)g.czp;
-  const int lid = xcd_contiguous(blockIdx.x, nwg);
+  // a batch of vectors (bstride elements apart): nwg workgroups per vector
+  const int lall = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int col = lall / nwg, lid = lall - col * nwg;
+  {
+    const int64_t o = (int64_t)col * bstride;
+    x += o;
+    v += o;
+    if (Y1G) y1 += o;
+    if (W1) out1 += o;
+    out2 += o;
+  }
   const int bx = lid % gx, by = (lid / gx) % gy, bz = lid / (gx * gy);
   const int i0 = bx * G::TX, j0 = by * TY;
   const int k0 = bz * kz, k1 = min(k0 + kz, g.nz);
@@ -332,11 +343,15 @@ hipError_t launch_multi_t(const Op& op, const void* x, const void* v, const void
   St7M g{op.dims[0], op.dims[1], op.dims[2], op.coef[0], op.coef[1], op.coef[2],
          op.coef[3], op.coef[4], op.coef[5], op.coef[6]};
   const int gx = (g.nx + 63) / 64, gy = (g.ny + TY - 1) / TY;
-  int gz = (int)std::max<int64_t>(1, std::min<int64_t>(g.nz / 2, blocks / ((int64_t)gx * gy)));
+  // about `blocks` workgroups over the batch
+  const int nb = std::max(1, op.nbatch);
+  int gz = (int)std::max<int64_t>(
+      1, std::min<int64_t>(g.nz / 2, blocks / ((int64_t)gx * gy * nb)));
   const int kz = (g.nz + gz - 1) / gz;
   gz = (g.nz + kz - 1) / kz;
   const int nwg = gx * gy * gz;
-  const dim3 grid(nwg), block(64 * TY);
+  const dim3 grid(nwg * nb), block(64 * TY);
+  const int64_t bs = nb > 1 ? op.bstride : 0;
   const TX* xp = (const TX*)x;
   const TX* vp = (const TX*)v;
   const TX* yp = (const TX*)y1;
@@ -345,7 +360,7 @@ hipError_t launch_multi_t(const Op& op, const void* x, const void* v, const void
   // the events (if any) take the start and end time of this dispatch itself
 #define FA_MULTI(A, B)                                                                          \
   hipExtLaunchKernelGGL(st7_multi<T, TX, TO, NT, TY, A, B>, grid, block, 0, st, ev0, ev1, 0, g, kz, \
-                        gx, gy, nwg, xp, vp, yp, o1, o2, c)
+                        gx, gy, nwg, bs, xp, vp, yp, o1, o2, c)
   if (y1 && out1)
     FA_MULTI(true, true);
   else if (y1)
@@ -388,7 +403,7 @@ hipError_t launch_chain_multi(const Op& op, int nt, const void* x, const void* v
                               void* out1, void* out2, const ChainCoef* k, hipStream_t s,
                               Prec pin, Prec pout, int blocks, hipEvent_t ev0, hipEvent_t ev1) {
   if (op.kind != OP_STENCIL7 || !x || !v || !out2) return hipErrorInvalidValue;
-  if (blocks <= 0) blocks = FA_MULTI_BLOCKS;
+  if (blocks <= 0) blocks = op.multi_blocks > 0 ? op.multi_blocks : FA_MULTI_BLOCKS;
   if (nt == 3)
     return launch_multi_nt<3>(op, x, v, y1, out1, out2, k, s, pin, pout, blocks, ev0, ev1);
   if (nt == 4)

@@ -437,6 +437,11 @@ static int poly_apply(const Op& op, const Poly& q, const void* x, void* out, voi
   return FA_OK;
 }
 
+int poly_apply_chain(const Op& op, const void* x, void* out, void* const tmp[4],
+                     const void** res, hipStream_t s, int64_t* mvms, Prec p) {
+  return poly_apply(op, op.poly, x, out, tmp, res, s, nullptr, mvms, 4, p, p);
+}
+
 int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_t s) {
   const Layout L = make_layout(op, 1, 0);
   CsrScratchScope csr(op, L.csr_bytes ? at(ws, L.off_csr) : nullptr, s);

@@ -52,6 +52,12 @@ class CsrScratchScope {
   void* prev_;
 };
 
+// q(A) x for the op's polynomial (and its batch settings), the chain in
+// precision p, fused up to four terms per launch on a stencil: the result is
+// left in *res, which is x, out or one of tmp (four vectors, none of them x or
+// out); x may be overwritten when out == x.  *mvms += the degree.
+int poly_apply_chain(const Op& op, const void* x, void* out, void* const tmp[4],
+                     const void** res, hipStream_t s, int64_t* mvms, Prec p);
 // y = A x; ws (may be null) of make_layout(op, 1, 0).bytes splits long CSR rows
 int op_apply(const Op& op, const void* x, void* y, void* ws, hipStream_t s);
 int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_t s);

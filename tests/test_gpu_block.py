@@ -171,7 +171,6 @@ def test_block_autotuned_launches_are_reproducible():
     X2, s2 = op.block_apply(Bd, m_max=12, tol=0.0, mixed=True)
     assert torch.equal(X1, X2)
     assert s1["ms_tune"] > 0.0 and s2["ms_tune"] == 0.0
-    assert s1["zc"] in (4, 8, 16) and s2["zc"] == s1["zc"]
     ref = bk.block_fAB(A, B, pl.chebyshev(a, b, 6), "invsqrt", m_max=12, tol=0.0)
     assert np.max(col_err(host(X2), ref.X)) < 1e-6
 
