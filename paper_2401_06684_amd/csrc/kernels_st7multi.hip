@@ -8,8 +8,9 @@
 // terms and 4 for one).  The intermediate terms never leave the chip.  NT = 4
 // in FP64 takes 77.8 KB of LDS and 124 VGPRs: two workgroups per CU.
 //
-// A workgroup owns a 64 x TY tile of the (x, y) plane and marches through its
-// slab of kz planes in z.  Term t is needed on the tile grown by NT - t
+// A workgroup owns a TW x TY tile of the (x, y) plane (64 x 8, or 32 x 16
+// when that wastes fewer points along x) and marches through its slab of kz
+// planes in z.  Term t is needed on the tile grown by NT - t
 // points on each side (its halo for the terms after it) and lags term t - 1
 // by one plane: at step q, term t produces plane q - t + 1 (term 0, x itself,
 // "produces" plane q + 1 by loading it).
@@ -34,9 +35,7 @@
 #include "devmath.hpp"
 #include "fa_internal.hpp"
 
-#ifndef FA_MULTI_TY
-#define FA_MULTI_TY 8
-#endif
+
 #ifndef FA_MULTI_BLOCKS
 #define FA_MULTI_BLOCKS 512
 #endif
@@ -55,9 +54,9 @@ struct MultiCoef {
   double a[NT], b[NT], g0[NT], g1[NT];
 };
 
-template <int NT, int TY>
+template <int NT, int TW, int TY>
 struct Geo {
-  static constexpr int TX = 64, P = TX * TY;
+  static constexpr int TX = TW, P = TX * TY;
   // region of term t: the tile grown by NT - t on each side
   static constexpr int W(int t) { return TX + 2 * (NT - t); }
   static constexpr int H(int t) { return TY + 2 * (NT - t); }
@@ -74,9 +73,9 @@ struct Geo {
 
 // (a, b) coordinates in region 1 of ring point h (region 1 minus the tile):
 // NT - 1 rows above and below the tile, NT - 1 columns left and right
-template <int NT, int TY>
+template <int NT, int TW, int TY>
 __device__ __forceinline__ void ring_point(int h, int& a, int& b) {
-  using G = Geo<NT, TY>;
+  using G = Geo<NT, TW, TY>;
   constexpr int w = NT - 1, W1 = G::W(1);
   if (h < w * W1) {  // rows above
     a = h % W1;
@@ -93,13 +92,13 @@ __device__ __forceinline__ void ring_point(int h, int& a, int& b) {
   }
 }
 
-template <typename T, typename TX, typename TO, int NT, int TY, bool Y1G, bool W1>
+template <typename T, typename TX, typename TO, int NT, int TW, int TY, bool Y1G, bool W1>
 // at least 4 waves per SIMD: two 512-thread workgroups per CU
-__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(4))) void st7_multi(
+__global__ __launch_bounds__(TW * TY) __attribute__((amdgpu_waves_per_eu(4))) void st7_multi(
     St7M g, int kz, int gx, int gy, int nwg, int64_t bstride, const TX* __restrict__ x,
     const TX* __restrict__ v, const TX* __restrict__ y1, TO* __restrict__ out1,
     TO* __restrict__ out2, MultiCoef<NT> cd) {
-  using G = Geo<NT, TY>;
+  using G = Geo<NT, TW, TY>;
   static_assert(G::RING <= G::P && G::HALO <= G::P, "one ring and one halo point per thread");
   constexpr int W0 = G::W(0);
   __shared__ T lds[G::total()];
@@ -136,7 +135,7 @@ __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(4))) vo
     int a[2], b[2];
     a[0] = tid % G::TX + (NT - 1);
     b[0] = tid / G::TX + (NT - 1);
-    ring_point<NT, TY>(tid < G::RING ? tid : 0, a[1], b[1]);
+    ring_point<NT, TW, TY>(tid < G::RING ? tid : 0, a[1], b[1]);
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int i = i0 - (NT - 1) + a[u], j = j0 - (NT - 1) + b[u];
@@ -336,13 +335,13 @@ __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(4))) vo
   }
 }
 
-template <typename T, typename TX, typename TO, int NT, int TY>
+template <typename T, typename TX, typename TO, int NT, int TW, int TY>
 hipError_t launch_multi_t(const Op& op, const void* x, const void* v, const void* y1, void* out1,
                           void* out2, const MultiCoef<NT>& c, int blocks, hipStream_t st,
                           hipEvent_t ev0, hipEvent_t ev1) {
   St7M g{op.dims[0], op.dims[1], op.dims[2], op.coef[0], op.coef[1], op.coef[2],
          op.coef[3], op.coef[4], op.coef[5], op.coef[6]};
-  const int gx = (g.nx + 63) / 64, gy = (g.ny + TY - 1) / TY;
+  const int gx = (g.nx + TW - 1) / TW, gy = (g.ny + TY - 1) / TY;
   // about `blocks` workgroups over the batch
   const int nb = std::max(1, op.nbatch);
   int gz = (int)std::max<int64_t>(
@@ -350,7 +349,7 @@ hipError_t launch_multi_t(const Op& op, const void* x, const void* v, const void
   const int kz = (g.nz + gz - 1) / gz;
   gz = (g.nz + kz - 1) / kz;
   const int nwg = gx * gy * gz;
-  const dim3 grid(nwg * nb), block(64 * TY);
+  const dim3 grid(nwg * nb), block(TW * TY);
   const int64_t bs = nb > 1 ? op.bstride : 0;
   const TX* xp = (const TX*)x;
   const TX* vp = (const TX*)v;
@@ -359,7 +358,7 @@ hipError_t launch_multi_t(const Op& op, const void* x, const void* v, const void
   TO* o2 = (TO*)out2;
   // the events (if any) take the start and end time of this dispatch itself
 #define FA_MULTI(A, B)                                                                          \
-  hipExtLaunchKernelGGL(st7_multi<T, TX, TO, NT, TY, A, B>, grid, block, 0, st, ev0, ev1, 0, g, kz, \
+  hipExtLaunchKernelGGL(st7_multi<T, TX, TO, NT, TW, TY, A, B>, grid, block, 0, st, ev0, ev1, 0, g, kz, \
                         gx, gy, nwg, bs, xp, vp, yp, o1, o2, c)
   if (y1 && out1)
     FA_MULTI(true, true);
@@ -386,16 +385,19 @@ static hipError_t launch_multi_nt(const Op& op, const void* x, const void* v, co
     c.g0[t] = k[t].g0.real();
     c.g1[t] = k[t].g1.real();
   }
-  constexpr int TY = FA_MULTI_TY;
-  if (pin == P64 && pout == P64)
-    return launch_multi_t<double, double, double, NT, TY>(op, x, v, y1, out1, out2, c, blocks, s,
-                                                          e0, e1);
-  if (pin == P32 && pout == P32)
-    return launch_multi_t<float, float, float, NT, TY>(op, x, v, y1, out1, out2, c, blocks, s, e0,
-                                                       e1);
-  if (pin == P32 && pout == P64 && out1 == nullptr)
-    return launch_multi_t<float, float, double, NT, TY>(op, x, v, y1, out1, out2, c, blocks, s,
-                                                        e0, e1);
+  // 64 x 8 tiles, or 32 x 16 where they waste fewer points along x (nx = 96:
+  // three tiles of 32 instead of two of 64, the second half empty)
+  const int nx = op.dims[0];
+  const bool narrow = (nx + 31) / 32 * 32 < (nx + 63) / 64 * 64;
+#define FA_MULTI_TILE(T_, TX_, TO_)                                                            \
+  return narrow ? launch_multi_t<T_, TX_, TO_, NT, 32, 16>(op, x, v, y1, out1, out2, c, blocks, \
+                                                           s, e0, e1)                           \
+                : launch_multi_t<T_, TX_, TO_, NT, 64, 8>(op, x, v, y1, out1, out2, c, blocks,  \
+                                                          s, e0, e1)
+  if (pin == P64 && pout == P64) FA_MULTI_TILE(double, double, double);
+  if (pin == P32 && pout == P32) FA_MULTI_TILE(float, float, float);
+  if (pin == P32 && pout == P64 && out1 == nullptr) FA_MULTI_TILE(float, float, double);
+#undef FA_MULTI_TILE
   return hipErrorInvalidValue;
 }
 
