@@ -683,24 +683,24 @@ static hipError_t launch_csr(const Op& op, const T* x, const T* y0, const T* y1,
 // sg M_mu^{-1} h, where M_k = -i s_k and M_t = I.  A hop therefore projects the
 // 4-spinor to the 2-spinor h, multiplies h by the 3x3 link (6 colour matvecs
 // instead of 12) and rebuilds the lower pair from the transported h.
+// Every M_mu is diagonal or anti-diagonal with entries in {+-1, +-i}.
 //
-// Every M_mu is diagonal or anti-diagonal with entries in {+-1, +-i}, so the
-// projections are written branch-free from a few per-direction unit
-// coefficients; multiplying by a unit in {+-1, +-i} is exact, so each hop
-// rounds exactly as the direction-specialised formulas would.
-//
-// Work split: one wave per 16 consecutive sites, four lanes per site, one per
-// direction mu (lane = 4 site + mu).  A lane does the forward and the
-// backward hop of its direction; the quad then reduce-scatters the four
-// partial sums so that lane mu owns spin row mu of the result.
-// Memory access: a spinor is 192 contiguous bytes, so a lane that reads its
-// own neighbour's spinor makes every load instruction touch 64 cache lines.
-// Instead the 16 lanes of one direction read the 16 neighbour spinors as
-// consecutive 16-byte chunks (contiguous but for lattice wrap-around) into a
-// wave-private LDS slice, and each lane then takes its spinor from there; the
-// result goes out the same way.  The links are kept in a structure-of-arrays
-// copy Us[mu][e][s] (made once at creation), so that link element e of 16
-// consecutive sites is 256 contiguous bytes.
+// Work split: a workgroup of four waves owns 64 consecutive sites; wave mu
+// does the forward and the backward hop in direction mu for all of them
+// (lane = site), so M_mu, M_mu^{-1} and the hop signs are compile-time
+// constants: multiplying by them is a sign change or a swap of real and
+// imaginary parts, exact, and no lane holds per-direction coefficients.
+// Memory access: a spinor is 192 contiguous bytes, so a lane that read its
+// own neighbour's spinor would make every load touch 64 cache lines.  Instead
+// the wave stages the 64 neighbours' projected half spinors h (6 complex each)
+// in its LDS slice: item p = 64 kk + lane is component p % 6 of neighbour
+// p / 6, formed from two 16-byte chunks of that spinor, so the lanes read
+// each spinor's upper and lower six chunks as contiguous runs; each lane then
+// takes its site's h from the slice.  The four directions' sums are added as
+// ((mu 0 + mu 2) + (mu 1 + mu 3)) through LDS and the workgroup writes the
+// result with coalesced stores.  The links are kept in a structure-of-arrays
+// copy Us[mu][e][s] (made once at creation), so that link element e of 64
+// consecutive sites is 1 KB contiguous.
 // --------------------------------------------------------------------------
 struct Wil {
   int L0, L1, L2, L3;  // x, y, z, t extents
@@ -708,43 +708,88 @@ struct Wil {
   double diag;         // 4 + m0
 };
 
-// p * a for a unit p = pr + i pi with pr, pi in {0, +-1}: exact
-__device__ __forceinline__ cplx unit_mul(double pr, double pi, cplx a) {
-  return {pr * a.x - pi * a.y, pr * a.y + pi * a.x};
+constexpr int kWilDSites = 64;  // sites per workgroup (one per lane)
+
+// p * a for a compile-time unit p = R + i I in {+-1, +-i}: exact
+template <int R, int I>
+__device__ __forceinline__ cplx umul(cplx a) {
+  static_assert((R == 0) != (I == 0) && R * R + I * I == 1, "a unit");
+  if constexpr (R == 1) return a;
+  else if constexpr (R == -1) return cplx{-a.x, -a.y};
+  else if constexpr (I == 1) return cplx{-a.y, a.x};
+  else return cplx{a.y, -a.x};
 }
 
-// value of lane (l ^ 1) or (l ^ 2) inside a quad (DPP quad permutation)
-template <int X>
-__device__ __forceinline__ double quad_xor(double v) {
-  constexpr int ctrl = X == 1 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] / [2,3,0,1]
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-template <int X>
-__device__ __forceinline__ cplx quad_xor(cplx v) {
-  return {quad_xor<X>(v.x), quad_xor<X>(v.y)};
-}
-
-constexpr int kWilSites = 16;                      // sites per wave
-constexpr int kWilChunks = kWilSites * 12;         // 16-byte chunks of their spinors
-constexpr int kWilDirStride = kWilChunks + 1;      // LDS slice of one direction (+1:
-                                                   // spreads the 4 directions over banks)
-
-struct HopCoef {
-  double sg;  // -1: forward hop (1 - g_mu), +1: backward hop (1 + g_mu)
-  bool swap;  // M_mu anti-diagonal
-  double p0r, p0i, p1r, p1i;  // M_mu entries (rows 0, 1)
-  double q0r, q0i, q1r, q1i;  // M_mu^{-1} entries (rows 0, 1)
+// M_mu (rows 0 and 1 of the lower-to-upper map) and M_mu^{-1}, as above:
+// x, y anti-diagonal (-i, -i), (-1, 1); z diagonal (-i, i); t identity
+template <int MU> struct WilDir;
+template <> struct WilDir<0> {
+  static constexpr bool swap = true;
+  template <int SP> static __device__ cplx m(cplx a) { return umul<0, -1>(a); }
+  template <int SP> static __device__ cplx mi(cplx a) { return umul<0, 1>(a); }
+};
+template <> struct WilDir<1> {
+  static constexpr bool swap = true;
+  template <int SP> static __device__ cplx m(cplx a) {
+    if constexpr (SP == 0) return umul<-1, 0>(a); else return umul<1, 0>(a);
+  }
+  template <int SP> static __device__ cplx mi(cplx a) {
+    if constexpr (SP == 0) return umul<1, 0>(a); else return umul<-1, 0>(a);
+  }
+};
+template <> struct WilDir<2> {
+  static constexpr bool swap = false;
+  template <int SP> static __device__ cplx m(cplx a) {
+    if constexpr (SP == 0) return umul<0, -1>(a); else return umul<0, 1>(a);
+  }
+  template <int SP> static __device__ cplx mi(cplx a) {
+    if constexpr (SP == 0) return umul<0, 1>(a); else return umul<0, -1>(a);
+  }
+};
+template <> struct WilDir<3> {
+  static constexpr bool swap = false;
+  template <int SP> static __device__ cplx m(cplx a) { return a; }
+  template <int SP> static __device__ cplx mi(cplx a) { return a; }
 };
 
-// one hop: acc += (1 + sg g_mu) W x(nb), W = U (forward) or U^H (backward).
-// xs: this lane's neighbour spinor in LDS; Ue: link element 0 of the site in
-// the structure-of-arrays copy, element e at Ue[e V].  R12: only rows 0 and 1
-// are stored (the links are special unitary) and row 2 = conj(row 0 x row 1).
-template <bool Adj, bool R12>
-__device__ __forceinline__ void wilson_hop(const cplx* xs, const cplx* __restrict__ Ue,
-                                           int64_t V, const HopCoef& k, cplx acc[4][3]) {
+// sg * a for a compile-time sign
+template <int SG>
+__device__ __forceinline__ cplx sgn(cplx a) {
+  if constexpr (SG > 0) return a; else return cplx{-a.x, -a.y};
+}
+
+// stage h of the neighbour of every lane's site (nb: this lane's neighbour):
+// item p = 64 kk + lane is component (sp, c) = (comp / 3, comp % 3), comp =
+// p % 6, of the neighbour of site p / 6: h_sp,c = u_sp,c + sg M_sp d_sp',c
+template <int MU, int SG>
+__device__ __forceinline__ void wilson_dir_stage(const cplx* __restrict__ x, int nb, int lane,
+                                                 cplx* slice) {
+  using D = WilDir<MU>;
+  cplx u[6], d[6];
+#pragma unroll
+  for (int kk = 0; kk < 6; ++kk) {
+    const int p = kk * kWilDSites + lane, j = p / 6, comp = p - 6 * j;
+    const int sp = comp >= 3 ? 1 : 0, c = comp - 3 * sp;
+    const int dsp = D::swap ? 1 - sp : sp;
+    const int nbj = __shfl(nb, j, 64);
+    const cplx* xs = x + (int64_t)nbj * 12;
+    u[kk] = xs[sp * 3 + c];
+    d[kk] = xs[(2 + dsp) * 3 + c];
+  }
+#pragma unroll
+  for (int kk = 0; kk < 6; ++kk) {
+    const int p = kk * kWilDSites + lane;
+    const bool s1 = p % 6 >= 3;
+    const cplx md = s1 ? D::template m<1>(d[kk]) : D::template m<0>(d[kk]);
+    slice[p] = u[kk] + sgn<SG>(md);
+  }
+}
+
+// one hop from the lane's staged h: acc += (1 + sg g_mu) W x(nb)
+template <int MU, int SG, bool Adj, bool R12>
+__device__ __forceinline__ void wilson_dir_hop(const cplx* hs, const cplx* __restrict__ Ue,
+                                               int64_t V, cplx acc[4][3]) {
+  using D = WilDir<MU>;
   cplx u[9];
 #pragma unroll
   for (int e = 0; e < (R12 ? 6 : 9); ++e) u[e] = Ue[e * V];
@@ -755,65 +800,32 @@ __device__ __forceinline__ void wilson_hop(const cplx* xs, const cplx* __restric
   }
   cplx h[2][3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const cplx u0 = xs[0 * 3 + c], u1 = xs[1 * 3 + c], d0 = xs[2 * 3 + c], d1 = xs[3 * 3 + c];
-    const cplx e0 = k.swap ? d1 : d0, e1 = k.swap ? d0 : d1;
-    h[0][c] = u0 + k.sg * unit_mul(k.p0r, k.p0i, e0);
-    h[1][c] = u1 + k.sg * unit_mul(k.p1r, k.p1i, e1);
-  }
-  cplx g[2][3];
-#pragma unroll
   for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int c = 0; c < 3; ++c) h[sp][c] = hs[sp * 3 + c];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cplx g[2];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
       if (Adj)  // (U^H h)_a = sum_b conj(U_ba) h_b
-        g[sp][a] = cmad(u[2 * 3 + a], h[sp][2],
-                        cmad(u[1 * 3 + a], h[sp][1], cmad(u[0 * 3 + a], h[sp][0], cplx{0.0, 0.0})));
+        g[sp] = cmad(u[2 * 3 + a], h[sp][2],
+                     cmad(u[1 * 3 + a], h[sp][1], cmad(u[0 * 3 + a], h[sp][0], cplx{0.0, 0.0})));
       else
-        g[sp][a] = mad(u[a * 3 + 2], h[sp][2], mad(u[a * 3 + 1], h[sp][1], u[a * 3 + 0] * h[sp][0]));
+        g[sp] = mad(u[a * 3 + 2], h[sp][2], mad(u[a * 3 + 1], h[sp][1], u[a * 3 + 0] * h[sp][0]));
     }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    acc[0][c] += g[0][c];
-    acc[1][c] += g[1][c];
-    const cplx f0 = k.swap ? g[1][c] : g[0][c], f1 = k.swap ? g[0][c] : g[1][c];
-    acc[2][c] += k.sg * unit_mul(k.q0r, k.q0i, f0);
-    acc[3][c] += k.sg * unit_mul(k.q1r, k.q1i, f1);
+    acc[0][a] += g[0];
+    acc[1][a] += g[1];
+    const cplx f0 = D::swap ? g[1] : g[0], f1 = D::swap ? g[0] : g[1];
+    acc[2][a] += sgn<SG>(D::template mi<0>(f0));
+    acc[3][a] += sgn<SG>(D::template mi<1>(f1));
   }
 }
 
-// the 16 neighbour spinors of this lane's direction into the wave's LDS slice
-// (chunk q of the slice = element q % 12 of the spinor of site q / 12); nb is
-// this lane's neighbour site, lanes 4 j + mu hold those of site j
-__device__ __forceinline__ void wilson_stage(const cplx* __restrict__ x, int nb, int sl, int mu,
-                                             cplx* slice) {
-  cplx v[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    const int q = k * kWilSites + sl, j = q / 12;
-    const int nbj = __shfl(nb, 4 * j + mu, 64);
-    v[k] = x[(int64_t)nbj * 12 + (q - 12 * j)];
-  }
-#pragma unroll
-  for (int k = 0; k < 12; ++k) slice[k * kWilSites + sl] = v[k];
-}
-
-template <bool Y0, bool Y1, bool R12>
-__global__ __launch_bounds__(64) void wilson_chain(Wil w, const cplx* __restrict__ Us,
-                                                   const cplx* __restrict__ x,
-                                                   const cplx* __restrict__ y0,
-                                                   const cplx* y1, cplx* out, cplx al,
-                                                   cplx be, cplx g0, cplx g1) {
-  __shared__ cplx lds[4 * kWilDirStride];
-  const int lane = threadIdx.x;
-  const int sl = lane >> 2, mu = lane & 3;
-  // each XCD takes one contiguous range of sites, so that the neighbours
-  // in x, y and z (and most in t) are fetched into the same L2
-  const int s0 = xcd_contiguous(blockIdx.x, gridDim.x) * kWilSites;
-  const int nsite = min(kWilSites, w.V - s0);
-  // lanes past the last site work on site V - 1 (all addresses stay in
-  // bounds) and store nothing
-  const int s = min(s0 + sl, w.V - 1);
+template <int MU, bool R12>
+__device__ __forceinline__ void wilson_dir_body(const Wil& w, const cplx* __restrict__ Us,
+                                                const cplx* __restrict__ x, int s, int lane,
+                                                cplx* slice, cplx acc[4][3]) {
   int c0, c1, c2, c3;
   {
     int r = s;
@@ -822,74 +834,98 @@ __global__ __launch_bounds__(64) void wilson_chain(Wil w, const cplx* __restrict
     c2 = r % w.L2;
     c3 = r / w.L2;
   }
-  const int L = mu == 0 ? w.L0 : mu == 1 ? w.L1 : mu == 2 ? w.L2 : w.L3;
-  const int co = mu == 0 ? c0 : mu == 1 ? c1 : mu == 2 ? c2 : c3;
-  const int st = mu == 0 ? 1 : mu == 1 ? w.L0 : mu == 2 ? w.L0 * w.L1 : w.L0 * w.L1 * w.L2;
+  const int L = MU == 0 ? w.L0 : MU == 1 ? w.L1 : MU == 2 ? w.L2 : w.L3;
+  const int co = MU == 0 ? c0 : MU == 1 ? c1 : MU == 2 ? c2 : c3;
+  const int st = MU == 0 ? 1 : MU == 1 ? w.L0 : MU == 2 ? w.L0 * w.L1 : w.L0 * w.L1 * w.L2;
   const int sf = (co + 1 < L) ? s + st : s - (L - 1) * st;
   const int sb = (co > 0) ? s - st : s + (L - 1) * st;
-  // M_mu: x, y anti-diagonal (-i, -i), (-1, 1); z diagonal (-i, i); t identity.
-  // M_mu^{-1}: x (i, i), y (1, -1), z (i, -i), t identity.
-  HopCoef k;
-  k.swap = mu < 2;
-  k.p0r = mu == 1 ? -1.0 : mu == 3 ? 1.0 : 0.0;
-  k.p0i = mu == 1 || mu == 3 ? 0.0 : -1.0;
-  k.p1r = mu == 1 || mu == 3 ? 1.0 : 0.0;
-  k.p1i = mu == 0 ? -1.0 : mu == 2 ? 1.0 : 0.0;
-  k.q0r = mu == 1 || mu == 3 ? 1.0 : 0.0;
-  k.q0i = mu == 1 || mu == 3 ? 0.0 : 1.0;
-  k.q1r = mu == 1 ? -1.0 : mu == 3 ? 1.0 : 0.0;
-  k.q1i = mu == 0 ? 1.0 : mu == 2 ? -1.0 : 0.0;
+  constexpr int NE = R12 ? 6 : 9;  // link elements stored per site and direction
+  const cplx* Um = Us + (int64_t)MU * NE * w.V;
+  const cplx* mine = slice + lane * 6;
+  // forward hop: (1 - g_mu) U_mu(s) x(s + mu)
+  wilson_dir_stage<MU, -1>(x, sf, lane, slice);
+  __builtin_amdgcn_wave_barrier();
+  wilson_dir_hop<MU, -1, false, R12>(mine, Um + s, w.V, acc);
+  __builtin_amdgcn_wave_barrier();
+  // backward hop: (1 + g_mu) U_mu(s - mu)^H x(s - mu)
+  wilson_dir_stage<MU, 1>(x, sb, lane, slice);
+  __builtin_amdgcn_wave_barrier();
+  wilson_dir_hop<MU, 1, true, R12>(mine, Um + sb, w.V, acc);
+}
 
-  cplx* slice = lds + mu * kWilDirStride;
-  const cplx* mine = slice + sl * 12;
-  const int64_t V = w.V;
+template <bool Y0, bool Y1, bool R12>
+__global__ __launch_bounds__(256) void wilson_dir_k(Wil w, const cplx* __restrict__ Us,
+                                                    const cplx* __restrict__ x,
+                                                    const cplx* __restrict__ y0,
+                                                    const cplx* y1, cplx* out, cplx al,
+                                                    cplx be, cplx g0, cplx g1) {
+  // four slices of 64 x 6 staged values; after the hops the same memory
+  // holds two 64 x 12 partial sums
+  __shared__ cplx lds[4 * kWilDSites * 6];
+  constexpr int kAcc = kWilDSites * 12;
+  const int lane = threadIdx.x & 63;
+  const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // each XCD takes one contiguous range of sites
+  const int s0 = xcd_contiguous(blockIdx.x, gridDim.x) * kWilDSites;
+  const int nsite = min(kWilDSites, w.V - s0);
+  // lanes past the last site work on site V - 1 and store nothing
+  const int s = min(s0 + lane, w.V - 1);
   cplx acc[4][3];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[a][c] = cplx{0.0, 0.0};
-  // forward hop: (1 - g_mu) U_mu(s) x(s + mu)
-  wilson_stage(x, sf, sl, mu, slice);
-  __builtin_amdgcn_wave_barrier();
-  k.sg = -1.0;
-  constexpr int NE = R12 ? 6 : 9;  // link elements stored per site and direction
-  wilson_hop<false, R12>(mine, Us + (int64_t)mu * NE * V + s, V, k, acc);
-  __builtin_amdgcn_wave_barrier();
-  // backward hop: (1 + g_mu) U_mu(s - mu)^H x(s - mu)
-  wilson_stage(x, sb, sl, mu, slice);
-  __builtin_amdgcn_wave_barrier();
-  k.sg = 1.0;
-  wilson_hop<true, R12>(mine, Us + (int64_t)mu * NE * V + sb, V, k, acc);
-  __builtin_amdgcn_wave_barrier();
-
-  // quad reduce-scatter: after the xor-2 step a lane holds rows {0,1} or
-  // {2,3} summed over its pair, after the xor-1 step row mu over the quad
-  const bool hi2 = (mu & 2) != 0, hi1 = (mu & 1) != 0;
-  cplx k2[2][3];
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const cplx keep = hi2 ? acc[r + 2][c] : acc[r][c];
-      const cplx send = hi2 ? acc[r][c] : acc[r + 2][c];
-      k2[r][c] = keep + quad_xor<2>(send);
-    }
-  // row mu of site sl -> chunks 12 sl + 3 mu + c of the first slice
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const cplx keep = hi1 ? k2[1][c] : k2[0][c];
-    const cplx send = hi1 ? k2[0][c] : k2[1][c];
-    lds[sl * 12 + mu * 3 + c] = keep + quad_xor<1>(send);
+  cplx* slice = lds + mu * kWilDSites * 6;
+  switch (mu) {
+    case 0: wilson_dir_body<0, R12>(w, Us, x, s, lane, slice, acc); break;
+    case 1: wilson_dir_body<1, R12>(w, Us, x, s, lane, slice, acc); break;
+    case 2: wilson_dir_body<2, R12>(w, Us, x, s, lane, slice, acc); break;
+    default: wilson_dir_body<3, R12>(w, Us, x, s, lane, slice, acc); break;
   }
-  __builtin_amdgcn_wave_barrier();
-  // out = al (diag x - sum / 2) + be x + g0 y0 + g1 y1, chunk by chunk
-  const int64_t base = (int64_t)s0 * 12;
+  // (mu 0 + mu 2) + (mu 1 + mu 3), element (site, 3 row + colour)
+  __syncthreads();
+  if (mu >= 2) {
+    cplx* R = lds + (mu - 2) * kAcc;
 #pragma unroll
-  for (int i = 0; i < kWilChunks / 64; ++i) {
-    const int q = lane + 64 * i;
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) R[lane * 12 + a * 3 + c] = acc[a][c];
+  }
+  __syncthreads();
+  if (mu < 2) {
+    const cplx* R = lds + mu * kAcc;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[a][c] += R[lane * 12 + a * 3 + c];
+  }
+  __syncthreads();
+  if (mu == 1) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) lds[lane * 12 + a * 3 + c] = acc[a][c];
+  }
+  __syncthreads();
+  if (mu == 0) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int e = lane * 12 + a * 3 + c;
+        lds[kAcc + e] = acc[a][c] + lds[e];
+      }
+  }
+  __syncthreads();
+  // out = al (diag x - sum / 2) + be x + g0 y0 + g1 y1, value by value
+  const int64_t base = (int64_t)s0 * 12;
+  const cplx* S = lds + kAcc;
+#pragma unroll
+  for (int i = 0; i < kAcc / 256; ++i) {
+    const int q = threadIdx.x + 256 * i;
     if (q < nsite * 12) {
       const cplx xc = x[base + q];
-      const cplx dx = w.diag * xc - 0.5 * lds[q];
+      const cplx dx = w.diag * xc - 0.5 * S[q];
       cplx r = mad(al, dx, be * xc);
       if (Y0) r = mad(g0, y0[base + q], r);
       if (Y1) r = mad(g1, y1[base + q], r);
@@ -902,11 +938,11 @@ static hipError_t launch_wilson(const Op& op, const cplx* x, const cplx* y0, con
                                 cplx* out, const ChainCoef& k, hipStream_t st) {
   Wil w{op.dims[0], op.dims[1], op.dims[2], op.dims[3],
         op.dims[0] * op.dims[1] * op.dims[2] * op.dims[3], 4.0 + op.m0};
-  const int grid = (w.V + kWilSites - 1) / kWilSites;
   const cplx al = host_to_dev<cplx>::conv(k.alpha), be = host_to_dev<cplx>::conv(k.beta),
              g0 = host_to_dev<cplx>::conv(k.g0), g1 = host_to_dev<cplx>::conv(k.g1);
   const cplx* U = (const cplx*)op.links;
-#define FA_WIL(A, B, R) wilson_chain<A, B, R><<<grid, 64, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1)
+  const int grid = (w.V + kWilDSites - 1) / kWilDSites;
+#define FA_WIL(A, B, R) wilson_dir_k<A, B, R><<<grid, 256, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1)
 #define FA_WIL_R(A, B)  \
   if (op.links_rows == 2) \
     FA_WIL(A, B, true);   \
