@@ -55,9 +55,8 @@ __global__ __launch_bounds__(ST_TX* ST_TY) void st7_chain(St7 s, int kz, int gx,
   const T al = (T)al_, be = (T)be_, g0 = (T)g0_, g1 = (T)g1_;
   const T c0 = (T)s.c0, cxm = (T)s.cxm, cxp = (T)s.cxp, cym = (T)s.cym, cyp = (T)s.cyp,
           czm = (T)s.czm, czp = (T)s.czp;
-  // a batch of vectors (bstride elements apart): nwg workgroups per vector
-  const int lall = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int col = lall / nwg, lid = lall - col * nwg;
+  // a batch of vectors (bstride elements apart): vector blockIdx.y
+  const int col = blockIdx.y, lid = xcd_contiguous(blockIdx.x, nwg);
   {
     const int64_t o = (int64_t)col * bstride;
     x += o;
@@ -114,7 +113,7 @@ static hipError_t launch_st7_t(const Op& op, const void* xv, const void* y0v, co
   const int nwg = gx * gy * gz;
   const int64_t bs = nb > 1 ? op.bstride : 0;
   const double al = k.alpha.real(), be = k.beta.real(), g0 = k.g0.real(), g1 = k.g1.real();
-  const dim3 grid(nwg * nb), block(ST_TX * ST_TY);
+  const dim3 grid(nwg, nb), block(ST_TX * ST_TY);
 #define FA_ST7(A, B) \
   st7_chain<TX, TO, A, B><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, bs, x, y0, y1, out, al, be, g0, g1)
   if (y0 && y1)
@@ -196,9 +195,8 @@ __global__ __launch_bounds__(P_THREADS) void st7_pair(St7 s, int kz, int gx, int
           czm = (T)s.czm, czp = (T)s.czp;
   __shared__ T xs[4][P_XH][P_XW];
   __shared__ T ss[3][P_SH][P_SW];
-  // a batch of vectors (bstride elements apart): nwg workgroups per vector
-  const int lall = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int col = lall / nwg, lid = lall - col * nwg;
+  // a batch of vectors (bstride elements apart): vector blockIdx.y
+  const int col = blockIdx.y, lid = xcd_contiguous(blockIdx.x, nwg);
   {
     const int64_t o = (int64_t)col * bstride;
     x += o;
@@ -389,7 +387,7 @@ static hipError_t launch_st7_pair_t(const Op& op, const void* xv, const void* y0
   const int nwg = gx * gy * gz;
   const int64_t bs = nb > 1 ? op.bstride : 0;
   const bool w1 = out1 != nullptr;
-  const dim3 grid(nwg * nb), block(P_THREADS);
+  const dim3 grid(nwg, nb), block(P_THREADS);
 #define FA_PAIR(A, B, C) \
   st7_pair<TX, TO, A, B, C><<<grid, block, 0, st>>>(s, kz, gx, gy, nwg, bs, x, y0, y1, out1, out2, c)
   if (y0 && y1) {

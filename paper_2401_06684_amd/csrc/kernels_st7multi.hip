@@ -104,9 +104,8 @@ __global__ __launch_bounds__(TW * TY) __attribute__((amdgpu_waves_per_eu(4))) vo
   __shared__ T lds[G::total()];
   const T c0 = (T)g.c0, cxm = (T)g.cxm, cxp = (T)g.cxp, cym = (T)g.cym, cyp = (T)g.cyp,
           czm = (T)g.czm, czp = (T)g.czp;
-  // a batch of vectors (bstride elements apart): nwg workgroups per vector
-  const int lall = xcd_contiguous(blockIdx.x, gridDim.x);
-  const int col = lall / nwg, lid = lall - col * nwg;
+  // a batch of vectors (bstride elements apart): vector blockIdx.y
+  const int col = blockIdx.y, lid = xcd_contiguous(blockIdx.x, nwg);
   {
     const int64_t o = (int64_t)col * bstride;
     x += o;
@@ -349,7 +348,7 @@ hipError_t launch_multi_t(const Op& op, const void* x, const void* v, const void
   const int kz = (g.nz + gz - 1) / gz;
   gz = (g.nz + kz - 1) / kz;
   const int nwg = gx * gy * gz;
-  const dim3 grid(nwg * nb), block(TW * TY);
+  const dim3 grid(nwg, nb), block(TW * TY);
   const int64_t bs = nb > 1 ? op.bstride : 0;
   const TX* xp = (const TX*)x;
   const TX* vp = (const TX*)v;
