@@ -15,6 +15,12 @@ on a vector) without any Krylov iteration, so they pin the iterative oracle:
   momentum space: D(p) = (m0 + sum(1 - cos p_mu)) I + i sum gamma_mu sin p_mu, a
   4x4 matrix a I + i S with S^2 = |s|^2 I, whose function is
   (f(a + i|s|) + f(a - i|s|))/2 I + (f(a + i|s|) - f(a - i|s|))/(2 i |s|) (i S).
+* ``wilson_free_q2_fAb``: Q^2 with Q = Gamma_5 D for unit links and a
+  chemical potential mu (the temporal momentum becomes p_t - i mu): Gamma_5
+  anticommutes with every gamma_nu, so Q^2 = (a - i S)(a + i S) = a^2 + S^2,
+  and S^2 = sum_nu s_nu^2 (complex s_nu when mu != 0) is a multiple of the
+  identity: f(Q^2) is the scalar f(a^2 + sum s_nu^2) in momentum space
+  (Sec. 6, Example 2 computes (Q^2)^{-1/2} b).
 * ``wilson_pure_gauge_fAb``: links U_mu(x) = G(x) G(x + mu)^H make the
   operator G D_free G^H, so f(D) b = G f(D_free) (G^H b).
 * ``dense_fAb``: scipy.linalg.sqrtm of a dense matrix (Schur method), for
@@ -102,6 +108,32 @@ def wilson_free_fAb(L, m0, b, kind="invsqrt"):
     # a plane wave e^{i p x} picks up e^{+i p_mu} from psi(x + mu): the forward
     # transform here uses e^{-i p x}, i.e. a mode b(x) = e^{+i p x} lands on p.
     yh = _fourier_symbol_apply(L, m0, bh, kind)
+    return np.fft.ifftn(yh, axes=(0, 1, 2, 3)).reshape(-1)
+
+
+def wilson_free_symbol(L, mu=0.0):
+    """(a, s) of D(p) = a I + i sum_nu gamma_nu s_nu for unit links on an
+    L = (L_t, L_z, L_y, L_x) lattice: a = sum_nu (1 - cos q_nu) (without the
+    mass shift), s_nu = sin q_nu, q = p except q_t = p_t - i mu.  Arrays over
+    the momentum grid in the layout of numpy's fftn of a [t][z][y][x] field;
+    s ordered x, y, z, t."""
+    Lt, Lz, Ly, Lx = L
+    pt, pz, py, px = np.meshgrid(*(2.0 * math.pi * np.arange(n) / n for n in (Lt, Lz, Ly, Lx)),
+                                 indexing="ij")
+    q = (px.astype(complex), py.astype(complex), pz.astype(complex), pt - 1j * mu)
+    a = sum(1.0 - np.cos(qi) for qi in q)
+    s = [np.sin(qi) for qi in q]
+    return a, s
+
+
+def wilson_free_q2_fAb(L, m0, b, mu=0.0, kind="invsqrt"):
+    """f(Q^2) b, Q = Gamma_5 D, for unit links with chemical potential mu."""
+    a, s = wilson_free_symbol(L, mu)
+    a = a + m0
+    lam = a * a + sum(si * si for si in s)
+    b4 = np.asarray(b, dtype=np.complex128).reshape(*L, 4, 3)
+    bh = np.fft.fftn(b4, axes=(0, 1, 2, 3))
+    yh = _f(kind)(lam)[..., None, None] * bh
     return np.fft.ifftn(yh, axes=(0, 1, 2, 3)).reshape(-1)
 
 

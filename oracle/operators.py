@@ -9,12 +9,17 @@ Test infrastructure only (see the package header).
 * CSR matrices (the sparse matrix-vector product of Examples 1 and 3).
 * A Wilson-Dirac-like operator on a periodic 4D lattice with 12 complex
   degrees of freedom per site (Example 2 describes the Wilson-Dirac operator
-  and its spinor layout: 4 spins x 3 colours).
+  and its spinor layout: 4 spins x 3 colours), with an optional chemical
+  potential, and the square Q^2 of Q = Gamma_5 D whose inverse square root
+  Example 2 computes.
 
 Pins: ``stencil_apply`` against the assembled CSR and the DST eigenbasis
 (tests/test_oracle_operators.py); ``wilson_apply`` against gamma-5
-hermiticity, the free-field Fourier symbol and the pure-gauge equivalence;
-``*_interval`` against dense eigenvalues on small grids.
+hermiticity (with a chemical potential: D(mu)^H = Gamma_5 D(-mu) Gamma_5),
+the free-field Fourier symbol (at a complex temporal momentum for mu != 0)
+and the pure-gauge equivalence; ``wilson_q2_apply`` against the Hermitian
+positive semidefinite Q^2 at mu = 0; ``*_interval`` against dense
+eigenvalues on small grids.
 """
 from __future__ import annotations
 
@@ -133,17 +138,20 @@ def gamma_matrices():
 _AXIS = (3, 2, 1, 0)
 
 
-def wilson_apply(links, m0, psi):
+def wilson_apply(links, m0, psi, mu=0.0):
     """y = D psi for the Wilson-Dirac-like operator with mass shift m0:
 
         (D psi)(x) = (4 + m0) psi(x)
-                     - 1/2 sum_mu [ (I - gamma_mu) U_mu(x) psi(x + mu)
-                                    + (I + gamma_mu) U_mu(x - mu)^H psi(x - mu) ].
+                     - 1/2 sum_nu [ e^{+mu d_nu,t} (I - gamma_nu) U_nu(x) psi(x + nu)
+                                    + e^{-mu d_nu,t} (I + gamma_nu) U_nu(x - nu)^H psi(x - nu) ].
 
     links: (4, L_t, L_z, L_y, L_x, 3, 3) complex; psi: flat complex vector of
     length V*12 in [t][z][y][x][spin][colour] order.  Periodic boundaries.
-    Its Hermitian part is m0 + 1/2 sum_mu (I - X_mu)^H (I - X_mu) >= m0 with
-    X_mu the (unitary) gauge-covariant forward shift, so spec(D) lies in the
+    mu: the chemical potential of Sec. 6, Example 2, as the factors e^{+-mu}
+    on the temporal hops (the usual lattice form; the paper gives no formula,
+    it only says that mu != 0 makes Gamma_5 D non-Hermitian).  For mu = 0 the
+    Hermitian part is m0 + 1/2 sum_nu (I - X_nu)^H (I - X_nu) >= m0 with X_nu
+    the (unitary) gauge-covariant forward shift, so spec(D) lies in the
     half-plane Re z >= m0.
     """
     g, _ = gamma_matrices()
@@ -151,17 +159,26 @@ def wilson_apply(links, m0, psi):
     shp = U.shape[1:5]
     p = np.asarray(psi, dtype=np.complex128).reshape(*shp, 4, 3)
     out = (4.0 + m0) * p
-    for mu in range(4):
-        ax = _AXIS[mu]
-        fwd = np.roll(p, -1, axis=ax)                         # psi(x + mu)
-        up = np.einsum("...ab,...sb->...sa", U[mu], fwd)      # U_mu(x) psi(x+mu)
-        Ub = np.roll(U[mu], 1, axis=ax)                       # U_mu(x - mu)
-        bwd = np.roll(p, 1, axis=ax)                          # psi(x - mu)
-        dn = np.einsum("...ba,...sb->...sa", Ub.conj(), bwd)  # U^H psi(x-mu)
-        gup = np.einsum("st,...tc->...sc", g[mu], up)
-        gdn = np.einsum("st,...tc->...sc", g[mu], dn)
+    for nu in range(4):
+        ax = _AXIS[nu]
+        ef, eb = (math.exp(mu), math.exp(-mu)) if nu == 3 else (1.0, 1.0)
+        fwd = np.roll(p, -1, axis=ax)                         # psi(x + nu)
+        up = ef * np.einsum("...ab,...sb->...sa", U[nu], fwd)  # U_nu(x) psi(x+nu)
+        Ub = np.roll(U[nu], 1, axis=ax)                       # U_nu(x - nu)
+        bwd = np.roll(p, 1, axis=ax)                          # psi(x - nu)
+        dn = eb * np.einsum("...ba,...sb->...sa", Ub.conj(), bwd)  # U^H psi(x-nu)
+        gup = np.einsum("st,...tc->...sc", g[nu], up)
+        gdn = np.einsum("st,...tc->...sc", g[nu], dn)
         out = out - 0.5 * ((up - gup) + (dn + gdn))
     return out.reshape(-1)
+
+
+def wilson_q2_apply(links, m0, psi, mu=0.0):
+    """y = Q^2 psi with Q = Gamma_5 D (Sec. 6, Example 2: the sign function
+    of Q through (Q^2)^{-1/2}; Q^2 is applied as two products with Q, never
+    formed)."""
+    q = gamma5_apply(wilson_apply(links, m0, psi, mu))
+    return gamma5_apply(wilson_apply(links, m0, q, mu))
 
 
 def gamma5_apply(psi):

@@ -136,6 +136,26 @@ def test_wilson_free_and_pure_gauge_against_fourier():
             assert rel(res.x, ref) < 1e-10
 
 
+def test_overlap_q2_free_field_against_fourier():
+    # Sec. 6, Example 2: (Q^2)^{-1/2} b and (Q^2)^{1/2} b, Q = Gamma_5 D(m_w, mu)
+    # at m_w = -1.4, mu = 0.3 (non-Hermitian Q^2), Ritz polynomials of degree
+    # 0 and 7, against the momentum-space closed form for unit links
+    Ls = (4, 3, 3, 3)
+    m0, mu = -1.4, 0.3
+    n = int(np.prod(Ls)) * 12
+    b = wl.rhs(n, seed=0, complex_=True)
+    U1 = np.zeros((4, *Ls, 3, 3), dtype=complex)
+    U1[...] = np.eye(3)
+    op = lambda x: ops.wilson_q2_apply(U1, m0, x, mu)  # noqa: E731
+    for kind in ("invsqrt", "sqrt"):
+        ref = exact.wilson_free_q2_fAb(Ls, m0, b, mu, kind)
+        for degree in (0, 7):
+            q = pl.ritz(op, wl.rhs(n, seed=1, complex_=True), degree, real_operator=False)
+            res = kr.fAb(op, b, q, kind, m_max=400, tol=1e-12)
+            assert res.converged
+            assert rel(res.x, ref) < 1e-10
+
+
 def test_wilson_random_links_against_dense():
     L = 2
     U = wl.su3_links(L, eps=0.3, seed=1)

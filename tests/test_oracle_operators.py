@@ -114,6 +114,61 @@ def test_wilson_free_field_symbol():
     assert np.allclose(y, s, atol=1e-12)
 
 
+def test_wilson_chemical_potential_free_symbol():
+    # unit links: D(mu) acts in momentum space as (m0 + a) + i sum gamma s at
+    # the complex temporal momentum p_t - i mu (a plane wave picks up e^{+mu}
+    # from the forward temporal hop and e^{-mu} from the backward one)
+    L = (4, 2, 3, 4)
+    m0, mu = -1.4, 0.3
+    U = np.zeros((4, *L, 3, 3), dtype=np.complex128)
+    U[...] = np.eye(3)
+    b = wl.rhs(int(np.prod(L)) * 12, seed=6, complex_=True)
+    y = ops.wilson_apply(U, m0, b, mu)
+    g, _ = ops.gamma_matrices()
+    a, s = exact.wilson_free_symbol(L, mu)
+    bh = np.fft.fftn(b.reshape(*L, 4, 3), axes=(0, 1, 2, 3))
+    yh = (m0 + a)[..., None, None] * bh + 1j * sum(
+        s[nu][..., None, None] * np.einsum("st,...tc->...sc", g[nu], bh) for nu in range(4))
+    assert np.allclose(y, np.fft.ifftn(yh, axes=(0, 1, 2, 3)).reshape(-1), atol=1e-12)
+
+
+def test_wilson_chemical_potential_gamma5_relation_and_q2():
+    # D(mu)^H = G5 D(-mu) G5; Q = G5 D(0) is Hermitian and Q^2 positive
+    # semidefinite; Q^2 for mu != 0 is not Hermitian
+    L = 2
+    U = wl.su3_links(L, eps=1.5, seed=11)
+    m0, mu = -1.4, 0.3
+    n = L ** 4 * 12
+    G5 = _dense(ops.gamma5_apply, n)
+    Dp = _dense(lambda v: ops.wilson_apply(U, m0, v, mu), n)
+    Dm = _dense(lambda v: ops.wilson_apply(U, m0, v, -mu), n)
+    assert np.allclose(Dp.conj().T, G5 @ Dm @ G5, atol=1e-13)
+    D0 = _dense(lambda v: ops.wilson_apply(U, m0, v), n)
+    Q0 = G5 @ D0
+    assert np.allclose(Q0, Q0.conj().T, atol=1e-13)
+    Q2 = _dense(lambda v: ops.wilson_q2_apply(U, m0, v), n)
+    assert np.allclose(Q2, Q0 @ Q0, atol=1e-12)
+    assert np.linalg.eigvalsh(0.5 * (Q2 + Q2.conj().T)).min() > -1e-12
+    Q2m = _dense(lambda v: ops.wilson_q2_apply(U, m0, v, mu), n)
+    assert np.allclose(Q2m, (G5 @ Dp) @ (G5 @ Dp), atol=1e-12)
+    assert not np.allclose(Q2m, Q2m.conj().T, atol=1e-3)
+
+
+def test_wilson_free_q2_closed_form_against_dense():
+    # the scalar symbol of Q^2 against the dense principal square root of the
+    # assembled Q^2 (unit links, mu = 0.3)
+    L = (2, 2, 2, 2)
+    m0, mu = -1.4, 0.3
+    U = np.zeros((4, *L, 3, 3), dtype=np.complex128)
+    U[...] = np.eye(3)
+    n = 16 * 12
+    Q2 = _dense(lambda v: ops.wilson_q2_apply(U, m0, v, mu), n)
+    b = wl.rhs(n, seed=9, complex_=True)
+    for kind in ("invsqrt", "sqrt"):
+        ref = exact.dense_fAb(Q2, b, kind)
+        assert np.allclose(exact.wilson_free_q2_fAb(L, m0, b, mu, kind), ref, atol=1e-11)
+
+
 def test_wilson_pure_gauge_equivalence():
     L = 3
     U, G = wl.pure_gauge_links(L, seed=4)
