@@ -141,6 +141,12 @@ enum {
                             parameters are tuned and replayed afterwards (per op,
                             polynomial, workspace address, block size, m_max,
                             precision and step index; released by fa_destroy) */
+  FA_Q2 = 4096u,         /* create (FA_WILSON4D): the operator is A = Q^2, Q = Gamma_5 D
+                            (Sec. 6, Example 2: the sign function of Q through
+                            (Q^2)^{-1/2}); each product with A is two products with
+                            Q, Q^2 is never formed.  Applying it needs one
+                            vector of scratch from the workspace (see
+                            fa_workspace_bytes, fa_op_apply).                    */
   FA_MIXED = 32u         /* apply: the polynomial chain (A and q(A) in the three-stage
                             product, and c = q(A) b) in FP32 storage with FP32
                             accumulation; Gram-Schmidt, H, H^{-1/2} e_1, the basis and
@@ -188,7 +194,8 @@ typedef struct {
  *                and 12 l bytes of long rows, each rounded up to a multiple
  *                of 256, where l = nnz / 4097 + 1, c = 2 l + nnz / 4096.
  *   FA_WILSON4D: 576 V bytes (V = Lx Ly Lz Lt from dims): the links in the
- *                kernels' order, whole; special unitary links use 384 V of it.
+ *                kernels' order, whole; special unitary links use 384 V of it
+ *                (with FA_Q2 too: its scratch vector is workspace, per call).
  * Returns 0 for an unknown kind or invalid dims.  Needs no GPU.
  */
 size_t fa_op_device_bytes(int kind, const int32_t dims[4], int64_t n, int64_t nnz);
@@ -231,9 +238,13 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
  *     c_dm c_dp > 0 in every direction the spectrum is real and the op gets the
  *     exact interval c0 -+ sum_d 2 sqrt(c_dm c_dp) cos(pi / (N_d + 1)) (for the
  *     Laplacian, the interval stated in Sec. 6, Example 1).
- *   FA_WILSON4D: dims = {Lx, Ly, Lz, Lt} (each >= 2), params = {m0} (1 double):
- *       (D psi)(x) = (4 + m0) psi(x) - 1/2 sum_mu [(I - g_mu) U_mu(x) psi(x + mu)
- *                                                + (I + g_mu) U_mu(x - mu)^H psi(x - mu)]
+ *   FA_WILSON4D: dims = {Lx, Ly, Lz, Lt} (each >= 2), params = {m0} or
+ *     {m0, mu} (1 or 2 doubles):
+ *       (D psi)(x) = (4 + m0) psi(x) - 1/2 sum_nu [e^{mu d_nu,t} (I - g_nu) U_nu(x) psi(x + nu)
+ *                                    + e^{-mu d_nu,t} (I + g_nu) U_nu(x - nu)^H psi(x - nu)]
+ *     (mu: chemical potential on the temporal hops, 0 by default; m0 < 0 is
+ *     allowed, e.g. the shift m_w = -1.4 of Example 2); with flags FA_Q2 the
+ *     op is A = (Gamma_5 D)^2, Gamma_5 = diag(1, 1, -1, -1) on spin;
  *     periodic, chiral-basis Euclidean gamma matrices; 12 complex per site,
  *     vectors [t][z][y][x][spin 4][colour 3] (FA_C128).  d_links: device
  *     double complex[4][Lt][Lz][Ly][Lx][3][3] (direction mu = x, y, z, t, row
@@ -245,8 +256,9 @@ int fa_create_csr(fa_op* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
  *     checked on the host at creation) only rows 0 and 1 are kept (24 V
  *     complex doubles) and the kernels rebuild row 2; otherwise all of it
  *     (36 V).  The Wilson-Dirac operator is the matrix of Sec. 6, Example 2
- *     (without clover term and chemical potential).
- *   flags: FA_HERMITIAN allowed only for symmetric stencils.
+ *     without its clover term.
+ *   flags: FA_HERMITIAN allowed only for symmetric stencils and for FA_Q2
+ *     with mu = 0 (then Gamma_5 D is Hermitian); FA_Q2 only for FA_WILSON4D.
  *   d_opmem, opmem_bytes: operator memory (256-byte aligned), at least
  *     fa_op_device_bytes(kind, dims, 0, 0) bytes; NULL for FA_STENCIL7.
  * Errors: FA_ERR_ARG, FA_ERR_WORKSPACE (Wilson: d_opmem NULL, misaligned or

@@ -19,8 +19,8 @@ import torch
 from . import _lib
 from ._lib import (FA_C128, FA_F64, FA_FORCE_ARNOLDI, FA_HERMITIAN, FA_INVSQRT,  # noqa: F401
                    FA_MIXED, FA_NO_FUSION, FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_HARMONIC,
-                   FA_POLY_LS, FA_POLY_RITZ, FA_PROFILE, FA_RIGHT_PREC, FA_SQRT, FA_TWO_PASS, FAError,
-                   check, lib)
+                   FA_POLY_LS, FA_POLY_RITZ, FA_PROFILE, FA_Q2, FA_RIGHT_PREC, FA_SQRT,
+                   FA_TWO_PASS, FAError, check, lib)
 
 __all__ = ["Stencil7", "CSR", "Wilson", "Server", "FAError", "lib", "dense_invsqrt_e1",
            "dense_tridiag_invsqrt_e1"]
@@ -281,11 +281,12 @@ class Operator:
     def op_apply(self, x, out=None, split_long_rows=True):
         """y = A x (one operator application).  A CSR op splits rows of more
         than 4096 entries over several workgroups in a scratch workspace
-        (split_long_rows=False: one workgroup per such row, the same bits)."""
+        (split_long_rows=False: one workgroup per such row, the same bits);
+        a squared Wilson op always takes the workspace (for Q x)."""
         x = self._vec(x, "x")
         y = out if out is not None else torch.empty_like(x)
         wsp, nbytes = C.c_void_p(0), 0
-        if split_long_rows:
+        if split_long_rows or getattr(self, "squared", False):
             _, wsp, nbytes = self._workspace(1)
         check(lib().fa_op_apply(self._h, _ptr(x), _ptr(y), wsp, nbytes, _stream(self.device)),
               "fa_op_apply")
@@ -347,9 +348,12 @@ class Wilson(Operator):
     """Wilson-Dirac-like operator on a periodic 4D lattice (12 complex per site).
 
     links: complex128 tensor [4][Lt][Lz][Ly][Lx][3][3] (mu = x, y, z, t).
+    mu: chemical potential on the temporal hops.  squared=True makes the op
+    A = Q^2 with Q = Gamma_5 D (Sec. 6, Example 2: sign(Q) b = Q (Q^2)^{-1/2} b);
+    hermitian=True (only with squared and mu = 0) selects Lanczos.
     """
 
-    def __init__(self, links, m0, device="cuda"):
+    def __init__(self, links, m0, device="cuda", mu=0.0, squared=False, hermitian=False):
         dev = torch.device(device)
         U = torch.as_tensor(links).to(device=dev, dtype=torch.complex128).contiguous()
         if U.dim() != 7 or U.shape[0] != 4 or tuple(U.shape[-2:]) != (3, 3):
@@ -357,15 +361,17 @@ class Wilson(Operator):
         Lt, Lz, Ly, Lx = (int(s) for s in U.shape[1:5])
         h = C.c_void_p()
         d4 = (C.c_int32 * 4)(Lx, Ly, Lz, Lt)
-        p = (C.c_double * 1)(float(m0))
+        p = (C.c_double * 2)(float(m0), float(mu))
+        flags = (FA_Q2 if squared else 0) | (FA_HERMITIAN if hermitian else 0)
         # operator memory for the library's reordered copy of the links
         mem, mp, mb = workspace(lib().fa_op_device_bytes(_lib.FA_WILSON4D, d4, 0, 0), dev)
         # the library copies the links (reordered) on this stream and waits
-        st = lib().fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1, _ptr(U), 0,
+        st = lib().fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 2, _ptr(U), flags,
                                      mp, mb, _stream(dev))
         check(st, "fa_create_stencil")
         super().__init__(h, dev, (mem,))
         self.lattice = (Lt, Lz, Ly, Lx)
+        self.squared = bool(squared)
 
 
 class Server:

@@ -25,7 +25,7 @@ FA_STENCIL7, FA_WILSON4D, FA_CSR = 0, 1, 2
 FA_POLY_AUTO, FA_POLY_CHEB, FA_POLY_RITZ, FA_POLY_HARMONIC, FA_POLY_LS = 0, 1, 2, 3, 4
 FA_HERMITIAN, FA_FORCE_ARNOLDI, FA_PROFILE, FA_NO_FUSION, FA_MIXED = 1, 4, 8, 16, 32
 FA_TWO_PASS, FA_RIGHT_PREC, FA_GRAPH, FA_CGS2, FA_FUSE2 = 64, 128, 256, 512, 1024
-FA_FUSE3 = 2048
+FA_FUSE3, FA_Q2 = 2048, 4096
 
 EXPORTS = [
     "fa_op_device_bytes", "fa_create_csr", "fa_create_stencil", "fa_set_spectral_interval",

@@ -172,7 +172,8 @@ int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double*
                       int nparams, const void* d_links, uint32_t flags, void* d_opmem,
                       size_t opmem_bytes, void* hip_stream) {
   if (!out || !dims || !params) return FA_ERR_ARG;
-  if (flags & ~uint32_t(FA_HERMITIAN)) return FA_ERR_ARG;
+  if (flags & ~uint32_t(FA_HERMITIAN | FA_Q2)) return FA_ERR_ARG;
+  if ((flags & FA_Q2) && kind != FA_WILSON4D) return FA_ERR_ARG;
   for (int d = 0; d < 4; ++d)
     if (dims[d] < 1) return FA_ERR_ARG;
   return guarded([&] {
@@ -199,7 +200,7 @@ int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double*
         op.hi = hi;
       }
     } else if (kind == FA_WILSON4D) {
-      if (nparams != 1 || !d_links || (flags & FA_HERMITIAN)) return FA_ERR_ARG;
+      if ((nparams != 1 && nparams != 2) || !d_links) return FA_ERR_ARG;
       for (int d = 0; d < 4; ++d)
         if (dims[d] < 2) return FA_ERR_ARG;
       const int64_t V = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
@@ -209,7 +210,12 @@ int fa_create_stencil(fa_op* out, int kind, const int32_t dims[4], const double*
       op.n = V * 12;
       for (int d = 0; d < 4; ++d) op.dims[d] = dims[d];
       op.m0 = params[0];
-      if (!std::isfinite(op.m0)) return FA_ERR_ARG;
+      op.mu = nparams > 1 ? params[1] : 0.0;
+      op.q2 = (flags & FA_Q2) != 0;
+      if (!std::isfinite(op.m0) || !std::isfinite(op.mu) || std::fabs(op.mu) > 20.0)
+        return FA_ERR_ARG;
+      // Gamma_5 D is Hermitian only without a chemical potential
+      if ((flags & FA_HERMITIAN) && !(op.q2 && op.mu == 0.0)) return FA_ERR_ARG;
       // Special unitary links (det 1: row 2 = conj(row 0 x row 1) to within
       // 1e-13) are stored as their first two rows and the kernel rebuilds the
       // third (a third less link traffic); other links are stored whole.

@@ -81,6 +81,8 @@ struct Op {
   const void* links = nullptr;
   int links_rows = 3;  // rows of each link stored (2: special unitary, row 2 rebuilt)
   double m0 = 0.0;
+  double mu = 0.0;     // chemical potential (temporal hops scaled by e^{+-mu})
+  bool q2 = false;     // the op is (Gamma_5 D)^2
   // spectral interval
   bool has_interval = false;
   double lo = 0, hi = 0;
@@ -136,15 +138,17 @@ hipError_t launch_chain_multi(const Op& op, int nt, const void* x, const void* v
                               Prec pin, Prec pout, int blocks = 0, hipEvent_t ev0 = nullptr,
                               hipEvent_t ev1 = nullptr);
 
-// Scratch of a CSR launch whose long rows are split over several workgroups
-// (their partial sums and one counter per long row): the bytes a call needs
-// (0: the op has no long rows), clearing its counters before the first launch
-// of a call, and the scratch the CSR launches of the calling thread use
-// (nullptr: each long row summed by one workgroup, the same bits); returns
-// the previous one.
-size_t csr_scratch_bytes(const Op& op);
-hipError_t csr_scratch_clear(const Op& op, void* scratch, hipStream_t s);
-void* set_csr_scratch(void* p);
+// Operator scratch, from the caller's workspace: for a CSR op whose long
+// rows are split over several workgroups, their partial sums and one counter
+// per long row (nullptr: each long row summed by one workgroup, the same
+// bits); for a Wilson op with q2, the intermediate vector Q x of a product
+// with Q^2 (required).  The bytes a call needs (0: none), clearing the
+// counters before the first launch of a call, and the scratch the chain
+// launches of the calling thread use; set_op_scratch returns the previous
+// one.
+size_t op_scratch_bytes(const Op& op);
+hipError_t op_scratch_clear(const Op& op, void* scratch, hipStream_t s);
+void* set_op_scratch(void* p);
 
 // Small Hermitian problems: the Lanczos steps j0 .. j1 - 1 of Algorithm 1 in
 // one workgroup (kernels_small.hip).  Real FP64, n <= kSmallMaxN, a 7-point

@@ -609,21 +609,22 @@ __global__ void csr_zero_counters(int* cnt, int n) {
 }
 
 namespace {
-thread_local void* t_csr_scratch = nullptr;
+thread_local void* t_op_scratch = nullptr;
 }
-void* set_csr_scratch(void* p) {
-  void* old = t_csr_scratch;
-  t_csr_scratch = p;
+void* set_op_scratch(void* p) {
+  void* old = t_op_scratch;
+  t_op_scratch = p;
   return old;
 }
 
-size_t csr_scratch_bytes(const Op& op) {
+size_t op_scratch_bytes(const Op& op) {
+  if (op.kind == OP_WILSON && op.q2) return (size_t)round_up(op.n * 16, 256);
   if (op.kind != OP_CSR || op.csr_nlong == 0) return 0;
   return (size_t)round_up((int64_t)op.csr_nchunk * (int64_t)elem_size(op.dtype), 256) +
          (size_t)round_up((int64_t)op.csr_nlong * 4, 256);
 }
 
-hipError_t csr_scratch_clear(const Op& op, void* scratch, hipStream_t st) {
+hipError_t op_scratch_clear(const Op& op, void* scratch, hipStream_t st) {
   if (op.kind != OP_CSR || op.csr_nlong == 0 || !scratch) return hipSuccess;
   int* cnt = (int*)((char*)scratch +
                     round_up((int64_t)op.csr_nchunk * (int64_t)elem_size(op.dtype), 256));
@@ -640,7 +641,7 @@ static void launch_csr_y(const Op& op, const T* x, const T* y0, const T* y1, T* 
   const int4* bk = (const int4*)op.csr_blk_dev;
   const int4* ck = (const int4*)op.csr_chunk_dev;
   const int32_t* lg = op.csr_long_dev;
-  void* sc = op.csr_nlong ? t_csr_scratch : nullptr;
+  void* sc = op.csr_nlong ? t_op_scratch : nullptr;
   if (sc) {
     T* part = (T*)sc;
     int* cnt = (int*)((char*)sc + round_up((int64_t)op.csr_nchunk * (int64_t)sizeof(T), 256));
@@ -704,6 +705,7 @@ struct Wil {
   int L0, L1, L2, L3;  // x, y, z, t extents
   int V;
   double diag;         // 4 + m0
+  double ef, eb;       // e^{+mu}, e^{-mu}: the forward / backward temporal hop
 };
 
 constexpr int kWilDSites = 64;  // sites per workgroup (one per lane)
@@ -761,7 +763,7 @@ __device__ __forceinline__ cplx sgn(cplx a) {
 // p % 6, of the neighbour of site p / 6: h_sp,c = u_sp,c + sg M_sp d_sp',c
 template <int MU, int SG>
 __device__ __forceinline__ void wilson_dir_stage(const cplx* __restrict__ x, int nb, int lane,
-                                                 cplx* slice) {
+                                                 double scale, cplx* slice) {
   using D = WilDir<MU>;
   cplx u[6], d[6];
 #pragma unroll
@@ -779,7 +781,9 @@ __device__ __forceinline__ void wilson_dir_stage(const cplx* __restrict__ x, int
     const int p = kk * kWilDSites + lane;
     const bool s1 = p % 6 >= 3;
     const cplx md = s1 ? D::template m<1>(d[kk]) : D::template m<0>(d[kk]);
-    slice[p] = u[kk] + sgn<SG>(md);
+    const cplx h = u[kk] + sgn<SG>(md);
+    // the temporal hops carry the chemical potential (x 1 exactly for mu = 0)
+    slice[p] = MU == 3 ? scale * h : h;
   }
 }
 
@@ -841,19 +845,22 @@ __device__ __forceinline__ void wilson_dir_body(const Wil& w, const cplx* __rest
   const cplx* Um = Us + (int64_t)MU * NE * w.V;
   const cplx* mine = slice + lane * 6;
   // forward hop: (1 - g_mu) U_mu(s) x(s + mu)
-  wilson_dir_stage<MU, -1>(x, sf, lane, slice);
+  wilson_dir_stage<MU, -1>(x, sf, lane, w.ef, slice);
   __builtin_amdgcn_wave_barrier();
   wilson_dir_hop<MU, -1, false, R12>(mine, Um + s, w.V, acc);
   __builtin_amdgcn_wave_barrier();
   // backward hop: (1 + g_mu) U_mu(s - mu)^H x(s - mu)
-  wilson_dir_stage<MU, 1>(x, sb, lane, slice);
+  wilson_dir_stage<MU, 1>(x, sb, lane, w.eb, slice);
   __builtin_amdgcn_wave_barrier();
   wilson_dir_hop<MU, 1, true, R12>(mine, Um + sb, w.V, acc);
 }
 
-template <bool Y0, bool Y1, bool R12>
+// out = al G (D x) + be xb + g0 y0 + g1 y1, G = Gamma_5 (G5) or I; xb is x
+// itself except in the second product of a Q^2 term
+template <bool Y0, bool Y1, bool R12, bool G5>
 __global__ __launch_bounds__(256) void wilson_dir_k(Wil w, const cplx* __restrict__ Us,
                                                     const cplx* __restrict__ x,
+                                                    const cplx* __restrict__ xb,
                                                     const cplx* __restrict__ y0,
                                                     const cplx* y1, cplx* out, cplx al,
                                                     cplx be, cplx g0, cplx g1) {
@@ -915,7 +922,8 @@ __global__ __launch_bounds__(256) void wilson_dir_k(Wil w, const cplx* __restric
       }
   }
   __syncthreads();
-  // out = al (diag x - sum / 2) + be x + g0 y0 + g1 y1, value by value
+  // out = al G (diag x - sum / 2) + be xb + g0 y0 + g1 y1, value by value
+  // (value q of a site is spin q % 12 / 3: Gamma_5 negates spins 2 and 3)
   const int64_t base = (int64_t)s0 * 12;
   const cplx* S = lds + kAcc;
 #pragma unroll
@@ -923,8 +931,9 @@ __global__ __launch_bounds__(256) void wilson_dir_k(Wil w, const cplx* __restric
     const int q = threadIdx.x + 256 * i;
     if (q < nsite * 12) {
       const cplx xc = x[base + q];
-      const cplx dx = w.diag * xc - 0.5 * S[q];
-      cplx r = mad(al, dx, be * xc);
+      cplx dx = w.diag * xc - 0.5 * S[q];
+      if (G5 && q % 12 >= 6) dx = cplx{-dx.x, -dx.y};
+      cplx r = mad(al, dx, be * (G5 ? xb[base + q] : xc));
       if (Y0) r = mad(g0, y0[base + q], r);
       if (Y1) r = mad(g1, y1[base + q], r);
       out[base + q] = r;
@@ -935,12 +944,34 @@ __global__ __launch_bounds__(256) void wilson_dir_k(Wil w, const cplx* __restric
 static hipError_t launch_wilson(const Op& op, const cplx* x, const cplx* y0, const cplx* y1,
                                 cplx* out, const ChainCoef& k, hipStream_t st) {
   Wil w{op.dims[0], op.dims[1], op.dims[2], op.dims[3],
-        op.dims[0] * op.dims[1] * op.dims[2] * op.dims[3], 4.0 + op.m0};
+        op.dims[0] * op.dims[1] * op.dims[2] * op.dims[3], 4.0 + op.m0, std::exp(op.mu),
+        std::exp(-op.mu)};
   const cplx al = host_to_dev<cplx>::conv(k.alpha), be = host_to_dev<cplx>::conv(k.beta),
              g0 = host_to_dev<cplx>::conv(k.g0), g1 = host_to_dev<cplx>::conv(k.g1);
   const cplx* U = (const cplx*)op.links;
   const int grid = (w.V + kWilDSites - 1) / kWilDSites;
-#define FA_WIL(A, B, R) wilson_dir_k<A, B, R><<<grid, 256, 0, st>>>(w, U, x, y0, y1, out, al, be, g0, g1)
+  // Q^2: t = Gamma_5 D x into the operator scratch, then out = al Gamma_5 D t
+  // + be x + g0 y0 + g1 y1
+  const cplx* hx = x;  // the vector the hops of the (last) product read
+  if (op.q2) {
+    cplx* t = (cplx*)t_op_scratch;
+    if (!t) return hipErrorInvalidValue;
+    const cplx one{1.0, 0.0}, zero{0.0, 0.0};
+    if (op.links_rows == 2)
+      wilson_dir_k<false, false, true, true><<<grid, 256, 0, st>>>(w, U, x, x, nullptr, nullptr,
+                                                                   t, one, zero, zero, zero);
+    else
+      wilson_dir_k<false, false, false, true><<<grid, 256, 0, st>>>(w, U, x, x, nullptr, nullptr,
+                                                                    t, one, zero, zero, zero);
+    hx = t;
+  }
+#define FA_WIL(A, B, R)                                                                         \
+  do {                                                                                          \
+    if (op.q2)                                                                                  \
+      wilson_dir_k<A, B, R, true><<<grid, 256, 0, st>>>(w, U, hx, x, y0, y1, out, al, be, g0, g1);  \
+    else                                                                                        \
+      wilson_dir_k<A, B, R, false><<<grid, 256, 0, st>>>(w, U, hx, x, y0, y1, out, al, be, g0, g1); \
+  } while (0)
 #define FA_WIL_R(A, B)  \
   if (op.links_rows == 2) \
     FA_WIL(A, B, true);   \
@@ -1011,6 +1042,10 @@ double chain_bytes(const Op& op, bool has_y0, bool has_y1, Prec p) {
   if (op.kind == OP_CSR)
     extra = (double)(op.n + 1) * 4 + (double)op.nnz * (4 + elem_size(op.dtype));
   if (op.kind == OP_WILSON) extra = 4.0 * (double)(op.n / 12) * (3 * op.links_rows) * 16;
+  if (op.kind == OP_WILSON && op.q2) {  // two products: x -> t, then t (and x) -> out
+    extra *= 2.0;
+    return (nvec + 3.0) * vec + extra;
+  }
   return nvec * vec + extra;
 }
 

@@ -63,8 +63,8 @@ Layout make_layout(const Op& op, int m_max, uint32_t flags, bool with_poly) {
   L.off_z = take((size_t)(m_max + 1) * es);
   if (with_poly && op.poly_ready && op.poly.method == FA_POLY_LS)
     L.off_W = take((size_t)(op.poly.degree + 1) * L.ldv * es);
-  L.csr_bytes = csr_scratch_bytes(op);
-  if (L.csr_bytes) L.off_csr = take(L.csr_bytes);
+  L.scr_bytes = op_scratch_bytes(op);
+  if (L.scr_bytes) L.off_scr = take(L.scr_bytes);
   L.bytes = off;
   return L;
 }
@@ -176,9 +176,10 @@ int op_apply(const Op& op, const void* x, void* y, void* ws, hipStream_t s) {
   void* sc = nullptr;
   if (ws) {
     const Layout L = make_layout(op, 1, 0);
-    if (L.csr_bytes) sc = at(ws, L.off_csr);
+    if (L.scr_bytes) sc = at(ws, L.off_scr);
   }
-  CsrScratchScope csr(op, sc, s);
+  if (!sc && op.kind == OP_WILSON && op.q2) return FA_ERR_WORKSPACE;  // Q x has to live somewhere
+  OpScratchScope csr(op, sc, s);
   if (!csr.ok()) return FA_ERR_HIP;
   return chain(op, x, nullptr, nullptr, y, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, nullptr);
 }
@@ -444,7 +445,7 @@ int poly_apply_chain(const Op& op, const void* x, void* out, void* const tmp[4],
 
 int poly_apply_public(const Op& op, const void* x, void* y, void* ws, hipStream_t s) {
   const Layout L = make_layout(op, 1, 0);
-  CsrScratchScope csr(op, L.csr_bytes ? at(ws, L.off_csr) : nullptr, s);
+  OpScratchScope csr(op, L.scr_bytes ? at(ws, L.off_scr) : nullptr, s);
   if (!csr.ok()) return FA_ERR_HIP;
   void* const tmp[4] = {at(ws, L.off_P), at(ws, L.off_Q), at(ws, L.off_R), at(ws, L.off_S)};
   const void* res = nullptr;
@@ -577,7 +578,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   std::memset(&S, 0, sizeof(S));
   const Layout L = make_layout(op, m_max, flags);
   if (!ws || ws_bytes < L.bytes || ((uintptr_t)ws & 255)) return FA_ERR_WORKSPACE;
-  CsrScratchScope csr(op, L.csr_bytes ? at(ws, L.off_csr) : nullptr, s);
+  OpScratchScope csr(op, L.scr_bytes ? at(ws, L.off_scr) : nullptr, s);
   if (!csr.ok()) return FA_ERR_HIP;
   const size_t es = elem_size(op.dtype);
   const int64_t n = op.n;
@@ -1185,11 +1186,13 @@ int setup_ritz_values(const Op& op, int steps, bool harmonic, const void* d_star
   double* nrm = (double*)at(ws, L.off_nrm);
   auto Vc = [&](int j) -> char* { return V + (size_t)j * L.ldv * es; };
   auto Hcol = [&](int j) -> char* { return Hd + (size_t)j * L.ldh * es; };
+  OpScratchScope scr(op, L.scr_bytes ? at(ws, L.off_scr) : nullptr, s);
+  if (!scr.ok()) return FA_ERR_HIP;
   FA_HIP(launch_update(op.dtype, n, 0, V, L.ldv, hcur, (void*)d_start, part, nrm, s));
   FA_HIP(launch_normalize(op.dtype, n, d_start, nrm, Vc(0), nullptr, s));
   for (int j = 0; j < d; ++j) {
     char* w = Vc(j + 1);
-    int st = op_apply(op, Vc(j), w, nullptr, s);
+    int st = chain(op, Vc(j), nullptr, nullptr, w, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, nullptr);
     if (st) return st;
     ++*mvms_setup;
     FA_HIP(launch_project(op.dtype, n, j + 1, V, L.ldv, w, part, hcur, Hcol(j), 1, s));

@@ -16,7 +16,7 @@ struct Layout {
          off_nrm = 0, off_z = 0;
   size_t off_W = 0;  // least-squares polynomial: its d basis vectors (0: none)
   size_t off_dc = 0; // coefficients of the delayed-reorthogonalization step
-  size_t off_csr = 0, csr_bytes = 0;  // CSR long rows split over workgroups (0: none)
+  size_t off_scr = 0, scr_bytes = 0;  // operator scratch (split CSR rows, Q x of Q^2; 0: none)
   size_t bytes = 0;
 };
 // with_poly: include the storage the op's polynomial needs (least squares)
@@ -36,16 +36,17 @@ std::vector<Term> poly_terms(const Poly& q);
 // (no half steps across the checks); profiling is refused by the caller
 constexpr uint32_t kApplyNoAlloc = 1u << 30;
 
-// the calling thread's CSR launches use `scratch` (may be null) while this
-// lives; the counters in it are cleared on construction (check ok())
-class CsrScratchScope {
+// the calling thread's chain launches use the operator scratch `scratch`
+// (may be null) while this lives; its counters are cleared on construction
+// (check ok())
+class OpScratchScope {
  public:
-  CsrScratchScope(const Op& op, void* scratch, hipStream_t s)
-      : err_(csr_scratch_clear(op, scratch, s)), prev_(set_csr_scratch(scratch)) {}
-  ~CsrScratchScope() { set_csr_scratch(prev_); }
+  OpScratchScope(const Op& op, void* scratch, hipStream_t s)
+      : err_(op_scratch_clear(op, scratch, s)), prev_(set_op_scratch(scratch)) {}
+  ~OpScratchScope() { set_op_scratch(prev_); }
   bool ok() const { return err_ == hipSuccess; }
-  CsrScratchScope(const CsrScratchScope&) = delete;
-  CsrScratchScope& operator=(const CsrScratchScope&) = delete;
+  OpScratchScope(const OpScratchScope&) = delete;
+  OpScratchScope& operator=(const OpScratchScope&) = delete;
 
  private:
   hipError_t err_;

@@ -78,6 +78,23 @@ def test_create_wilson_validation_and_link_copy_without_gpu():
                                mem, nb, None) == _lib.FA_ERR_ARG
     assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p, 1, C.c_void_p(256),
                                _lib.FA_HERMITIAN, mem, nb, None) == _lib.FA_ERR_ARG
+    # Q^2 (Gamma_5 D squared): only for the Wilson op; Hermitian only without a
+    # chemical potential; at most 2 parameters, finite
+    p2 = (C.c_double * 3)(-1.4, 0.3, 0.0)
+    assert L.fa_create_stencil(C.byref(h), _lib.FA_STENCIL7, (C.c_int32 * 4)(4, 4, 4, 1),
+                               (C.c_double * 7)(*([1.0] * 7)), 7, None, _lib.FA_Q2,
+                               None, 0, None) == _lib.FA_ERR_ARG
+    assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p2, 2, C.c_void_p(256),
+                               _lib.FA_Q2 | _lib.FA_HERMITIAN, mem, nb, None) == _lib.FA_ERR_ARG
+    assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p2, 3, C.c_void_p(256),
+                               _lib.FA_Q2, mem, nb, None) == _lib.FA_ERR_ARG
+    pinf = (C.c_double * 2)(-1.4, float("inf"))
+    assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, pinf, 2, C.c_void_p(256),
+                               _lib.FA_Q2, mem, nb, None) == _lib.FA_ERR_ARG
+    # mu = 0: the Hermitian Q^2 passes the checks (then needs the GPU)
+    p0 = (C.c_double * 2)(-1.4, 0.0)
+    assert L.fa_create_stencil(C.byref(h), _lib.FA_WILSON4D, d4, p0, 2, C.c_void_p(256),
+                               _lib.FA_Q2 | _lib.FA_HERMITIAN, mem, nb, None) == _lib.FA_ERR_HIP
     # operator memory missing, too small for the two-row links, misaligned
     V = 4 ** 4
     for m, b in ((None, nb), (mem, 4 * 6 * 16 * V - 256), (C.c_void_p((1 << 20) + 8), nb)):

@@ -630,6 +630,92 @@ def test_wilson_16_fixed_m_solve_against_oracle(wilson16):
     assert_close(host(x), ref.x, 1e-10)
 
 
+# --------------------------------------------------------------------------
+# Sec. 6, Example 2: (Q^2)^{-1/2} b with Q = Gamma_5 D(m_w, mu)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+@pytest.mark.parametrize("Ls", [(4, 4, 4, 4), (4, 3, 5, 4)])
+def test_overlap_q2_operator_against_oracle(mu, Ls):
+    """D with a chemical potential and Q^2 = (Gamma_5 D)^2 at m_w = -1.4, one
+    application each, against the oracle (a lattice whose 240 sites leave the
+    last 64-site workgroup partly empty, too)."""
+    U = wl.su3_links(Ls, eps=0.5, seed=3)
+    m0 = -1.4
+    opD = fa().Wilson(U, m0, mu=mu)
+    opQ = fa().Wilson(U, m0, mu=mu, squared=True)
+    x = wl.rhs(opD.n, seed=5, complex_=True)
+    assert_close(host(opD.op_apply(dev(x))), ops.wilson_apply(U, m0, x, mu), 1e-13)
+    assert_close(host(opQ.op_apply(dev(x))), ops.wilson_q2_apply(U, m0, x, mu), 1e-13)
+    # a squared op takes its scratch vector from the workspace even when the
+    # caller asks for none
+    assert_close(host(opQ.op_apply(dev(x), split_long_rows=False)),
+                 ops.wilson_q2_apply(U, m0, x, mu), 1e-13)
+
+
+@pytest.mark.parametrize("kind", ["invsqrt", "sqrt"])
+def test_overlap_q2_solve_against_oracle(kind):
+    """(Q^2)^{-1/2} b and (Q^2)^{1/2} b at m_w = -1.4, mu = 0.3 (non-Hermitian
+    Q^2), Ritz degree 7: a fixed m = 3 and a converged solve at tol 1e-12 on
+    both sides against the oracle with the exported polynomial."""
+    Ls = (4, 4, 4, 4)
+    U = wl.su3_links(Ls, eps=0.5, seed=3)
+    m0, mu = -1.4, 0.3
+    op = fa().Wilson(U, m0, mu=mu, squared=True)
+    op.poly_setup(7, "ritz", start=dev(wl.rhs(op.n, seed=11, complex_=True)))
+    b = wl.rhs(op.n, seed=0, complex_=True)
+    A = lambda v: ops.wilson_q2_apply(U, m0, v, mu)  # noqa: E731
+    q = exported_newton_poly(op, False)
+    x, st = op.apply(dev(b), kind=kind, m_max=3, tol=0.0)
+    ref = kr.fAb(A, b, q, kind, m_max=3, tol=0.0)
+    assert st["iters"] == ref.iters == 3 and st["mvms"] == ref.mvms
+    assert_close(host(x), ref.x, 1e-10)
+    x, st = op.apply(dev(b), kind=kind, m_max=200, tol=1e-12)
+    ref = kr.fAb(A, b, q, kind, m_max=200, tol=1e-12)
+    assert st["converged"] and st["iters"] == ref.iters
+    assert_close(host(x), ref.x, 1e-10)
+
+
+def test_overlap_q2_free_field_closed_form_and_hermitian_lanczos():
+    """Unit links: (Q^2)^{-1/2} b against the momentum-space closed form
+    (mu = 0.3, Arnoldi); at mu = 0 Q^2 is Hermitian and Lanczos gives the
+    same closed form."""
+    Ls = (4, 4, 4, 6)
+    U = np.zeros((4, *Ls, 3, 3), dtype=np.complex128)
+    U[...] = np.eye(3)
+    m0 = -1.4
+    b = wl.rhs(int(np.prod(Ls)) * 12, seed=2, complex_=True)
+    for mu, herm in ((0.3, False), (0.0, True)):
+        op = fa().Wilson(U, m0, mu=mu, squared=True, hermitian=herm)
+        op.poly_setup(6, "ritz", start=dev(wl.rhs(op.n, seed=11, complex_=True)))
+        x, st = op.apply(dev(b), m_max=300, tol=1e-12)
+        assert st["converged"]
+        if herm:  # three-term recurrence: two inner products per step
+            assert st["inner_products"] == 2 * st["iters"]
+        assert_close(host(x), exact.wilson_free_q2_fAb(Ls, m0, b, mu), 1e-10)
+
+
+def test_overlap_sign_function_squares_to_one():
+    """sign(Q) b = Q (Q^2)^{-1/2} b on an 8^4 lattice (m_w = -1.4, mu = 0.3):
+    sign(Q)^2 b = b, a property that holds at any size."""
+    L = 8
+    U = wl.su3_links(L, eps=0.3, seed=1)
+    m0, mu = -1.4, 0.3
+    opD = fa().Wilson(U, m0, mu=mu)
+    opQ = fa().Wilson(U, m0, mu=mu, squared=True)
+    opQ.poly_setup(16, "ritz", start=dev(wl.rhs(opQ.n, seed=11, complex_=True)))
+
+    def sign_q(v):
+        y, st = opQ.apply(v, m_max=200, tol=1e-12)
+        assert st["converged"]
+        d = opD.op_apply(y).reshape(-1, 4, 3)
+        d[:, 2:, :] *= -1.0  # Gamma_5
+        return d.reshape(-1)
+
+    b = dev(wl.rhs(opQ.n, seed=0, complex_=True))
+    z = sign_q(sign_q(b))
+    assert_close(host(z), host(b), 1e-9)
+
+
 def test_wilson_16_full_size():
     """16^4 lattice, links exp(0.3 i H), m0 = 0.05, Ritz degree 16, tol 1e-8.
 

@@ -222,17 +222,19 @@ def random_su3(count: int, eps: float, rng) -> np.ndarray:
     return _expi_hermitian(H, eps)
 
 
-def su3_links(L: int, eps: float = 0.3, seed: int = 1) -> np.ndarray:
-    """Random SU(3) links near the identity on an L^4 periodic lattice.
+def su3_links(L, eps: float = 0.3, seed: int = 1) -> np.ndarray:
+    """Random SU(3) links near the identity on a periodic 4D lattice: L^4
+    for an int L, else L = (L_t, L_z, L_y, L_x).
 
-    Returned shape (4, L, L, L, L, 3, 3) = [mu][t][z][y][x][a][b], i.e. one
-    3x3 complex matrix per direction and site, sites with x fastest.
+    Returned shape (4, L_t, L_z, L_y, L_x, 3, 3) = [mu][t][z][y][x][a][b],
+    i.e. one 3x3 complex matrix per direction and site, sites with x fastest.
     Direction mu = 0, 1, 2, 3 is x, y, z, t.
     """
+    dims = (L, L, L, L) if np.isscalar(L) else tuple(int(d) for d in L)
     rng = np.random.default_rng(seed)
-    V = L ** 4
+    V = int(np.prod(dims))
     U = random_su3(4 * V, eps, rng)
-    return U.reshape(4, L, L, L, L, 3, 3)
+    return U.reshape(4, *dims, 3, 3)
 
 
 def pure_gauge_links(L: int, seed: int = 7, eps: float = 2.0):
