@@ -96,6 +96,13 @@ def test_wilson_gamma5_hermiticity_and_field_of_values():
     assert np.linalg.eigvals(D).real.min() >= m0 - 1e-12
 
 
+def test_device_link_generator_matches_host():
+    # the torch matrix exponential used for the 64 x 32^3 lattice gives the
+    # host generator's links (eigendecomposition) to rounding
+    U = wl.su3_links_device((2, 2, 2, 3), eps=0.3, seed=1, device="cpu").numpy()
+    assert np.abs(U - wl.su3_links((2, 2, 2, 3), eps=0.3, seed=1)).max() < 1e-13
+
+
 def test_links_are_su3():
     U = wl.su3_links(2, eps=0.3, seed=1).reshape(-1, 3, 3)
     assert np.allclose(U @ U.conj().transpose(0, 2, 1), np.eye(3), atol=1e-13)

@@ -237,6 +237,25 @@ def su3_links(L, eps: float = 0.3, seed: int = 1) -> np.ndarray:
     return U.reshape(4, *dims, 3, 3)
 
 
+def su3_links_device(L, eps: float = 0.3, seed: int = 1, device="cuda"):
+    """su3_links for lattices where the host eigendecompositions would take
+    long (a 64 x 32^3 lattice has 8.4 M links): the same H from the same
+    seeded stream, exp(i eps H) taken by torch's matrix exponential on
+    `device` (equal to su3_links' result to rounding).  Returns a complex128
+    tensor on `device` of shape (4, L_t, L_z, L_y, L_x, 3, 3)."""
+    import torch
+
+    dims = (L, L, L, L) if np.isscalar(L) else tuple(int(d) for d in L)
+    rng = np.random.default_rng(seed)
+    V = int(np.prod(dims))
+    xi = torch.from_numpy(rng.standard_normal((4 * V, 8))).to(device)
+    lam = torch.from_numpy(_gell_mann()).to(device)
+    H = torch.einsum("na,aij->nij", xi.to(torch.complex128), lam) / 2.0
+    del xi
+    U = torch.linalg.matrix_exp((1j * eps) * H)
+    return U.reshape(4, *dims, 3, 3)
+
+
 def pure_gauge_links(L: int, seed: int = 7, eps: float = 2.0):
     """Links U_mu(x) = G(x) G(x+mu)^H of a random gauge transformation G.
 
