@@ -704,6 +704,9 @@ static hipError_t launch_csr(const Op& op, const T* x, const T* y0, const T* y1,
 struct Wil {
   int L0, L1, L2, L3;  // x, y, z, t extents
   int V;
+  // site-block order (workgroup w -> sites): P blocks of 64 sites per (x, y)
+  // plane, T t-slices per XCD (0: lexicographic), ZB z-planes per z-block
+  int P, T, ZB;
   double diag;         // 4 + m0
   double ef, eb;       // e^{+mu}, e^{-mu}: the forward / backward temporal hop
 };
@@ -870,8 +873,21 @@ __global__ __launch_bounds__(256) void wilson_dir_k(Wil w, const cplx* __restric
   constexpr int kAcc = kWilDSites * 12;
   const int lane = threadIdx.x & 63;
   const int mu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // each XCD takes one contiguous range of sites
-  const int s0 = xcd_contiguous(blockIdx.x, gridDim.x) * kWilDSites;
+  // each XCD takes one contiguous range of sites: T whole t-slices when the
+  // lattice allows it, walked in the order (z-block, xy-block, t, z within
+  // the block), so that the t- and z-neighbours of a workgroup's sites are
+  // read by workgroups the same XCD runs at about the same time (its L2);
+  // otherwise the lexicographic order
+  int blk = xcd_contiguous(blockIdx.x, gridDim.x);
+  if (w.T > 0) {
+    const int per = w.P * w.L2 * w.T;
+    const int xc = blk / per, r = blk - xc * per;
+    const int zi = r % w.ZB, r2 = r / w.ZB;
+    const int tr = r2 % w.T, r3 = r2 / w.T;
+    const int xy = r3 % w.P, z = (r3 / w.P) * w.ZB + zi;
+    blk = ((xc * w.T + tr) * w.L2 + z) * w.P + xy;
+  }
+  const int s0 = blk * kWilDSites;
   const int nsite = min(kWilDSites, w.V - s0);
   // lanes past the last site work on site V - 1 and store nothing
   const int s = min(s0 + lane, w.V - 1);
@@ -943,9 +959,13 @@ __global__ __launch_bounds__(256) void wilson_dir_k(Wil w, const cplx* __restric
 
 static hipError_t launch_wilson(const Op& op, const cplx* x, const cplx* y0, const cplx* y1,
                                 cplx* out, const ChainCoef& k, hipStream_t st) {
+  const int plane = op.dims[0] * op.dims[1];
+  const bool zt = plane % kWilDSites == 0 && op.dims[3] % kXcds == 0;
+  const int zb = op.dims[2] % 2 == 0 ? 2 : 1;
   Wil w{op.dims[0], op.dims[1], op.dims[2], op.dims[3],
-        op.dims[0] * op.dims[1] * op.dims[2] * op.dims[3], 4.0 + op.m0, std::exp(op.mu),
-        std::exp(-op.mu)};
+        op.dims[0] * op.dims[1] * op.dims[2] * op.dims[3],
+        zt ? plane / kWilDSites : 0, zt ? op.dims[3] / kXcds : 0, zb,
+        4.0 + op.m0, std::exp(op.mu), std::exp(-op.mu)};
   const cplx al = host_to_dev<cplx>::conv(k.alpha), be = host_to_dev<cplx>::conv(k.beta),
              g0 = host_to_dev<cplx>::conv(k.g0), g1 = host_to_dev<cplx>::conv(k.g1);
   const cplx* U = (const cplx*)op.links;

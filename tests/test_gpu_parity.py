@@ -91,12 +91,15 @@ def test_csr_apply(which):
 
 
 @pytest.mark.parametrize("links", ["su3", "scaled", "phase"])
-@pytest.mark.parametrize("shape", [(4, 4, 4, 4), (6, 2, 4, 5), (4, 8, 4, 32), (4, 2, 6, 16)])
+@pytest.mark.parametrize("shape", [(4, 4, 4, 4), (6, 2, 4, 5), (4, 8, 4, 32), (4, 2, 6, 16),
+                                   (8, 4, 4, 16), (16, 3, 8, 8)])
 def test_wilson_apply(shape, links):
-    """(Lt, Lz, Ly, Lx); the last two shapes have whole 16-site rows.  Special
-    unitary links are kept as two rows (the third rebuilt in the kernel);
-    links scaled by 1.01 or multiplied by a phase (unitary, det != 1) are not
-    special unitary and are kept whole."""
+    """(Lt, Lz, Ly, Lx); the third and fourth shapes have whole 16-site rows.
+    Special unitary links are kept as two rows (the third rebuilt in the
+    kernel); links scaled by 1.01 or multiplied by a phase (unitary, det != 1)
+    are not special unitary and are kept whole.  The last two shapes (whole
+    64-site (x, y) planes, Lt a multiple of 8) take the t-walk workgroup
+    order, with z-blocks of two planes and of one (odd Lz)."""
     Lt, Lz, Ly, Lx = shape
     rng_links = wl.random_su3(4 * Lt * Lz * Ly * Lx, 0.8, np.random.default_rng(5))
     if links == "scaled":
@@ -634,11 +637,12 @@ def test_wilson_16_fixed_m_solve_against_oracle(wilson16):
 # Sec. 6, Example 2: (Q^2)^{-1/2} b with Q = Gamma_5 D(m_w, mu)
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("mu", [0.0, 0.3])
-@pytest.mark.parametrize("Ls", [(4, 4, 4, 4), (4, 3, 5, 4)])
+@pytest.mark.parametrize("Ls", [(4, 4, 4, 4), (4, 3, 5, 4), (8, 2, 8, 8)])
 def test_overlap_q2_operator_against_oracle(mu, Ls):
     """D with a chemical potential and Q^2 = (Gamma_5 D)^2 at m_w = -1.4, one
     application each, against the oracle (a lattice whose 240 sites leave the
-    last 64-site workgroup partly empty, too)."""
+    last 64-site workgroup partly empty, and one in the t-walk workgroup
+    order, too)."""
     U = wl.su3_links(Ls, eps=0.5, seed=3)
     m0 = -1.4
     opD = fa().Wilson(U, m0, mu=mu)
