@@ -199,6 +199,8 @@ struct RedPlan {
   int rows;     // rows per block
 };
 RedPlan red_plan(int64_t n);
+// first-stage blocks of the projections on vectors of `dtype` (at least red_plan's)
+int proj_nblk(int64_t n, int dtype);
 // h[c] = sum_r conj(V[r, c]) w[r], c < ncols (h may be null); hsum_mode 1 also
 // stores hsum[c] = h[c], mode 2 adds it (CGS2: H(:, j) = h1 + h2), 0 ignores hsum
 hipError_t launch_project(int dtype, int64_t n, int ncols, const void* V, int64_t ldv,

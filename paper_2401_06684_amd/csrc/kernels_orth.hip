@@ -29,14 +29,19 @@ constexpr int kCb = 4;   // columns per reduction round in project
 // 4: with 4 columns of two complex vectors the round's loads and sums held
 // 146 registers (three waves per SIMD) and the two-vector sweep ran at
 // 3.45 TB/s on the 16^4 lattice; measured over rows per thread {2, 4, 8}
-// x columns per round {1, 2, 3, 4} (2048 / rows threads per workgroup, the
-// same 2048 rows per workgroup and so the same partial sums layout), 8 rows
-// and 2 columns reach 4.7 TB/s at bases of 64 to 191 vectors.
+// x columns per round {1, 2, 3, 4} (2048 rows per workgroup), 8 rows and 2
+// columns reach 4.7 TB/s at bases of 64 to 191 vectors.  Their workgroups
+// are one wave (512 rows): 2048-row workgroups left a 16^4 vector (786,432
+// entries) 384 workgroups, one and a half per CU, and the plain 16^4 solve
+// (m = 192) takes 4.5 % less time with 1,536 (1,024-row workgroups: 3 %).
 #ifndef FA_PROJ_CPLX_RPT
 #define FA_PROJ_CPLX_RPT 8
 #endif
 #ifndef FA_PROJ_CPLX_CB
 #define FA_PROJ_CPLX_CB 2
+#endif
+#ifndef FA_PROJ_CPLX_NTH
+#define FA_PROJ_CPLX_NTH 64
 #endif
 template <typename T>
 constexpr int proj_rpt() {
@@ -47,9 +52,10 @@ template <typename T>
 constexpr int proj_cb() {
   return sizeof(T) == 16 ? FA_PROJ_CPLX_CB : kCb;
 }
+// threads per workgroup of the projections
 template <typename T>
 constexpr int proj_threads() {
-  return kThreads * kRpt / proj_rpt<T>();
+  return sizeof(T) == 16 ? FA_PROJ_CPLX_NTH : kThreads * kRpt / proj_rpt<T>();
 }
 
 RedPlan red_plan(int64_t n) {
@@ -57,6 +63,17 @@ RedPlan red_plan(int64_t n) {
   p.rows = kThreads * kRpt;
   p.nblk = (int)((n + p.rows - 1) / p.rows);
   return p;
+}
+// the projections' first stage (rows per workgroup of project_k / project2_k)
+template <typename T>
+static RedPlan proj_plan(int64_t n) {
+  RedPlan p;
+  p.rows = proj_threads<T>() * proj_rpt<T>();
+  p.nblk = (int)((n + p.rows - 1) / p.rows);
+  return p;
+}
+int proj_nblk(int64_t n, int dtype) {
+  return dtype == FA_C128 ? proj_plan<cplx>(n).nblk : proj_plan<double>(n).nblk;
 }
 
 template <typename T>
@@ -558,6 +575,7 @@ __global__ __launch_bounds__(kThreads) void update2_k(int64_t n, int ncols, cons
 hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv, void* part,
                         void* S, void* H, int64_t ldh, void* coef, hipStream_t s) {
   const RedPlan p = red_plan(n);
+  const RedPlan pp = dtype == FA_C128 ? proj_plan<cplx>(n) : proj_plan<double>(n);
   const size_t es = dtype == FA_C128 ? 16 : 8;
   void* u = (char*)V + (size_t)j * ldv * es;
   void* z = (char*)V + (size_t)(j + 1) * ldv * es;
@@ -570,13 +588,13 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
   const size_t lds = 2 * (size_t)(j + 1) * es;
   const bool fused = lds <= 32768 && j <= 32;
   if (dtype == FA_C128) {
-    project2_k<cplx><<<p.nblk, proj_threads<cplx>(), 0, s>>>(n, j + 1, (const cplx*)V, ldv, (const cplx*)u,
-                                                 (const cplx*)z, (cplx*)part, p.nblk);
+    project2_k<cplx><<<pp.nblk, proj_threads<cplx>(), 0, s>>>(n, j + 1, (const cplx*)V, ldv, (const cplx*)u,
+                                                 (const cplx*)z, (cplx*)part, pp.nblk);
     if (fused) {
-      dcgs2_finish_k<cplx><<<1, kFinThreads, lds, s>>>(j, p.nblk, (const cplx*)part, (cplx*)H,
+      dcgs2_finish_k<cplx><<<1, kFinThreads, lds, s>>>(j, pp.nblk, (const cplx*)part, (cplx*)H,
                                                       ldh, (cplx*)cs, (cplx*)cp, (cplx*)sc);
     } else {
-      reduce_cols_k<cplx><<<2 * (j + 1), kThreads, 0, s>>>(p.nblk, (const cplx*)part, (cplx*)S,
+      reduce_cols_k<cplx><<<2 * (j + 1), kThreads, 0, s>>>(pp.nblk, (const cplx*)part, (cplx*)S,
                                                            nullptr, 0);
       dcgs2_coef_k<cplx><<<1, kThreads, 0, s>>>(j, (const cplx*)S, (cplx*)H, ldh, (cplx*)cs,
                                                 (cplx*)cp, (cplx*)sc);
@@ -587,15 +605,15 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
                                                 (const cplx*)cp, (const cplx*)sc, (cplx*)u,
                                                 (cplx*)z);
   } else {
-    project2_k<double><<<p.nblk, proj_threads<double>(), 0, s>>>(n, j + 1, (const double*)V, ldv,
+    project2_k<double><<<pp.nblk, proj_threads<double>(), 0, s>>>(n, j + 1, (const double*)V, ldv,
                                                    (const double*)u, (const double*)z,
-                                                   (double*)part, p.nblk);
+                                                   (double*)part, pp.nblk);
     if (fused) {
-      dcgs2_finish_k<double><<<1, kFinThreads, lds, s>>>(j, p.nblk, (const double*)part,
+      dcgs2_finish_k<double><<<1, kFinThreads, lds, s>>>(j, pp.nblk, (const double*)part,
                                                         (double*)H, ldh, (double*)cs,
                                                         (double*)cp, (double*)sc);
     } else {
-      reduce_cols_k<double><<<2 * (j + 1), kThreads, 0, s>>>(p.nblk, (const double*)part,
+      reduce_cols_k<double><<<2 * (j + 1), kThreads, 0, s>>>(pp.nblk, (const double*)part,
                                                              (double*)S, nullptr, 0);
       dcgs2_coef_k<double><<<1, kThreads, 0, s>>>(j, (const double*)S, (double*)H, ldh,
                                                   (double*)cs, (double*)cp, (double*)sc);
@@ -613,7 +631,7 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
 template <typename T>
 static hipError_t project_t(int64_t n, int ncols, const T* V, int64_t ldv, const T* w, T* part,
                             T* h, T* hsum, int mode, hipStream_t s) {
-  const RedPlan p = red_plan(n);
+  const RedPlan p = proj_plan<T>(n);
   project_k<T><<<p.nblk, proj_threads<T>(), 0, s>>>(n, ncols, V, ldv, w, part, p.nblk);
   reduce_cols_k<T><<<ncols, kThreads, 0, s>>>(p.nblk, part, h, hsum, mode);
   return hipGetLastError();

@@ -55,7 +55,8 @@ Layout make_layout(const Op& op, int m_max, uint32_t flags, bool with_poly) {
   // per-block partial sums of one projection (Lanczos projects on one
   // vector; the delayed-reorthogonalization step projects two vectors on
   // m_max + 1 columns)
-  L.off_part = take((size_t)(L.band ? 3 : 2 * m_max + 4) * rp.nblk * es + 64);
+  L.off_part = take((size_t)(L.band ? 3 : 2 * m_max + 4) *
+                        std::max(rp.nblk, proj_nblk(op.n, op.dtype)) * es + 64);
   L.off_h = take((size_t)(2 * m_max + 4) * es);
   L.off_dc = take((size_t)(2 * m_max + 4) * es);
   L.off_H = take((size_t)L.ldh * m_max * es);
