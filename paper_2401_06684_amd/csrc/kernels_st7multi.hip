@@ -6,7 +6,7 @@
 // on).  Memory sees x, y1 and v read and s_{NT-1}, s_NT written: 5 vector
 // passes for NT terms (NT = 4: 5/4 per term, NT = 3: 5/3, against 5/2 for two
 // terms and 4 for one).  The intermediate terms never leave the chip.  NT = 4
-// in FP64 takes 77.8 KB of LDS and 124 VGPRs: two workgroups per CU.
+// in FP64 takes 79.9 KB of LDS and 124 VGPRs: two workgroups per CU.
 //
 // A workgroup owns a TW x TY tile of the (x, y) plane (64 x 8, or 32 x 16
 // when that wastes fewer points along x) and marches through its slab of kz
@@ -39,6 +39,12 @@
 #ifndef FA_MULTI_BLOCKS
 #define FA_MULTI_BLOCKS 512
 #endif
+// LDS row pitch beyond the region width: 2 elements (72 -> 74 doubles for
+// the 64 x 8 tile) move the ring's column points, 16 dwords apart per row
+// at pitch 72, onto more banks (29.7 -> 29.4 us per 128^3 launch)
+#ifndef FA_MULTI_LDS_PAD
+#define FA_MULTI_LDS_PAD 2
+#endif
 
 namespace fa {
 
@@ -63,10 +69,12 @@ struct Geo {
   static constexpr int N(int t) { return W(t) * H(t); }
   static constexpr int RING = N(1) - P;   // region 1 minus the tile
   static constexpr int HALO = N(0) - N(1);  // region 0 minus region 1 (x only)
+  // LDS row pitch (elements)
+  static constexpr int RP = W(0) + FA_MULTI_LDS_PAD;
   // LDS (elements): two plane buffers of region-0 size for x and for each of
   // the terms 1 .. NT-1, then one slot per thread for lanes with nothing to
   // store
-  static constexpr int BUF = N(0);
+  static constexpr int BUF = H(0) * RP;
   static constexpr int DUMMY = 2 * NT * BUF;
   static constexpr int total() { return DUMMY + P; }
 };
@@ -100,7 +108,7 @@ __global__ __launch_bounds__(TW * TY) __attribute__((amdgpu_waves_per_eu(4))) vo
     TO* __restrict__ out2, MultiCoef<NT> cd) {
   using G = Geo<NT, TW, TY>;
   static_assert(G::RING <= G::P && G::HALO <= G::P, "one ring and one halo point per thread");
-  constexpr int W0 = G::W(0);
+  constexpr int W0 = G::W(0), RP = G::RP;
   __shared__ T lds[G::total()];
   const T c0 = (T)g.c0, cxm = (T)g.cxm, cxp = (T)g.cxp, cym = (T)g.cym, cyp = (T)g.cyp,
           czm = (T)g.czm, czp = (T)g.czp;
@@ -140,7 +148,7 @@ __global__ __launch_bounds__(TW * TY) __attribute__((amdgpu_waves_per_eu(4))) vo
       const int i = i0 - (NT - 1) + a[u], j = j0 - (NT - 1) + b[u];
       ing[u] = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
       soff[u] = (int64_t)min(max(j, 0), g.ny - 1) * g.nx + min(max(i, 0), g.nx - 1);
-      ci[u] = (b[u] + 1) * W0 + (a[u] + 1);
+      ci[u] = (b[u] + 1) * RP + (a[u] + 1);
     }
     if (tid >= G::RING) ci[1] = G::DUMMY + tid;
   }
@@ -164,7 +172,7 @@ __global__ __launch_bounds__(TW * TY) __attribute__((amdgpu_waves_per_eu(4))) vo
       xa = W0 - 1;
       ya = 1 + (h - 2 * W0 - G::H(1));
     }
-    if (tid < G::HALO) hci = ya * W0 + xa;
+    if (tid < G::HALO) hci = ya * RP + xa;
     const int i = i0 - NT + xa, j = j0 - NT + ya;
     hing = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
     hoff = (int64_t)min(max(j, 0), g.ny - 1) * g.nx + min(max(i, 0), g.nx - 1);
@@ -288,15 +296,15 @@ __global__ __launch_bounds__(TW * TY) __attribute__((amdgpu_waves_per_eu(4))) vo
         const int64_t po = (int64_t)p * plane;
 #pragma unroll
         for (int u = 0; u < (t == NT ? 1 : 2); ++u) {
-          const int c = u == 0 ? ci[0] : (ci[1] >= G::DUMMY ? W0 + 1 : ci[1]);
+          const int c = u == 0 ? ci[0] : (ci[1] >= G::DUMMY ? RP + 1 : ci[1]);
           const T sv = ring[t - 1][1][u];
           T as = c0 * sv;
           as = fma(czm, ring[t - 1][0][u], as);
           as = fma(czp, ring[t - 1][2][u], as);
           as = fma(cxm, L[c - 1], as);
           as = fma(cxp, L[c + 1], as);
-          as = fma(cym, L[c - W0], as);
-          as = fma(cyp, L[c + W0], as);
+          as = fma(cym, L[c - RP], as);
+          as = fma(cyp, L[c + RP], as);
           T val = fma(a, as, b * sv);
           val = fma(e0, vr[t - 1][u], val);
           if (t == 1) {
