@@ -383,7 +383,7 @@ int tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double be
   std::vector<double> d(alpha, alpha + m), e(std::max(m - 1, 1), 0.0);
   for (int i = 0; i + 1 < m; ++i) e[i] = offd[i];
   std::vector<Rot> rot;
-  rot.reserve((size_t)8 * m);
+  rot.reserve((size_t)2 * m * m + 64);  // about two sweeps per eigenvalue
   int hi = m - 1;
   long sweeps = 0;
   while (hi > 0) {
@@ -404,7 +404,8 @@ int tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double be
     double x = d[lo] - mu, y = e[lo];  // the vector the next rotation acts on
     for (int k = lo; k < hi; ++k) {
       const double r = std::sqrt(x * x + y * y);
-      const double c = r == 0.0 ? 1.0 : x / r, s = r == 0.0 ? 0.0 : y / r;
+      const double ir = r == 0.0 ? 0.0 : 1.0 / r;  // one division per rotation
+      const double c = r == 0.0 ? 1.0 : x * ir, s = y * ir;
       if (k > lo) e[k - 1] = r;  // the bulge T(k-1, k+1) is now zero
       // the 2 x 2 block on rows and columns k, k+1
       const double a = d[k], bb = d[k + 1], f = e[k];
