@@ -383,7 +383,9 @@ int tridiag_invsqrt_e1(int m, const double* alpha, const double* offd, double be
   std::vector<double> d(alpha, alpha + m), e(std::max(m - 1, 1), 0.0);
   for (int i = 0; i + 1 < m; ++i) e[i] = offd[i];
   std::vector<Rot> rot;
-  rot.reserve((size_t)2 * m * m + 64);  // about two sweeps per eigenvalue
+  // about m^2 rotations in all (two sweeps per eigenvalue, each over about
+  // half of T); the record grows beyond this if it has to
+  rot.reserve(std::min<size_t>((size_t)m * m + 64, (size_t)1 << 20));
   int hi = m - 1;
   long sweeps = 0;
   while (hi > 0) {
