@@ -335,8 +335,10 @@ def test_wilson_solve(degree):
     assert_close(host(x), orc.x, 1e-10)
 
 
-def test_wilson_free_field_closed_form():
-    L = 4
+@pytest.mark.parametrize("L", [4, 8])
+def test_wilson_free_field_closed_form(L):
+    """(D = free Wilson operator) A^{-1/2} b against its momentum-space closed
+    form; the 8^4 lattice takes the t-walk workgroup order."""
     Ls = (L, L, L, L)
     U = np.zeros((4, *Ls, 3, 3), dtype=complex)
     U[...] = np.eye(3)
@@ -637,12 +639,12 @@ def test_wilson_16_fixed_m_solve_against_oracle(wilson16):
 # Sec. 6, Example 2: (Q^2)^{-1/2} b with Q = Gamma_5 D(m_w, mu)
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("mu", [0.0, 0.3])
-@pytest.mark.parametrize("Ls", [(4, 4, 4, 4), (4, 3, 5, 4), (8, 2, 8, 8)])
+@pytest.mark.parametrize("Ls", [(4, 4, 4, 4), (4, 3, 5, 4), (8, 2, 8, 8), (8, 3, 8, 8)])
 def test_overlap_q2_operator_against_oracle(mu, Ls):
     """D with a chemical potential and Q^2 = (Gamma_5 D)^2 at m_w = -1.4, one
     application each, against the oracle (a lattice whose 240 sites leave the
-    last 64-site workgroup partly empty, and one in the t-walk workgroup
-    order, too)."""
+    last 64-site workgroup partly empty, and two in the t-walk workgroup
+    order, with z-blocks of two planes and of one, too)."""
     U = wl.su3_links(Ls, eps=0.5, seed=3)
     m0 = -1.4
     opD = fa().Wilson(U, m0, mu=mu)
