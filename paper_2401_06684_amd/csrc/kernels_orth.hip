@@ -584,9 +584,12 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
   char* sc = cp + (size_t)j * es;
   // one launch up to j = 32, else the three kernels: the one workgroup's
   // work grows linearly in j (8.8 us at j = 20, 14.4 at 32, 75 at 158 on the
-  // 128^3 grid), the three kernels' stays near 15 us
+  // 128^3 grid), the three kernels' stays near 15 us.  The one workgroup
+  // also reads all 2 (j + 1) x nblk partial sums, so large vectors (many
+  // first-stage blocks, e.g. 49,152 for a 64 x 32^3 lattice) take the three
+  // kernels, whose partial sums are read by 2 (j + 1) workgroups
   const size_t lds = 2 * (size_t)(j + 1) * es;
-  const bool fused = lds <= 32768 && j <= 32;
+  const bool fused = lds <= 32768 && j <= 32 && 2 * (int64_t)(j + 1) * pp.nblk <= (1 << 17);
   if (dtype == FA_C128) {
     project2_k<cplx><<<pp.nblk, proj_threads<cplx>(), 0, s>>>(n, j + 1, (const cplx*)V, ldv, (const cplx*)u,
                                                  (const cplx*)z, (cplx*)part, pp.nblk);
