@@ -8,8 +8,8 @@
 // terms and 4 for one).  The intermediate terms never leave the chip.  NT = 4
 // in FP64 takes 79.9 KB of LDS and 124 VGPRs: two workgroups per CU.
 //
-// A workgroup owns a TW x TY tile of the (x, y) plane (64 x 8, or 32 x 16
-// when that wastes fewer points along x) and marches through its slab of kz
+// A workgroup owns a TW x TY tile of the (x, y) plane (64 x 8, 32 x 16 or
+// 56 x 8, whichever wastes the fewest points along x) and marches through its slab of kz
 // planes in z.  Term t is needed on the tile grown by NT - t
 // points on each side (its halo for the terms after it) and lags term t - 1
 // by one plane: at step q, term t produces plane q - t + 1 (term 0, x itself,
@@ -30,6 +30,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "devmath.hpp"
@@ -392,15 +393,22 @@ static hipError_t launch_multi_nt(const Op& op, const void* x, const void* v, co
     c.g0[t] = k[t].g0.real();
     c.g1[t] = k[t].g1.real();
   }
-  // 64 x 8 tiles, or 32 x 16 where they waste fewer points along x (nx = 96:
-  // three tiles of 32 instead of two of 64, the second half empty)
+  // the tile that wastes the fewest points along x: 64 x 8, else 32 x 16
+  // (nx = 96: three tiles of 32 instead of two of 64, the second half
+  // empty), else 56 x 8 (448 threads; nx = 100: two tiles of 56 instead of
+  // two of 64 or four of 32)
   const int nx = op.dims[0];
-  const bool narrow = (nx + 31) / 32 * 32 < (nx + 63) / 64 * 64;
+  auto waste = [nx](int w) { return (nx + w - 1) / w * w - nx; };
+  const int tile = waste(64) <= std::min(waste(32), waste(56)) ? 64
+                   : waste(32) <= waste(56)                     ? 32
+                                                                : 56;
 #define FA_MULTI_TILE(T_, TX_, TO_)                                                            \
-  return narrow ? launch_multi_t<T_, TX_, TO_, NT, 32, 16>(op, x, v, y1, out1, out2, c, blocks, \
-                                                           s, e0, e1)                           \
-                : launch_multi_t<T_, TX_, TO_, NT, 64, 8>(op, x, v, y1, out1, out2, c, blocks,  \
-                                                          s, e0, e1)
+  return tile == 64 ? launch_multi_t<T_, TX_, TO_, NT, 64, 8>(op, x, v, y1, out1, out2, c,     \
+                                                              blocks, s, e0, e1)               \
+         : tile == 32 ? launch_multi_t<T_, TX_, TO_, NT, 32, 16>(op, x, v, y1, out1, out2, c,  \
+                                                                 blocks, s, e0, e1)            \
+                      : launch_multi_t<T_, TX_, TO_, NT, 56, 8>(op, x, v, y1, out1, out2, c,   \
+                                                                blocks, s, e0, e1)
   if (pin == P64 && pout == P64) FA_MULTI_TILE(double, double, double);
   if (pin == P32 && pout == P32) FA_MULTI_TILE(float, float, float);
   if (pin == P32 && pout == P64 && out1 == nullptr) FA_MULTI_TILE(float, float, double);
