@@ -46,6 +46,14 @@
 #ifndef FA_MULTI_LDS_PAD
 #define FA_MULTI_LDS_PAD 2
 #endif
+// Two workgroups share each CU, and the one dispatched first gets more of it:
+// on 128^3 (8-plane slabs) the first finished its slab in 22.5 us, the
+// second in 28.4, so the launch waited on the second.  Slabs are therefore
+// paired on a CU with the first one FA_MULTI_PAIR_SHIFT planes longer (10
+// and 6 planes: 25.3 and 27.4 us; the solve 137.5 -> 140.7 solves/s)
+#ifndef FA_MULTI_PAIR_SHIFT
+#define FA_MULTI_PAIR_SHIFT 2
+#endif
 
 namespace fa {
 
@@ -104,7 +112,7 @@ __device__ __forceinline__ void ring_point(int h, int& a, int& b) {
 template <typename T, typename TX, typename TO, int NT, int TW, int TY, bool Y1G, bool W1>
 // at least 4 waves per SIMD: two 512-thread workgroups per CU
 __global__ __launch_bounds__(TW * TY) __attribute__((amdgpu_waves_per_eu(4))) void st7_multi(
-    St7M g, int kz, int gx, int gy, int nwg, int64_t bstride, const TX* __restrict__ x,
+    St7M g, int kz, int gx, int gy, int nwg, int pd, int64_t bstride, const TX* __restrict__ x,
     const TX* __restrict__ v, const TX* __restrict__ y1, TO* __restrict__ out1,
     TO* __restrict__ out2, MultiCoef<NT> cd) {
   using G = Geo<NT, TW, TY>;
@@ -123,9 +131,24 @@ __global__ __launch_bounds__(TW * TY) __attribute__((amdgpu_waves_per_eu(4))) vo
     if (W1) out1 += o;
     out2 += o;
   }
-  const int bx = lid % gx, by = (lid / gx) % gy, bz = lid / (gx * gy);
+  int bx, by, bz;
+  if (pd >= 0) {
+    // paired slabs: the two workgroups that share a CU (the k-th and the
+    // (k + 32)-th an XCD receives) take slabs 2p and 2p + 1 of one column,
+    // the first one pd planes more (it gets more of the CU)
+    const int xc = lid / 64, k = lid % 64, G = gx * gy / 32;
+    const int cid = (xc % G) * 32 + (k & 31);
+    bx = cid % gx;
+    by = cid / gx;
+    bz = 2 * (xc / G) + (k >> 5);
+  } else {
+    bx = lid % gx;
+    by = (lid / gx) % gy;
+    bz = lid / (gx * gy);
+  }
   const int i0 = bx * G::TX, j0 = by * TY;
-  const int k0 = bz * kz, k1 = min(k0 + kz, g.nz);
+  const int k0 = pd >= 0 ? (bz >> 1) * 2 * kz + ((bz & 1) ? kz + pd : 0) : bz * kz;
+  const int k1 = min(pd >= 0 ? (bz >> 1) * 2 * kz + ((bz & 1) ? 2 * kz : kz + pd) : k0 + kz, g.nz);
   const int tid = threadIdx.x;
   const int64_t plane = (int64_t)g.nx * g.ny;
 
@@ -357,6 +380,13 @@ hipError_t launch_multi_t(const Op& op, const void* x, const void* v, const void
   const int kz = (g.nz + gz - 1) / gz;
   gz = (g.nz + kz - 1) / kz;
   const int nwg = gx * gy * gz;
+  // paired slabs (see the kernel) where the grid is two workgroups on each
+  // of the 256 CUs, 32 per XCD, and every XCD takes whole slab pairs of 32
+  // columns
+  const int pd = (nb == 1 && nwg == 512 && (gx * gy) % 32 == 0 && gz % 2 == 0 &&
+                  FA_MULTI_PAIR_SHIFT < kz)
+                     ? FA_MULTI_PAIR_SHIFT
+                     : -1;
   const dim3 grid(nwg, nb), block(TW * TY);
   const int64_t bs = nb > 1 ? op.bstride : 0;
   const TX* xp = (const TX*)x;
@@ -367,7 +397,7 @@ hipError_t launch_multi_t(const Op& op, const void* x, const void* v, const void
   // the events (if any) take the start and end time of this dispatch itself
 #define FA_MULTI(A, B)                                                                          \
   hipExtLaunchKernelGGL(st7_multi<T, TX, TO, NT, TW, TY, A, B>, grid, block, 0, st, ev0, ev1, 0, g, kz, \
-                        gx, gy, nwg, bs, xp, vp, yp, o1, o2, c)
+                        gx, gy, nwg, pd, bs, xp, vp, yp, o1, o2, c)
   if (y1 && out1)
     FA_MULTI(true, true);
   else if (y1)
