@@ -39,15 +39,15 @@ METRIC = "f(A)b solves/s at rel err 1e-8, poly-precond vs plain Arnoldi; SpMV HB
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel (the multi-term middle launch
 # st7_multi<..., NT, 64, 8, true, true> at 128^3 with the LDS pitch padded
-# by 2, keyed by NT): FETCH_SIZE x 2 + WRITE_SIZE, from the rocprofv3 counter
+# by 2 and paired slabs, keyed by NT): FETCH_SIZE x 2 + WRITE_SIZE, from the rocprofv3 counter
 # runs in profiles/st7_multi_convdiff128_deg16_hbm_counters.md (FETCH_SIZE
 # counts gfx950's 128-byte L2 read requests at 64 bytes: the 2 GiB copy and
 # the raw request-size counters there both give the factor 2); only the
 # current build's kernels are listed (others report null)
-MULTI_TRAFFIC_BYTES = {4: (84106 + 32768) * 1024}
+MULTI_TRAFFIC_BYTES = {4: (87254 + 32768) * 1024}
 # the same at the larger grid of the chain leg beyond the 256 MB Infinity
 # Cache, keyed by (N, NT), from profiles/st7_multi_convdiff256_deg16_hbm_counters.md
-BIG_TRAFFIC_BYTES = {(256, 4): (253042 * 2 + 262144) * 1024}
+BIG_TRAFFIC_BYTES = {(256, 4): (276520 * 2 + 262144) * 1024}
 
 
 def log(msg):
