@@ -91,8 +91,9 @@ def main():
     ap.add_argument("--serve-pool-gb", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(one GPU's share of a row-sharded operator is what it measures)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
