@@ -502,6 +502,56 @@ def test_multi_term_launches_match_single_terms(degree, dims):
     assert torch.equal(x1, x4)
 
 
+
+@pytest.mark.parametrize("degree", [4, 16, 17])
+@pytest.mark.parametrize("dims", [(64, 256, 62), (64, 256, 63)])
+def test_paired_slabs_uneven_last_pair(degree, dims):
+    """Grids that take paired z-slabs (512 workgroups, 32 x-y tiles, slabs
+    of 4 planes, the first of each pair 2 planes longer) where the last
+    pair is cut by the grid: at nz = 62 its second slab is empty, at
+    nz = 63 it has one plane.  q(A) x against the oracle; solves with four,
+    three and two terms per launch the same bits."""
+    coeffs = wl.convdiff_stencil(max(dims), 50.0)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(degree, "cheb")
+    a, b = ops.stencil_interval(coeffs, dims)
+    q = pl.chebyshev(a, b, degree)
+    x = wl.rhs(op.n, seed=4)
+    ref, _ = q.apply(lambda v: ops.stencil_apply(coeffs, dims, v), x)
+    assert_close(host(op.poly_apply(dev(x))), ref, 1e-12)
+    bd = dev(wl.rhs(op.n, seed=0))
+    x1, _ = op.apply(bd, m_max=4, tol=0.0)
+    x3, _ = op.apply(bd, m_max=4, tol=0.0, fuse=2)
+    x4, _ = op.apply(bd, m_max=4, tol=0.0, fuse=3)
+    assert torch.equal(x1, x3)
+    assert torch.equal(x1, x4)
+
+
+
+def test_convdiff_256_paired_slabs():
+    """The 256^3 grid (one launch's five vectors 671 MB, beyond the
+    Infinity Cache) in the launch the bench times there: 512 workgroups,
+    paired slabs of 66 and 62 planes.  q(A) x (degree 4, one four-term
+    launch) against the oracle, and a fixed-m degree-16 solve whose
+    four-term launches equal the two-term path bit for bit."""
+    N = 256
+    dims = (N, N, N)
+    coeffs = wl.convdiff_stencil(N, 50.0)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(4, "cheb")
+    a, b = ops.stencil_interval(coeffs, dims)
+    q = pl.chebyshev(a, b, 4)
+    x = wl.rhs(op.n, seed=5)
+    ref, _ = q.apply(lambda v: ops.stencil_apply(coeffs, dims, v), x)
+    assert_close(host(op.poly_apply(dev(x))), ref, 1e-12)
+    del ref
+    op.poly_setup(16, "cheb")
+    bd = dev(wl.rhs(op.n, seed=0))
+    x1, _ = op.apply(bd, m_max=2, tol=0.0)
+    x2, _ = op.apply(bd, m_max=2, tol=0.0, fuse=2)
+    assert torch.equal(x1, x2)
+
+
 # --------------------------------------------------------------------------
 # the 128^3 convection-diffusion workload at full size
 # --------------------------------------------------------------------------
