@@ -220,9 +220,13 @@ hipError_t launch_normalize(int dtype, int64_t n, const void* w, const double* n
 // j + 1 the new z = Op u_j.  Finishes column j - 1 of H (column-major, ldh),
 // forms the first-pass column j, and leaves q_j in column j and u_{j+1} in
 // column j + 1.  part: 2 (j + 1) x nblk partials; S: 2 (j + 1) values;
-// coef: 2 j + 2 values.
+// coef: 2 j + 2 values.  stage: kDcgs2All; kDcgs2Project, the projection
+// and H (column j - 1 final, first-pass column j) only; kDcgs2Update, the
+// update of columns j and j + 1 only (after a kDcgs2Project of the same j).
+enum { kDcgs2All = 0, kDcgs2Project = 1, kDcgs2Update = 2 };
 hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv, void* part,
-                        void* S, void* H, int64_t ldh, void* coef, hipStream_t s);
+                        void* S, void* H, int64_t ldh, void* coef, hipStream_t s,
+                        int stage = kDcgs2All);
 // y = a * x for a scalar on the host
 hipError_t launch_scale(int dtype, int64_t n, cd a, const void* x, void* y, hipStream_t s);
 

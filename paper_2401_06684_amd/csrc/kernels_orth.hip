@@ -573,7 +573,8 @@ __global__ __launch_bounds__(kThreads) void update2_k(int64_t n, int ncols, cons
 }
 
 hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv, void* part,
-                        void* S, void* H, int64_t ldh, void* coef, hipStream_t s) {
+                        void* S, void* H, int64_t ldh, void* coef, hipStream_t s, int stage) {
+  const bool proj = stage != kDcgs2Update, upd = stage != kDcgs2Project;
   const RedPlan p = red_plan(n);
   const RedPlan pp = dtype == FA_C128 ? proj_plan<cplx>(n) : proj_plan<double>(n);
   const size_t es = dtype == FA_C128 ? 16 : 8;
@@ -591,12 +592,13 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
   const size_t lds = 2 * (size_t)(j + 1) * es;
   const bool fused = lds <= 32768 && j <= 32 && 2 * (int64_t)(j + 1) * pp.nblk <= (1 << 17);
   if (dtype == FA_C128) {
-    project2_k<cplx><<<pp.nblk, proj_threads<cplx>(), 0, s>>>(n, j + 1, (const cplx*)V, ldv, (const cplx*)u,
-                                                 (const cplx*)z, (cplx*)part, pp.nblk);
-    if (fused) {
+    if (proj)
+      project2_k<cplx><<<pp.nblk, proj_threads<cplx>(), 0, s>>>(
+          n, j + 1, (const cplx*)V, ldv, (const cplx*)u, (const cplx*)z, (cplx*)part, pp.nblk);
+    if (proj && fused) {
       dcgs2_finish_k<cplx><<<1, kFinThreads, lds, s>>>(j, pp.nblk, (const cplx*)part, (cplx*)H,
                                                       ldh, (cplx*)cs, (cplx*)cp, (cplx*)sc);
-    } else {
+    } else if (proj) {
       reduce_cols_k<cplx><<<2 * (j + 1), kThreads, 0, s>>>(pp.nblk, (const cplx*)part, (cplx*)S,
                                                            nullptr, 0);
       dcgs2_coef_k<cplx><<<1, kThreads, 0, s>>>(j, (const cplx*)S, (cplx*)H, ldh, (cplx*)cs,
@@ -604,18 +606,20 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
       dcgs2_col_k<cplx><<<(j + 64) / 64, kThreads, 0, s>>>(j, (const cplx*)S, (cplx*)H, ldh,
                                                            (const cplx*)sc);
     }
-    update2_k<cplx><<<p.nblk, kThreads, 0, s>>>(n, j, (const cplx*)V, ldv, (const cplx*)cs,
+    if (upd)
+      update2_k<cplx><<<p.nblk, kThreads, 0, s>>>(n, j, (const cplx*)V, ldv, (const cplx*)cs,
                                                 (const cplx*)cp, (const cplx*)sc, (cplx*)u,
                                                 (cplx*)z);
   } else {
-    project2_k<double><<<pp.nblk, proj_threads<double>(), 0, s>>>(n, j + 1, (const double*)V, ldv,
-                                                   (const double*)u, (const double*)z,
-                                                   (double*)part, pp.nblk);
-    if (fused) {
+    if (proj)
+      project2_k<double><<<pp.nblk, proj_threads<double>(), 0, s>>>(
+          n, j + 1, (const double*)V, ldv, (const double*)u, (const double*)z, (double*)part,
+          pp.nblk);
+    if (proj && fused) {
       dcgs2_finish_k<double><<<1, kFinThreads, lds, s>>>(j, pp.nblk, (const double*)part,
                                                         (double*)H, ldh, (double*)cs,
                                                         (double*)cp, (double*)sc);
-    } else {
+    } else if (proj) {
       reduce_cols_k<double><<<2 * (j + 1), kThreads, 0, s>>>(pp.nblk, (const double*)part,
                                                              (double*)S, nullptr, 0);
       dcgs2_coef_k<double><<<1, kThreads, 0, s>>>(j, (const double*)S, (double*)H, ldh,
@@ -623,7 +627,8 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
       dcgs2_col_k<double><<<(j + 64) / 64, kThreads, 0, s>>>(j, (const double*)S, (double*)H,
                                                              ldh, (const double*)sc);
     }
-    update2_k<double><<<p.nblk, kThreads, 0, s>>>(n, j, (const double*)V, ldv,
+    if (upd)
+      update2_k<double><<<p.nblk, kThreads, 0, s>>>(n, j, (const double*)V, ldv,
                                                   (const double*)cs, (const double*)cp,
                                                   (const double*)sc, (double*)u, (double*)z);
   }

@@ -666,12 +666,21 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   // the basis (CGS2) or the two latest vectors (Lanczos), normalized into v_{j+1}.
   // phase 0: the whole step; phase 1: only u = A v_j and y = q(A) u
   // (Algorithm 1, K >= 1), y kept in half_y; phase 2: the rest of a step
-  // begun by phase 1
+  // begun by phase 1.  Delayed CGS2, j >= 1: phases 3 and 4 are phases 0
+  // and 2 without the update of the basis (H's column j - 1 is final after
+  // them), phase 5 is that update alone.
   int64_t ips = 0;
   const void* half_y = nullptr;
   auto step = [&](int j, int phase) -> int {
     char* vj = Vc(j);
     char* w = Vc(j + 1);
+    if (phase == 5) {
+      FA_HIP(launch_dcgs2(op.dtype, n, j, V, L.ldv, part, hcur, Hd, L.ldh, dcoef, s,
+                          kDcgs2Update));
+      return FA_OK;
+    }
+    const bool cont = phase == 2 || phase == 4;  // continues a step begun by phase 1
+    const bool no_update = phase == 3 || phase == 4;
     if (K == 0) {
       const int r = chain(op, vj, nullptr, nullptr, w, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, pp);
       if (r) return r;
@@ -689,7 +698,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       ++mvms;
     } else {  // Algorithm 1: u = A v_j, y = q(A) u, w = q(A) y
       const void* y = half_y;
-      if (phase != 2) {
+      if (!cont) {
         FA_HIP(launch_chain(op, vj, nullptr, nullptr, U, ChainCoef{1.0, 0.0, 0.0, 0.0}, s, P64,
                             pm));
         ++mvms;
@@ -721,7 +730,8 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
         FA_HIP(launch_update(op.dtype, n, 1, V, L.ldv, hcur, w, part, nullptr, s));
         ips += 1;
       } else {
-        FA_HIP(launch_dcgs2(op.dtype, n, j, V, L.ldv, part, hcur, Hd, L.ldh, dcoef, s));
+        FA_HIP(launch_dcgs2(op.dtype, n, j, V, L.ldv, part, hcur, Hd, L.ldh, dcoef, s,
+                            no_update ? kDcgs2Project : kDcgs2All));
         ips += 2 * (j + 1);
       }
       return FA_OK;
@@ -881,6 +891,14 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   const bool can_half =
       K > 0 && !right && !two_pass && tol > 0.0 && !(flags & kApplyNoAlloc) && !small;
   int half_j = -1;  // the step whose first half is enqueued
+  // Delayed CGS2: at a check the iteration is expected to pass, the next
+  // step is enqueued up to its projection before the check's data goes to
+  // the host.  That projection finishes column j of H on the device (its
+  // second pass), so no projection of u_{j+1} for the check is needed; the
+  // step's update and the first half of the step after it follow, so the
+  // GPU works through the check's round trip.  If the iteration stops there
+  // after all, their output is never read and their counts are undone.
+  const bool can_defer = dcgs2 && !two_pass && tol > 0.0 && !(flags & kApplyNoAlloc) && !small;
   std::vector<double> est_hist;
   auto run_step = [&](int j) -> int {
     if (small) {
@@ -911,12 +929,27 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     const int from = std::min(copied, refresh);
     double* const h_dst = H.buf + (size_t)from * L.ldh * ed;
     const int64_t h_len = (int64_t)(jj - from) * L.ldh * ed;  // doubles
-    // column j still lacks its second pass (done on the device in the next
-    // step): project u_{j+1} on [q_0 .. q_j, u_{j+1}] and finish the host
-    // copy: H(0:j, j) += s', H(j+1, j) = (||u_{j+1}||^2 - ||s'||^2)^{1/2}
-    if (dcgs2)
+    bool predict_more = true;
+    if (est_hist.size() >= 2 && est_hist[est_hist.size() - 2] > 0.0) {
+      const double a = est_hist[est_hist.size() - 2], b = est_hist.back();
+      predict_more = b * (b / a) > 10.0 * tol;
+    }
+    // counts and timings before the work enqueued ahead at this check
+    const int64_t mvms_pre = mvms, ips_pre = ips;
+    const Prof prof_pre = prof;
+    const bool defer = can_defer && predict_more && jj < m_max && jj >= ahead_until;
+    if (defer) {  // step jj up to its projection: column j of H final on the device
+      st = step(jj, half_j == jj ? 4 : 3);
+      if (st) return st;
+      half_j = -1;
+    }
+    // without it, column j still lacks its second pass (done on the device in
+    // the next step): project u_{j+1} on [q_0 .. q_j, u_{j+1}] and finish the
+    // host copy: H(0:j, j) += s', H(j+1, j) = (||u_{j+1}||^2 - ||s'||^2)^{1/2}
+    const bool fin_host = dcgs2 && !defer;
+    if (fin_host)
       FA_HIP(launch_project(op.dtype, n, jj + 1, V, L.ldv, Vc(jj), part, hcur, nullptr, 0, s));
-    const int64_t p_len = dcgs2 ? (int64_t)(jj + 1) * ed : 0;
+    const int64_t p_len = fin_host ? (int64_t)(jj + 1) * ed : 0;
     if (pin_dev) {
       FA_HIP(launch_check_export((const double*)Hcol(from), h_len, dev_of(h_dst),
                                  (const double*)hcur, p_len, dev_of(sh_host),
@@ -930,12 +963,23 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     }
     int64_t half_mvms = 0;  // counts of a half step enqueued at this check
     Prof prof_before_half = prof;
-    bool predict_more = true;
-    if (est_hist.size() >= 2 && est_hist[est_hist.size() - 2] > 0.0) {
-      const double a = est_hist[est_hist.size() - 2], b = est_hist.back();
-      predict_more = b * (b / a) > 10.0 * tol;
-    }
-    if (can_half && jj < m_max && predict_more) {
+    if (defer) {
+      // the rest of step jj and the first half of step jj + 1 (if any)
+      st = step(jj, 5);
+      if (st) return st;
+      ahead_until = jj + 1;
+      if (can_half && jj + 1 < m_max) {
+        st = step(jj + 1, 1);
+        if (st) return st;
+        half_j = jj + 1;
+      }
+      if (pin_dev) {
+        st = wait_flag(chk_seq);
+        if (st) return st;
+      } else {
+        FA_HIP(hipStreamSynchronize(s));
+      }
+    } else if (can_half && jj < m_max && predict_more) {
       hipEvent_t ev = nullptr;
       if (!pin_dev) {
         FA_HIP(check_event(&ev));
@@ -958,14 +1002,23 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     } else {
       FA_HIP(hipStreamSynchronize(s));
     }
-    // takes the half step's counts and timings back out (the iteration stops here)
+    // takes the counts and timings of what was enqueued ahead back out (the
+    // iteration stops here); the second pass of column j counts as the
+    // check's projection would
     auto undo_half = [&]() {
+      if (defer) {
+        mvms = mvms_pre;
+        ips = ips_pre + jj + 1;
+        prof = prof_pre;
+        half_j = -1;
+        return;
+      }
       if (half_j != jj) return;
       mvms -= half_mvms;
       prof = prof_before_half;
       half_j = -1;
     };
-    if (dcgs2) {
+    if (fin_host) {
       const double* sh = sh_host;
       auto sv = [&](int i) {
         return op.dtype == FA_C128 ? cd(sh[2 * i], sh[2 * i + 1]) : cd(sh[i], 0.0);
@@ -998,7 +1051,7 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       }
     }
     copied = jj;
-    refresh = dcgs2 ? j : jj;
+    refresh = fin_host ? j : jj;
     if (mb > 0) {
       undo_half();
       m = mb;
@@ -1006,19 +1059,20 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       break;
     }
     if (tol <= 0.0) break;
-    const int64_t mvms_here = mvms - (half_j == jj ? half_mvms : 0), ips_here = ips;
-    const Prof prof_here = half_j == jj ? prof_before_half : prof;
+    const int64_t mvms_here = defer ? mvms_pre : mvms - (half_j == jj ? half_mvms : 0);
+    const int64_t ips_here = defer ? ips_pre + jj + 1 : ips;
+    const Prof prof_here = defer ? prof_pre : half_j == jj ? prof_before_half : prof;
     {
       const double step_ms = (now_ms() - t_resume) / std::max(1, jj - j_resume);
       const double ratio = last_host_m > 0 ? (double)jj / last_host_m : 0.0;
       const double host_est = last_host_ms * ratio * ratio * ratio;
       int r = step_ms > 0.0 ? (int)(host_est / step_ms) : 0;
       r = std::min(r, std::min(k_chk - 1, m_max - jj));
-      for (int a = 0; a < r; ++a) {
-        st = run_step(jj + a);
+      for (int a = std::max(jj, ahead_until); a < jj + r; ++a) {
+        st = run_step(a);
         if (st) return st;
       }
-      ahead_until = jj + std::max(r, 0);
+      ahead_until = std::max(ahead_until, jj + std::max(r, 0));
     }
     const double th = now_ms();
     st = host_coeffs(H, jj, lanczos, beta, z);
