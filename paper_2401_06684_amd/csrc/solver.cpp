@@ -899,6 +899,8 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
   // GPU works through the check's round trip.  If the iteration stops there
   // after all, their output is never read and their counts are undone.
   const bool can_defer = dcgs2 && !two_pass && tol > 0.0 && !(flags & kApplyNoAlloc) && !small;
+  int64_t pend_mvms = 0;  // counts and timings before the first half of a step
+  Prof pend_prof = prof;  // that such a check enqueued (still pending at the next check)
   std::vector<double> est_hist;
   auto run_step = [&](int j) -> int {
     if (small) {
@@ -934,10 +936,17 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       const double a = est_hist[est_hist.size() - 2], b = est_hist.back();
       predict_more = b * (b / a) > 10.0 * tol;
     }
-    // counts and timings before the work enqueued ahead at this check
-    const int64_t mvms_pre = mvms, ips_pre = ips;
-    const Prof prof_pre = prof;
-    const bool defer = can_defer && predict_more && jj < m_max && jj >= ahead_until;
+    // counts and timings of the iteration so far, without the work enqueued
+    // ahead (a first half of step jj from the previous check, or what this
+    // check enqueues)
+    const bool pend = half_j == jj;
+    const int64_t mvms_base = pend ? mvms - pend_mvms : mvms, ips_base = ips;
+    const Prof prof_base = pend ? pend_prof : prof;
+    // (the first check cannot stop the iteration: its estimate is 1; the
+    // second has no extrapolation, and a step thrown away costs far more
+    // than the projection saved when the polynomial is long)
+    const bool defer = can_defer && jj < m_max && jj >= ahead_until &&
+                       ((est_hist.empty() && tol < 1.0) || (est_hist.size() >= 2 && predict_more));
     if (defer) {  // step jj up to its projection: column j of H final on the device
       st = step(jj, half_j == jj ? 4 : 3);
       if (st) return st;
@@ -961,16 +970,18 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
         FA_HIP(hipMemcpyAsync(sh_host, hcur, (size_t)p_len * sizeof(double),
                               hipMemcpyDeviceToHost, s));
     }
-    int64_t half_mvms = 0;  // counts of a half step enqueued at this check
-    Prof prof_before_half = prof;
     if (defer) {
       // the rest of step jj and the first half of step jj + 1 (if any)
       st = step(jj, 5);
       if (st) return st;
       ahead_until = jj + 1;
       if (can_half && jj + 1 < m_max) {
+        const int64_t m0 = mvms;
+        const Prof p0 = prof;
         st = step(jj + 1, 1);
         if (st) return st;
+        pend_mvms = mvms - m0;
+        pend_prof = p0;
         half_j = jj + 1;
       }
       if (pin_dev) {
@@ -979,16 +990,14 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       } else {
         FA_HIP(hipStreamSynchronize(s));
       }
-    } else if (can_half && jj < m_max && predict_more) {
+    } else if (can_half && jj < m_max && predict_more && !pend) {  // (pend: enqueued already)
       hipEvent_t ev = nullptr;
       if (!pin_dev) {
         FA_HIP(check_event(&ev));
         FA_HIP(hipEventRecord(ev, s));
       }
-      const int64_t m0 = mvms;
       st = step(jj, 1);
       if (st) return st;
-      half_mvms = mvms - m0;
       half_j = jj;
       if (pin_dev) {
         st = wait_flag(chk_seq);
@@ -1006,16 +1015,9 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     // iteration stops here); the second pass of column j counts as the
     // check's projection would
     auto undo_half = [&]() {
-      if (defer) {
-        mvms = mvms_pre;
-        ips = ips_pre + jj + 1;
-        prof = prof_pre;
-        half_j = -1;
-        return;
-      }
-      if (half_j != jj) return;
-      mvms -= half_mvms;
-      prof = prof_before_half;
+      mvms = mvms_base;
+      if (defer) ips = ips_base + jj + 1;
+      prof = prof_base;
       half_j = -1;
     };
     if (fin_host) {
@@ -1059,9 +1061,8 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
       break;
     }
     if (tol <= 0.0) break;
-    const int64_t mvms_here = defer ? mvms_pre : mvms - (half_j == jj ? half_mvms : 0);
-    const int64_t ips_here = defer ? ips_pre + jj + 1 : ips;
-    const Prof prof_here = defer ? prof_pre : half_j == jj ? prof_before_half : prof;
+    const int64_t mvms_here = mvms_base, ips_here = defer ? ips_base + jj + 1 : ips;
+    const Prof prof_here = prof_base;
     {
       const double step_ms = (now_ms() - t_resume) / std::max(1, jj - j_resume);
       const double ratio = last_host_m > 0 ? (double)jj / last_host_m : 0.0;

@@ -291,6 +291,29 @@ def test_check_overlap_leaves_no_trace(hermitian, check_every, kind):
     assert torch.equal(x, x2) and st2["mvms"] == st["mvms"]
 
 
+@pytest.mark.parametrize("N,degree,tol", [(10, 48, 1e-6), (10, 32, 1e-6), (12, 16, 1e-6),
+                                           (12, 48, 1e-8)])
+def test_checks_every_step_count_no_work_enqueued_ahead(N, degree, tol):
+    """Delayed CGS2 with a check after every step: a check the iteration is
+    expected to pass enqueues the next step and the first half of the one
+    after it; when the iteration stops at the following check (m = 2, 3, 4
+    here) neither may show in the counts.  Iterations and products with A
+    equal the oracle's, x agrees with it."""
+    dims = (N, N, N)
+    coeffs = wl.convdiff_stencil(N, 10.0)
+    op = fa().Stencil7(dims, coeffs)
+    op.poly_setup(degree, "cheb")
+    b = wl.rhs(op.n, seed=3)
+    x, st = op.apply(dev(b), m_max=50, tol=tol, check_every=1)
+    a, bb = ops.stencil_interval(coeffs, dims)
+    orc = kr.fAb(lambda v: ops.stencil_apply(coeffs, dims, v), b, pl.chebyshev(a, bb, degree),
+                 "invsqrt", m_max=50, tol=tol, check_every=1, orth="cgs2")
+    assert st["converged"] == 1
+    assert st["iters"] == orc.iters
+    assert st["mvms"] == orc.mvms
+    assert_close(host(x), orc.x, 1e-10)
+
+
 @pytest.mark.parametrize("degree", [0, 8])
 def test_poisson2d_32_lanczos(degree):
     """2D Poisson 32x32, CSR, Hermitian: Lanczos, m_max 200.  Compared at
