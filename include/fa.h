@@ -162,8 +162,10 @@ typedef struct {
   int32_t checks;         /* number of host evaluations of H_j^{-1/2} e_1               */
   int64_t mvms;           /* products with A in fa_apply: m (2K + 1) + K (+1 for sqrt)  */
   int64_t mvms_setup;     /* products with A in fa_poly_setup (Ritz: d)                 */
-  int64_t inner_products; /* length-n inner products in the iteration (CGS2: 2j + 1 at
-                             step j; Lanczos: 2 per step)                                */
+  int64_t inner_products; /* length-n inner products in the iteration (FA_CGS2: 2j + 1
+                             at step j of m; delayed CGS2: 2j at step j, its second
+                             pass taken in step j + 1, plus j + 1 for a check that
+                             projects u_{j+1} itself; Lanczos: 2 per step)              */
   double est_rel_change;  /* last ||f_j - f_{j-k}|| / ||f_j||                           */
   double h_last;          /* h_{m+1,m}                                                  */
   double ms_total;        /* wall time of fa_apply                                      */
