@@ -197,9 +197,10 @@ hipError_t launch_chain(const Op& op, const void* x, const void* y0, const void*
 struct RedPlan {
   int nblk;     // blocks of the first stage
   int rows;     // rows per block
+  int threads;  // threads per block
 };
 RedPlan red_plan(int64_t n);
-// first-stage blocks of the projections on vectors of `dtype` (at least red_plan's)
+// first-stage blocks of the projections on vectors of `dtype`
 int proj_nblk(int64_t n, int dtype);
 // h[c] = sum_r conj(V[r, c]) w[r], c < ncols (h may be null); hsum_mode 1 also
 // stores hsum[c] = h[c], mode 2 adds it (CGS2: H(:, j) = h1 + h2), 0 ignores hsum

@@ -52,18 +52,27 @@ template <typename T>
 constexpr int proj_cb() {
   return sizeof(T) == 16 ? FA_PROJ_CPLX_CB : kCb;
 }
-// threads per workgroup of the projections
-// Real projections run 512-thread workgroups (4096 rows): half the partial
-// sums of 256-thread ones for the one-workgroup finish of the delayed CGS2
-// to read (128^3: 512 workgroups, 2 (j + 1) x 512 partials); the plain
-// 128^3 solve (m = 448) took 2 % less time, the degree-16 one 0.6 %.
+// threads per workgroup of the projections (the kernels' default)
 template <typename T>
 constexpr int proj_threads() {
-  return sizeof(T) == 16 ? FA_PROJ_CPLX_NTH : 2 * kThreads;
+  return sizeof(T) == 16 ? FA_PROJ_CPLX_NTH : kThreads * kRpt / proj_rpt<T>();
+}
+// Real projections of vectors of at least 512 x 4096 entries run 512-thread
+// workgroups (4096 rows), still two per CU: half the partial sums for the
+// one-workgroup finish of the delayed CGS2 to read (128^3: 2 (j + 1) x 512);
+// the plain 128^3 solve (m = 448) took 2 % less time, the degree-16 one
+// 0.6 %.  Smaller vectors keep 256 threads: at n = 281,903 the wider
+// workgroups left 69 of them and the solves ran 8-11 % slower.
+constexpr int kProjWide = 2 * kThreads;
+template <typename T>
+static int proj_nth(int64_t n) {
+  if (sizeof(T) == 16) return FA_PROJ_CPLX_NTH;
+  return n >= (int64_t)512 * kProjWide * kRpt ? kProjWide : proj_threads<T>();
 }
 
 RedPlan red_plan(int64_t n) {
   RedPlan p;
+  p.threads = kThreads;
   p.rows = kThreads * kRpt;
   p.nblk = (int)((n + p.rows - 1) / p.rows);
   return p;
@@ -72,7 +81,8 @@ RedPlan red_plan(int64_t n) {
 template <typename T>
 static RedPlan proj_plan(int64_t n) {
   RedPlan p;
-  p.rows = proj_threads<T>() * proj_rpt<T>();
+  p.threads = proj_nth<T>(n);
+  p.rows = p.threads * proj_rpt<T>();
   p.nblk = (int)((n + p.rows - 1) / p.rows);
   return p;
 }
@@ -615,7 +625,11 @@ hipError_t launch_dcgs2(int dtype, int64_t n, int j, const void* V, int64_t ldv,
                                                 (const cplx*)cp, (const cplx*)sc, (cplx*)u,
                                                 (cplx*)z);
   } else {
-    if (proj)
+    if (proj && pp.threads == kProjWide)
+      project2_k<double, kRpt, kProjWide><<<pp.nblk, kProjWide, 0, s>>>(
+          n, j + 1, (const double*)V, ldv, (const double*)u, (const double*)z, (double*)part,
+          pp.nblk);
+    else if (proj)
       project2_k<double><<<pp.nblk, proj_threads<double>(), 0, s>>>(
           n, j + 1, (const double*)V, ldv, (const double*)u, (const double*)z, (double*)part,
           pp.nblk);
@@ -644,6 +658,14 @@ template <typename T>
 static hipError_t project_t(int64_t n, int ncols, const T* V, int64_t ldv, const T* w, T* part,
                             T* h, T* hsum, int mode, hipStream_t s) {
   const RedPlan p = proj_plan<T>(n);
+  if constexpr (sizeof(T) == 8) {
+    if (p.threads == kProjWide) {
+      project_k<T, kRpt, kProjWide><<<p.nblk, kProjWide, 0, s>>>(n, ncols, V, ldv, w, part,
+                                                                 p.nblk);
+      reduce_cols_k<T><<<ncols, kThreads, 0, s>>>(p.nblk, part, h, hsum, mode);
+      return hipGetLastError();
+    }
+  }
   project_k<T><<<p.nblk, proj_threads<T>(), 0, s>>>(n, ncols, V, ldv, w, part, p.nblk);
   reduce_cols_k<T><<<ncols, kThreads, 0, s>>>(p.nblk, part, h, hsum, mode);
   return hipGetLastError();
