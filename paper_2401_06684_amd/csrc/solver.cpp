@@ -821,26 +821,42 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
 
   st = start_vector();
   if (st) return st;
-  if (pin_dev) {  // ||c||^2 to the host through the flag (see the checks)
+  const int64_t mvms_start = mvms;
+  // ||c||^2 to the host.  With page-locked memory it goes through the flag
+  // without a wait here: beta is first needed at the first check, whose
+  // data arrive after it, so the steps are enqueued at once.  A zero or
+  // nonfinite ||c|| is then handled at that check (the steps before it ran
+  // on the zero vector the normalization leaves).
+  bool beta_pending = false;
+  if (pin_dev) {
     FA_HIP(launch_check_export(nrm, 1, dev_of(sc_host), nullptr, 0, nullptr,
                                (int*)dev_of(sc_host + 3), chk_seq = next_seq(), s));
-    st = wait_flag(chk_seq);
-    if (st) return st;
+    beta_pending = true;
   } else {
     FA_HIP(hipMemcpyAsync(sc_host, nrm, sizeof(double), hipMemcpyDeviceToHost, s));
     FA_HIP(hipStreamSynchronize(s));
   }
-  const double beta2 = sc_host[0];
-  if (!std::isfinite(beta2)) return FA_ERR_NONFINITE;
-  const double beta = std::sqrt(beta2);
-  if (beta == 0.0) {
-    FA_HIP(launch_scale(op.dtype, n, cd(0.0), Vc(0), d_x, s));
-    FA_HIP(hipStreamSynchronize(s));
-    S.converged = 1;
-    S.mvms = mvms;
-    S.ms_total = now_ms() - t0;
-    if (stats) *stats = S;
+  double beta = 0.0;
+  // beta from the host copy of ||c||^2; `done`: b' = 0 gave x = 0 (returned)
+  auto take_beta = [&](bool& done) -> int {
+    const double beta2 = sc_host[0];
+    if (!std::isfinite(beta2)) return FA_ERR_NONFINITE;
+    beta = std::sqrt(beta2);
+    done = beta == 0.0;
+    if (done) {
+      FA_HIP(launch_scale(op.dtype, n, cd(0.0), Vc(0), d_x, s));
+      FA_HIP(hipStreamSynchronize(s));
+      S.converged = 1;
+      S.mvms = mvms_start;
+      S.ms_total = now_ms() - t0;
+      if (stats) *stats = S;
+    }
     return FA_OK;
+  };
+  if (!beta_pending) {
+    bool done = false;
+    st = take_beta(done);
+    if (st || done) return st;
   }
 
   HostH H;
@@ -1011,6 +1027,12 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     } else {
       FA_HIP(hipStreamSynchronize(s));
     }
+    if (beta_pending) {  // ||c||^2 arrived with this check's data
+      beta_pending = false;
+      bool done = false;
+      st = take_beta(done);
+      if (st || done) return st;
+    }
     // takes the counts and timings of what was enqueued ahead back out (the
     // iteration stops here); the second pass of column j counts as the
     // check's projection would
@@ -1120,6 +1142,13 @@ int apply(const Op& op, int kind, const void* d_b, void* d_x, int m_max, double 
     }
     t_resume = now_ms();
     j_resume = std::max(jj, ahead_until);
+  }
+  if (beta_pending) {  // (no check ran)
+    FA_HIP(hipStreamSynchronize(s));
+    beta_pending = false;
+    bool done = false;
+    st = take_beta(done);
+    if (st || done) return st;
   }
   // final coefficients (if the loop did not end on a fresh check of size m)
   if ((int)z.size() != m || breakdown) {
